@@ -29,6 +29,8 @@ def lib():
         ip = ctypes.POINTER(ctypes.c_int)
         u32p = ctypes.POINTER(ctypes.c_uint32)
         L4 = ctypes.c_int * 4
+        L.orc_num_threads.argtypes = []
+        L.orc_num_threads.restype = ctypes.c_int
         L.orc_philox4x32_10.argtypes = [u32p, u32p, u32p]
         L.orc_uniform.argtypes = [ctypes.c_uint32]
         L.orc_uniform.restype = ctypes.c_double
@@ -82,6 +84,10 @@ def _field(U, nc, L):
 
 def valid(nc, L):
     return lib().orc_check(int(nc), _L4(L)) == 0
+
+
+def num_threads():
+    return int(lib().orc_num_threads())
 
 
 def philox(ctr, key):

@@ -37,6 +37,7 @@
 
 #include <complex.h>
 #include <math.h>
+#include <omp.h>
 #include <stdlib.h>
 #include <string.h>
 
@@ -72,6 +73,11 @@ void orc_philox4x32_10(const uint32_t ctr[4], const uint32_t key[2], uint32_t ou
         k1 += W1;
     }
     out[0] = c[0]; out[1] = c[1]; out[2] = c[2]; out[3] = c[3];
+}
+
+int orc_num_threads(void)
+{
+    return omp_get_max_threads();
 }
 
 /* 24-bit uniform in (0, 1]; exactly representable in float and double. */

@@ -31,6 +31,9 @@
 extern "C" {
 #endif
 
+/* OpenMP threads the lattice-wide calls use. */
+int orc_num_threads(void);
+
 /* Raw generator, for known-answer tests. */
 void orc_philox4x32_10(const uint32_t ctr[4], const uint32_t key[2], uint32_t out[4]);
 double orc_uniform(uint32_t w);
