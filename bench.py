@@ -1,0 +1,188 @@
+#!/usr/bin/env python3
+"""Throughput of the SU(3) Wilson-action checkerboard sweep on one MI355X.
+
+Workload: SU(3), 32^4 periodic lattice, beta = 6.2, Haar hot start, FP32 link
+storage with FP64 reductions and FP64 re-unitarization.  One step is one pass
+of the whole hot path over the lattice: 1 heatbath step + 4 overrelaxation
+steps (each 4 directions x {even, odd} phases), re-unitarization (reporting
+the unitarity drift it removed), the plaquette (FP64) and the Polyakov loop.
+The same workload with FP64 link storage is timed beside it.
+
+Prints one JSON line.  `value` is link updates per second (one update = one
+heatbath or overrelaxation visit of one link) with the field resident in HBM.
+"""
+import argparse
+import json
+import os
+import sys
+import time
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+PEAK_HBM_GBS = 8000.0           # MI355X HBM3E, published peak
+METRIC = "link updates/sec + HBM GB/s (%roofline), SU(3) 32^4, batched FP32 vs plain FP64"
+
+
+def link_bytes(nc, dtype):
+    reals = 4 if nc == 2 else 2 * nc * nc
+    return reals * (4 if dtype == "f32" else 8)
+
+
+def phase_bytes(nc, V, dtype):
+    """Algorithmic HBM bytes of one checkerboard phase: the whole field is
+    read once (4V links: the updated U_mu of both parities and every U_nu),
+    and the V/2 updated links are written: 9 link transfers per update."""
+    return 9 * link_bytes(nc, dtype) * (V // 2)
+
+
+def step_bytes(nc, V, dtype, n_hb, n_or):
+    """Per step: 8 (n_hb + n_or) phases, re-unitarization (read + write 4V),
+    plaquette (read 4V), Polyakov loop (read V)."""
+    lb = link_bytes(nc, dtype)
+    return 8 * (n_hb + n_or) * phase_bytes(nc, V, dtype) + (8 * V + 4 * V + V) * lb
+
+
+def run_gpu(run, steps, warmup):
+    import torch
+    from paper_1112_4533_amd import sun
+
+    lat = sun.Lattice(run.nc, run.L, run.dtype)
+    lat.init(hot=run.hot, seed=run.seed)
+    dev = lat.links.device
+    plaq = torch.zeros(3, dtype=torch.float64, device=dev)
+    poly = torch.zeros(2, dtype=torch.float64, device=dev)
+    drift = torch.zeros(2, dtype=torch.float64, device=dev)
+    lib, stream = sun.load(), sun._stream()
+
+    def step():
+        lat.sweep(run.beta, run.n_hb, run.n_or, seed=run.seed, reunit=False)
+        sun._check(lib.sun_reunitarize(lat._h, sun._ptr(drift), stream))
+        lat.plaquette(plaq)
+        lat.polyakov(poly)
+
+    for _ in range(warmup):
+        step()
+    torch.cuda.synchronize()
+    lat.profile(True)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for _ in range(steps):
+        step()
+    torch.cuda.synchronize()
+    elapsed = time.perf_counter() - t0
+    kernels = {}
+    for name in ("heatbath", "overrelax", "reunit", "plaquette", "polyakov"):
+        ms, n = lat.profile_read(name)
+        kernels[name] = {"avg_ms": ms / n if n else None, "launches": n}
+    lat.profile(False)
+    V = run.volume
+    updates = steps * (run.n_hb + run.n_or) * 4 * V
+    return {
+        "elapsed_s": elapsed,
+        "ms_per_step": 1e3 * elapsed / steps,
+        "updates_per_s": updates / elapsed,
+        "kernels": kernels,
+        "plaquette": plaq.cpu().tolist(),
+        "polyakov": poly.cpu().tolist(),
+        "unitarity_before_reunit": drift.cpu().tolist(),
+        "step_counter": lat.step,
+    }
+
+
+def run_cpu_baseline(run):
+    """The FP64 CPU oracle on a bounded sample of the same workload: one full
+    sweep (1 HB + 4 OR, re-unitarization, plaquette) of the 32^4 lattice."""
+    import oracle as O
+
+    U = O.new_field(run.nc, run.L, hot=run.hot, seed=run.seed)
+    t0 = time.perf_counter()
+    O.sweep(U, run.nc, run.L, run.beta, run.n_hb, run.n_or, run.seed, 0, reunit=True)
+    O.plaquette(U, run.nc, run.L)
+    dt = time.perf_counter() - t0
+    updates = (run.n_hb + run.n_or) * 4 * run.volume
+    return {
+        "value": updates / dt,
+        "unit": "link_updates/s",
+        "cores": O.num_threads(),
+        "kind": "oracle",
+        "sample": (f"1 sweep (1 HB + 4 OR + re-unitarization + plaquette) of SU(3) {run.L[0]}^4, FP64, "
+                   f"{updates} link updates in {dt:.2f} s"),
+    }
+
+
+def main():
+    ap = argparse.ArgumentParser(description=__doc__, formatter_class=argparse.RawDescriptionHelpFormatter)
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=20)
+    ap.add_argument("--warmup", type=int, default=3)
+    ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--no-f64", action="store_true")
+    args = ap.parse_args()
+    if args.gpus != 1:
+        print(f"bench.py: this build runs on one GPU; --gpus {args.gpus} is not supported "
+              "(independent chains shard without communication; one lattice needs a halo exchange per phase)",
+              file=sys.stderr)
+        sys.exit(2)
+
+    from paper_1112_4533_amd.workloads import SU3_32_F32, SU3_32_F64
+
+    run = SU3_32_F32
+    r32 = run_gpu(run, args.steps, args.warmup)
+    r64 = None if args.no_f64 else run_gpu(SU3_32_F64, max(2, args.steps // 2), max(1, args.warmup // 2))
+
+    V = run.volume
+    k_or = r32["kernels"]["overrelax"]
+    per_launch = phase_bytes(run.nc, V, run.dtype)
+    achieved = per_launch / (k_or["avg_ms"] * 1e-3) / 1e9
+    line = {
+        "metric": METRIC,
+        "value": r32["updates_per_s"],
+        "unit": "link_updates/s",
+        "n_gpus": 1,
+        "steps": args.steps,
+        "warmup": args.warmup,
+        "ms_per_step": r32["ms_per_step"],
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "f32",
+        "data": "synthetic (Haar hot start from Philox, seed 1234)",
+        "config": {
+            "workload": run.name, "nc": run.nc, "L": list(run.L), "beta": run.beta,
+            "n_hb": run.n_hb, "n_or": run.n_or, "reunit": "every sweep",
+            "step": "sweep + reunitarize(drift) + plaquette + polyakov",
+        },
+        "roofline": {
+            "bound": "hbm",
+            "kernel": "overrelaxation phase (k_update<3,float,OR>)",
+            "achieved": achieved,
+            "peak": PEAK_HBM_GBS,
+            "unit": "GB/s",
+            "frac": achieved / PEAK_HBM_GBS,
+            "traffic": None,
+            "bytes_per_launch": per_launch,
+            "avg_launch_ms": k_or["avg_ms"],
+        },
+        "effective_GBps_whole_step": step_bytes(run.nc, V, run.dtype, run.n_hb, run.n_or) / (r32["ms_per_step"] * 1e-3) / 1e9,
+        "kernels": r32["kernels"],
+        "accuracy": {
+            "plaquette": r32["plaquette"],
+            "polyakov": r32["polyakov"],
+            "max_unitarity_dev_before_reunit": r32["unitarity_before_reunit"],
+        },
+    }
+    if r64:
+        line["fp64"] = {
+            "value": r64["updates_per_s"], "unit": "link_updates/s", "ms_per_step": r64["ms_per_step"],
+            "steps": max(2, args.steps // 2), "kernels": r64["kernels"], "plaquette": r64["plaquette"],
+            "max_unitarity_dev_before_reunit": r64["unitarity_before_reunit"],
+            "f32_over_f64": r32["updates_per_s"] / r64["updates_per_s"],
+        }
+    if not args.no_cpu_baseline:
+        line["cpu_baseline"] = run_cpu_baseline(run)
+    print(json.dumps(line), flush=True)
+
+
+if __name__ == "__main__":
+    main()

@@ -1,0 +1,148 @@
+/*
+ * sun.h -- C ABI of libsun, the MI355X (gfx950) implementation of the
+ * pure-gauge SU(Nc) Wilson-action checkerboard sweep of Cardoso & Bicudo,
+ * "Generating SU(Nc) pure gauge lattice QCD configurations on GPUs with CUDA"
+ * (arXiv:1112.4533).
+ *
+ * Conventions shared by every call
+ * --------------------------------
+ *  - Every function returns SUN_OK (0) or a negative SUN_E* code; the text of
+ *    the last error of the calling thread is returned by sun_last_error().
+ *  - Device memory is owned by the caller.  The library allocates no device
+ *    memory; the link field and a scratch buffer are handed in at creation
+ *    and must outlive the handle.  Sizes come from sun_lattice_bytes().
+ *  - Every call that takes a stream is asynchronous on that stream (a
+ *    hipStream_t passed as void*; NULL is the null stream).  Output pointers
+ *    named dev_* are device pointers written by kernels on that stream.
+ *  - A handle is used by one host thread at a time.  Calls on one handle that
+ *    overlap on different streams race on its scratch buffer.
+ *  - Lattice: extents L[0..3] (directions x, y, z, t).  L[0] is even >= 2;
+ *    every other extent is even >= 2, or 1 for an absent direction (2D and 3D
+ *    lattices).  Links of absent directions are the identity and are never
+ *    updated.  Site index s = x + L0*(y + L1*(z + L2*t)), parity
+ *    (x+y+z+t) mod 2.  Periodic boundaries (paper Sec. 2).
+ *  - Randomness: Philox4x32-10 (Salmon et al., SC'11) with key
+ *    (lo32(seed), hi32(seed)) and counter
+ *    (site, lo32(step), (mu << 16) | subgroup, (purpose << 24) | attempt);
+ *    uniforms u = ((w >> 8) + 1) * 2^-24.  Heatbath step h of a sweep uses
+ *    step = (current step counter) + h; the counter advances by n_hb per sweep
+ *    and is part of the chain state (sun_get_step / sun_set_step).
+ */
+#ifndef SUN_H
+#define SUN_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef struct sun_lattice_s *sun_lattice_t;
+typedef void *sun_stream_t; /* hipStream_t */
+
+enum {
+    SUN_OK = 0,
+    SUN_EINVAL = -1, /* bad Nc, extent, dtype, direction, parity or count */
+    SUN_ESIZE = -2,  /* null or undersized buffer */
+    SUN_EHIP = -3,   /* a HIP runtime error (text in sun_last_error) */
+    SUN_EUNSUP = -4  /* valid request this build does not implement */
+};
+
+/* Link storage precision.  Reductions, re-unitarization and the start
+ * configuration are always computed in FP64. */
+enum { SUN_F32 = 0, SUN_F64 = 1 };
+
+/* Update kinds of one checkerboard phase (paper Sec. 3 kernel list). */
+enum { SUN_HEATBATH = 0, SUN_OVERRELAX = 1 };
+
+/* Largest Nc this build instantiates. */
+#define SUN_NC_MAX 8
+
+/* Bytes of device memory a lattice needs: the link field (SoA planes split by
+ * direction, parity and matrix element) and the scratch buffer used by the
+ * reductions.  Either output pointer may be NULL. */
+int sun_lattice_bytes(int nc, const int L[4], int dtype, size_t *link_bytes,
+                      size_t *scratch_bytes);
+
+/* Creates a handle over caller-owned device buffers (links: link_bytes,
+ * scratch: scratch_bytes, both 256-byte aligned).  Nc in 2..SUN_NC_MAX.
+ * The field content is undefined until sun_init or sun_import. */
+int sun_lattice_create(int nc, const int L[4], int dtype, void *links, size_t link_bytes,
+                       void *scratch, size_t scratch_bytes, sun_lattice_t *out);
+void sun_lattice_destroy(sun_lattice_t h);
+
+/* Start configuration (paper Sec. 3, "Initialization of the lattice
+ * array"): cold (hot = 0) sets every link to the identity; hot draws each
+ * link Haar-distributed (complex Gaussian matrix from Box-Muller on Philox
+ * uniforms, then the re-unitarization below).  Resets the step counter to 0. */
+int sun_init(sun_lattice_t h, int hot, uint64_t seed, sun_stream_t stream);
+
+/* One checkerboard phase (paper Sec. 3: the update kernels run by direction
+ * and by even/odd sites): updates U_mu(x) for every site x of the given
+ * parity by the Cabibbo-Marinari pseudo-heatbath (kind SUN_HEATBATH, paper
+ * Sec. 2, using RNG step `step`) or by subgroup overrelaxation (kind
+ * SUN_OVERRELAX, paper Sec. 2).  Does not touch the step counter. */
+int sun_phase(sun_lattice_t h, int kind, int mu, int parity, double beta, uint64_t seed,
+              uint64_t step, sun_stream_t stream);
+
+/* One sweep (paper Sec. 4 protocol): n_hb heatbath steps, then n_or
+ * overrelaxation steps, each step running for mu = 0..3 the even then the
+ * odd phase; then, if reunit != 0, re-unitarization of every link.  The
+ * heatbath steps use RNG steps counter .. counter + n_hb - 1; the counter
+ * then advances by n_hb. */
+int sun_sweep(sun_lattice_t h, double beta, int n_hb, int n_or, uint64_t seed, int reunit,
+              sun_stream_t stream);
+
+/* Re-unitarization (paper Sec. 2, last paragraph), in FP64: Nc = 2 normalizes
+ * the quaternion; Nc = 3 Gram-Schmidt on rows 0, 1 and row 2 =
+ * conj(row0 x row1); Nc > 3 Gram-Schmidt on all rows, then the last row times
+ * conj(det)/|det|.  If dev_out2 is not NULL it receives the deviation of the
+ * field BEFORE projection: {max_ij |(U^dag U - 1)_ij|, max |det U - 1|}. */
+int sun_reunitarize(sun_lattice_t h, double *dev_out2, sun_stream_t stream);
+
+/* Mean plaquette (paper Sec. 2, plaquette; Sec. 3, plaquette kernel with a
+ * reduction over sites), in FP64 with a deterministic reduction order:
+ * dev_out3 = {mean of ReTr P/Nc over all planes, over planes without
+ * direction 3, over planes with direction 3}. */
+int sun_plaquette(sun_lattice_t h, double *dev_out3, sun_stream_t stream);
+
+/* Polyakov loop along direction 3, (1/(Nc Vs)) sum_x Tr prod_t U_3(x, t),
+ * FP64: dev_out2 = {Re, Im}. */
+int sun_polyakov(sun_lattice_t h, double *dev_out2, sun_stream_t stream);
+
+/* Unitarity diagnostics, FP64: dev_out2 = {max_ij |(U^dag U - 1)_ij|,
+ * max |det U - 1|} over present links. */
+int sun_unitarity(sun_lattice_t h, double *dev_out2, sun_stream_t stream);
+
+/* Field in the canonical layout: 4*V*Nc*Nc complex FP64 values, indexed
+ * [mu][s][i][j], (re, im) interleaved, on the device.  Import of Nc = 2 reads
+ * row 0 of each matrix (an SU(2) matrix is fixed by it). */
+int sun_export(sun_lattice_t h, double *dev_canonical, sun_stream_t stream);
+int sun_import(sun_lattice_t h, const double *dev_canonical, sun_stream_t stream);
+
+/* RNG step counter (chain state for checkpoint / resume). */
+int sun_get_step(sun_lattice_t h, uint64_t *step);
+int sun_set_step(sun_lattice_t h, uint64_t step);
+
+/* Per-kernel timing with HIP events recorded around each launch on the
+ * launch stream.  kernel: 0 heatbath phase, 1 overrelaxation phase,
+ * 2 re-unitarization, 3 plaquette, 4 Polyakov loop.  sun_profile(h, 1)
+ * clears and starts recording; sun_profile_read synchronizes the recorded
+ * events and returns the summed milliseconds and the launch count. */
+int sun_profile(sun_lattice_t h, int enable);
+int sun_profile_read(sun_lattice_t h, int kernel, double *total_ms, int64_t *launches);
+
+/* The SU(2) heatbath draw alone (paper Sec. 2, SU(2) heatbath), for tests:
+ * for i < n draws x in SU(2) with density ~ exp(alpha[i] x0) dHaar using the
+ * counter (i, step, mu_sg, ...), computing in the given dtype.  dev_x gets 4n
+ * doubles, dev_attempts n ints (0 = attempt cap reached). */
+int sun_sample_su2(int dtype, const double *dev_alpha, int n, uint64_t seed, uint32_t step,
+                   uint32_t mu_sg, double *dev_x, int *dev_attempts, sun_stream_t stream);
+
+const char *sun_last_error(void);
+
+#ifdef __cplusplus
+}
+#endif
+#endif /* SUN_H */

@@ -1,0 +1,394 @@
+// sun_api.hip -- the C ABI of libsun (declared in include/sun.h): argument
+// checks, lattice handles, the phase schedule of a sweep, reductions and
+// per-kernel event timing.  All device work is done by the kernels of
+// sun_kernels.hpp; this file only validates and launches.
+#include <hip/hip_runtime.h>
+
+#include <cstdarg>
+#include <cstdio>
+#include <cstring>
+#include <string>
+#include <vector>
+
+#include "sun.h"
+#include "sun_kernels.hpp"
+#include "sun_ops.hpp"
+
+namespace {
+
+thread_local std::string g_last_error;
+
+int fail(int code, const char* fmt, ...) __attribute__((format(printf, 2, 3)));
+int fail(int code, const char* fmt, ...) {
+    char buf[512];
+    va_list ap;
+    va_start(ap, fmt);
+    vsnprintf(buf, sizeof buf, fmt, ap);
+    va_end(ap);
+    g_last_error = buf;
+    return code;
+}
+
+int hip_check(hipError_t e, const char* what) {
+    if (e == hipSuccess) return SUN_OK;
+    return fail(SUN_EHIP, "%s: %s", what, hipGetErrorString(e));
+}
+
+// Any launch error of the kernels just queued.
+int launch_check(const char* what) { return hip_check(hipGetLastError(), what); }
+
+constexpr int kKernels = 5;  // heatbath, overrelaxation, reunit, plaquette, polyakov
+
+}  // namespace
+
+struct sun_lattice_s {
+    int nc = 0;
+    int dtype = 0;
+    sun::Geom g{};
+    void* links = nullptr;
+    double* scratch = nullptr;
+    uint64_t step = 0;
+    const sun::Ops* ops = nullptr;
+    // event timing
+    bool profiling = false;
+    struct Pending {
+        int kernel;
+        hipEvent_t a, b;
+    };
+    std::vector<Pending> pending;
+    std::vector<hipEvent_t> pool;
+    double total_ms[kKernels] = {};
+    int64_t launches[kKernels] = {};
+
+    sun::Ctx ctx(hipStream_t s) const { return sun::Ctx{links, g, s}; }
+};
+
+namespace {
+
+const sun::Ops* ops_for(int nc, int f64) {
+    switch (nc) {
+        case 2: return sun::ops_nc2(f64);
+        case 3: return sun::ops_nc3(f64);
+        case 4: return sun::ops_nc4(f64);
+        case 5: return sun::ops_nc5(f64);
+        case 6: return sun::ops_nc6(f64);
+        case 7: return sun::ops_nc7(f64);
+        case 8: return sun::ops_nc8(f64);
+        default: return nullptr;
+    }
+}
+
+int check_lattice(int nc, const int L[4], int dtype) {
+    if (!L) return fail(SUN_EINVAL, "L is null");
+    if (nc < 2 || nc > SUN_NC_MAX) return fail(SUN_EINVAL, "Nc = %d outside 2..%d", nc, SUN_NC_MAX);
+    if (dtype != SUN_F32 && dtype != SUN_F64) return fail(SUN_EINVAL, "dtype %d is neither SUN_F32 nor SUN_F64", dtype);
+    if (L[0] < 2 || (L[0] & 1)) return fail(SUN_EINVAL, "L[0] = %d must be even and >= 2", L[0]);
+    long long V = 1;
+    for (int mu = 0; mu < 4; ++mu) {
+        if (!(L[mu] == 1 || (L[mu] >= 2 && !(L[mu] & 1))))
+            return fail(SUN_EINVAL, "L[%d] = %d must be 1 or even >= 2 (checkerboard)", mu, L[mu]);
+        V *= L[mu];
+    }
+    if (4 * V >= (1LL << 31)) return fail(SUN_EINVAL, "volume %lld too large (4V must fit in int32)", V);
+    return SUN_OK;
+}
+
+sun::Geom make_geom(const int L[4]) {
+    sun::Geom g{};
+    int V = 1;
+    g.present = 0;
+    for (int mu = 0; mu < 4; ++mu) {
+        g.L[mu] = L[mu];
+        g.stride[mu] = V;
+        V *= L[mu];
+        if (L[mu] > 1) g.present |= 1 << mu;
+    }
+    g.V = V;
+    g.Vh = V / 2;
+    return g;
+}
+
+size_t link_bytes_of(int nc, const sun::Geom& g, int dtype) {
+    const size_t reals = (nc == 2) ? 4 : 2 * (size_t)nc * nc;
+    return reals * 4 * (size_t)g.V * (dtype == SUN_F64 ? 8 : 4);
+}
+
+size_t scratch_bytes_of(const sun::Geom& g) {
+    const int nblk = sun::link_blocks(g);  // the largest partial array
+    const size_t b = 2 * sizeof(double) * (size_t)nblk;
+    return (b + 255) & ~(size_t)255;
+}
+
+inline hipStream_t as_stream(sun_stream_t s) { return reinterpret_cast<hipStream_t>(s); }
+
+// Records an event pair around one launch when profiling is on.
+struct Timed {
+    sun_lattice_s* h;
+    int kernel;
+    hipStream_t s;
+    hipEvent_t a = nullptr, b = nullptr;
+    int rc = SUN_OK;
+    Timed(sun_lattice_s* h_, int k, hipStream_t s_) : h(h_), kernel(k), s(s_) {
+        if (!h->profiling) return;
+        for (hipEvent_t* e : {&a, &b}) {
+            if (!h->pool.empty()) {
+                *e = h->pool.back();
+                h->pool.pop_back();
+            } else if ((rc = hip_check(hipEventCreate(e), "hipEventCreate")) != SUN_OK) {
+                return;
+            }
+        }
+        rc = hip_check(hipEventRecord(a, s), "hipEventRecord");
+    }
+    int done() {
+        if (!h->profiling || rc != SUN_OK) return rc;
+        rc = hip_check(hipEventRecord(b, s), "hipEventRecord");
+        if (rc == SUN_OK) h->pending.push_back({kernel, a, b});
+        return rc;
+    }
+};
+
+}  // namespace
+
+extern "C" {
+
+const char* sun_last_error(void) { return g_last_error.c_str(); }
+
+int sun_lattice_bytes(int nc, const int L[4], int dtype, size_t* link_bytes, size_t* scratch_bytes) {
+    if (int rc = check_lattice(nc, L, dtype)) return rc;
+    const sun::Geom g = make_geom(L);
+    if (link_bytes) *link_bytes = link_bytes_of(nc, g, dtype);
+    if (scratch_bytes) *scratch_bytes = scratch_bytes_of(g);
+    return SUN_OK;
+}
+
+int sun_lattice_create(int nc, const int L[4], int dtype, void* links, size_t link_bytes, void* scratch,
+                       size_t scratch_bytes, sun_lattice_t* out) {
+    if (!out) return fail(SUN_EINVAL, "out is null");
+    *out = nullptr;
+    if (int rc = check_lattice(nc, L, dtype)) return rc;
+    const sun::Geom g = make_geom(L);
+    if (!links || link_bytes < link_bytes_of(nc, g, dtype))
+        return fail(SUN_ESIZE, "link buffer %p of %zu bytes, need %zu", links, link_bytes, link_bytes_of(nc, g, dtype));
+    if (!scratch || scratch_bytes < scratch_bytes_of(g))
+        return fail(SUN_ESIZE, "scratch buffer %p of %zu bytes, need %zu", scratch, scratch_bytes,
+                    scratch_bytes_of(g));
+    if (((uintptr_t)links & 255) || ((uintptr_t)scratch & 255))
+        return fail(SUN_EINVAL, "buffers must be 256-byte aligned");
+    auto* h = new sun_lattice_s;
+    h->nc = nc;
+    h->dtype = dtype;
+    h->g = g;
+    h->links = links;
+    h->scratch = static_cast<double*>(scratch);
+    h->ops = ops_for(nc, dtype == SUN_F64);
+    *out = h;
+    return SUN_OK;
+}
+
+void sun_lattice_destroy(sun_lattice_t h) {
+    if (!h) return;
+    for (auto& p : h->pending) {
+        (void)hipEventSynchronize(p.b);
+        (void)hipEventDestroy(p.a);
+        (void)hipEventDestroy(p.b);
+    }
+    for (hipEvent_t e : h->pool) (void)hipEventDestroy(e);
+    delete h;
+}
+
+int sun_init(sun_lattice_t h, int hot, uint64_t seed, sun_stream_t stream) {
+    if (!h) return fail(SUN_EINVAL, "null handle");
+    h->ops->init(h->ctx(as_stream(stream)), hot ? 1 : 0, (uint32_t)seed, (uint32_t)(seed >> 32));
+    h->step = 0;
+    return launch_check("init");
+}
+
+static int run_phase(sun_lattice_t h, int kind, int mu, int parity, double beta, uint64_t seed, uint64_t step,
+                     hipStream_t s) {
+    if (!((h->g.present >> mu) & 1)) return SUN_OK;  // absent direction: nothing to update
+    Timed t(h, kind == SUN_HEATBATH ? 0 : 1, s);
+    if (t.rc) return t.rc;
+    h->ops->update(h->ctx(s), kind, mu, parity, beta, (uint32_t)seed, (uint32_t)(seed >> 32), (uint32_t)step);
+    if (int rc = launch_check(kind == SUN_HEATBATH ? "heatbath phase" : "overrelaxation phase")) return rc;
+    return t.done();
+}
+
+int sun_phase(sun_lattice_t h, int kind, int mu, int parity, double beta, uint64_t seed, uint64_t step,
+              sun_stream_t stream) {
+    if (!h) return fail(SUN_EINVAL, "null handle");
+    if (kind != SUN_HEATBATH && kind != SUN_OVERRELAX) return fail(SUN_EINVAL, "kind %d", kind);
+    if (mu < 0 || mu > 3) return fail(SUN_EINVAL, "mu %d", mu);
+    if (parity != 0 && parity != 1) return fail(SUN_EINVAL, "parity %d", parity);
+    return run_phase(h, kind, mu, parity, beta, seed, step, as_stream(stream));
+}
+
+static int run_reunit(sun_lattice_t h, double* dev_out2, hipStream_t s) {
+    Timed t(h, 2, s);
+    if (t.rc) return t.rc;
+    h->ops->reunit(h->ctx(s), dev_out2 ? h->scratch : nullptr);
+    if (dev_out2) sun::launch_finalize_max2(h->scratch, sun::link_blocks(h->g), dev_out2, s);
+    if (int rc = launch_check("reunitarize")) return rc;
+    return t.done();
+}
+
+int sun_sweep(sun_lattice_t h, double beta, int n_hb, int n_or, uint64_t seed, int reunit, sun_stream_t stream) {
+    if (!h) return fail(SUN_EINVAL, "null handle");
+    if (n_hb < 0 || n_or < 0) return fail(SUN_EINVAL, "negative step count (n_hb %d, n_or %d)", n_hb, n_or);
+    const hipStream_t s = as_stream(stream);
+    for (int k = 0; k < n_hb; ++k)
+        for (int mu = 0; mu < 4; ++mu)
+            for (int p = 0; p < 2; ++p)
+                if (int rc = run_phase(h, SUN_HEATBATH, mu, p, beta, seed, h->step + (uint64_t)k, s)) return rc;
+    for (int k = 0; k < n_or; ++k)
+        for (int mu = 0; mu < 4; ++mu)
+            for (int p = 0; p < 2; ++p)
+                if (int rc = run_phase(h, SUN_OVERRELAX, mu, p, beta, seed, 0, s)) return rc;
+    if (reunit)
+        if (int rc = run_reunit(h, nullptr, s)) return rc;
+    h->step += (uint64_t)n_hb;
+    return SUN_OK;
+}
+
+int sun_reunitarize(sun_lattice_t h, double* dev_out2, sun_stream_t stream) {
+    if (!h) return fail(SUN_EINVAL, "null handle");
+    return run_reunit(h, dev_out2, as_stream(stream));
+}
+
+int sun_plaquette(sun_lattice_t h, double* dev_out3, sun_stream_t stream) {
+    if (!h) return fail(SUN_EINVAL, "null handle");
+    if (!dev_out3) return fail(SUN_ESIZE, "dev_out3 is null");
+    const hipStream_t s = as_stream(stream);
+    Timed t(h, 3, s);
+    if (t.rc) return t.rc;
+    int n_sp = 0, n_tm = 0;
+    for (int mu = 0; mu < 4; ++mu)
+        for (int nu = mu + 1; nu < 4; ++nu)
+            if (((h->g.present >> mu) & 1) && ((h->g.present >> nu) & 1)) (nu == 3 ? n_tm : n_sp)++;
+    const double norm = (double)h->nc * (double)h->g.V;
+    h->ops->plaquette(h->ctx(s), h->scratch);
+    sun::launch_plaquette_final(h->scratch, sun::site_blocks(h->g), dev_out3, norm * n_sp, norm * n_tm,
+                                norm * (n_sp + n_tm), s);
+    if (int rc = launch_check("plaquette")) return rc;
+    return t.done();
+}
+
+int sun_polyakov(sun_lattice_t h, double* dev_out2, sun_stream_t stream) {
+    if (!h) return fail(SUN_EINVAL, "null handle");
+    if (!dev_out2) return fail(SUN_ESIZE, "dev_out2 is null");
+    const hipStream_t s = as_stream(stream);
+    Timed t(h, 4, s);
+    if (t.rc) return t.rc;
+    const double Vs = (double)(h->g.V / h->g.L[3]);
+    h->ops->polyakov(h->ctx(s), h->scratch);
+    sun::launch_finalize_sum2(h->scratch, sun::spatial_blocks(h->g), dev_out2, 1.0 / (h->nc * Vs), s);
+    if (int rc = launch_check("polyakov")) return rc;
+    return t.done();
+}
+
+int sun_unitarity(sun_lattice_t h, double* dev_out2, sun_stream_t stream) {
+    if (!h) return fail(SUN_EINVAL, "null handle");
+    if (!dev_out2) return fail(SUN_ESIZE, "dev_out2 is null");
+    const hipStream_t s = as_stream(stream);
+    h->ops->unitarity(h->ctx(s), h->scratch);
+    sun::launch_finalize_max2(h->scratch, sun::link_blocks(h->g), dev_out2, s);
+    return launch_check("unitarity");
+}
+
+int sun_export(sun_lattice_t h, double* dev_canonical, sun_stream_t stream) {
+    if (!h) return fail(SUN_EINVAL, "null handle");
+    if (!dev_canonical) return fail(SUN_ESIZE, "dev_canonical is null");
+    h->ops->export_field(h->ctx(as_stream(stream)), dev_canonical);
+    return launch_check("export");
+}
+
+int sun_import(sun_lattice_t h, const double* dev_canonical, sun_stream_t stream) {
+    if (!h) return fail(SUN_EINVAL, "null handle");
+    if (!dev_canonical) return fail(SUN_ESIZE, "dev_canonical is null");
+    h->ops->import_field(h->ctx(as_stream(stream)), dev_canonical);
+    return launch_check("import");
+}
+
+int sun_get_step(sun_lattice_t h, uint64_t* step) {
+    if (!h || !step) return fail(SUN_EINVAL, "null argument");
+    *step = h->step;
+    return SUN_OK;
+}
+
+int sun_set_step(sun_lattice_t h, uint64_t step) {
+    if (!h) return fail(SUN_EINVAL, "null handle");
+    h->step = step;
+    return SUN_OK;
+}
+
+int sun_profile(sun_lattice_t h, int enable) {
+    if (!h) return fail(SUN_EINVAL, "null handle");
+    for (auto& p : h->pending) {
+        if (int rc = hip_check(hipEventSynchronize(p.b), "hipEventSynchronize")) return rc;
+        h->pool.push_back(p.a);
+        h->pool.push_back(p.b);
+    }
+    h->pending.clear();
+    for (int k = 0; k < kKernels; ++k) {
+        h->total_ms[k] = 0.0;
+        h->launches[k] = 0;
+    }
+    h->profiling = enable != 0;
+    return SUN_OK;
+}
+
+int sun_profile_read(sun_lattice_t h, int kernel, double* total_ms, int64_t* launches) {
+    if (!h) return fail(SUN_EINVAL, "null handle");
+    if (kernel < 0 || kernel >= kKernels) return fail(SUN_EINVAL, "kernel id %d", kernel);
+    for (auto& p : h->pending) {
+        if (int rc = hip_check(hipEventSynchronize(p.b), "hipEventSynchronize")) return rc;
+        float ms = 0.0f;
+        if (int rc = hip_check(hipEventElapsedTime(&ms, p.a, p.b), "hipEventElapsedTime")) return rc;
+        h->total_ms[p.kernel] += ms;
+        h->launches[p.kernel] += 1;
+        h->pool.push_back(p.a);
+        h->pool.push_back(p.b);
+    }
+    h->pending.clear();
+    if (total_ms) *total_ms = h->total_ms[kernel];
+    if (launches) *launches = h->launches[kernel];
+    return SUN_OK;
+}
+
+int sun_sample_su2(int dtype, const double* dev_alpha, int n, uint64_t seed, uint32_t step, uint32_t mu_sg,
+                   double* dev_x, int* dev_attempts, sun_stream_t stream) {
+    if (dtype != SUN_F32 && dtype != SUN_F64) return fail(SUN_EINVAL, "dtype %d", dtype);
+    if (n < 0) return fail(SUN_EINVAL, "n = %d", n);
+    if (n == 0) return SUN_OK;
+    if (!dev_alpha || !dev_x || !dev_attempts) return fail(SUN_ESIZE, "null buffer");
+    sun::launch_sample_su2(dtype == SUN_F64, dev_alpha, n, (uint32_t)seed, (uint32_t)(seed >> 32), step, mu_sg,
+                           dev_x, dev_attempts, as_stream(stream));
+    return launch_check("sample_su2");
+}
+
+}  // extern "C"
+
+namespace sun {
+
+void launch_finalize_max2(const double* partial, int nblk, double* out, hipStream_t s) {
+    k_finalize<2, true><<<1, kBlock, 0, s>>>(partial, nblk, out, 1.0, 1.0, 1.0);
+}
+
+void launch_finalize_sum2(const double* partial, int nblk, double* out, double scale, hipStream_t s) {
+    k_finalize<2, false><<<1, kBlock, 0, s>>>(partial, nblk, out, scale, scale, scale);
+}
+
+void launch_plaquette_final(const double* partial, int nblk, double* out, double norm_sp, double norm_tm,
+                            double norm_all, hipStream_t s) {
+    k_plaquette_final<2><<<1, kBlock, 0, s>>>(partial, nblk, out, norm_sp, norm_tm, norm_all);
+}
+
+void launch_sample_su2(int f64, const double* alpha, int n, uint32_t k0, uint32_t k1, uint32_t step,
+                       uint32_t mu_sg, double* x, int* attempts, hipStream_t s) {
+    if (f64)
+        k_sample_su2<double><<<blocks_for(n), kBlock, 0, s>>>(alpha, n, k0, k1, step, mu_sg, x, attempts);
+    else
+        k_sample_su2<float><<<blocks_for(n), kBlock, 0, s>>>(alpha, n, k0, k1, step, mu_sg, x, attempts);
+}
+
+}  // namespace sun

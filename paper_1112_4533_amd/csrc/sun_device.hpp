@@ -1,0 +1,424 @@
+// sun_device.hpp -- device-side building blocks for the SU(Nc) sweep on
+// gfx950: counter-based RNG, lattice geometry, the SoA link layout, and
+// register-resident complex matrix / quaternion algebra.
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+// Loops over matrix indices are fully unrolled, so that register-array
+// indices are compile-time constants.  Large-Nc translation units define
+// SUN_MAT_UNROLL to _Pragma("unroll 1") first: their matrices spill anyway and
+// full unrolling only multiplies compile time.
+#ifndef SUN_MAT_UNROLL
+#define SUN_MAT_UNROLL _Pragma("unroll")
+#endif
+
+namespace sun {
+
+// ---------------------------------------------------------------------------
+// Philox4x32-10 (Salmon, Moraes, Dror, Shaw, SC'11): ten rounds, each two
+// 32x32 -> 64-bit multiplies, key bumped by the Weyl constants between rounds.
+// Stateless: every draw is a pure function of (key, counter), so no generator
+// state is read from or written to HBM.
+// ---------------------------------------------------------------------------
+struct U4 {
+    uint32_t w[4];
+};
+
+__device__ __forceinline__ U4 philox(uint32_t c0, uint32_t c1, uint32_t c2, uint32_t c3, uint32_t k0,
+                                     uint32_t k1) {
+#pragma unroll
+    for (int r = 0; r < 10; ++r) {
+        const uint32_t lo0 = 0xD2511F53u * c0, hi0 = __umulhi(0xD2511F53u, c0);
+        const uint32_t lo1 = 0xCD9E8D57u * c2, hi1 = __umulhi(0xCD9E8D57u, c2);
+        const uint32_t n0 = hi1 ^ c1 ^ k0, n2 = hi0 ^ c3 ^ k1;
+        c0 = n0;
+        c1 = lo1;
+        c2 = n2;
+        c3 = lo0;
+        k0 += 0x9E3779B9u;
+        k1 += 0xBB67AE85u;
+    }
+    return U4{{c0, c1, c2, c3}};
+}
+
+// 24-bit uniform in (0, 1]: exact in float and double, so both precisions see
+// the same numbers.
+template <typename T>
+__device__ __forceinline__ T uniform(uint32_t w) {
+    return T((w >> 8) + 1u) * T(5.9604644775390625e-08);  // 2^-24
+}
+
+// Purpose tags in the top byte of counter word 3.
+enum : uint32_t { RNG_ATTEMPT = 0u, RNG_DIRECTION = 1u, RNG_HOTSTART = 2u };
+
+// ---------------------------------------------------------------------------
+// Geometry.  Logical site s = x + L0 (y + L1 (z + L2 t)); with L0 even,
+// s and s^1 have opposite parity, so h = s >> 1 indexes the sites of one
+// parity contiguously (the checkerboard index).
+// ---------------------------------------------------------------------------
+struct Geom {
+    int L[4];
+    int stride[4];
+    int V;
+    int Vh;
+    int present;  // bit mu set when L[mu] > 1
+};
+
+struct Site {
+    int x[4];
+    int s;
+};
+
+// Site of checkerboard index h in the given parity.
+__device__ __forceinline__ Site site_of(const Geom& g, int par, int h) {
+    Site st;
+    const int s0 = 2 * h;
+    int r = s0 / g.L[0];
+    const int x0 = s0 - r * g.L[0];
+    const int q1 = r / g.L[1];
+    st.x[1] = r - q1 * g.L[1];
+    const int q2 = q1 / g.L[2];
+    st.x[2] = q1 - q2 * g.L[2];
+    st.x[3] = q2;
+    const int fix = (st.x[1] + st.x[2] + st.x[3] + par) & 1;  // x0 is even
+    st.x[0] = x0 + fix;
+    st.s = s0 + fix;
+    return st;
+}
+
+// Site shifted by +1 / -1 along nu (periodic).
+__device__ __forceinline__ Site step_up(const Geom& g, Site a, int nu) {
+    if (a.x[nu] == g.L[nu] - 1) {
+        a.x[nu] = 0;
+        a.s -= (g.L[nu] - 1) * g.stride[nu];
+    } else {
+        a.x[nu] += 1;
+        a.s += g.stride[nu];
+    }
+    return a;
+}
+
+__device__ __forceinline__ Site step_down(const Geom& g, Site a, int nu) {
+    if (a.x[nu] == 0) {
+        a.x[nu] = g.L[nu] - 1;
+        a.s += (g.L[nu] - 1) * g.stride[nu];
+    } else {
+        a.x[nu] -= 1;
+        a.s -= g.stride[nu];
+    }
+    return a;
+}
+
+__device__ __forceinline__ int parity_of(const Site& a) {
+    return (a.x[0] + a.x[1] + a.x[2] + a.x[3]) & 1;
+}
+
+// ---------------------------------------------------------------------------
+// Register matrices.
+// ---------------------------------------------------------------------------
+template <int N, typename T>
+struct Mat {
+    T re[N][N];
+    T im[N][N];
+};
+
+template <int N, typename T>
+__device__ __forceinline__ void set_zero(Mat<N, T>& a) {
+SUN_MAT_UNROLL
+    for (int i = 0; i < N; ++i)
+SUN_MAT_UNROLL
+        for (int j = 0; j < N; ++j) a.re[i][j] = a.im[i][j] = T(0);
+}
+
+template <int N, typename T>
+__device__ __forceinline__ void set_identity(Mat<N, T>& a) {
+SUN_MAT_UNROLL
+    for (int i = 0; i < N; ++i)
+SUN_MAT_UNROLL
+        for (int j = 0; j < N; ++j) {
+            a.re[i][j] = (i == j) ? T(1) : T(0);
+            a.im[i][j] = T(0);
+        }
+}
+
+// c = a b
+template <int N, typename T>
+__device__ __forceinline__ Mat<N, T> mul_nn(const Mat<N, T>& a, const Mat<N, T>& b) {
+    Mat<N, T> c;
+SUN_MAT_UNROLL
+    for (int i = 0; i < N; ++i)
+SUN_MAT_UNROLL
+        for (int j = 0; j < N; ++j) {
+            T r = T(0), m = T(0);
+SUN_MAT_UNROLL
+            for (int k = 0; k < N; ++k) {
+                r += a.re[i][k] * b.re[k][j] - a.im[i][k] * b.im[k][j];
+                m += a.re[i][k] * b.im[k][j] + a.im[i][k] * b.re[k][j];
+            }
+            c.re[i][j] = r;
+            c.im[i][j] = m;
+        }
+    return c;
+}
+
+// c = a b^dag
+template <int N, typename T>
+__device__ __forceinline__ Mat<N, T> mul_nd(const Mat<N, T>& a, const Mat<N, T>& b) {
+    Mat<N, T> c;
+SUN_MAT_UNROLL
+    for (int i = 0; i < N; ++i)
+SUN_MAT_UNROLL
+        for (int j = 0; j < N; ++j) {
+            T r = T(0), m = T(0);
+SUN_MAT_UNROLL
+            for (int k = 0; k < N; ++k) {
+                r += a.re[i][k] * b.re[j][k] + a.im[i][k] * b.im[j][k];
+                m += a.im[i][k] * b.re[j][k] - a.re[i][k] * b.im[j][k];
+            }
+            c.re[i][j] = r;
+            c.im[i][j] = m;
+        }
+    return c;
+}
+
+// acc += a^dag b
+template <int N, typename T>
+__device__ __forceinline__ void add_mul_dn(Mat<N, T>& acc, const Mat<N, T>& a, const Mat<N, T>& b) {
+SUN_MAT_UNROLL
+    for (int i = 0; i < N; ++i)
+SUN_MAT_UNROLL
+        for (int j = 0; j < N; ++j) {
+            T r = T(0), m = T(0);
+SUN_MAT_UNROLL
+            for (int k = 0; k < N; ++k) {
+                r += a.re[k][i] * b.re[k][j] + a.im[k][i] * b.im[k][j];
+                m += a.re[k][i] * b.im[k][j] - a.im[k][i] * b.re[k][j];
+            }
+            acc.re[i][j] += r;
+            acc.im[i][j] += m;
+        }
+}
+
+// acc += a b^dag
+template <int N, typename T>
+__device__ __forceinline__ void add_mul_nd(Mat<N, T>& acc, const Mat<N, T>& a, const Mat<N, T>& b) {
+    const Mat<N, T> c = mul_nd(a, b);
+SUN_MAT_UNROLL
+    for (int i = 0; i < N; ++i)
+SUN_MAT_UNROLL
+        for (int j = 0; j < N; ++j) {
+            acc.re[i][j] += c.re[i][j];
+            acc.im[i][j] += c.im[i][j];
+        }
+}
+
+// ---------------------------------------------------------------------------
+// Quaternions: q <-> [[q0 + i q3, q2 + i q1], [-q2 + i q1, q0 - i q3]]
+// (paper Sec. 2, U = a0 + i a.sigma).  Product:
+// (a0, a)(b0, b) = (a0 b0 - a.b, a0 b + b0 a - a x b); conjugate = dagger.
+// ---------------------------------------------------------------------------
+template <typename T>
+struct Quat {
+    T q[4];
+};
+
+template <typename T>
+__device__ __forceinline__ Quat<T> qmul(const Quat<T>& a, const Quat<T>& b) {
+    Quat<T> c;
+    c.q[0] = a.q[0] * b.q[0] - a.q[1] * b.q[1] - a.q[2] * b.q[2] - a.q[3] * b.q[3];
+    c.q[1] = a.q[0] * b.q[1] + b.q[0] * a.q[1] - (a.q[2] * b.q[3] - a.q[3] * b.q[2]);
+    c.q[2] = a.q[0] * b.q[2] + b.q[0] * a.q[2] - (a.q[3] * b.q[1] - a.q[1] * b.q[3]);
+    c.q[3] = a.q[0] * b.q[3] + b.q[0] * a.q[3] - (a.q[1] * b.q[2] - a.q[2] * b.q[1]);
+    return c;
+}
+
+template <typename T>
+__device__ __forceinline__ Quat<T> qconj(const Quat<T>& a) {
+    return Quat<T>{{a.q[0], -a.q[1], -a.q[2], -a.q[3]}};
+}
+
+template <typename T>
+__device__ __forceinline__ void qadd(Quat<T>& acc, const Quat<T>& a) {
+#pragma unroll
+    for (int c = 0; c < 4; ++c) acc.q[c] += a.q[c];
+}
+
+// Quaternion (SU(2)-proportional) part of the 2x2 block (i, j) of W:
+// P(w) = (w + conj-adjugate) / 2, returned in quaternion components.
+template <int N, typename T>
+__device__ __forceinline__ Quat<T> block_quat(const Mat<N, T>& W, int i, int j) {
+    Quat<T> p;
+    p.q[0] = T(0.5) * (W.re[i][i] + W.re[j][j]);
+    p.q[3] = T(0.5) * (W.im[i][i] - W.im[j][j]);
+    p.q[2] = T(0.5) * (W.re[i][j] - W.re[j][i]);
+    p.q[1] = T(0.5) * (W.im[i][j] + W.im[j][i]);
+    return p;
+}
+
+// Rows i, j of M <- a (2x2 from quaternion a) times rows i, j.
+template <int N, typename T>
+__device__ __forceinline__ void rows_left_mul(Mat<N, T>& M, int i, int j, const Quat<T>& a) {
+    // a11 = a0 + i a3, a12 = a2 + i a1, a21 = -a2 + i a1, a22 = a0 - i a3
+SUN_MAT_UNROLL
+    for (int c = 0; c < N; ++c) {
+        const T xr = M.re[i][c], xi = M.im[i][c], yr = M.re[j][c], yi = M.im[j][c];
+        M.re[i][c] = a.q[0] * xr - a.q[3] * xi + a.q[2] * yr - a.q[1] * yi;
+        M.im[i][c] = a.q[0] * xi + a.q[3] * xr + a.q[2] * yi + a.q[1] * yr;
+        M.re[j][c] = -a.q[2] * xr - a.q[1] * xi + a.q[0] * yr + a.q[3] * yi;
+        M.im[j][c] = -a.q[2] * xi + a.q[1] * xr + a.q[0] * yi - a.q[3] * yr;
+    }
+}
+
+// ---------------------------------------------------------------------------
+// Link storage (SoA).  A link is E "pair planes" of T2 values: Nc^2 complex
+// entries (row-major) for Nc >= 3, or (a0, a1), (a2, a3) for the SU(2)
+// quaternion.  Plane p of link (mu, parity) lives at
+//   base + (((mu * 2 + parity) * E + p) * Vh + h),
+// so the V/2 links a phase updates, and each of their neighbour sets, are
+// read with unit stride across a wavefront.
+// ---------------------------------------------------------------------------
+template <typename T>
+struct Pair;
+template <>
+struct Pair<float> {
+    using type = float2;
+};
+template <>
+struct Pair<double> {
+    using type = double2;
+};
+template <typename T>
+using T2 = typename Pair<T>::type;
+
+template <int N>
+struct Planes {
+    static constexpr int E = (N == 2) ? 2 : N * N;
+};
+
+template <int N, typename T>
+__device__ __forceinline__ const T2<T>* plane0(const T2<T>* base, int mu, int par, int Vh) {
+    return base + (size_t)((mu * 2 + par) * Planes<N>::E) * (size_t)Vh;
+}
+
+template <int N, typename T>
+__device__ __forceinline__ Mat<N, T> load_mat(const T2<T>* base, int mu, int par, int h, int Vh) {
+    const T2<T>* p = plane0<N, T>(base, mu, par, Vh) + h;
+    Mat<N, T> m;
+SUN_MAT_UNROLL
+    for (int e = 0; e < N * N; ++e) {
+        const T2<T> v = p[(size_t)e * Vh];
+        m.re[e / N][e % N] = v.x;
+        m.im[e / N][e % N] = v.y;
+    }
+    return m;
+}
+
+template <int N, typename T>
+__device__ __forceinline__ void store_mat(T2<T>* base, int mu, int par, int h, int Vh, const Mat<N, T>& m) {
+    T2<T>* p = const_cast<T2<T>*>(plane0<N, T>(base, mu, par, Vh)) + h;
+SUN_MAT_UNROLL
+    for (int e = 0; e < N * N; ++e) {
+        T2<T> v;
+        v.x = m.re[e / N][e % N];
+        v.y = m.im[e / N][e % N];
+        p[(size_t)e * Vh] = v;
+    }
+}
+
+template <typename T>
+__device__ __forceinline__ Quat<T> load_quat(const T2<T>* base, int mu, int par, int h, int Vh) {
+    const T2<T>* p = plane0<2, T>(base, mu, par, Vh) + h;
+    const T2<T> a = p[0], b = p[Vh];
+    return Quat<T>{{a.x, a.y, b.x, b.y}};
+}
+
+template <typename T>
+__device__ __forceinline__ void store_quat(T2<T>* base, int mu, int par, int h, int Vh, const Quat<T>& q) {
+    T2<T>* p = const_cast<T2<T>*>(plane0<2, T>(base, mu, par, Vh)) + h;
+    T2<T> a, b;
+    a.x = q.q[0];
+    a.y = q.q[1];
+    b.x = q.q[2];
+    b.y = q.q[3];
+    p[0] = a;
+    p[Vh] = b;
+}
+
+// ---------------------------------------------------------------------------
+// Math wrappers that pick the float or double device routine.
+// ---------------------------------------------------------------------------
+__device__ __forceinline__ float d_log(float x) { return logf(x); }
+__device__ __forceinline__ double d_log(double x) { return log(x); }
+__device__ __forceinline__ float d_log1p(float x) { return log1pf(x); }
+__device__ __forceinline__ double d_log1p(double x) { return log1p(x); }
+__device__ __forceinline__ float d_expm1(float x) { return expm1f(x); }
+__device__ __forceinline__ double d_expm1(double x) { return expm1(x); }
+__device__ __forceinline__ float d_cos(float x) { return cosf(x); }
+__device__ __forceinline__ double d_cos(double x) { return cos(x); }
+__device__ __forceinline__ float d_sin(float x) { return sinf(x); }
+__device__ __forceinline__ double d_sin(double x) { return sin(x); }
+__device__ __forceinline__ float d_sqrt(float x) { return sqrtf(x); }
+__device__ __forceinline__ double d_sqrt(double x) { return sqrt(x); }
+
+template <typename T>
+struct Const {
+    static constexpr T two_pi = T(6.283185307179586476925286766559);
+    static constexpr T switch_alpha = T(1.7);  // Creutz below, Kennedy-Pendleton above
+};
+
+constexpr int kMaxAttempts = 64;
+
+// ---------------------------------------------------------------------------
+// SU(2) heatbath draw (paper Sec. 2): x0 with density sqrt(1-x0^2) e^{alpha x0},
+// (x1,x2,x3) uniform on the sphere of radius sqrt(1-x0^2).  Creutz inversion
+// for alpha < 1.7, Kennedy-Pendleton above.  Returns the attempt count, or 0
+// when kMaxAttempts draws were rejected (the caller then skips the step).
+// ---------------------------------------------------------------------------
+template <typename T>
+__device__ __forceinline__ int sample_su2(T alpha, uint32_t k0, uint32_t k1, uint32_t site, uint32_t step,
+                                          uint32_t mu_sg, Quat<T>& x) {
+    T x0 = T(1), rad = T(0);
+    int hit = 0;
+    bool ok = false;
+    const bool creutz = alpha < Const<T>::switch_alpha;
+    // expm1(-2 alpha) is loop invariant
+    const T em = creutz ? d_expm1(T(-2) * alpha) : T(0);
+    for (; hit < kMaxAttempts; ++hit) {
+        const U4 r = philox(site, step, mu_sg, (RNG_ATTEMPT << 24) | (uint32_t)hit, k0, k1);
+        const T r0 = uniform<T>(r.w[0]), r1 = uniform<T>(r.w[1]);
+        const T r2 = uniform<T>(r.w[2]), r3 = uniform<T>(r.w[3]);
+        if (creutz) {
+            x0 = (alpha == T(0)) ? T(2) * r0 - T(1) : T(1) + d_log1p((T(1) - r0) * em) / alpha;
+            const T rhs = T(1) - x0 * x0;
+            if (r1 * r1 <= rhs) {
+                rad = d_sqrt(rhs);
+                ok = true;
+                break;
+            }
+        } else {
+            const T c = d_cos(Const<T>::two_pi * r1);
+            const T lam2 = -(d_log(r0) + c * c * d_log(r2)) / (T(2) * alpha);
+            const T rhs = T(1) - lam2;
+            if (r3 * r3 <= rhs) {
+                x0 = T(1) - T(2) * lam2;
+                rad = T(2) * d_sqrt(lam2) * d_sqrt(rhs);
+                ok = true;
+                break;
+            }
+        }
+    }
+    if (!ok) return 0;
+    const U4 d = philox(site, step, mu_sg, RNG_DIRECTION << 24, k0, k1);
+    const T cos_t = T(1) - T(2) * uniform<T>(d.w[0]);
+    const T sin_t = d_sqrt(T(1) - cos_t * cos_t);
+    const T phi = Const<T>::two_pi * uniform<T>(d.w[1]);
+    x.q[0] = x0;
+    x.q[1] = rad * sin_t * d_cos(phi);
+    x.q[2] = rad * sin_t * d_sin(phi);
+    x.q[3] = rad * cos_t;
+    return hit + 1;
+}
+
+}  // namespace sun

@@ -1,0 +1,642 @@
+// sun_kernels.hpp -- the gfx950 kernels of the SU(Nc) checkerboard sweep.
+//
+// One work-item per updated link; a phase launch covers the V/2 links
+// U_mu(x) of one parity.  Every kernel is templated on (Nc, storage type);
+// the update kernel also on the update kind and on mu, so that all neighbour
+// arithmetic and register-array indices are compile-time constants.
+#pragma once
+
+#include "sun_device.hpp"
+
+namespace sun {
+
+constexpr int kBlock = 256;  // 4 wave64 per workgroup
+constexpr int kWaves = kBlock / 64;
+
+// ---------------------------------------------------------------------------
+// Deterministic block reductions (fixed butterfly inside a wave64, then the
+// waves in order).  Every thread of the block must call them.
+// ---------------------------------------------------------------------------
+template <int K>
+__device__ __forceinline__ void block_sum(double (&v)[K], double* out) {
+    __shared__ double red[kWaves][K];
+#pragma unroll
+    for (int c = 0; c < K; ++c)
+#pragma unroll
+        for (int off = 32; off > 0; off >>= 1) v[c] += __shfl_xor(v[c], off, 64);
+    const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+    if (lane == 0)
+#pragma unroll
+        for (int c = 0; c < K; ++c) red[wave][c] = v[c];
+    __syncthreads();
+    if (threadIdx.x == 0)
+#pragma unroll
+        for (int c = 0; c < K; ++c) {
+            double s = red[0][c];
+#pragma unroll
+            for (int w = 1; w < kWaves; ++w) s += red[w][c];
+            out[c] = s;
+        }
+}
+
+template <int K>
+__device__ __forceinline__ void block_max(double (&v)[K], double* out) {
+    __shared__ double red[kWaves][K];
+#pragma unroll
+    for (int c = 0; c < K; ++c)
+#pragma unroll
+        for (int off = 32; off > 0; off >>= 1) v[c] = fmax(v[c], __shfl_xor(v[c], off, 64));
+    const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+    if (lane == 0)
+#pragma unroll
+        for (int c = 0; c < K; ++c) red[wave][c] = v[c];
+    __syncthreads();
+    if (threadIdx.x == 0)
+#pragma unroll
+        for (int c = 0; c < K; ++c) {
+            double s = red[0][c];
+#pragma unroll
+            for (int w = 1; w < kWaves; ++w) s = fmax(s, red[w][c]);
+            out[c] = s;
+        }
+}
+
+// Second pass: one block folds nblk partial records of K doubles, each
+// thread a fixed strided subset in order, then the block tree.
+template <int K, bool MAX>
+__global__ __launch_bounds__(kBlock) void k_finalize(const double* __restrict__ partial, int nblk,
+                                                     double* __restrict__ out, double s0, double s1,
+                                                     double s2) {
+    double v[K];
+#pragma unroll
+    for (int c = 0; c < K; ++c) v[c] = 0.0;
+    for (int b = threadIdx.x; b < nblk; b += kBlock)
+#pragma unroll
+        for (int c = 0; c < K; ++c) v[c] = MAX ? fmax(v[c], partial[(size_t)b * K + c]) : v[c] + partial[(size_t)b * K + c];
+    __shared__ double res[K];
+    if (MAX)
+        block_max<K>(v, res);
+    else
+        block_sum<K>(v, res);
+    if (threadIdx.x == 0) {
+        const double sc[3] = {s0, s1, s2};
+#pragma unroll
+        for (int c = 0; c < K; ++c) out[c] = res[c] * sc[c < 3 ? c : 2];
+    }
+}
+
+// ---------------------------------------------------------------------------
+// Staple (paper Sec. 2), closing orientation: for nu != mu
+//   U_nu(x+mu) U_mu(x+nu)^dag U_nu(x)^dag + U_nu(x+mu-nu)^dag U_mu(x-nu)^dag U_nu(x-nu)
+// so that ReTr(U_mu(x) A) is the sum of the plaquettes containing the link.
+// ---------------------------------------------------------------------------
+template <int N, typename T, int MU>
+__device__ __forceinline__ Mat<N, T> staple(const T2<T>* __restrict__ U, const Geom& g, const Site& x, int par,
+                                            int h) {
+    const int op = par ^ 1;
+    const Site xp = step_up(g, x, MU);
+    Mat<N, T> A;
+    set_zero(A);
+#pragma unroll
+    for (int nu = 0; nu < 4; ++nu) {
+        if (nu == MU || !((g.present >> nu) & 1)) continue;
+        const Site xpn = step_up(g, x, nu);
+        const Site xmn = step_down(g, x, nu);
+        const Site xpmn = step_down(g, xp, nu);
+        const Mat<N, T> m = mul_nd(load_mat<N, T>(U, nu, op, xp.s >> 1, g.Vh),
+                                   load_mat<N, T>(U, MU, op, xpn.s >> 1, g.Vh));
+        add_mul_nd(A, m, load_mat<N, T>(U, nu, par, h, g.Vh));
+        const Mat<N, T> l = mul_nn(load_mat<N, T>(U, MU, op, xmn.s >> 1, g.Vh),
+                                   load_mat<N, T>(U, nu, par, xpmn.s >> 1, g.Vh));
+        add_mul_dn(A, l, load_mat<N, T>(U, nu, op, xmn.s >> 1, g.Vh));
+    }
+    return A;
+}
+
+template <typename T, int MU>
+__device__ __forceinline__ Quat<T> staple_su2(const T2<T>* __restrict__ U, const Geom& g, const Site& x, int par,
+                                              int h) {
+    const int op = par ^ 1;
+    const Site xp = step_up(g, x, MU);
+    Quat<T> A{{T(0), T(0), T(0), T(0)}};
+#pragma unroll
+    for (int nu = 0; nu < 4; ++nu) {
+        if (nu == MU || !((g.present >> nu) & 1)) continue;
+        const Site xpn = step_up(g, x, nu);
+        const Site xmn = step_down(g, x, nu);
+        const Site xpmn = step_down(g, xp, nu);
+        const Quat<T> m = qmul(load_quat<T>(U, nu, op, xp.s >> 1, g.Vh), qconj(load_quat<T>(U, MU, op, xpn.s >> 1, g.Vh)));
+        qadd(A, qmul(m, qconj(load_quat<T>(U, nu, par, h, g.Vh))));
+        const Quat<T> l = qmul(load_quat<T>(U, MU, op, xmn.s >> 1, g.Vh), load_quat<T>(U, nu, par, xpmn.s >> 1, g.Vh));
+        qadd(A, qmul(qconj(l), load_quat<T>(U, nu, op, xmn.s >> 1, g.Vh)));
+    }
+    return A;
+}
+
+// Normalised subgroup direction V = P / |P| (identity when P = 0); returns k.
+template <typename T>
+__device__ __forceinline__ T unit_quat(const Quat<T>& p, Quat<T>& v) {
+    const T k2 = p.q[0] * p.q[0] + p.q[1] * p.q[1] + p.q[2] * p.q[2] + p.q[3] * p.q[3];
+    const T k = k2 > T(0) ? d_sqrt(k2) : T(0);
+    if (k > T(0)) {
+        const T inv = T(1) / k;
+#pragma unroll
+        for (int c = 0; c < 4; ++c) v.q[c] = p.q[c] * inv;
+    } else {
+        v = Quat<T>{{T(1), T(0), T(0), T(0)}};
+    }
+    return k;
+}
+
+// ---------------------------------------------------------------------------
+// Phase update, Nc >= 3 (paper Sec. 2, Cabibbo-Marinari steps 1-5, and the
+// subgroup overrelaxation).  W = U A is kept in registers and updated with U.
+// ---------------------------------------------------------------------------
+template <int N, typename T, bool HB, int MU>
+__global__ __launch_bounds__(kBlock) void k_update(T2<T>* __restrict__ U, Geom g, int par, T beta,
+                                                   uint32_t k0, uint32_t k1, uint32_t step) {
+    const int h = blockIdx.x * kBlock + threadIdx.x;
+    if (h >= g.Vh) return;
+    const Site x = site_of(g, par, h);
+    const Mat<N, T> A = staple<N, T, MU>(U, g, x, par, h);
+    Mat<N, T> Ul = load_mat<N, T>(U, MU, par, h, g.Vh);
+    Mat<N, T> W = mul_nn(Ul, A);
+    int sg = 0;
+SUN_MAT_UNROLL
+    for (int i = 0; i < N; ++i)
+SUN_MAT_UNROLL
+        for (int j = i + 1; j < N; ++j, ++sg) {
+            Quat<T> v;
+            const T k = unit_quat(block_quat(W, i, j), v);
+            Quat<T> a;
+            if (HB) {
+                const T alpha = T(2) * beta * k / T(N);
+                Quat<T> xs;
+                if (!sample_su2<T>(alpha, k0, k1, (uint32_t)x.s, step, ((uint32_t)MU << 16) | (uint32_t)sg, xs))
+                    continue;
+                a = qmul(xs, qconj(v));
+            } else {
+                const Quat<T> vc = qconj(v);
+                a = qmul(vc, vc);
+            }
+            rows_left_mul(Ul, i, j, a);
+            rows_left_mul(W, i, j, a);
+        }
+    store_mat<N, T>(U, MU, par, h, g.Vh, Ul);
+}
+
+// Phase update, SU(2) in the 4-real parameterization (paper Sec. 2, Sec. 3).
+template <typename T, bool HB, int MU>
+__global__ __launch_bounds__(kBlock) void k_update_su2(T2<T>* __restrict__ U, Geom g, int par, T beta,
+                                                       uint32_t k0, uint32_t k1, uint32_t step) {
+    const int h = blockIdx.x * kBlock + threadIdx.x;
+    if (h >= g.Vh) return;
+    const Site x = site_of(g, par, h);
+    const Quat<T> A = staple_su2<T, MU>(U, g, x, par, h);
+    const Quat<T> u = load_quat<T>(U, MU, par, h, g.Vh);
+    Quat<T> v;
+    const T k = unit_quat(qmul(u, A), v);
+    Quat<T> a;
+    if (HB) {
+        Quat<T> xs;
+        if (!sample_su2<T>(beta * k, k0, k1, (uint32_t)x.s, step, (uint32_t)MU << 16, xs)) return;
+        a = qmul(xs, qconj(v));
+    } else {
+        const Quat<T> vc = qconj(v);
+        a = qmul(vc, vc);
+    }
+    store_quat<T>(U, MU, par, h, g.Vh, qmul(a, u));
+}
+
+// ---------------------------------------------------------------------------
+// FP64 helpers for re-unitarization and diagnostics.
+// ---------------------------------------------------------------------------
+template <int N, typename T>
+__device__ __forceinline__ Mat<N, double> load_link_f64(const T2<T>* __restrict__ U, int mu, int par, int h,
+                                                        int Vh) {
+    Mat<N, double> m;
+    if constexpr (N == 2) {
+        const Quat<T> q = load_quat<T>(U, mu, par, h, Vh);
+        m.re[0][0] = q.q[0];
+        m.im[0][0] = q.q[3];
+        m.re[0][1] = q.q[2];
+        m.im[0][1] = q.q[1];
+        m.re[1][0] = -(double)q.q[2];
+        m.im[1][0] = q.q[1];
+        m.re[1][1] = q.q[0];
+        m.im[1][1] = -(double)q.q[3];
+    } else {
+        const Mat<N, T> t = load_mat<N, T>(U, mu, par, h, Vh);
+SUN_MAT_UNROLL
+        for (int i = 0; i < N; ++i)
+SUN_MAT_UNROLL
+            for (int j = 0; j < N; ++j) {
+                m.re[i][j] = t.re[i][j];
+                m.im[i][j] = t.im[i][j];
+            }
+    }
+    return m;
+}
+
+template <int N, typename T>
+__device__ __forceinline__ void store_link_from_f64(T2<T>* __restrict__ U, int mu, int par, int h, int Vh,
+                                                    const Mat<N, double>& m) {
+    if constexpr (N == 2) {
+        store_quat<T>(U, mu, par, h, Vh, Quat<T>{{(T)m.re[0][0], (T)m.im[0][1], (T)m.re[0][1], (T)m.im[0][0]}});
+    } else {
+        Mat<N, T> t;
+SUN_MAT_UNROLL
+        for (int i = 0; i < N; ++i)
+SUN_MAT_UNROLL
+            for (int j = 0; j < N; ++j) {
+                t.re[i][j] = (T)m.re[i][j];
+                t.im[i][j] = (T)m.im[i][j];
+            }
+        store_mat<N, T>(U, mu, par, h, Vh, t);
+    }
+}
+
+// Determinant by Gaussian elimination with partial pivoting (row swaps done
+// with selects so that every register index stays compile-time).
+template <int N>
+__device__ __forceinline__ void det_lu(Mat<N, double> m, double& dr, double& di) {
+    dr = 1.0;
+    di = 0.0;
+SUN_MAT_UNROLL
+    for (int col = 0; col < N; ++col) {
+        int piv = col;
+        double best = m.re[col][col] * m.re[col][col] + m.im[col][col] * m.im[col][col];
+SUN_MAT_UNROLL
+        for (int r = col + 1; r < N; ++r) {
+            const double a = m.re[r][col] * m.re[r][col] + m.im[r][col] * m.im[r][col];
+            if (a > best) {
+                best = a;
+                piv = r;
+            }
+        }
+        if (best == 0.0) {
+            dr = di = 0.0;
+            return;
+        }
+SUN_MAT_UNROLL
+        for (int r = col + 1; r < N; ++r) {
+            const bool sw = (r == piv);
+SUN_MAT_UNROLL
+            for (int c = 0; c < N; ++c) {
+                const double ar = m.re[col][c], ai = m.im[col][c], br = m.re[r][c], bi = m.im[r][c];
+                m.re[col][c] = sw ? br : ar;
+                m.im[col][c] = sw ? bi : ai;
+                m.re[r][c] = sw ? ar : br;
+                m.im[r][c] = sw ? ai : bi;
+            }
+        }
+        if (piv != col) {
+            dr = -dr;
+            di = -di;
+        }
+        const double pr = m.re[col][col], pi = m.im[col][col];
+        const double nr = dr * pr - di * pi, ni = dr * pi + di * pr;
+        dr = nr;
+        di = ni;
+        const double inv = 1.0 / (pr * pr + pi * pi);
+SUN_MAT_UNROLL
+        for (int r = col + 1; r < N; ++r) {
+            // f = m[r][col] / m[col][col]
+            const double fr = (m.re[r][col] * pr + m.im[r][col] * pi) * inv;
+            const double fi = (m.im[r][col] * pr - m.re[r][col] * pi) * inv;
+SUN_MAT_UNROLL
+            for (int c = col; c < N; ++c) {
+                m.re[r][c] -= fr * m.re[col][c] - fi * m.im[col][c];
+                m.im[r][c] -= fr * m.im[col][c] + fi * m.re[col][c];
+            }
+        }
+    }
+}
+
+template <int N>
+__device__ __forceinline__ void normalize_row(Mat<N, double>& M, int i) {
+    double s = 0.0;
+SUN_MAT_UNROLL
+    for (int c = 0; c < N; ++c) s += M.re[i][c] * M.re[i][c] + M.im[i][c] * M.im[i][c];
+    const double inv = 1.0 / sqrt(s);
+SUN_MAT_UNROLL
+    for (int c = 0; c < N; ++c) {
+        M.re[i][c] *= inv;
+        M.im[i][c] *= inv;
+    }
+}
+
+// Re-unitarization (paper Sec. 2, last paragraph), FP64.
+template <int N>
+__device__ __forceinline__ void reunit(Mat<N, double>& M) {
+    if constexpr (N == 2) {
+        normalize_row<2>(M, 0);
+        M.re[1][0] = -M.re[0][1];
+        M.im[1][0] = M.im[0][1];
+        M.re[1][1] = M.re[0][0];
+        M.im[1][1] = -M.im[0][0];
+        return;
+    } else {
+        constexpr int gs_rows = (N == 3) ? 2 : N;
+SUN_MAT_UNROLL
+        for (int i = 0; i < gs_rows; ++i) {
+SUN_MAT_UNROLL
+            for (int k = 0; k < i; ++k) {
+                double pr = 0.0, pi = 0.0;  // <r_k, r_i> = sum conj(r_k) r_i
+SUN_MAT_UNROLL
+                for (int c = 0; c < N; ++c) {
+                    pr += M.re[k][c] * M.re[i][c] + M.im[k][c] * M.im[i][c];
+                    pi += M.re[k][c] * M.im[i][c] - M.im[k][c] * M.re[i][c];
+                }
+SUN_MAT_UNROLL
+                for (int c = 0; c < N; ++c) {
+                    M.re[i][c] -= pr * M.re[k][c] - pi * M.im[k][c];
+                    M.im[i][c] -= pr * M.im[k][c] + pi * M.re[k][c];
+                }
+            }
+            normalize_row<N>(M, i);
+        }
+        if constexpr (N == 3) {
+            // row 2 = conj(row0 x row1)
+#pragma unroll
+            for (int c = 0; c < 3; ++c) {
+                const int a = (c + 1) % 3, b = (c + 2) % 3;
+                const double xr = M.re[0][a] * M.re[1][b] - M.im[0][a] * M.im[1][b] -
+                                  (M.re[0][b] * M.re[1][a] - M.im[0][b] * M.im[1][a]);
+                const double xi = M.re[0][a] * M.im[1][b] + M.im[0][a] * M.re[1][b] -
+                                  (M.re[0][b] * M.im[1][a] + M.im[0][b] * M.re[1][a]);
+                M.re[2][c] = xr;
+                M.im[2][c] = -xi;
+            }
+        } else {
+            double dr, di;
+            det_lu<N>(M, dr, di);
+            const double mod = sqrt(dr * dr + di * di);
+            const double cr = dr / mod, ci = -di / mod;  // conj(det)/|det|
+SUN_MAT_UNROLL
+            for (int c = 0; c < N; ++c) {
+                const double r = M.re[N - 1][c], i = M.im[N - 1][c];
+                M.re[N - 1][c] = r * cr - i * ci;
+                M.im[N - 1][c] = r * ci + i * cr;
+            }
+        }
+    }
+}
+
+// {max_ij |(U^dag U - 1)_ij|, |det U - 1|}
+template <int N>
+__device__ __forceinline__ void unitarity_dev(const Mat<N, double>& M, double& du, double& dd) {
+    du = 0.0;
+SUN_MAT_UNROLL
+    for (int i = 0; i < N; ++i)
+SUN_MAT_UNROLL
+        for (int j = 0; j < N; ++j) {
+            double r = (i == j) ? -1.0 : 0.0, m = 0.0;
+SUN_MAT_UNROLL
+            for (int k = 0; k < N; ++k) {
+                r += M.re[k][i] * M.re[k][j] + M.im[k][i] * M.im[k][j];
+                m += M.re[k][i] * M.im[k][j] - M.im[k][i] * M.re[k][j];
+            }
+            du = fmax(du, sqrt(r * r + m * m));
+        }
+    double dr, di;
+    det_lu<N>(M, dr, di);
+    dd = sqrt((dr - 1.0) * (dr - 1.0) + di * di);
+}
+
+// Link id in [0, 4V): mu-major, then parity, then checkerboard index.
+struct LinkId {
+    int mu, par, h;
+};
+__device__ __forceinline__ LinkId link_of(const Geom& g, int id) {
+    LinkId l;
+    l.mu = id / g.V;
+    const int rem = id - l.mu * g.V;
+    l.par = rem >= g.Vh ? 1 : 0;
+    l.h = rem - l.par * g.Vh;
+    return l;
+}
+
+// ---------------------------------------------------------------------------
+// Re-unitarization of every link, optionally reporting the deviation found
+// before the projection.
+// ---------------------------------------------------------------------------
+template <int N, typename T>
+__global__ __launch_bounds__(kBlock) void k_reunit(T2<T>* __restrict__ U, Geom g, double* __restrict__ partial) {
+    const int id = blockIdx.x * kBlock + threadIdx.x;
+    double dev[2] = {0.0, 0.0};
+    if (id < 4 * g.V) {
+        const LinkId l = link_of(g, id);
+        if ((g.present >> l.mu) & 1) {
+            Mat<N, double> M = load_link_f64<N, T>(U, l.mu, l.par, l.h, g.Vh);
+            if (partial) unitarity_dev<N>(M, dev[0], dev[1]);
+            reunit<N>(M);
+            store_link_from_f64<N, T>(U, l.mu, l.par, l.h, g.Vh, M);
+        }
+    }
+    if (partial) block_max<2>(dev, partial + 2 * (size_t)blockIdx.x);
+}
+
+template <int N, typename T>
+__global__ __launch_bounds__(kBlock) void k_unitarity(const T2<T>* __restrict__ U, Geom g,
+                                                      double* __restrict__ partial) {
+    const int id = blockIdx.x * kBlock + threadIdx.x;
+    double dev[2] = {0.0, 0.0};
+    if (id < 4 * g.V) {
+        const LinkId l = link_of(g, id);
+        if ((g.present >> l.mu) & 1) {
+            const Mat<N, double> M = load_link_f64<N, T>(U, l.mu, l.par, l.h, g.Vh);
+            unitarity_dev<N>(M, dev[0], dev[1]);
+        }
+    }
+    block_max<2>(dev, partial + 2 * (size_t)blockIdx.x);
+}
+
+// ---------------------------------------------------------------------------
+// Plaquette (paper Sec. 2): P_mu_nu(x) = U_mu(x) U_nu(x+mu) U_mu(x+nu)^dag U_nu(x)^dag,
+// evaluated in FP64 from the stored links; per-block partial sums
+// {spatial planes, planes with direction 3}.
+// ---------------------------------------------------------------------------
+template <int N, typename T, int MU, int NU>
+__device__ __forceinline__ double re_tr_plaq(const T2<T>* __restrict__ U, const Geom& g, const Site& x, int par,
+                                             int h) {
+    const Site xm = step_up(g, x, MU), xn = step_up(g, x, NU);
+    const int op = par ^ 1;
+    const Mat<N, double> a = mul_nn(load_link_f64<N, T>(U, MU, par, h, g.Vh),
+                                    load_link_f64<N, T>(U, NU, op, xm.s >> 1, g.Vh));
+    const Mat<N, double> b = mul_nd(a, load_link_f64<N, T>(U, MU, op, xn.s >> 1, g.Vh));
+    const Mat<N, double> un = load_link_f64<N, T>(U, NU, par, h, g.Vh);
+    // ReTr(b un^dag) = sum_ij Re(b_ij conj(un_ij))
+    double t = 0.0;
+SUN_MAT_UNROLL
+    for (int i = 0; i < N; ++i)
+SUN_MAT_UNROLL
+        for (int j = 0; j < N; ++j) t += b.re[i][j] * un.re[i][j] + b.im[i][j] * un.im[i][j];
+    return t;
+}
+
+template <int N, typename T>
+__global__ __launch_bounds__(kBlock) void k_plaquette(const T2<T>* __restrict__ U, Geom g,
+                                                      double* __restrict__ partial) {
+    const int id = blockIdx.x * kBlock + threadIdx.x;
+    double acc[2] = {0.0, 0.0};
+    if (id < g.V) {
+        const int par = id >= g.Vh ? 1 : 0;
+        const int h = id - par * g.Vh;
+        const Site x = site_of(g, par, h);
+        const int p = g.present;
+#define SUN_PLAQ(m, n, slot) \
+    if (((p >> m) & 1) && ((p >> n) & 1)) acc[slot] += re_tr_plaq<N, T, m, n>(U, g, x, par, h);
+        SUN_PLAQ(0, 1, 0)
+        SUN_PLAQ(0, 2, 0)
+        SUN_PLAQ(1, 2, 0)
+        SUN_PLAQ(0, 3, 1)
+        SUN_PLAQ(1, 3, 1)
+        SUN_PLAQ(2, 3, 1)
+#undef SUN_PLAQ
+    }
+    block_sum<2>(acc, partial + 2 * (size_t)blockIdx.x);
+}
+
+// Second pass for the plaquette: {total, spatial, temporal} means.
+template <int K = 2>
+__global__ __launch_bounds__(kBlock) void k_plaquette_final(const double* __restrict__ partial, int nblk,
+                                                            double* __restrict__ out, double norm_sp,
+                                                            double norm_tm, double norm_all) {
+    double v[K] = {};
+    for (int b = threadIdx.x; b < nblk; b += kBlock)
+#pragma unroll
+        for (int c = 0; c < K; ++c) v[c] += partial[K * (size_t)b + c];
+    __shared__ double res[K];
+    block_sum<K>(v, res);
+    if (threadIdx.x == 0) {
+        out[0] = norm_all > 0.0 ? (res[0] + res[1]) / norm_all : 0.0;
+        out[1] = norm_sp > 0.0 ? res[0] / norm_sp : 0.0;
+        out[2] = norm_tm > 0.0 ? res[1] / norm_tm : 0.0;
+    }
+}
+
+// ---------------------------------------------------------------------------
+// Polyakov loop along direction 3, FP64.
+// ---------------------------------------------------------------------------
+template <int N, typename T>
+__global__ __launch_bounds__(kBlock) void k_polyakov(const T2<T>* __restrict__ U, Geom g,
+                                                     double* __restrict__ partial) {
+    const int xs = blockIdx.x * kBlock + threadIdx.x;
+    const int Vs = g.V / g.L[3];
+    double tr[2] = {0.0, 0.0};
+    if (xs < Vs) {
+        Mat<N, double> P;
+        set_identity(P);
+        for (int t = 0; t < g.L[3]; ++t) {
+            const int s = xs + t * Vs;
+            Site st;
+            int r = s;
+#pragma unroll
+            for (int m = 0; m < 4; ++m) {
+                const int q = r / g.L[m];
+                st.x[m] = r - q * g.L[m];
+                r = q;
+            }
+            st.s = s;
+            P = mul_nn(P, load_link_f64<N, T>(U, 3, parity_of(st), s >> 1, g.Vh));
+        }
+SUN_MAT_UNROLL
+        for (int i = 0; i < N; ++i) {
+            tr[0] += P.re[i][i];
+            tr[1] += P.im[i][i];
+        }
+    }
+    block_sum<2>(tr, partial + 2 * (size_t)blockIdx.x);
+}
+
+// ---------------------------------------------------------------------------
+// Start configuration (paper Sec. 3): identity, or Haar links from a complex
+// Gaussian matrix (Box-Muller on Philox uniforms) re-unitarized in FP64.
+// ---------------------------------------------------------------------------
+template <int N, typename T>
+__global__ __launch_bounds__(kBlock) void k_init(T2<T>* __restrict__ U, Geom g, int hot, uint32_t k0,
+                                                 uint32_t k1) {
+    const int id = blockIdx.x * kBlock + threadIdx.x;
+    if (id >= 4 * g.V) return;
+    const LinkId l = link_of(g, id);
+    Mat<N, double> M;
+    set_identity(M);
+    if (hot && ((g.present >> l.mu) & 1)) {
+        const int s = site_of(g, l.par, l.h).s;
+        constexpr int rows_needed = (N == 2) ? 1 : N;  // SU(2): row 0 fixes the matrix
+        constexpr int ncalls = (2 * N * rows_needed + 3) / 4;
+        double gs[4 * ncalls];
+#pragma unroll
+        for (int call = 0; call < ncalls; ++call) {
+            const U4 r = philox((uint32_t)s, 0xFFFFFFFFu, (uint32_t)l.mu << 16,
+                                (RNG_HOTSTART << 24) | (uint32_t)call, k0, k1);
+#pragma unroll
+            for (int p = 0; p < 2; ++p) {
+                const double rad = sqrt(-2.0 * log(uniform<double>(r.w[2 * p])));
+                const double ang = Const<double>::two_pi * uniform<double>(r.w[2 * p + 1]);
+                gs[4 * call + 2 * p] = rad * cos(ang);
+                gs[4 * call + 2 * p + 1] = rad * sin(ang);
+            }
+        }
+SUN_MAT_UNROLL
+        for (int e = 0; e < N * rows_needed; ++e) {
+            M.re[e / N][e % N] = gs[2 * e];
+            M.im[e / N][e % N] = gs[2 * e + 1];
+        }
+        reunit<N>(M);
+    }
+    store_link_from_f64<N, T>(U, l.mu, l.par, l.h, g.Vh, M);
+}
+
+// ---------------------------------------------------------------------------
+// Canonical FP64 field <-> SoA storage.
+// ---------------------------------------------------------------------------
+template <int N, typename T>
+__global__ __launch_bounds__(kBlock) void k_export(const T2<T>* __restrict__ U, Geom g, double* __restrict__ out) {
+    const int id = blockIdx.x * kBlock + threadIdx.x;
+    if (id >= 4 * g.V) return;
+    const LinkId l = link_of(g, id);
+    const int s = site_of(g, l.par, l.h).s;
+    const Mat<N, double> M = load_link_f64<N, T>(U, l.mu, l.par, l.h, g.Vh);
+    double* o = out + ((size_t)l.mu * g.V + s) * (2 * N * N);
+SUN_MAT_UNROLL
+    for (int e = 0; e < N * N; ++e) {
+        o[2 * e] = M.re[e / N][e % N];
+        o[2 * e + 1] = M.im[e / N][e % N];
+    }
+}
+
+template <int N, typename T>
+__global__ __launch_bounds__(kBlock) void k_import(T2<T>* __restrict__ U, Geom g, const double* __restrict__ in) {
+    const int id = blockIdx.x * kBlock + threadIdx.x;
+    if (id >= 4 * g.V) return;
+    const LinkId l = link_of(g, id);
+    const int s = site_of(g, l.par, l.h).s;
+    const double* p = in + ((size_t)l.mu * g.V + s) * (2 * N * N);
+    Mat<N, double> M;
+SUN_MAT_UNROLL
+    for (int e = 0; e < N * N; ++e) {
+        M.re[e / N][e % N] = p[2 * e];
+        M.im[e / N][e % N] = p[2 * e + 1];
+    }
+    store_link_from_f64<N, T>(U, l.mu, l.par, l.h, g.Vh, M);
+}
+
+// ---------------------------------------------------------------------------
+// The SU(2) draw alone, for distribution and parity tests.
+// ---------------------------------------------------------------------------
+template <typename T>
+__global__ __launch_bounds__(kBlock) void k_sample_su2(const double* __restrict__ alpha, int n, uint32_t k0,
+                                                       uint32_t k1, uint32_t step, uint32_t mu_sg,
+                                                       double* __restrict__ x, int* __restrict__ attempts) {
+    const int i = blockIdx.x * kBlock + threadIdx.x;
+    if (i >= n) return;
+    Quat<T> q{{T(1), T(0), T(0), T(0)}};
+    const int a = sample_su2<T>((T)alpha[i], k0, k1, (uint32_t)i, step, mu_sg, q);
+#pragma unroll
+    for (int c = 0; c < 4; ++c) x[4 * (size_t)i + c] = q.q[c];
+    attempts[i] = a;
+}
+
+}  // namespace sun

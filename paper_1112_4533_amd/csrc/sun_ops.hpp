@@ -1,0 +1,56 @@
+// sun_ops.hpp -- host-side launchers, one table per (Nc, storage type).
+// Each ops_nc*.hip translation unit instantiates the kernels of one Nc.
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+#include "sun_device.hpp"
+
+namespace sun {
+
+struct Ctx {
+    void* links;
+    Geom g;
+    hipStream_t stream;
+};
+
+struct Ops {
+    // one checkerboard phase; kind 0 heatbath, 1 overrelaxation
+    void (*update)(const Ctx&, int kind, int mu, int par, double beta, uint32_t k0, uint32_t k1, uint32_t step);
+    void (*init)(const Ctx&, int hot, uint32_t k0, uint32_t k1);
+    // partial: 2 doubles per block of link_blocks(g), or null
+    void (*reunit)(const Ctx&, double* partial);
+    void (*unitarity)(const Ctx&, double* partial);
+    // partial: 2 doubles per block of site_blocks(g)
+    void (*plaquette)(const Ctx&, double* partial);
+    // partial: 2 doubles per block of spatial_blocks(g)
+    void (*polyakov)(const Ctx&, double* partial);
+    void (*export_field)(const Ctx&, double* out);
+    void (*import_field)(const Ctx&, const double* in);
+};
+
+constexpr int kLaunchBlock = 256;
+inline int blocks_for(long long n) { return (int)((n + kLaunchBlock - 1) / kLaunchBlock); }
+inline int link_blocks(const Geom& g) { return blocks_for(4LL * g.V); }
+inline int site_blocks(const Geom& g) { return blocks_for(g.V); }
+inline int half_blocks(const Geom& g) { return blocks_for(g.Vh); }
+inline int spatial_blocks(const Geom& g) { return blocks_for(g.V / g.L[3]); }
+
+// f64 = 0: float storage, 1: double storage
+const Ops* ops_nc2(int f64);
+const Ops* ops_nc3(int f64);
+const Ops* ops_nc4(int f64);
+const Ops* ops_nc5(int f64);
+const Ops* ops_nc6(int f64);
+const Ops* ops_nc7(int f64);
+const Ops* ops_nc8(int f64);
+
+void launch_finalize_max2(const double* partial, int nblk, double* out, hipStream_t s);
+void launch_finalize_sum2(const double* partial, int nblk, double* out, double scale, hipStream_t s);
+void launch_plaquette_final(const double* partial, int nblk, double* out, double norm_sp, double norm_tm,
+                            double norm_all, hipStream_t s);
+void launch_sample_su2(int f64, const double* alpha, int n, uint32_t k0, uint32_t k1, uint32_t step,
+                       uint32_t mu_sg, double* x, int* attempts, hipStream_t s);
+
+}  // namespace sun

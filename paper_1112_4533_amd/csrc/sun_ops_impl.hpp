@@ -1,0 +1,77 @@
+// sun_ops_impl.hpp -- launcher bodies; included once per Nc by ops_nc*.hip.
+#pragma once
+
+#include "sun_kernels.hpp"
+#include "sun_ops.hpp"
+
+namespace sun {
+
+template <int N, typename T>
+struct OpsImpl {
+    using P = T2<T>;
+
+    template <bool HB, int MU>
+    static void update_mu(const Ctx& c, int par, T beta, uint32_t k0, uint32_t k1, uint32_t step) {
+        if constexpr (N == 2)
+            k_update_su2<T, HB, MU><<<half_blocks(c.g), kBlock, 0, c.stream>>>((P*)c.links, c.g, par, beta, k0,
+                                                                               k1, step);
+        else
+            k_update<N, T, HB, MU><<<half_blocks(c.g), kBlock, 0, c.stream>>>((P*)c.links, c.g, par, beta, k0, k1,
+                                                                             step);
+    }
+
+    template <bool HB>
+    static void update_kind(const Ctx& c, int mu, int par, T beta, uint32_t k0, uint32_t k1, uint32_t step) {
+        switch (mu) {
+            case 0: update_mu<HB, 0>(c, par, beta, k0, k1, step); break;
+            case 1: update_mu<HB, 1>(c, par, beta, k0, k1, step); break;
+            case 2: update_mu<HB, 2>(c, par, beta, k0, k1, step); break;
+            default: update_mu<HB, 3>(c, par, beta, k0, k1, step); break;
+        }
+    }
+
+    static void update(const Ctx& c, int kind, int mu, int par, double beta, uint32_t k0, uint32_t k1,
+                       uint32_t step) {
+        if (kind == 0)
+            update_kind<true>(c, mu, par, (T)beta, k0, k1, step);
+        else
+            update_kind<false>(c, mu, par, (T)beta, k0, k1, step);
+    }
+
+    static void init(const Ctx& c, int hot, uint32_t k0, uint32_t k1) {
+        k_init<N, T><<<link_blocks(c.g), kBlock, 0, c.stream>>>((P*)c.links, c.g, hot, k0, k1);
+    }
+    static void reunit(const Ctx& c, double* partial) {
+        k_reunit<N, T><<<link_blocks(c.g), kBlock, 0, c.stream>>>((P*)c.links, c.g, partial);
+    }
+    static void unitarity(const Ctx& c, double* partial) {
+        k_unitarity<N, T><<<link_blocks(c.g), kBlock, 0, c.stream>>>((const P*)c.links, c.g, partial);
+    }
+    static void plaquette(const Ctx& c, double* partial) {
+        k_plaquette<N, T><<<site_blocks(c.g), kBlock, 0, c.stream>>>((const P*)c.links, c.g, partial);
+    }
+    static void polyakov(const Ctx& c, double* partial) {
+        k_polyakov<N, T><<<spatial_blocks(c.g), kBlock, 0, c.stream>>>((const P*)c.links, c.g, partial);
+    }
+    static void export_field(const Ctx& c, double* out) {
+        k_export<N, T><<<link_blocks(c.g), kBlock, 0, c.stream>>>((const P*)c.links, c.g, out);
+    }
+    static void import_field(const Ctx& c, const double* in) {
+        k_import<N, T><<<link_blocks(c.g), kBlock, 0, c.stream>>>((P*)c.links, c.g, in);
+    }
+
+    static const Ops* table() {
+        static const Ops ops = {&update, &init, &reunit, &unitarity, &plaquette, &polyakov, &export_field,
+                                &import_field};
+        return &ops;
+    }
+};
+
+}  // namespace sun
+
+#define SUN_DEFINE_OPS(NC)                                                     \
+    namespace sun {                                                            \
+    const Ops* ops_nc##NC(int f64) {                                           \
+        return f64 ? OpsImpl<NC, double>::table() : OpsImpl<NC, float>::table(); \
+    }                                                                          \
+    }

@@ -1,0 +1,213 @@
+"""Python binding of libsun (include/sun.h): argument marshalling only.
+
+Device memory comes from PyTorch (uint8 tensors on the current CUDA/HIP
+device) and every call is queued on torch's current stream.  All work runs in
+the HIP kernels of libsun; there is no CPU fallback: if the library is not
+built, load() raises.
+"""
+import ctypes
+import os
+
+import torch
+
+_PKG = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(_PKG, "_lib", "libsun.so")
+
+F32, F64 = 0, 1
+HEATBATH, OVERRELAX = 0, 1
+KERNEL_IDS = {"heatbath": 0, "overrelax": 1, "reunit": 2, "plaquette": 3, "polyakov": 4}
+SUN_OK = 0
+NC_MAX = 8
+
+_lib = None
+
+
+class SunError(RuntimeError):
+    pass
+
+
+def load():
+    """Loads libsun.so (after torch, so both use one HIP runtime)."""
+    global _lib
+    if _lib is not None:
+        return _lib
+    if not os.path.exists(LIB_PATH):
+        raise SunError(f"{LIB_PATH} is missing: build it with paper_1112_4533_amd.build.build()")
+    L = ctypes.CDLL(LIB_PATH)
+    c_int, c_u64, c_u32, c_dbl, vp = ctypes.c_int, ctypes.c_uint64, ctypes.c_uint32, ctypes.c_double, ctypes.c_void_p
+    L4 = ctypes.c_int * 4
+    sz = ctypes.c_size_t
+    sigs = {
+        "sun_lattice_bytes": [c_int, L4, c_int, ctypes.POINTER(sz), ctypes.POINTER(sz)],
+        "sun_lattice_create": [c_int, L4, c_int, vp, sz, vp, sz, ctypes.POINTER(vp)],
+        "sun_init": [vp, c_int, c_u64, vp],
+        "sun_phase": [vp, c_int, c_int, c_int, c_dbl, c_u64, c_u64, vp],
+        "sun_sweep": [vp, c_dbl, c_int, c_int, c_u64, c_int, vp],
+        "sun_reunitarize": [vp, vp, vp],
+        "sun_plaquette": [vp, vp, vp],
+        "sun_polyakov": [vp, vp, vp],
+        "sun_unitarity": [vp, vp, vp],
+        "sun_export": [vp, vp, vp],
+        "sun_import": [vp, vp, vp],
+        "sun_get_step": [vp, ctypes.POINTER(c_u64)],
+        "sun_set_step": [vp, c_u64],
+        "sun_profile": [vp, c_int],
+        "sun_profile_read": [vp, c_int, ctypes.POINTER(c_dbl), ctypes.POINTER(ctypes.c_int64)],
+        "sun_sample_su2": [c_int, vp, c_int, c_u64, c_u32, c_u32, vp, vp, vp],
+    }
+    for name, args in sigs.items():
+        f = getattr(L, name)
+        f.argtypes = args
+        f.restype = c_int
+    L.sun_lattice_destroy.argtypes = [vp]
+    L.sun_lattice_destroy.restype = None
+    L.sun_last_error.argtypes = []
+    L.sun_last_error.restype = ctypes.c_char_p
+    _lib = L
+    return L
+
+
+def exported_symbols():
+    """Names declared in include/sun.h that libsun exports."""
+    L = load()
+    return [n for n in ("sun_lattice_bytes", "sun_lattice_create", "sun_lattice_destroy", "sun_init",
+                        "sun_phase", "sun_sweep", "sun_reunitarize", "sun_plaquette", "sun_polyakov",
+                        "sun_unitarity", "sun_export", "sun_import", "sun_get_step", "sun_set_step",
+                        "sun_profile", "sun_profile_read", "sun_sample_su2", "sun_last_error")
+            if hasattr(L, n)]
+
+
+def _check(rc):
+    if rc != SUN_OK:
+        raise SunError(f"libsun error {rc}: {load().sun_last_error().decode()}")
+
+
+def _stream():
+    return ctypes.c_void_p(torch.cuda.current_stream().cuda_stream)
+
+
+def _ptr(t):
+    return ctypes.c_void_p(t.data_ptr())
+
+
+def _dtype_code(dtype):
+    if dtype in ("f32", "float32", torch.float32, F32):
+        return F32
+    if dtype in ("f64", "float64", torch.float64, F64):
+        return F64
+    raise ValueError(f"unknown link dtype {dtype!r}")
+
+
+def lattice_bytes(nc, L, dtype="f32"):
+    lb, sb = ctypes.c_size_t(), ctypes.c_size_t()
+    _check(load().sun_lattice_bytes(int(nc), (ctypes.c_int * 4)(*L), _dtype_code(dtype), ctypes.byref(lb),
+                                    ctypes.byref(sb)))
+    return lb.value, sb.value
+
+
+class Lattice:
+    """An SU(Nc) gauge field on an L[0] x L[1] x L[2] x L[3] periodic lattice,
+    stored on the GPU in the library's SoA layout."""
+
+    def __init__(self, nc, L, dtype="f32", device=None):
+        self.nc = int(nc)
+        self.L = tuple(int(v) for v in L)
+        self.dtype = _dtype_code(dtype)
+        self.V = 1
+        for v in self.L:
+            self.V *= v
+        lib = load()
+        lb, sb = lattice_bytes(self.nc, self.L, self.dtype)
+        dev = torch.device(device) if device is not None else torch.device("cuda", torch.cuda.current_device())
+        self.links = torch.empty(lb, dtype=torch.uint8, device=dev)
+        self.scratch = torch.empty(sb, dtype=torch.uint8, device=dev)
+        h = ctypes.c_void_p()
+        _check(lib.sun_lattice_create(self.nc, (ctypes.c_int * 4)(*self.L), self.dtype, _ptr(self.links), lb,
+                                      _ptr(self.scratch), sb, ctypes.byref(h)))
+        self._h = h
+
+    def __del__(self):
+        h = getattr(self, "_h", None)
+        if h is not None and _lib is not None:
+            _lib.sun_lattice_destroy(h)
+            self._h = None
+
+    # -- updates ---------------------------------------------------------
+    def init(self, hot=True, seed=0):
+        _check(load().sun_init(self._h, int(bool(hot)), int(seed), _stream()))
+
+    def phase(self, kind, mu, parity, beta, seed, step):
+        _check(load().sun_phase(self._h, int(kind), int(mu), int(parity), float(beta), int(seed), int(step),
+                                _stream()))
+
+    def sweep(self, beta, n_hb=1, n_or=4, seed=0, reunit=True):
+        _check(load().sun_sweep(self._h, float(beta), int(n_hb), int(n_or), int(seed), int(bool(reunit)),
+                                _stream()))
+
+    def reunitarize(self, report=False):
+        """Returns a device tensor {max|U^dag U - 1|, max|det - 1|} measured
+        before the projection when report is true."""
+        out = torch.zeros(2, dtype=torch.float64, device=self.links.device) if report else None
+        _check(load().sun_reunitarize(self._h, _ptr(out) if report else None, _stream()))
+        return out
+
+    # -- measurements (device tensors, asynchronous) ---------------------
+    def plaquette(self, out=None):
+        out = out if out is not None else torch.empty(3, dtype=torch.float64, device=self.links.device)
+        _check(load().sun_plaquette(self._h, _ptr(out), _stream()))
+        return out
+
+    def polyakov(self, out=None):
+        out = out if out is not None else torch.empty(2, dtype=torch.float64, device=self.links.device)
+        _check(load().sun_polyakov(self._h, _ptr(out), _stream()))
+        return out
+
+    def unitarity(self, out=None):
+        out = out if out is not None else torch.empty(2, dtype=torch.float64, device=self.links.device)
+        _check(load().sun_unitarity(self._h, _ptr(out), _stream()))
+        return out
+
+    # -- field transfer --------------------------------------------------
+    def export(self):
+        """Canonical FP64 field as a (4, V, Nc, Nc) complex128 device tensor."""
+        out = torch.empty((4, self.V, self.nc, self.nc, 2), dtype=torch.float64, device=self.links.device)
+        _check(load().sun_export(self._h, _ptr(out), _stream()))
+        return torch.view_as_complex(out)
+
+    def import_(self, field):
+        """Loads a canonical (4, V, Nc, Nc) complex field (device or host)."""
+        t = torch.as_tensor(field)
+        assert tuple(t.shape) == (4, self.V, self.nc, self.nc), t.shape
+        t = torch.view_as_real(t.to(torch.complex128)).contiguous().to(self.links.device)
+        _check(load().sun_import(self._h, _ptr(t), _stream()))
+        torch.cuda.current_stream().synchronize()
+
+    @property
+    def step(self):
+        v = ctypes.c_uint64()
+        _check(load().sun_get_step(self._h, ctypes.byref(v)))
+        return v.value
+
+    @step.setter
+    def step(self, value):
+        _check(load().sun_set_step(self._h, int(value)))
+
+    # -- event timing ----------------------------------------------------
+    def profile(self, enable=True):
+        _check(load().sun_profile(self._h, int(bool(enable))))
+
+    def profile_read(self, kernel):
+        ms, n = ctypes.c_double(), ctypes.c_int64()
+        _check(load().sun_profile_read(self._h, KERNEL_IDS.get(kernel, kernel), ctypes.byref(ms), ctypes.byref(n)))
+        return ms.value, n.value
+
+
+def sample_su2(alpha, seed, step=0, mu_sg=0, dtype="f64"):
+    """SU(2) heatbath draws on the GPU for a device float64 tensor alpha."""
+    alpha = alpha.to(torch.float64).contiguous()
+    n = alpha.numel()
+    x = torch.empty((n, 4), dtype=torch.float64, device=alpha.device)
+    att = torch.empty(n, dtype=torch.int32, device=alpha.device)
+    _check(load().sun_sample_su2(_dtype_code(dtype), _ptr(alpha), n, int(seed), int(step), int(mu_sg), _ptr(x),
+                                 _ptr(att), _stream()))
+    return x, att

@@ -1,0 +1,78 @@
+"""The C ABI library without a GPU: it loads, exports every function that
+include/sun.h declares, and validates arguments on the host."""
+import ctypes
+import os
+import re
+
+import pytest
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+HEADER = os.path.join(ROOT, "include", "sun.h")
+
+
+def declared():
+    src = open(HEADER).read()
+    src = re.sub(r"/\*.*?\*/", "", src, flags=re.S)
+    return sorted(set(re.findall(r"\b(sun_[a-z0-9_]+)\s*\(", src)))
+
+
+@pytest.fixture(scope="module")
+def lib():
+    from paper_1112_4533_amd import sun
+    return sun.load()
+
+
+def test_every_declared_symbol_is_exported(lib):
+    names = declared()
+    assert len(names) >= 18
+    missing = [n for n in names if not hasattr(lib, n)]
+    assert not missing, missing
+
+
+def _bytes(lib, nc, L, dtype):
+    lb, sb = ctypes.c_size_t(), ctypes.c_size_t()
+    rc = lib.sun_lattice_bytes(nc, (ctypes.c_int * 4)(*L), dtype, ctypes.byref(lb), ctypes.byref(sb))
+    return rc, lb.value, sb.value
+
+
+def test_lattice_bytes(lib):
+    rc, lb, sb = _bytes(lib, 3, (32, 32, 32, 32), 0)
+    assert rc == 0 and lb == 4 * 32 ** 4 * 18 * 4 and sb >= 16 * 4 * 32 ** 4 // 256
+    rc, lb, _ = _bytes(lib, 2, (8, 8, 8, 8), 1)
+    assert rc == 0 and lb == 4 * 8 ** 4 * 4 * 8           # SU(2): 4 reals per link
+    rc, lb, _ = _bytes(lib, 8, (12, 12, 12, 12), 1)
+    assert rc == 0 and lb == 4 * 12 ** 4 * 128 * 8
+
+
+@pytest.mark.parametrize("nc,L,dtype", [
+    (1, (8, 8, 8, 8), 0), (9, (8, 8, 8, 8), 0), (3, (7, 8, 8, 8), 0), (3, (1, 8, 8, 8), 0),
+    (3, (8, 8, 3, 8), 0), (3, (8, 8, 8, 8), 2), (3, (256, 256, 256, 256), 0)])
+def test_lattice_bytes_rejects(lib, nc, L, dtype):
+    rc, _, _ = _bytes(lib, nc, L, dtype)
+    assert rc == -1
+    assert lib.sun_last_error()
+
+
+def test_create_validates_buffers_without_touching_them(lib):
+    L = (4, 4, 4, 4)
+    rc, lb, sb = _bytes(lib, 3, L, 0)
+    h = ctypes.c_void_p()
+    args = lambda links, lbytes, scr, sbytes: (3, (ctypes.c_int * 4)(*L), 0, ctypes.c_void_p(links), lbytes,
+                                               ctypes.c_void_p(scr), sbytes, ctypes.byref(h))
+    assert lib.sun_lattice_create(*args(0, lb, 0x20000, sb)) == -2          # null links
+    assert lib.sun_lattice_create(*args(0x10000, lb - 1, 0x20000, sb)) == -2
+    assert lib.sun_lattice_create(*args(0x10000, lb, 0x20000, sb - 256)) == -2
+    assert lib.sun_lattice_create(*args(0x10010, lb, 0x20000, sb)) == -1    # misaligned
+    assert lib.sun_lattice_create(*args(0x10000, lb, 0x20000, sb)) == 0
+    v = ctypes.c_uint64()
+    assert lib.sun_get_step(h, ctypes.byref(v)) == 0 and v.value == 0
+    assert lib.sun_set_step(h, 77) == 0
+    assert lib.sun_get_step(h, ctypes.byref(v)) == 0 and v.value == 77
+    # bad phase arguments are rejected before any launch
+    assert lib.sun_phase(h, 2, 0, 0, 6.0, 1, 0, None) == -1
+    assert lib.sun_phase(h, 0, 4, 0, 6.0, 1, 0, None) == -1
+    assert lib.sun_phase(h, 0, 0, 2, 6.0, 1, 0, None) == -1
+    assert lib.sun_sweep(h, 6.0, -1, 0, 1, 1, None) == -1
+    assert lib.sun_plaquette(h, None, None) == -2
+    assert lib.sun_profile_read(h, 9, None, None) == -1
+    lib.sun_lattice_destroy(h)
