@@ -90,24 +90,26 @@ def run_gpu(run, steps, warmup):
     }
 
 
-def run_cpu_baseline(run):
-    """The FP64 CPU oracle on a bounded sample of the same workload: one full
-    sweep (1 HB + 4 OR, re-unitarization, plaquette) of the 32^4 lattice."""
+def run_cpu_baseline(run, sweeps):
+    """The FP64 CPU oracle on a bounded sample of the same workload: a few
+    full sweeps (1 HB + 4 OR, re-unitarization, plaquette) of the 32^4 lattice
+    from the same hot start."""
     import oracle as O
 
     U = O.new_field(run.nc, run.L, hot=run.hot, seed=run.seed)
     t0 = time.perf_counter()
-    O.sweep(U, run.nc, run.L, run.beta, run.n_hb, run.n_or, run.seed, 0, reunit=True)
-    O.plaquette(U, run.nc, run.L)
+    for k in range(sweeps):
+        O.sweep(U, run.nc, run.L, run.beta, run.n_hb, run.n_or, run.seed, k * run.n_hb, reunit=True)
+        O.plaquette(U, run.nc, run.L)
     dt = time.perf_counter() - t0
-    updates = (run.n_hb + run.n_or) * 4 * run.volume
+    updates = sweeps * (run.n_hb + run.n_or) * 4 * run.volume
     return {
         "value": updates / dt,
         "unit": "link_updates/s",
         "cores": O.num_threads(),
         "kind": "oracle",
-        "sample": (f"1 sweep (1 HB + 4 OR + re-unitarization + plaquette) of SU(3) {run.L[0]}^4, FP64, "
-                   f"{updates} link updates in {dt:.2f} s"),
+        "sample": (f"{sweeps} sweeps (1 HB + 4 OR + re-unitarization + plaquette) of SU(3) {run.L[0]}^4 "
+                   f"from the hot start, FP64: {updates} link updates in {dt:.2f} s"),
     }
 
 
@@ -117,8 +119,22 @@ def main():
     ap.add_argument("--steps", type=int, default=20)
     ap.add_argument("--warmup", type=int, default=3)
     ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--cpu-sweeps", type=int, default=8, help="oracle sweeps in the CPU-baseline sample")
     ap.add_argument("--no-f64", action="store_true")
+    ap.add_argument("--copy-calibration", type=float, default=0.0, metavar="GB",
+                    help="only copy a GB-sized device buffer 5 times (the reference kernel for "
+                         "scaling HBM byte counters), then exit")
     args = ap.parse_args()
+    if args.copy_calibration > 0:
+        import torch
+        n = int(args.copy_calibration * 1e9) // 4
+        a = torch.ones(n, dtype=torch.float32, device="cuda")
+        b = torch.empty_like(a)
+        for _ in range(5):
+            b.copy_(a)
+        torch.cuda.synchronize()
+        print(json.dumps({"copy_bytes_read": 4 * n, "copy_bytes_written": 4 * n, "launches": 5}), flush=True)
+        return
     if args.gpus != 1:
         print(f"bench.py: this build runs on one GPU; --gpus {args.gpus} is not supported "
               "(independent chains shard without communication; one lattice needs a halo exchange per phase)",
@@ -180,7 +196,7 @@ def main():
             "f32_over_f64": r32["updates_per_s"] / r64["updates_per_s"],
         }
     if not args.no_cpu_baseline:
-        line["cpu_baseline"] = run_cpu_baseline(run)
+        line["cpu_baseline"] = run_cpu_baseline(run, args.cpu_sweeps)
     print(json.dumps(line), flush=True)
 
 

@@ -37,7 +37,7 @@ def lib():
         L.orc_check.argtypes = [ctypes.c_int, L4]
         L.orc_init.argtypes = [ctypes.c_int, L4, dp, ctypes.c_int, ctypes.c_uint64]
         L.orc_phase.argtypes = [ctypes.c_int, L4, dp, ctypes.c_int, ctypes.c_int, ctypes.c_int,
-                                ctypes.c_double, ctypes.c_uint64, ctypes.c_uint64, dp, ip]
+                                ctypes.c_double, ctypes.c_uint64, ctypes.c_uint64, dp, ip, dp]
         L.orc_sweep.argtypes = [ctypes.c_int, L4, dp, ctypes.c_double, ctypes.c_int, ctypes.c_int,
                                 ctypes.c_uint64, ctypes.c_uint64, ctypes.c_int]
         L.orc_reunitarize.argtypes = [ctypes.c_int, L4, dp]
@@ -109,18 +109,22 @@ def new_field(nc, L, hot=False, seed=0):
 
 
 def phase(U, nc, L, kind, mu, parity, beta, seed, step, want_margin=False):
-    """One checkerboard phase in place; kind 0 = heatbath, 1 = overrelaxation."""
+    """One checkerboard phase in place; kind 0 = heatbath, 1 = overrelaxation.
+    With want_margin, returns per-site (decision margin, attempts, conditioning
+    |A|_F / k_min); sites not updated get -1."""
     _field(U, nc, L)
     V = volume(L)
     margin = np.empty(V) if want_margin else None
     attempts = np.empty(V, dtype=np.int32) if want_margin else None
+    cond = np.empty(V) if want_margin else None
     rc = lib().orc_phase(nc, _L4(L), _dp(U), int(kind), int(mu), int(parity), float(beta),
                          int(seed), int(step),
                          _dp(margin) if margin is not None else None,
                          attempts.ctypes.data_as(ctypes.POINTER(ctypes.c_int))
-                         if attempts is not None else None)
+                         if attempts is not None else None,
+                         _dp(cond) if cond is not None else None)
     _check(rc, "phase")
-    return (margin, attempts) if want_margin else None
+    return (margin, attempts, cond) if want_margin else None
 
 
 def sweep(U, nc, L, beta, n_hb, n_or, seed, step0, reunit=True):

@@ -464,20 +464,35 @@ static double subgroup_projection(int n, const cplx *W, int i, int j, cplx V[4])
 /* Cabibbo-Marinari pseudo-heatbath of one link (Sec. 2, steps 1-5):
  * staple, W = U A, then for every subgroup draw x ~ exp(alpha x0) and
  * left-multiply U (and W) by a = x V^dag. */
+static double frobenius(int n, const cplx *a)
+{
+    double s = 0.0;
+    for (int i = 0; i < n * n; ++i) s += creal(a[i]) * creal(a[i]) + cimag(a[i]) * cimag(a[i]);
+    return sqrt(s);
+}
+
+/* Conditioning of a link update: |A|_F / min_k, the staple norm over the
+ * smallest subgroup projection norm (V = P / k divides rounding by k). */
+static double conditioning(double a_norm, double kmin)
+{
+    return kmin > 0.0 ? a_norm / kmin : INFINITY;
+}
+
 static double heatbath_link(const geom *g, cplx *U, int64_t s, int mu, double beta,
-                            uint64_t seed, uint64_t step, int *attempts_out)
+                            uint64_t seed, uint64_t step, int *attempts_out, double *cond_out)
 {
     const int n = g->nc;
     cplx A[NC_MAX * NC_MAX], W[NC_MAX * NC_MAX];
     cplx *Ul = link(g, U, mu, s);
     staple(g, U, s, mu, A);
     mat_mul(n, Ul, A, W);
-    double margin = INFINITY;
+    double margin = INFINITY, kmin = INFINITY;
     int attempts = 0, sg = 0;
     for (int i = 0; i < n; ++i)
         for (int j = i + 1; j < n; ++j, ++sg) {
             cplx V[4], Vd[4], X[4], a[4];
             double k = subgroup_projection(n, W, i, j, V);
+            if (k < kmin) kmin = k;
             double alpha = 2.0 * beta * k / n;
             double x[4];
             uint32_t mu_sg = ((uint32_t)mu << 16) | (uint32_t)sg;
@@ -491,12 +506,13 @@ static double heatbath_link(const geom *g, cplx *U, int64_t s, int mu, double be
             rows_left_mul(n, W, i, j, a);
         }
     if (attempts_out) *attempts_out = attempts;
+    if (cond_out) *cond_out = conditioning(frobenius(n, A), kmin);
     return margin;
 }
 
 /* Overrelaxation of one link (Sec. 2): per subgroup a = V^dag V^dag, the
  * SU(2) reflection applied inside each subgroup of SU(Nc). */
-static void overrelax_link(const geom *g, cplx *U, int64_t s, int mu, int reverse)
+static double overrelax_link(const geom *g, cplx *U, int64_t s, int mu, int reverse)
 {
     const int n = g->nc;
     cplx A[NC_MAX * NC_MAX], W[NC_MAX * NC_MAX];
@@ -511,15 +527,18 @@ static void overrelax_link(const geom *g, cplx *U, int64_t s, int mu, int revers
             pj[np] = j;
             ++np;
         }
+    double kmin = INFINITY;
     for (int q = 0; q < npairs; ++q) {
         int p = reverse ? npairs - 1 - q : q;
         cplx V[4], Vd[4], a[4];
-        subgroup_projection(n, W, pi[p], pj[p], V);
+        double k = subgroup_projection(n, W, pi[p], pj[p], V);
+        if (k < kmin) kmin = k;
         mat2_dag(V, Vd);
         mat2_mul(Vd, Vd, a);
         rows_left_mul(n, Ul, pi[p], pj[p], a);
         rows_left_mul(n, W, pi[p], pj[p], a);
     }
+    return conditioning(frobenius(n, A), kmin);
 }
 
 /* ------------------------------------------------------------------------ */
@@ -562,7 +581,8 @@ int orc_init(int nc, const int L[4], double *Ud, int hot, uint64_t seed)
 }
 
 int orc_phase(int nc, const int L[4], double *Ud, int kind, int mu, int parity,
-              double beta, uint64_t seed, uint64_t step, double *margin, int *attempts)
+              double beta, uint64_t seed, uint64_t step, double *margin, int *attempts,
+              double *cond)
 {
     if (orc_check(nc, L) || mu < 0 || mu > 3 || (kind != 0 && kind != 1)) return -1;
     geom g;
@@ -574,17 +594,21 @@ int orc_phase(int nc, const int L[4], double *Ud, int kind, int mu, int parity,
         if (parity_of(&g, s) != (parity & 1)) {
             if (margin) margin[s] = -1.0;
             if (attempts) attempts[s] = 0;
+            if (cond) cond[s] = -1.0;
             continue;
         }
         if (kind == 0) {
             int a = 0;
-            double m = heatbath_link(&g, U, s, mu, beta, seed, step, &a);
+            double c = INFINITY;
+            double m = heatbath_link(&g, U, s, mu, beta, seed, step, &a, &c);
             if (margin) margin[s] = m;
             if (attempts) attempts[s] = a;
+            if (cond) cond[s] = c;
         } else {
-            overrelax_link(&g, U, s, mu, 0);
+            double c = overrelax_link(&g, U, s, mu, 0);
             if (margin) margin[s] = INFINITY;
             if (attempts) attempts[s] = 0;
+            if (cond) cond[s] = c;
         }
     }
     return 0;
@@ -610,11 +634,11 @@ int orc_sweep(int nc, const int L[4], double *Ud, double beta, int n_hb, int n_o
     for (int h = 0; h < n_hb; ++h)
         for (int mu = 0; mu < 4; ++mu)
             for (int p = 0; p < 2; ++p)
-                orc_phase(nc, L, Ud, 0, mu, p, beta, seed, step0 + (uint64_t)h, NULL, NULL);
+                orc_phase(nc, L, Ud, 0, mu, p, beta, seed, step0 + (uint64_t)h, NULL, NULL, NULL);
     for (int o = 0; o < n_or; ++o)
         for (int mu = 0; mu < 4; ++mu)
             for (int p = 0; p < 2; ++p)
-                orc_phase(nc, L, Ud, 1, mu, p, beta, seed, 0, NULL, NULL);
+                orc_phase(nc, L, Ud, 1, mu, p, beta, seed, 0, NULL, NULL, NULL);
     if (reunitarize) orc_reunitarize(nc, L, Ud);
     return 0;
 }
@@ -793,7 +817,7 @@ int orc_heatbath_link(int nc, const int L[4], double *Ud, int64_t s, int mu, dou
     geom g;
     make_geom(nc, L, &g);
     if (s < 0 || s >= g.V) return -1;
-    heatbath_link(&g, (cplx *)Ud, s, mu, beta, seed, step, NULL);
+    heatbath_link(&g, (cplx *)Ud, s, mu, beta, seed, step, NULL, NULL);
     return 0;
 }
 

@@ -48,9 +48,13 @@ int orc_init(int nc, const int L[4], double *U, int hot, uint64_t seed);
  * NULL) receives, for each updated site, the smallest distance of any
  * floating-point decision (branch switch or accept test) from its threshold;
  * other sites get -1.  attempts (length V, may be NULL) receives the number
- * of a0 attempts summed over subgroups. */
+ * of a0 attempts summed over subgroups; cond (length V, may be NULL) the
+ * conditioning |A|_F / k_min of the update (staple norm over the smallest
+ * subgroup projection norm, since V = P / k divides rounding by k), -1 for
+ * sites not updated. */
 int orc_phase(int nc, const int L[4], double *U, int kind, int mu, int parity,
-              double beta, uint64_t seed, uint64_t step, double *margin, int *attempts);
+              double beta, uint64_t seed, uint64_t step, double *margin, int *attempts,
+              double *cond);
 /* n_hb heatbath steps (steps step0 .. step0+n_hb-1), then n_or
  * overrelaxation steps, then re-unitarization if reunit != 0. */
 int orc_sweep(int nc, const int L[4], double *U, double beta, int n_hb, int n_or,

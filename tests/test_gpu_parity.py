@@ -1,16 +1,28 @@
 """GPU parity: the HIP path (through the C ABI) against the FP64 CPU oracle.
 
 Both sides draw the same Philox words, so one chain is one sample path.
-FP64 links must agree element by element to 1e-12; FP32 links to 1e-5, except
-links where a floating-point decision (Creutz/KP switch, accept test) lies
-within 1e-4 of its threshold in the oracle: there FP32 rounding may take the
-other branch, and such links are listed and counted instead.
+
+Tolerances.  Within one checkerboard phase every updated link depends only on
+links the phase does not touch, so a phase is compared link by link without
+cascades: FP64 to 1e-12 and FP32 to 1e-5, both scaled by max(1, c / 4), where
+c = |A|_F / k_min is the conditioning of that link's update (the rounding of
+W = U A is of order eps |A|, and the subgroup direction V = P / k divides it
+by k; c is about 4 for a typical link of a hot start).  For
+FP32, a link may also differ by O(1) when one of its floating-point decisions
+(Creutz/KP switch, accept test) sits within 1e-4 of its threshold in the
+oracle; such links are counted and bounded.  Over several sweeps the chain is
+chaotic (the oracle itself, perturbed at 1e-16, drifts by orders of magnitude
+per sweep), so free-running sweeps are compared against that measured
+sensitivity, and whole-sweep parity is instead checked phase by phase along
+the trajectory, plus bitwise equality of a sweep with its documented sequence
+of phases.
 """
 import numpy as np
 import pytest
 import torch
 
 import oracle as O
+from stats import binned_mean_err
 
 pytestmark = pytest.mark.gpu
 
@@ -41,20 +53,40 @@ def rounded(field, dtype):
     return r + 1j * i
 
 
-def compare_links(gpu_field, orc_field, dtype, margin=None, what=""):
+def compare_links(gpu_field, orc_field, dtype, margin=None, cond=None, what=""):
+    """Link-by-link comparison; margin and cond are (4, V) arrays from the
+    oracle's phase diagnostics (entries < 0: link not updated)."""
     d = np.abs(gpu_field - orc_field).reshape(4, gpu_field.shape[1], -1).max(axis=2)
-    bad = d > TOL[dtype]
-    if dtype == "f64" or margin is None:
-        assert not bad.any(), f"{what}: max |dU| = {d.max():.3e} at {np.argwhere(d == d.max())[:3]}"
+    scale = np.ones_like(d)
+    if cond is not None:
+        c = np.asarray(cond, dtype=np.float64)
+        scale = np.maximum(1.0, np.where(c > 0, c, 0.0) / 4.0)
+        ratio = d / (TOL[dtype] * scale)
+        print(f"{what}: max |dU| {d.max():.2e}, max |dU| / tol {ratio.max():.3f}")
+    bad = d > TOL[dtype] * scale
+    if not bad.any():
         return 0
-    # FP32: every out-of-tolerance link must sit at a near-threshold decision
-    margin = np.where(np.asarray(margin) < 0, np.inf, margin)   # -1: site not updated
     idx = np.argwhere(bad)
+    if dtype == "f64" or margin is None:
+        mu, s = idx[0]
+        raise AssertionError(f"{what}: {len(idx)} links out of tolerance, e.g. (mu={mu}, s={s}) "
+                             f"|dU| = {d[mu, s]:.3e}, tol {TOL[dtype] * scale[mu, s]:.2e}")
+    m = np.where(np.asarray(margin) < 0, np.inf, margin)
     for mu, s in idx:
-        assert margin[mu][s] < FLIP_MARGIN, (
-            f"{what}: link (mu={mu}, s={s}) differs by {d[mu, s]:.3e} with decision margin {margin[mu][s]:.3e}")
+        assert m[mu][s] < FLIP_MARGIN, (
+            f"{what}: link (mu={mu}, s={s}) differs by {d[mu, s]:.3e} with decision margin {m[mu][s]:.3e}")
     assert len(idx) <= max(3, 1e-4 * d.size), f"{what}: {len(idx)} flipped links"
     return len(idx)
+
+
+def oracle_phase_diag(field, nc, L, kind, mu, par, beta, seed, step):
+    """Runs the oracle phase in place; returns (4, V) margin and conditioning maps."""
+    margin, _, cond = O.phase(field, nc, L, kind, mu, par, beta, seed, step, want_margin=True)
+    mfull = np.full((4, field.shape[1]), -1.0)
+    cfull = np.full((4, field.shape[1]), -1.0)
+    mfull[mu] = margin
+    cfull[mu] = cond
+    return mfull, cfull
 
 
 def thermal_field(nc, L, beta, sweeps=2, seed=77):
@@ -101,7 +133,8 @@ def test_hot_start_parity(gpu, nc, dtype):
     lat = gpu_lattice(gpu, nc, L, dtype, hot=True, seed=1234)
     got = to_np(lat.export())
     want = O.new_field(nc, L, hot=True, seed=1234)
-    tol = 1e-13 if dtype == "f64" else 1e-6
+    # one Gram-Schmidt pass over a Gaussian matrix: rounding ~ cond(M) * eps
+    tol = 1e-12 if dtype == "f64" else 1e-6
     assert np.abs(got - want).max() < tol
 
 
@@ -147,6 +180,9 @@ def test_reunitarize_parity(gpu, nc):
     rng = np.random.default_rng(nc)
     U = thermal_field(nc, L, BETA[nc], sweeps=1)
     U = U + 1e-3 * (rng.standard_normal(U.shape) + 1j * rng.standard_normal(U.shape))
+    if nc == 2:   # SU(2) is stored as a quaternion: keep the matrix in a0 + i a.sigma form
+        U[..., 1, 0] = -np.conj(U[..., 0, 1])
+        U[..., 1, 1] = np.conj(U[..., 0, 0])
     lat = gpu_lattice(gpu, nc, L, "f64", field=U)
     before = to_np(lat.reunitarize(report=True))
     after = to_np(lat.export())
@@ -174,10 +210,8 @@ def test_phase_parity(gpu, nc, dtype, kind):
             lat.phase(kind, mu, par, beta, seed=99, step=7)
             got = to_np(lat.export())
             want = base.copy()
-            margin, _ = O.phase(want, nc, L, kind, mu, par, beta, 99, 7, want_margin=True)
-            mfull = np.full((4, want.shape[1]), np.inf)
-            mfull[mu] = margin
-            flips += compare_links(got, want, dtype, mfull, f"nc={nc} {dtype} kind={kind} mu={mu} p={par}")
+            m, k = oracle_phase_diag(want, nc, L, kind, mu, par, beta, 99, 7)
+            flips += compare_links(got, want, dtype, m, k, f"nc={nc} {dtype} kind={kind} mu={mu} p={par}")
     print(f"flips: {flips}")
 
 
@@ -192,62 +226,156 @@ def test_phase_parity_beta_zero_and_two_site_extent(gpu, dtype):
         lat.phase(0, 1, 1, beta, seed=5, step=3)
         got = to_np(lat.export())
         want = base.copy()
-        margin, _ = O.phase(want, nc, L, 0, 1, 1, beta, 5, 3, want_margin=True)
-        mfull = np.full((4, want.shape[1]), np.inf)
-        mfull[1] = margin
-        compare_links(got, want, dtype, mfull, f"beta={beta}")
+        m, k = oracle_phase_diag(want, nc, L, 0, 1, 1, beta, 5, 3)
+        compare_links(got, want, dtype, m, k, f"beta={beta}")
 
 
 # ---------------------------------------------------------------------------
-# Whole sweeps (the sample path over several sweeps)
+# Whole sweeps
 # ---------------------------------------------------------------------------
-@pytest.mark.parametrize("nc,L,beta,hot,n_hb,n_or", [
-    (2, (8, 8, 8, 8), 2.3, False, 1, 3),        # SU(2) 8^4 cold start, 1 HB + 3 OR
-    (3, (8, 8, 8, 8), 6.0, True, 1, 4),          # SU(3) hot start, 1 HB + 4 OR
-    (4, (6, 6, 6, 6), 11.1, True, 1, 1),         # SU(4), 1 HB + 1 OR
-    (3, (10, 6, 4, 6), 5.7, True, 2, 1),         # ragged volume, 2 HB steps per sweep
+def run_phases_like_a_sweep(lat, beta, n_hb, n_or, seed):
+    """The documented sweep: n_hb heatbath steps (RNG steps counter + h), then
+    n_or overrelaxation steps, each over mu = 0..3, even then odd; then
+    re-unitarization; the counter advances by n_hb."""
+    step0 = lat.step
+    for h in range(n_hb):
+        for mu in range(4):
+            for p in range(2):
+                lat.phase(0, mu, p, beta, seed, step0 + h)
+    for _ in range(n_or):
+        for mu in range(4):
+            for p in range(2):
+                lat.phase(1, mu, p, beta, seed, 0)
+    lat.reunitarize()
+    lat.step = step0 + n_hb
+
+
+@pytest.mark.parametrize("nc,dtype,n_hb,n_or", [(2, "f64", 1, 3), (3, "f32", 1, 4), (3, "f64", 2, 1),
+                                                (4, "f32", 1, 1)])
+def test_sweep_is_its_phase_sequence_bitwise(gpu, nc, dtype, n_hb, n_or):
+    L = (6, 4, 4, 8)
+    a = gpu_lattice(gpu, nc, L, dtype, hot=True, seed=21)
+    b = gpu_lattice(gpu, nc, L, dtype, hot=True, seed=21)
+    for _ in range(2):
+        a.sweep(BETA[nc], n_hb, n_or, seed=21)
+        run_phases_like_a_sweep(b, BETA[nc], n_hb, n_or, 21)
+    torch.cuda.synchronize()
+    assert torch.equal(a.links, b.links)
+    assert a.step == b.step == 2 * n_hb
+
+
+@pytest.mark.parametrize("nc,dtype,hot", [(2, "f64", False), (3, "f64", True), (4, "f64", True),
+                                          (3, "f32", True), (2, "f32", True)])
+def test_sweep_trajectory_parity_phase_by_phase(gpu, nc, dtype, hot):
+    """Two sweeps (1 HB + 2 OR) from a start configuration, every phase and
+    the re-unitarization compared with the oracle applied to the GPU's own
+    state before that phase."""
+    L, beta, seed = (6, 4, 4, 8), BETA[nc], 1234
+    lat = gpu_lattice(gpu, nc, L, dtype, hot=hot, seed=seed)
+    flips = 0
+    for sweep in range(2):
+        for kind, step in [(0, sweep)] + [(1, 0)] * 2:
+            for mu in range(4):
+                for p in range(2):
+                    before = to_np(lat.export())
+                    lat.phase(kind, mu, p, beta, seed, step)
+                    m, k = oracle_phase_diag(before, nc, L, kind, mu, p, beta, seed, step)
+                    flips += compare_links(to_np(lat.export()), before, dtype, m, k,
+                                           f"sweep {sweep} kind {kind} mu {mu} p {p}")
+        before = to_np(lat.export())
+        lat.reunitarize()
+        O.reunitarize(before, nc, L)
+        compare_links(to_np(lat.export()), before, dtype, what=f"reunit after sweep {sweep}")
+    print(f"FP32 decision flips along the trajectory: {flips}")
+
+
+def sensitivity(U0, nc, L, beta, n_hb, n_or, seed, nsweeps, eps):
+    """Max |U - U'| per sweep between two oracle chains whose start differs
+    by eps-sized noise: how far rounding alone can move this trajectory."""
+    rng = np.random.default_rng(0)
+    a = U0.copy()
+    b = U0 + eps * (rng.standard_normal(U0.shape) + 1j * rng.standard_normal(U0.shape))
+    out = []
+    for k in range(nsweeps):
+        O.sweep(a, nc, L, beta, n_hb, n_or, seed, k * n_hb)
+        O.sweep(b, nc, L, beta, n_hb, n_or, seed, k * n_hb)
+        out.append(np.abs(a - b).max())
+    return out
+
+
+@pytest.mark.parametrize("nc,L,beta,start,n_hb,n_or", [
+    (2, (8, 8, 8, 8), 2.3, "cold", 1, 3),        # SU(2) 8^4 cold start, 1 HB + 3 OR
+    (3, (8, 8, 8, 8), 6.0, "thermal", 1, 4),     # SU(3), 1 HB + 4 OR
+    (3, (8, 8, 8, 8), 6.0, "hot", 1, 4),
+    (4, (6, 6, 6, 6), 11.1, "thermal", 1, 1),    # SU(4), 1 HB + 1 OR
+    (3, (10, 6, 4, 6), 5.7, "hot", 2, 1),        # ragged volume, 2 HB steps per sweep
+    (3, (8, 8, 1, 1), 3.0, "hot", 1, 2),         # 2D lattice
 ])
-def test_sweep_parity_f64(gpu, nc, L, beta, hot, n_hb, n_or):
-    lat = gpu_lattice(gpu, nc, L, "f64", hot=hot, seed=1234)
-    U = O.new_field(nc, L, hot=hot, seed=1234)
-    step = 0
-    for sweep in range(3):
-        lat.sweep(beta, n_hb, n_or, seed=1234)
-        O.sweep(U, nc, L, beta, n_hb, n_or, 1234, step)
-        step += n_hb
-        assert lat.step == step
-        got = to_np(lat.export())
-        compare_links(got, U, "f64", what=f"sweep {sweep}")
-        np.testing.assert_allclose(to_np(lat.plaquette()), O.plaquette(U, nc, L), rtol=1e-12)
-
-
-def test_sweep_2d_lattice(gpu):
-    nc, L = 3, (8, 8, 1, 1)
-    lat = gpu_lattice(gpu, nc, L, "f64", hot=True, seed=4)
-    U = O.new_field(nc, L, hot=True, seed=4)
+def test_free_running_sweeps_f64(gpu, nc, L, beta, start, n_hb, n_or):
+    """Three free-running FP64 sweeps: the GPU chain stays within the
+    rounding sensitivity of the oracle chain (1e-12 + 100 x the spread of a
+    1e-15-perturbed oracle twin), and the plaquettes agree to the same bound."""
+    seed = 1234
+    if start == "thermal":
+        U = O.new_field(nc, L, hot=False, seed=seed)
+        for k in range(10):
+            O.sweep(U, nc, L, beta, 1, 2, 99, k)
+    else:
+        U = O.new_field(nc, L, hot=(start == "hot"), seed=seed)
+    bound = [1e-12 + 100 * s for s in sensitivity(U, nc, L, beta, n_hb, n_or, seed, 3, 1e-15)]
+    lat = gpu_lattice(gpu, nc, L, "f64", field=U)
+    lat.step = 0
     for k in range(3):
-        lat.sweep(3.0, 1, 2, seed=4)
-        O.sweep(U, nc, L, 3.0, 1, 2, 4, k)
-    compare_links(to_np(lat.export()), U, "f64", what="2D")
+        lat.sweep(beta, n_hb, n_or, seed=seed)
+        O.sweep(U, nc, L, beta, n_hb, n_or, seed, k * n_hb)
+        assert lat.step == (k + 1) * n_hb
+        dev = np.abs(to_np(lat.export()) - U).max()
+        print(f"sweep {k}: max |dU| = {dev:.2e}, bound {bound[k]:.2e}")
+        assert dev <= bound[k], (k, dev, bound[k])
+        if bound[k] < 1e-6:
+            assert np.abs(to_np(lat.plaquette()) - O.plaquette(U, nc, L)).max() <= bound[k]
 
 
-def test_sweep_f32_tracks_f64_oracle(gpu):
-    """FP32 links over whole sweeps: first-sweep links within 1e-5 except
-    near-threshold decisions; plaquette after 3 sweeps within 1e-5."""
-    nc, L, beta = 3, (8, 8, 8, 8), 6.0
-    lat = gpu_lattice(gpu, nc, L, "f32", hot=True, seed=1234)
-    U = O.new_field(nc, L, hot=True, seed=1234)
-    lat.sweep(beta, 1, 4, seed=1234)
-    O.sweep(U, nc, L, beta, 1, 4, 1234, 0)
-    d = np.abs(to_np(lat.export()) - U).max()
-    for k in range(1, 3):
-        lat.sweep(beta, 1, 4, seed=1234)
-        O.sweep(U, nc, L, beta, 1, 4, 1234, k)
-    p_gpu, p_orc = to_np(lat.plaquette()), O.plaquette(U, nc, L)
-    print(f"sweep-1 max |dU| = {d:.2e}; plaquette gpu {p_gpu[0]:.8f} oracle {p_orc[0]:.8f}")
-    if d > 1e-5:
-        pytest.skip(f"a near-threshold FP32 decision flipped in sweep 1 (max |dU| {d:.2e})")
-    assert abs(p_gpu[0] - p_orc[0]) < 1e-5
+def test_f32_chain_matches_f64_oracle_statistically(gpu):
+    """FP32 links with FP64 reductions against the FP64 oracle chain: the
+    long-run plaquette agrees within the combined statistical error."""
+    nc, L, beta = 3, (6, 6, 6, 6), 5.7
+    lat = gpu_lattice(gpu, nc, L, "f32", hot=True, seed=11)
+    U = O.new_field(nc, L, hot=True, seed=12)
+    pg, po = [], []
+    out = torch.empty(3, dtype=torch.float64, device="cuda")
+    series = torch.empty(300, dtype=torch.float64, device="cuda")
+    for k in range(350):
+        lat.sweep(beta, 1, 2, seed=11)
+        O.sweep(U, nc, L, beta, 1, 2, 12, k)
+        if k >= 50:
+            lat.plaquette(out)
+            series[k - 50] = out[0]
+            po.append(O.plaquette(U, nc, L)[0])
+    pg = to_np(series)
+    mg, eg = binned_mean_err(pg)
+    mo, eo = binned_mean_err(po)
+    print(f"plaquette FP32 GPU {mg:.5f} +- {eg:.5f}, FP64 oracle {mo:.5f} +- {eo:.5f}")
+    assert abs(mg - mo) < 4 * np.hypot(eg, eo)
+
+
+def test_2d_su2_exact_plaquette_on_gpu(gpu):
+    """The GPU chain alone against the exact 2D SU(2) torus result."""
+    from closed_forms import su2_torus_plaquette
+    L, beta = (16, 16, 1, 1), 2.3
+    lat = gpu_lattice(gpu, 2, L, "f32", hot=True, seed=5)
+    out = torch.empty(3, dtype=torch.float64, device="cuda")
+    n = 4000
+    series = torch.empty(n, dtype=torch.float64, device="cuda")
+    for k in range(100 + n):
+        lat.sweep(beta, 1, 3, seed=5)
+        if k >= 100:
+            lat.plaquette(out)
+            series[k - 100] = out[0]
+    m, e = binned_mean_err(to_np(series))
+    exact = su2_torus_plaquette(beta, 256)
+    print(f"2D SU(2) GPU {m:.5f} +- {e:.5f}, exact {exact:.5f}")
+    assert abs(m - exact) < 4 * e
 
 
 # ---------------------------------------------------------------------------
@@ -262,11 +390,10 @@ def test_full_size_su3_32_phase_parity(gpu):
     lat.phase(0, 2, 0, beta, seed=1234, step=0)
     lat.phase(1, 3, 1, beta, seed=1234, step=0)
     got = to_np(lat.export())
-    m_hb, _ = O.phase(base, nc, L, 0, 2, 0, beta, 1234, 0, want_margin=True)
-    O.phase(base, nc, L, 1, 3, 1, beta, 1234, 0)
-    margin = np.full((4, base.shape[1]), np.inf)
-    margin[2] = m_hb
-    flips = compare_links(got, base, "f32", margin, "32^4")
+    m2, k2 = oracle_phase_diag(base, nc, L, 0, 2, 0, beta, 1234, 0)
+    m3, k3 = oracle_phase_diag(base, nc, L, 1, 3, 1, beta, 1234, 0)
+    m2[3], k2[3] = m3[3], k3[3]
+    flips = compare_links(got, base, "f32", m2, k2, "32^4")
     print(f"32^4 flips: {flips}")
     np.testing.assert_allclose(to_np(lat.plaquette()), O.plaquette(base, nc, L), atol=2e-6)
 
