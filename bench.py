@@ -90,6 +90,75 @@ def run_gpu(run, steps, warmup):
     }
 
 
+def run_batch(steps, warmup, f64_sweeps):
+    """The 64-chain batch (mixed SU(2)/SU(3), extents 8..20, per-chain beta
+    and seed): FP32 links swept together from a captured graph (each replay
+    is one sweep of every chain: 1 HB + 4 OR, re-unitarization, plaquettes),
+    against the same chains in FP64 swept one chain at a time with eager
+    launches."""
+    import torch
+    from paper_1112_4533_amd import sun
+    from paper_1112_4533_amd.workloads import batch_spec
+
+    spec = batch_spec()
+    total_sites = sum(r.volume for r in spec)
+    n_hb, n_or = spec[0].n_hb, spec[0].n_or
+    lats = []
+    for r in spec:
+        lat = sun.Lattice(r.nc, r.L, "f32")
+        lat.init(hot=True, seed=r.seed)
+        lats.append(lat)
+    bt = sun.Batch(lats, [r.beta for r in spec], [r.seed for r in spec])
+    plaq32 = torch.zeros((len(spec), 3), dtype=torch.float64, device="cuda")
+    bt.capture(n_sweeps=1, n_hb=n_hb, n_or=n_or, reunit=True, plaq_out=plaq32)
+    for _ in range(warmup):
+        bt.replay()
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for _ in range(steps):
+        bt.replay()
+    torch.cuda.synchronize()
+    dt32 = time.perf_counter() - t0
+    upd32 = steps * (n_hb + n_or) * 4 * total_sites / dt32
+
+    l64 = []
+    for r in spec:
+        lat = sun.Lattice(r.nc, r.L, "f64")
+        lat.init(hot=True, seed=r.seed)
+        l64.append(lat)
+    plaq64 = torch.zeros((len(spec), 3), dtype=torch.float64, device="cuda")
+
+    def sweep64():
+        for i, (r, lat) in enumerate(zip(spec, l64)):
+            lat.sweep(r.beta, n_hb, n_or, seed=r.seed)
+            lat.plaquette(plaq64[i])
+
+    for _ in range(warmup):
+        sweep64()
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for _ in range(f64_sweeps):
+        sweep64()
+    torch.cuda.synchronize()
+    dt64 = time.perf_counter() - t0
+    upd64 = f64_sweeps * (n_hb + n_or) * 4 * total_sites / dt64
+    # both chains sets have now run warmup + timed sweeps; compare their plaquettes
+    # after catching the FP64 set up to the same sweep count
+    for _ in range(steps - f64_sweeps):
+        sweep64()
+    d = (plaq32[:, 0] - plaq64[:, 0]).cpu()
+    return {
+        "chains": len(spec), "sites": total_sites,
+        "fp32_batched_graph": {"value": upd32, "unit": "link_updates/s", "ms_per_sweep": 1e3 * dt32 / steps,
+                               "sweeps": steps},
+        "fp64_per_chain_eager": {"value": upd64, "unit": "link_updates/s", "ms_per_sweep": 1e3 * dt64 / f64_sweeps,
+                                 "sweeps": f64_sweeps},
+        "speedup": upd32 / upd64,
+        "plaquette_f32_minus_f64": {"mean": float(d.mean()), "std": float(d.std()),
+                                    "after_sweeps": warmup + steps},
+    }
+
+
 def run_cpu_baseline(run, sweeps):
     """The FP64 CPU oracle on a bounded sample of the same workload: a few
     full sweeps (1 HB + 4 OR, re-unitarization, plaquette) of the 32^4 lattice
@@ -121,6 +190,7 @@ def main():
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--cpu-sweeps", type=int, default=8, help="oracle sweeps in the CPU-baseline sample")
     ap.add_argument("--no-f64", action="store_true")
+    ap.add_argument("--no-batch", action="store_true")
     ap.add_argument("--copy-calibration", type=float, default=0.0, metavar="GB",
                     help="only copy a GB-sized device buffer 5 times (the reference kernel for "
                          "scaling HBM byte counters), then exit")
@@ -195,6 +265,8 @@ def main():
             "max_unitarity_dev_before_reunit": r64["unitarity_before_reunit"],
             "f32_over_f64": r32["updates_per_s"] / r64["updates_per_s"],
         }
+    if not args.no_batch:
+        line["batch"] = run_batch(max(4, args.steps), args.warmup, max(2, args.steps // 4))
     if not args.no_cpu_baseline:
         line["cpu_baseline"] = run_cpu_baseline(run, args.cpu_sweeps)
     print(json.dumps(line), flush=True)

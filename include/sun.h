@@ -140,6 +140,47 @@ int sun_profile_read(sun_lattice_t h, int kernel, double *total_ms, int64_t *lau
 int sun_sample_su2(int dtype, const double *dev_alpha, int n, uint64_t seed, uint32_t step,
                    uint32_t mu_sg, double *dev_x, int *dev_attempts, sun_stream_t stream);
 
+/* ------------------------------------------------------------------------
+ * Batches of independent chains (many small lattices in one launch per
+ * phase).  A batch groups n lattices of any Nc, precision and extents; each
+ * chain has its own coupling beta[i] and seed[i].  One launch per phase and
+ * per (Nc, precision) group covers every chain of the group; the chains'
+ * RNG step counters live in the device table, so a captured graph replays
+ * with fresh random numbers.  A chain run in a batch gives bitwise the same
+ * field as the same chain run alone with sun_sweep.
+ * While the batch exists, drive its lattices only through it; sun_batch_sync
+ * hands the advanced step counters back to the lattice handles.
+ * ------------------------------------------------------------------------ */
+typedef struct sun_batch_s *sun_batch_t;
+
+/* Device bytes of the descriptor table of an n-chain batch. */
+int sun_batch_bytes(int n, size_t *table_bytes);
+
+/* Creates a batch over n existing lattice handles (which must outlive it).
+ * betas, seeds: host arrays of n values.  table: caller-owned device memory
+ * of sun_batch_bytes() bytes, 256-byte aligned; it is written once here with
+ * a synchronous copy. */
+int sun_batch_create(int n, const sun_lattice_t *chains, const double *betas, const uint64_t *seeds,
+                     void *table, size_t table_bytes, sun_batch_t *out);
+
+/* One sweep of every chain (same schedule as sun_sweep). */
+int sun_batch_sweep(sun_batch_t b, int n_hb, int n_or, int reunit, sun_stream_t stream);
+
+/* Mean plaquettes, FP64: dev_out[3 i .. 3 i + 2] = {total, spatial, temporal}
+ * of chain i (caller's order). */
+int sun_batch_plaquette(sun_batch_t b, double *dev_out, sun_stream_t stream);
+
+/* Captures n_sweeps sweeps (each followed by the plaquettes into dev_plaq if
+ * not NULL) as one HIP graph owned by the batch, replacing any earlier one.
+ * stream must not be the null stream.  Nothing runs until sun_batch_replay. */
+int sun_batch_capture(sun_batch_t b, int n_sweeps, int n_hb, int n_or, int reunit, double *dev_plaq,
+                      sun_stream_t stream);
+int sun_batch_replay(sun_batch_t b, sun_stream_t stream);
+
+/* Writes the chains' advanced RNG step counters back to their handles. */
+int sun_batch_sync(sun_batch_t b);
+void sun_batch_destroy(sun_batch_t b);
+
 const char *sun_last_error(void);
 
 #ifdef __cplusplus

@@ -368,7 +368,191 @@ int sun_sample_su2(int dtype, const double* dev_alpha, int n, uint64_t seed, uin
 
 }  // extern "C"
 
+// ---------------------------------------------------------------------------
+// Batches of independent chains.
+// ---------------------------------------------------------------------------
+struct sun_batch_s {
+    struct Group {
+        const sun::Ops* ops;
+        int first, count;      // range of the device table
+        int tiles[4];          // total tiles per grid kind
+    };
+    std::vector<sun_lattice_t> chains;  // in the caller's order
+    std::vector<Group> groups;
+    sun::ChainDesc* table = nullptr;    // device
+    uint64_t hb_steps_done = 0;         // heatbath steps run since creation (all chains alike)
+    std::vector<uint64_t> step0;        // chain step counters at creation
+    hipGraph_t graph = nullptr;
+    hipGraphExec_t exec = nullptr;
+    uint64_t hb_per_replay = 0;
+};
+
+namespace {
+
+int batch_sweep_launches(sun_batch_t b, int n_hb, int n_or, int reunit, hipStream_t s) {
+    for (const auto& gr : b->groups) {
+        const sun::ChainDesc* d = b->table + gr.first;
+        for (int k = 0; k < n_hb; ++k)
+            for (int mu = 0; mu < 4; ++mu)
+                for (int p = 0; p < 2; ++p)
+                    gr.ops->update_batch(d, gr.count, gr.tiles[0], SUN_HEATBATH, mu, p, (uint32_t)k, s);
+        for (int k = 0; k < n_or; ++k)
+            for (int mu = 0; mu < 4; ++mu)
+                for (int p = 0; p < 2; ++p)
+                    gr.ops->update_batch(d, gr.count, gr.tiles[0], SUN_OVERRELAX, mu, p, 0, s);
+        if (reunit) gr.ops->reunit_batch(d, gr.count, gr.tiles[2], s);
+    }
+    if (n_hb > 0) sun::launch_advance_steps(b->table, (int)b->chains.size(), n_hb, s);
+    return launch_check("batch sweep");
+}
+
+int batch_plaquette_launches(sun_batch_t b, double* out, hipStream_t s) {
+    for (const auto& gr : b->groups) gr.ops->plaquette_batch(b->table + gr.first, gr.count, gr.tiles[1], out, s);
+    return launch_check("batch plaquette");
+}
+
+}  // namespace
+
+extern "C" {
+
+int sun_batch_bytes(int n, size_t* table_bytes) {
+    if (n <= 0) return fail(SUN_EINVAL, "batch of %d chains", n);
+    if (table_bytes) *table_bytes = ((sizeof(sun::ChainDesc) * (size_t)n) + 255) & ~(size_t)255;
+    return SUN_OK;
+}
+
+int sun_batch_create(int n, const sun_lattice_t* chains, const double* betas, const uint64_t* seeds, void* table,
+                     size_t table_bytes, sun_batch_t* out) {
+    if (!out) return fail(SUN_EINVAL, "out is null");
+    *out = nullptr;
+    size_t need = 0;
+    if (int rc = sun_batch_bytes(n, &need)) return rc;
+    if (!chains || !betas || !seeds) return fail(SUN_EINVAL, "null chain, beta or seed array");
+    if (!table || table_bytes < need) return fail(SUN_ESIZE, "table of %zu bytes, need %zu", table_bytes, need);
+    if ((uintptr_t)table & 255) return fail(SUN_EINVAL, "table must be 256-byte aligned");
+    for (int i = 0; i < n; ++i)
+        if (!chains[i]) return fail(SUN_EINVAL, "chain %d is null", i);
+    auto* b = new sun_batch_s;
+    b->chains.assign(chains, chains + n);
+    b->table = static_cast<sun::ChainDesc*>(table);
+    // group by (Nc, dtype), keeping the caller's order inside a group
+    std::vector<sun::ChainDesc> host;
+    for (int nc = 2; nc <= SUN_NC_MAX; ++nc)
+        for (int dt = SUN_F32; dt <= SUN_F64; ++dt) {
+            sun_batch_s::Group gr{ops_for(nc, dt == SUN_F64), (int)host.size(), 0, {0, 0, 0, 0}};
+            for (int i = 0; i < n; ++i) {
+                const sun_lattice_t h = chains[i];
+                if (h->nc != nc || h->dtype != dt) continue;
+                sun::ChainDesc c{};
+                c.links = h->links;
+                c.scratch = h->scratch;
+                c.g = h->g;
+                c.beta = betas[i];
+                c.k0 = (uint32_t)seeds[i];
+                c.k1 = (uint32_t)(seeds[i] >> 32);
+                c.step = h->step;
+                c.tile0[0] = gr.tiles[0];
+                c.tile0[1] = gr.tiles[1];
+                c.tile0[2] = gr.tiles[2];
+                c.tile0[3] = gr.tiles[3];
+                c.out_index = i;
+                gr.tiles[0] += sun::half_blocks(h->g);
+                gr.tiles[1] += sun::site_blocks(h->g);
+                gr.tiles[2] += sun::link_blocks(h->g);
+                gr.tiles[3] += sun::spatial_blocks(h->g);
+                host.push_back(c);
+                ++gr.count;
+            }
+            if (gr.count) b->groups.push_back(gr);
+        }
+    for (int i = 0; i < n; ++i) b->step0.push_back(chains[i]->step);
+    if (int rc = hip_check(hipMemcpy(table, host.data(), sizeof(sun::ChainDesc) * host.size(), hipMemcpyHostToDevice),
+                           "batch table upload")) {
+        delete b;
+        return rc;
+    }
+    *out = b;
+    return SUN_OK;
+}
+
+int sun_batch_sweep(sun_batch_t b, int n_hb, int n_or, int reunit, sun_stream_t stream) {
+    if (!b) return fail(SUN_EINVAL, "null batch");
+    if (n_hb < 0 || n_or < 0) return fail(SUN_EINVAL, "negative step count (n_hb %d, n_or %d)", n_hb, n_or);
+    if (int rc = batch_sweep_launches(b, n_hb, n_or, reunit, as_stream(stream))) return rc;
+    b->hb_steps_done += (uint64_t)n_hb;
+    return SUN_OK;
+}
+
+int sun_batch_plaquette(sun_batch_t b, double* dev_out, sun_stream_t stream) {
+    if (!b) return fail(SUN_EINVAL, "null batch");
+    if (!dev_out) return fail(SUN_ESIZE, "dev_out is null");
+    return batch_plaquette_launches(b, dev_out, as_stream(stream));
+}
+
+int sun_batch_capture(sun_batch_t b, int n_sweeps, int n_hb, int n_or, int reunit, double* dev_plaq,
+                      sun_stream_t stream) {
+    if (!b) return fail(SUN_EINVAL, "null batch");
+    if (n_sweeps <= 0 || n_hb < 0 || n_or < 0) return fail(SUN_EINVAL, "n_sweeps %d, n_hb %d, n_or %d", n_sweeps, n_hb, n_or);
+    const hipStream_t s = as_stream(stream);
+    if (!s) return fail(SUN_EINVAL, "graph capture needs a non-null stream");
+    if (b->exec) {
+        (void)hipGraphExecDestroy(b->exec);
+        b->exec = nullptr;
+    }
+    if (b->graph) {
+        (void)hipGraphDestroy(b->graph);
+        b->graph = nullptr;
+    }
+    if (int rc = hip_check(hipStreamBeginCapture(s, hipStreamCaptureModeThreadLocal), "hipStreamBeginCapture"))
+        return rc;
+    int rc = SUN_OK;
+    for (int k = 0; k < n_sweeps && rc == SUN_OK; ++k) {
+        rc = batch_sweep_launches(b, n_hb, n_or, reunit, s);
+        if (rc == SUN_OK && dev_plaq) rc = batch_plaquette_launches(b, dev_plaq, s);
+    }
+    hipGraph_t g = nullptr;
+    const int rc_end = hip_check(hipStreamEndCapture(s, &g), "hipStreamEndCapture");
+    if (rc != SUN_OK || rc_end != SUN_OK) {
+        if (g) (void)hipGraphDestroy(g);
+        return rc != SUN_OK ? rc : rc_end;
+    }
+    if (int rc2 = hip_check(hipGraphInstantiate(&b->exec, g, nullptr, nullptr, 0), "hipGraphInstantiate")) {
+        (void)hipGraphDestroy(g);
+        return rc2;
+    }
+    b->graph = g;
+    b->hb_per_replay = (uint64_t)n_sweeps * (uint64_t)n_hb;
+    return SUN_OK;
+}
+
+int sun_batch_replay(sun_batch_t b, sun_stream_t stream) {
+    if (!b) return fail(SUN_EINVAL, "null batch");
+    if (!b->exec) return fail(SUN_EINVAL, "no captured graph (call sun_batch_capture first)");
+    if (int rc = hip_check(hipGraphLaunch(b->exec, as_stream(stream)), "hipGraphLaunch")) return rc;
+    b->hb_steps_done += b->hb_per_replay;
+    return SUN_OK;
+}
+
+int sun_batch_sync(sun_batch_t b) {
+    if (!b) return fail(SUN_EINVAL, "null batch");
+    for (size_t i = 0; i < b->chains.size(); ++i) b->chains[i]->step = b->step0[i] + b->hb_steps_done;
+    return SUN_OK;
+}
+
+void sun_batch_destroy(sun_batch_t b) {
+    if (!b) return;
+    if (b->exec) (void)hipGraphExecDestroy(b->exec);
+    if (b->graph) (void)hipGraphDestroy(b->graph);
+    delete b;
+}
+
+}  // extern "C"
+
 namespace sun {
+
+void launch_advance_steps(ChainDesc* d, int n, int n_hb, hipStream_t s) {
+    k_advance_steps<><<<(n + 63) / 64, 64, 0, s>>>(d, n, n_hb);
+}
 
 void launch_finalize_max2(const double* partial, int nblk, double* out, hipStream_t s) {
     k_finalize<2, true><<<1, kBlock, 0, s>>>(partial, nblk, out, 1.0, 1.0, 1.0);

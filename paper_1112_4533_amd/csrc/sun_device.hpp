@@ -66,6 +66,22 @@ struct Geom {
     int present;  // bit mu set when L[mu] > 1
 };
 
+// One chain of a batch (device-resident table entry): its field, its own
+// partials buffer, geometry, coupling, Philox key, RNG step counter, and the
+// first tile it occupies in batched grids over V/2, V, 4V and Vs items.
+struct ChainDesc {
+    void* links;
+    double* scratch;     // the chain's own partials buffer
+    Geom g;
+    double beta;
+    uint32_t k0, k1;     // Philox key (seed)
+    uint64_t step;       // RNG step counter
+    int tile0[4];        // first tile of the chain in grids over V/2, V, 4V and Vs items
+    int out_index;       // position of the chain in the caller's list (result slots)
+};
+
+enum TileKind { TILE_HALF = 0, TILE_SITE = 1, TILE_LINK = 2, TILE_SPATIAL = 3 };
+
 struct Site {
     int x[4];
     int s;
@@ -113,6 +129,20 @@ __device__ __forceinline__ Site step_down(const Geom& g, Site a, int nu) {
 
 __device__ __forceinline__ int parity_of(const Site& a) {
     return (a.x[0] + a.x[1] + a.x[2] + a.x[3]) & 1;
+}
+
+// ---------------------------------------------------------------------------
+// Workgroup -> tile mapping.  The dispatcher hands workgroups to the 8 XCDs
+// round-robin (XCD = blockIdx % 8), each XCD with its own L2.  Giving each XCD
+// one contiguous eighth of the tiles keeps the z-neighbour planes a phase
+// re-reads (2 tiles apart at 32^4) in the same L2.  Bijective for any count.
+// ---------------------------------------------------------------------------
+constexpr int kXcds = 8;
+
+__device__ __forceinline__ int xcd_tile(int b, int nblk) {
+    const int q = nblk / kXcds, r = nblk - q * kXcds;
+    const int x = b % kXcds;
+    return x * q + (x < r ? x : r) + b / kXcds;
 }
 
 // ---------------------------------------------------------------------------
@@ -325,6 +355,82 @@ SUN_MAT_UNROLL
         v.y = m.im[e / N][e % N];
         p[(size_t)e * Vh] = v;
     }
+}
+
+// Streaming (nontemporal) access for data a phase touches exactly once: the
+// link being updated is read once and written once, while the neighbour
+// planes are re-read and should keep the cache.
+template <typename T>
+struct NativePair;
+template <>
+struct NativePair<float> {
+    typedef float type __attribute__((ext_vector_type(2)));
+};
+template <>
+struct NativePair<double> {
+    typedef double type __attribute__((ext_vector_type(2)));
+};
+
+template <typename T>
+__device__ __forceinline__ T2<T> load_stream(const T2<T>* p) {
+    const typename NativePair<T>::type v =
+        __builtin_nontemporal_load(reinterpret_cast<const typename NativePair<T>::type*>(p));
+    T2<T> r;
+    r.x = v.x;
+    r.y = v.y;
+    return r;
+}
+
+template <typename T>
+__device__ __forceinline__ void store_stream(T2<T>* p, const T2<T>& a) {
+    typename NativePair<T>::type v;
+    v.x = a.x;
+    v.y = a.y;
+    __builtin_nontemporal_store(v, reinterpret_cast<typename NativePair<T>::type*>(p));
+}
+
+template <int N, typename T>
+__device__ __forceinline__ Mat<N, T> load_mat_stream(const T2<T>* base, int mu, int par, int h, int Vh) {
+    const T2<T>* p = plane0<N, T>(base, mu, par, Vh) + h;
+    Mat<N, T> m;
+SUN_MAT_UNROLL
+    for (int e = 0; e < N * N; ++e) {
+        const T2<T> v = load_stream<T>(p + (size_t)e * Vh);
+        m.re[e / N][e % N] = v.x;
+        m.im[e / N][e % N] = v.y;
+    }
+    return m;
+}
+
+template <int N, typename T>
+__device__ __forceinline__ void store_mat_stream(T2<T>* base, int mu, int par, int h, int Vh, const Mat<N, T>& m) {
+    T2<T>* p = const_cast<T2<T>*>(plane0<N, T>(base, mu, par, Vh)) + h;
+SUN_MAT_UNROLL
+    for (int e = 0; e < N * N; ++e) {
+        T2<T> v;
+        v.x = m.re[e / N][e % N];
+        v.y = m.im[e / N][e % N];
+        store_stream<T>(p + (size_t)e * Vh, v);
+    }
+}
+
+template <typename T>
+__device__ __forceinline__ Quat<T> load_quat_stream(const T2<T>* base, int mu, int par, int h, int Vh) {
+    const T2<T>* p = plane0<2, T>(base, mu, par, Vh) + h;
+    const T2<T> a = load_stream<T>(p), b = load_stream<T>(p + Vh);
+    return Quat<T>{{a.x, a.y, b.x, b.y}};
+}
+
+template <typename T>
+__device__ __forceinline__ void store_quat_stream(T2<T>* base, int mu, int par, int h, int Vh, const Quat<T>& q) {
+    T2<T>* p = const_cast<T2<T>*>(plane0<2, T>(base, mu, par, Vh)) + h;
+    T2<T> a, b;
+    a.x = q.q[0];
+    a.y = q.q[1];
+    b.x = q.q[2];
+    b.y = q.q[3];
+    store_stream<T>(p, a);
+    store_stream<T>(p + Vh, b);
 }
 
 template <typename T>

@@ -149,17 +149,17 @@ __device__ __forceinline__ T unit_quat(const Quat<T>& p, Quat<T>& v) {
 }
 
 // ---------------------------------------------------------------------------
-// Phase update, Nc >= 3 (paper Sec. 2, Cabibbo-Marinari steps 1-5, and the
-// subgroup overrelaxation).  W = U A is kept in registers and updated with U.
+// Update of one link U_mu(x), x = site h of parity par, Nc >= 3 (paper Sec. 2,
+// Cabibbo-Marinari steps 1-5, and the subgroup overrelaxation).  W = U A is
+// kept in registers and updated with U.  Shared by the single-lattice and the
+// batched kernels, so a chain gives the same bits either way.
 // ---------------------------------------------------------------------------
 template <int N, typename T, bool HB, int MU>
-__global__ __launch_bounds__(kBlock) void k_update(T2<T>* __restrict__ U, Geom g, int par, T beta,
-                                                   uint32_t k0, uint32_t k1, uint32_t step) {
-    const int h = blockIdx.x * kBlock + threadIdx.x;
-    if (h >= g.Vh) return;
+__device__ __forceinline__ void update_link(T2<T>* __restrict__ U, const Geom& g, int par, int h, T beta,
+                                            uint32_t k0, uint32_t k1, uint32_t step) {
     const Site x = site_of(g, par, h);
     const Mat<N, T> A = staple<N, T, MU>(U, g, x, par, h);
-    Mat<N, T> Ul = load_mat<N, T>(U, MU, par, h, g.Vh);
+    Mat<N, T> Ul = load_mat_stream<N, T>(U, MU, par, h, g.Vh);
     Mat<N, T> W = mul_nn(Ul, A);
     int sg = 0;
 SUN_MAT_UNROLL
@@ -182,18 +182,16 @@ SUN_MAT_UNROLL
             rows_left_mul(Ul, i, j, a);
             rows_left_mul(W, i, j, a);
         }
-    store_mat<N, T>(U, MU, par, h, g.Vh, Ul);
+    store_mat_stream<N, T>(U, MU, par, h, g.Vh, Ul);
 }
 
-// Phase update, SU(2) in the 4-real parameterization (paper Sec. 2, Sec. 3).
+// The same for SU(2) in the 4-real parameterization (paper Sec. 2, Sec. 3).
 template <typename T, bool HB, int MU>
-__global__ __launch_bounds__(kBlock) void k_update_su2(T2<T>* __restrict__ U, Geom g, int par, T beta,
-                                                       uint32_t k0, uint32_t k1, uint32_t step) {
-    const int h = blockIdx.x * kBlock + threadIdx.x;
-    if (h >= g.Vh) return;
+__device__ __forceinline__ void update_link_su2(T2<T>* __restrict__ U, const Geom& g, int par, int h, T beta,
+                                                uint32_t k0, uint32_t k1, uint32_t step) {
     const Site x = site_of(g, par, h);
     const Quat<T> A = staple_su2<T, MU>(U, g, x, par, h);
-    const Quat<T> u = load_quat<T>(U, MU, par, h, g.Vh);
+    const Quat<T> u = load_quat_stream<T>(U, MU, par, h, g.Vh);
     Quat<T> v;
     const T k = unit_quat(qmul(u, A), v);
     Quat<T> a;
@@ -205,7 +203,67 @@ __global__ __launch_bounds__(kBlock) void k_update_su2(T2<T>* __restrict__ U, Ge
         const Quat<T> vc = qconj(v);
         a = qmul(vc, vc);
     }
-    store_quat<T>(U, MU, par, h, g.Vh, qmul(a, u));
+    store_quat_stream<T>(U, MU, par, h, g.Vh, qmul(a, u));
+}
+
+template <int N, typename T, bool HB, int MU>
+__device__ __forceinline__ void update_any(T2<T>* __restrict__ U, const Geom& g, int par, int h, T beta, uint32_t k0,
+                                           uint32_t k1, uint32_t step) {
+    if constexpr (N == 2)
+        update_link_su2<T, HB, MU>(U, g, par, h, beta, k0, k1, step);
+    else
+        update_link<N, T, HB, MU>(U, g, par, h, beta, k0, k1, step);
+}
+
+// One checkerboard phase of one lattice.
+template <int N, typename T, bool HB, int MU>
+__global__ __launch_bounds__(kBlock) void k_update(T2<T>* __restrict__ U, Geom g, int par, T beta,
+                                                   uint32_t k0, uint32_t k1, uint32_t step) {
+    const int h = xcd_tile(blockIdx.x, gridDim.x) * kBlock + threadIdx.x;
+    if (h >= g.Vh) return;
+    update_any<N, T, HB, MU>(U, g, par, h, beta, k0, k1, step);
+}
+
+// ---------------------------------------------------------------------------
+// Batches of independent chains (same Nc and storage type, any extents,
+// couplings and seeds).  One launch covers one phase of every chain: the
+// grid is the concatenation of each chain's tiles, and the chain of a tile is
+// found by binary search over the first-tile prefix of the descriptor table.
+// The RNG step counter of each chain lives in the table, so a captured graph
+// replays with fresh randomness.
+// ---------------------------------------------------------------------------
+
+
+template <int KIND>
+__device__ __forceinline__ int find_chain(const ChainDesc* __restrict__ d, int n, int tile) {
+    int lo = 0, hi = n - 1;  // last chain whose first tile <= tile
+    while (lo < hi) {
+        const int mid = (lo + hi + 1) >> 1;
+        if (d[mid].tile0[KIND] <= tile)
+            lo = mid;
+        else
+            hi = mid - 1;
+    }
+    return lo;
+}
+
+template <int N, typename T, bool HB, int MU>
+__global__ __launch_bounds__(kBlock) void k_update_batch(const ChainDesc* __restrict__ d, int n, int par,
+                                                         uint32_t step_offset) {
+    const int tile = xcd_tile(blockIdx.x, gridDim.x);
+    const int c = find_chain<TILE_HALF>(d, n, tile);
+    const Geom g = d[c].g;
+    const int h = (tile - d[c].tile0[TILE_HALF]) * kBlock + threadIdx.x;
+    if (h >= g.Vh || !((g.present >> MU) & 1)) return;
+    update_any<N, T, HB, MU>((T2<T>*)d[c].links, g, par, h, (T)d[c].beta, d[c].k0, d[c].k1,
+                             (uint32_t)(d[c].step + step_offset));
+}
+
+// Advances every chain's RNG step counter after a sweep of n_hb heatbath steps.
+template <int Dummy = 0>
+__global__ void k_advance_steps(ChainDesc* __restrict__ d, int n, int n_hb) {
+    const int c = blockIdx.x * blockDim.x + threadIdx.x;
+    if (c < n) d[c].step += (uint64_t)n_hb;
 }
 
 // ---------------------------------------------------------------------------
@@ -422,19 +480,31 @@ __device__ __forceinline__ LinkId link_of(const Geom& g, int id) {
 // before the projection.
 // ---------------------------------------------------------------------------
 template <int N, typename T>
+__device__ __forceinline__ void reunit_link(T2<T>* __restrict__ U, const Geom& g, int id, bool report,
+                                            double (&dev)[2]) {
+    if (id >= 4 * g.V) return;
+    const LinkId l = link_of(g, id);
+    if (!((g.present >> l.mu) & 1)) return;
+    Mat<N, double> M = load_link_f64<N, T>(U, l.mu, l.par, l.h, g.Vh);
+    if (report) unitarity_dev<N>(M, dev[0], dev[1]);
+    reunit<N>(M);
+    store_link_from_f64<N, T>(U, l.mu, l.par, l.h, g.Vh, M);
+}
+
+template <int N, typename T>
 __global__ __launch_bounds__(kBlock) void k_reunit(T2<T>* __restrict__ U, Geom g, double* __restrict__ partial) {
-    const int id = blockIdx.x * kBlock + threadIdx.x;
     double dev[2] = {0.0, 0.0};
-    if (id < 4 * g.V) {
-        const LinkId l = link_of(g, id);
-        if ((g.present >> l.mu) & 1) {
-            Mat<N, double> M = load_link_f64<N, T>(U, l.mu, l.par, l.h, g.Vh);
-            if (partial) unitarity_dev<N>(M, dev[0], dev[1]);
-            reunit<N>(M);
-            store_link_from_f64<N, T>(U, l.mu, l.par, l.h, g.Vh, M);
-        }
-    }
+    reunit_link<N, T>(U, g, blockIdx.x * kBlock + threadIdx.x, partial != nullptr, dev);
     if (partial) block_max<2>(dev, partial + 2 * (size_t)blockIdx.x);
+}
+
+template <int N, typename T>
+__global__ __launch_bounds__(kBlock) void k_reunit_batch(const ChainDesc* __restrict__ d, int n) {
+    const int tile = blockIdx.x;
+    const int c = find_chain<TILE_LINK>(d, n, tile);
+    double dev[2] = {0.0, 0.0};
+    reunit_link<N, T>((T2<T>*)d[c].links, d[c].g, (tile - d[c].tile0[TILE_LINK]) * kBlock + threadIdx.x, false,
+                      dev);
 }
 
 template <int N, typename T>
@@ -475,34 +545,51 @@ SUN_MAT_UNROLL
     return t;
 }
 
+// Sums ReTr P over the planes of site id (checkerboard order: parity, then h)
+// into acc = {planes without direction 3, planes with direction 3}.
+template <int N, typename T>
+__device__ __forceinline__ void plaquette_site(const T2<T>* __restrict__ U, const Geom& g, int id, double (&acc)[2]) {
+    if (id >= g.V) return;
+    const int par = id >= g.Vh ? 1 : 0;
+    const int h = id - par * g.Vh;
+    const Site x = site_of(g, par, h);
+    const int p = g.present;
+#define SUN_PLAQ(m, n, slot) \
+    if (((p >> m) & 1) && ((p >> n) & 1)) acc[slot] += re_tr_plaq<N, T, m, n>(U, g, x, par, h);
+    SUN_PLAQ(0, 1, 0)
+    SUN_PLAQ(0, 2, 0)
+    SUN_PLAQ(1, 2, 0)
+    SUN_PLAQ(0, 3, 1)
+    SUN_PLAQ(1, 3, 1)
+    SUN_PLAQ(2, 3, 1)
+#undef SUN_PLAQ
+}
+
 template <int N, typename T>
 __global__ __launch_bounds__(kBlock) void k_plaquette(const T2<T>* __restrict__ U, Geom g,
                                                       double* __restrict__ partial) {
-    const int id = blockIdx.x * kBlock + threadIdx.x;
+    const int tile = xcd_tile(blockIdx.x, gridDim.x);
     double acc[2] = {0.0, 0.0};
-    if (id < g.V) {
-        const int par = id >= g.Vh ? 1 : 0;
-        const int h = id - par * g.Vh;
-        const Site x = site_of(g, par, h);
-        const int p = g.present;
-#define SUN_PLAQ(m, n, slot) \
-    if (((p >> m) & 1) && ((p >> n) & 1)) acc[slot] += re_tr_plaq<N, T, m, n>(U, g, x, par, h);
-        SUN_PLAQ(0, 1, 0)
-        SUN_PLAQ(0, 2, 0)
-        SUN_PLAQ(1, 2, 0)
-        SUN_PLAQ(0, 3, 1)
-        SUN_PLAQ(1, 3, 1)
-        SUN_PLAQ(2, 3, 1)
-#undef SUN_PLAQ
-    }
-    block_sum<2>(acc, partial + 2 * (size_t)blockIdx.x);
+    plaquette_site<N, T>(U, g, tile * kBlock + threadIdx.x, acc);
+    block_sum<2>(acc, partial + 2 * (size_t)tile);
+}
+
+// Batched plaquette: each chain's per-tile partials go to that chain's own
+// scratch at the same index the single-lattice kernel uses.
+template <int N, typename T>
+__global__ __launch_bounds__(kBlock) void k_plaquette_batch(const ChainDesc* __restrict__ d, int n) {
+    const int tile = xcd_tile(blockIdx.x, gridDim.x);
+    const int c = find_chain<TILE_SITE>(d, n, tile);
+    const int local = tile - d[c].tile0[TILE_SITE];
+    double acc[2] = {0.0, 0.0};
+    plaquette_site<N, T>((const T2<T>*)d[c].links, d[c].g, local * kBlock + threadIdx.x, acc);
+    block_sum<2>(acc, d[c].scratch + 2 * (size_t)local);
 }
 
 // Second pass for the plaquette: {total, spatial, temporal} means.
 template <int K = 2>
-__global__ __launch_bounds__(kBlock) void k_plaquette_final(const double* __restrict__ partial, int nblk,
-                                                            double* __restrict__ out, double norm_sp,
-                                                            double norm_tm, double norm_all) {
+__device__ __forceinline__ void plaquette_final(const double* __restrict__ partial, int nblk, double* __restrict__ out,
+                                                double norm_sp, double norm_tm, double norm_all) {
     double v[K] = {};
     for (int b = threadIdx.x; b < nblk; b += kBlock)
 #pragma unroll
@@ -514,6 +601,45 @@ __global__ __launch_bounds__(kBlock) void k_plaquette_final(const double* __rest
         out[1] = norm_sp > 0.0 ? res[0] / norm_sp : 0.0;
         out[2] = norm_tm > 0.0 ? res[1] / norm_tm : 0.0;
     }
+}
+
+template <int K = 2>
+__global__ __launch_bounds__(kBlock) void k_plaquette_final(const double* __restrict__ partial, int nblk,
+                                                            double* __restrict__ out, double norm_sp,
+                                                            double norm_tm, double norm_all) {
+    plaquette_final<K>(partial, nblk, out, norm_sp, norm_tm, norm_all);
+}
+
+// Normalisations {spatial, temporal, all}: Nc V times the number of planes.
+template <int N>
+__device__ __forceinline__ void plaquette_norms(const Geom& g, double& sp, double& tm, double& all) {
+    int n_sp = 0, n_tm = 0;
+#pragma unroll
+    for (int m = 0; m < 4; ++m)
+#pragma unroll
+        for (int n = m + 1; n < 4; ++n)
+            if (((g.present >> m) & 1) && ((g.present >> n) & 1)) {
+                if (n == 3)
+                    ++n_tm;
+                else
+                    ++n_sp;
+            }
+    const double norm = (double)N * (double)g.V;
+    sp = norm * n_sp;
+    tm = norm * n_tm;
+    all = norm * (n_sp + n_tm);
+}
+
+// One block per chain: out[3 c .. 3 c + 2].
+template <int N>
+__global__ __launch_bounds__(kBlock) void k_plaquette_final_batch(const ChainDesc* __restrict__ d, int n,
+                                                                  double* __restrict__ out) {
+    const int c = blockIdx.x;
+    if (c >= n) return;
+    double sp, tm, all;
+    plaquette_norms<N>(d[c].g, sp, tm, all);
+    plaquette_final<2>(d[c].scratch, (d[c].g.V + kBlock - 1) / kBlock, out + 3 * (size_t)d[c].out_index, sp, tm,
+                       all);
 }
 
 // ---------------------------------------------------------------------------

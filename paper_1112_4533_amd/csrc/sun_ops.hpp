@@ -28,6 +28,12 @@ struct Ops {
     void (*polyakov)(const Ctx&, double* partial);
     void (*export_field)(const Ctx&, double* out);
     void (*import_field)(const Ctx&, const double* in);
+    // batches: d is a device table of n chains of this Nc and storage type;
+    // tiles is the total tile count of the grid kind the call uses
+    void (*update_batch)(const ChainDesc* d, int n, int tiles, int kind, int mu, int par, uint32_t step_offset,
+                         hipStream_t s);
+    void (*reunit_batch)(const ChainDesc* d, int n, int tiles, hipStream_t s);
+    void (*plaquette_batch)(const ChainDesc* d, int n, int tiles, double* out, hipStream_t s);
 };
 
 constexpr int kLaunchBlock = 256;
@@ -50,6 +56,7 @@ void launch_finalize_max2(const double* partial, int nblk, double* out, hipStrea
 void launch_finalize_sum2(const double* partial, int nblk, double* out, double scale, hipStream_t s);
 void launch_plaquette_final(const double* partial, int nblk, double* out, double norm_sp, double norm_tm,
                             double norm_all, hipStream_t s);
+void launch_advance_steps(ChainDesc* d, int n, int n_hb, hipStream_t s);
 void launch_sample_su2(int f64, const double* alpha, int n, uint32_t k0, uint32_t k1, uint32_t step,
                        uint32_t mu_sg, double* x, int* attempts, hipStream_t s);
 

@@ -12,12 +12,35 @@ struct OpsImpl {
 
     template <bool HB, int MU>
     static void update_mu(const Ctx& c, int par, T beta, uint32_t k0, uint32_t k1, uint32_t step) {
-        if constexpr (N == 2)
-            k_update_su2<T, HB, MU><<<half_blocks(c.g), kBlock, 0, c.stream>>>((P*)c.links, c.g, par, beta, k0,
-                                                                               k1, step);
+        k_update<N, T, HB, MU><<<half_blocks(c.g), kBlock, 0, c.stream>>>((P*)c.links, c.g, par, beta, k0, k1, step);
+    }
+
+    template <bool HB>
+    static void update_batch_kind(const ChainDesc* d, int n, int tiles, int mu, int par, uint32_t off,
+                                  hipStream_t s) {
+        switch (mu) {
+            case 0: k_update_batch<N, T, HB, 0><<<tiles, kBlock, 0, s>>>(d, n, par, off); break;
+            case 1: k_update_batch<N, T, HB, 1><<<tiles, kBlock, 0, s>>>(d, n, par, off); break;
+            case 2: k_update_batch<N, T, HB, 2><<<tiles, kBlock, 0, s>>>(d, n, par, off); break;
+            default: k_update_batch<N, T, HB, 3><<<tiles, kBlock, 0, s>>>(d, n, par, off); break;
+        }
+    }
+
+    static void update_batch(const ChainDesc* d, int n, int tiles, int kind, int mu, int par, uint32_t off,
+                             hipStream_t s) {
+        if (kind == 0)
+            update_batch_kind<true>(d, n, tiles, mu, par, off, s);
         else
-            k_update<N, T, HB, MU><<<half_blocks(c.g), kBlock, 0, c.stream>>>((P*)c.links, c.g, par, beta, k0, k1,
-                                                                             step);
+            update_batch_kind<false>(d, n, tiles, mu, par, off, s);
+    }
+
+    static void reunit_batch(const ChainDesc* d, int n, int tiles, hipStream_t s) {
+        k_reunit_batch<N, T><<<tiles, kBlock, 0, s>>>(d, n);
+    }
+
+    static void plaquette_batch(const ChainDesc* d, int n, int tiles, double* out, hipStream_t s) {
+        k_plaquette_batch<N, T><<<tiles, kBlock, 0, s>>>(d, n);
+        k_plaquette_final_batch<N><<<n, kBlock, 0, s>>>(d, n, out);
     }
 
     template <bool HB>
@@ -61,8 +84,9 @@ struct OpsImpl {
     }
 
     static const Ops* table() {
-        static const Ops ops = {&update, &init, &reunit, &unitarity, &plaquette, &polyakov, &export_field,
-                                &import_field};
+        static const Ops ops = {&update,       &init,         &reunit,       &unitarity,
+                                &plaquette,    &polyakov,     &export_field, &import_field,
+                                &update_batch, &reunit_batch, &plaquette_batch};
         return &ops;
     }
 };

@@ -54,6 +54,14 @@ def load():
         "sun_profile": [vp, c_int],
         "sun_profile_read": [vp, c_int, ctypes.POINTER(c_dbl), ctypes.POINTER(ctypes.c_int64)],
         "sun_sample_su2": [c_int, vp, c_int, c_u64, c_u32, c_u32, vp, vp, vp],
+        "sun_batch_bytes": [c_int, ctypes.POINTER(sz)],
+        "sun_batch_create": [c_int, ctypes.POINTER(vp), ctypes.POINTER(c_dbl), ctypes.POINTER(c_u64), vp, sz,
+                             ctypes.POINTER(vp)],
+        "sun_batch_sweep": [vp, c_int, c_int, c_int, vp],
+        "sun_batch_plaquette": [vp, vp, vp],
+        "sun_batch_capture": [vp, c_int, c_int, c_int, c_int, vp, vp],
+        "sun_batch_replay": [vp, vp],
+        "sun_batch_sync": [vp],
     }
     for name, args in sigs.items():
         f = getattr(L, name)
@@ -61,6 +69,8 @@ def load():
         f.restype = c_int
     L.sun_lattice_destroy.argtypes = [vp]
     L.sun_lattice_destroy.restype = None
+    L.sun_batch_destroy.argtypes = [vp]
+    L.sun_batch_destroy.restype = None
     L.sun_last_error.argtypes = []
     L.sun_last_error.restype = ctypes.c_char_p
     _lib = L
@@ -73,7 +83,9 @@ def exported_symbols():
     return [n for n in ("sun_lattice_bytes", "sun_lattice_create", "sun_lattice_destroy", "sun_init",
                         "sun_phase", "sun_sweep", "sun_reunitarize", "sun_plaquette", "sun_polyakov",
                         "sun_unitarity", "sun_export", "sun_import", "sun_get_step", "sun_set_step",
-                        "sun_profile", "sun_profile_read", "sun_sample_su2", "sun_last_error")
+                        "sun_profile", "sun_profile_read", "sun_sample_su2", "sun_last_error",
+                        "sun_batch_bytes", "sun_batch_create", "sun_batch_sweep", "sun_batch_plaquette",
+                        "sun_batch_capture", "sun_batch_replay", "sun_batch_sync", "sun_batch_destroy")
             if hasattr(L, n)]
 
 
@@ -200,6 +212,64 @@ class Lattice:
         ms, n = ctypes.c_double(), ctypes.c_int64()
         _check(load().sun_profile_read(self._h, KERNEL_IDS.get(kernel, kernel), ctypes.byref(ms), ctypes.byref(n)))
         return ms.value, n.value
+
+
+class Batch:
+    """Independent chains advanced together: one launch per phase and per
+    (Nc, precision) group, optionally replayed from a captured HIP graph.
+    The lattices keep their fields; while the batch is in use they should be
+    driven only through it (sync() hands the step counters back)."""
+
+    def __init__(self, lattices, betas, seeds):
+        self.lattices = list(lattices)
+        n = len(self.lattices)
+        assert n > 0 and len(betas) == n and len(seeds) == n
+        lib = load()
+        tb = ctypes.c_size_t()
+        _check(lib.sun_batch_bytes(n, ctypes.byref(tb)))
+        dev = self.lattices[0].links.device
+        self.table = torch.empty(tb.value, dtype=torch.uint8, device=dev)
+        handles = (ctypes.c_void_p * n)(*[l._h.value for l in self.lattices])
+        b = (ctypes.c_double * n)(*[float(x) for x in betas])
+        sd = (ctypes.c_uint64 * n)(*[int(x) for x in seeds])
+        h = ctypes.c_void_p()
+        _check(lib.sun_batch_create(n, handles, b, sd, _ptr(self.table), tb.value, ctypes.byref(h)))
+        self._h = h
+        self.n = n
+        self.stream = torch.cuda.Stream(device=dev)   # graphs need a non-null stream
+
+    def __del__(self):
+        h = getattr(self, "_h", None)
+        if h is not None and _lib is not None:
+            _lib.sun_batch_destroy(h)
+            self._h = None
+
+    def sweep(self, n_hb=1, n_or=4, reunit=True):
+        _check(load().sun_batch_sweep(self._h, int(n_hb), int(n_or), int(bool(reunit)), _stream()))
+
+    def plaquette(self, out=None):
+        out = out if out is not None else torch.empty((self.n, 3), dtype=torch.float64,
+                                                      device=self.table.device)
+        _check(load().sun_batch_plaquette(self._h, _ptr(out), _stream()))
+        return out
+
+    def capture(self, n_sweeps=1, n_hb=1, n_or=4, reunit=True, plaq_out=None):
+        """Captures n_sweeps sweeps (plus plaquettes into plaq_out, an (n, 3)
+        float64 device tensor, if given) as one graph."""
+        cur = torch.cuda.current_stream()
+        self.stream.wait_stream(cur)
+        _check(load().sun_batch_capture(self._h, int(n_sweeps), int(n_hb), int(n_or), int(bool(reunit)),
+                                        _ptr(plaq_out) if plaq_out is not None else None,
+                                        ctypes.c_void_p(self.stream.cuda_stream)))
+
+    def replay(self):
+        cur = torch.cuda.current_stream()
+        self.stream.wait_stream(cur)
+        _check(load().sun_batch_replay(self._h, ctypes.c_void_p(self.stream.cuda_stream)))
+        cur.wait_stream(self.stream)
+
+    def sync(self):
+        _check(load().sun_batch_sync(self._h))
 
 
 def sample_su2(alpha, seed, step=0, mu_sg=0, dtype="f64"):
