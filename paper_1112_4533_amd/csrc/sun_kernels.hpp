@@ -479,23 +479,25 @@ __device__ __forceinline__ LinkId link_of(const Geom& g, int id) {
 // Re-unitarization of every link, optionally reporting the deviation found
 // before the projection.
 // ---------------------------------------------------------------------------
-template <int N, typename T>
-__device__ __forceinline__ void reunit_link(T2<T>* __restrict__ U, const Geom& g, int id, bool report,
-                                            double (&dev)[2]) {
+// REPORT is a template flag (not a runtime one) so that the projection
+// compiles to the same instructions in every kernel that runs it: a chain in
+// a batch must get the same bits as the chain alone.
+template <int N, typename T, bool REPORT>
+__device__ __forceinline__ void reunit_link(T2<T>* __restrict__ U, const Geom& g, int id, double (&dev)[2]) {
     if (id >= 4 * g.V) return;
     const LinkId l = link_of(g, id);
     if (!((g.present >> l.mu) & 1)) return;
     Mat<N, double> M = load_link_f64<N, T>(U, l.mu, l.par, l.h, g.Vh);
-    if (report) unitarity_dev<N>(M, dev[0], dev[1]);
+    if (REPORT) unitarity_dev<N>(M, dev[0], dev[1]);
     reunit<N>(M);
     store_link_from_f64<N, T>(U, l.mu, l.par, l.h, g.Vh, M);
 }
 
-template <int N, typename T>
+template <int N, typename T, bool REPORT>
 __global__ __launch_bounds__(kBlock) void k_reunit(T2<T>* __restrict__ U, Geom g, double* __restrict__ partial) {
     double dev[2] = {0.0, 0.0};
-    reunit_link<N, T>(U, g, blockIdx.x * kBlock + threadIdx.x, partial != nullptr, dev);
-    if (partial) block_max<2>(dev, partial + 2 * (size_t)blockIdx.x);
+    reunit_link<N, T, REPORT>(U, g, blockIdx.x * kBlock + threadIdx.x, dev);
+    if (REPORT) block_max<2>(dev, partial + 2 * (size_t)blockIdx.x);
 }
 
 template <int N, typename T>
@@ -503,8 +505,7 @@ __global__ __launch_bounds__(kBlock) void k_reunit_batch(const ChainDesc* __rest
     const int tile = blockIdx.x;
     const int c = find_chain<TILE_LINK>(d, n, tile);
     double dev[2] = {0.0, 0.0};
-    reunit_link<N, T>((T2<T>*)d[c].links, d[c].g, (tile - d[c].tile0[TILE_LINK]) * kBlock + threadIdx.x, false,
-                      dev);
+    reunit_link<N, T, false>((T2<T>*)d[c].links, d[c].g, (tile - d[c].tile0[TILE_LINK]) * kBlock + threadIdx.x, dev);
 }
 
 template <int N, typename T>

@@ -65,7 +65,10 @@ struct OpsImpl {
         k_init<N, T><<<link_blocks(c.g), kBlock, 0, c.stream>>>((P*)c.links, c.g, hot, k0, k1);
     }
     static void reunit(const Ctx& c, double* partial) {
-        k_reunit<N, T><<<link_blocks(c.g), kBlock, 0, c.stream>>>((P*)c.links, c.g, partial);
+        if (partial)
+            k_reunit<N, T, true><<<link_blocks(c.g), kBlock, 0, c.stream>>>((P*)c.links, c.g, partial);
+        else
+            k_reunit<N, T, false><<<link_blocks(c.g), kBlock, 0, c.stream>>>((P*)c.links, c.g, nullptr);
     }
     static void unitarity(const Ctx& c, double* partial) {
         k_unitarity<N, T><<<link_blocks(c.g), kBlock, 0, c.stream>>>((const P*)c.links, c.g, partial);
