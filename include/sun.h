@@ -125,6 +125,13 @@ int sun_import(sun_lattice_t h, const double *dev_canonical, sun_stream_t stream
 int sun_get_step(sun_lattice_t h, uint64_t *step);
 int sun_set_step(sun_lattice_t h, uint64_t step);
 
+/* Launch shape of the phase kernels: block work-items per workgroup (64,
+ * 128 or 256; default 256) and the XCD-aware workgroup order (1, default) or
+ * the plain order (0).  A tuning choice only: results are bitwise the same
+ * for every shape. */
+int sun_set_launch(sun_lattice_t h, int block, int xcd);
+int sun_get_launch(sun_lattice_t h, int *block, int *xcd);
+
 /* Per-kernel timing with HIP events recorded around each launch on the
  * launch stream.  kernel: 0 heatbath phase, 1 overrelaxation phase,
  * 2 re-unitarization, 3 plaquette, 4 Polyakov loop.  sun_profile(h, 1)
@@ -176,6 +183,10 @@ int sun_batch_plaquette(sun_batch_t b, double *dev_out, sun_stream_t stream);
 int sun_batch_capture(sun_batch_t b, int n_sweeps, int n_hb, int n_or, int reunit, double *dev_plaq,
                       sun_stream_t stream);
 int sun_batch_replay(sun_batch_t b, sun_stream_t stream);
+
+/* Launch shape of the batch's phase kernels (as sun_set_launch).  Waits for
+ * the device, rewrites the table, and drops any captured graph. */
+int sun_batch_set_launch(sun_batch_t b, int block, int xcd);
 
 /* Writes the chains' advanced RNG step counters back to their handles. */
 int sun_batch_sync(sun_batch_t b);

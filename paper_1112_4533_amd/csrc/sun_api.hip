@@ -59,8 +59,11 @@ struct sun_lattice_s {
     std::vector<hipEvent_t> pool;
     double total_ms[kKernels] = {};
     int64_t launches[kKernels] = {};
+    // launch shape of the phase kernels (sun_set_launch)
+    int block = 256;
+    int xcd = 1;
 
-    sun::Ctx ctx(hipStream_t s) const { return sun::Ctx{links, g, s}; }
+    sun::Ctx ctx(hipStream_t s) const { return sun::Ctx{links, g, s, block, xcd}; }
 };
 
 namespace {
@@ -321,6 +324,21 @@ int sun_set_step(sun_lattice_t h, uint64_t step) {
     return SUN_OK;
 }
 
+int sun_set_launch(sun_lattice_t h, int block, int xcd) {
+    if (!h) return fail(SUN_EINVAL, "null handle");
+    if (!sun::valid_phase_block(block)) return fail(SUN_EINVAL, "block %d is not 64, 128 or 256", block);
+    h->block = block;
+    h->xcd = xcd ? 1 : 0;
+    return SUN_OK;
+}
+
+int sun_get_launch(sun_lattice_t h, int* block, int* xcd) {
+    if (!h || !block || !xcd) return fail(SUN_EINVAL, "null argument");
+    *block = h->block;
+    *xcd = h->xcd;
+    return SUN_OK;
+}
+
 int sun_profile(sun_lattice_t h, int enable) {
     if (!h) return fail(SUN_EINVAL, "null handle");
     for (auto& p : h->pending) {
@@ -379,7 +397,10 @@ struct sun_batch_s {
     };
     std::vector<sun_lattice_t> chains;  // in the caller's order
     std::vector<Group> groups;
+    std::vector<sun::ChainDesc> host;   // host copy of the table
     sun::ChainDesc* table = nullptr;    // device
+    int block = 256;                    // launch shape of the phase kernels
+    int xcd = 1;
     uint64_t hb_steps_done = 0;         // heatbath steps run since creation (all chains alike)
     std::vector<uint64_t> step0;        // chain step counters at creation
     hipGraph_t graph = nullptr;
@@ -395,15 +416,36 @@ int batch_sweep_launches(sun_batch_t b, int n_hb, int n_or, int reunit, hipStrea
         for (int k = 0; k < n_hb; ++k)
             for (int mu = 0; mu < 4; ++mu)
                 for (int p = 0; p < 2; ++p)
-                    gr.ops->update_batch(d, gr.count, gr.tiles[0], SUN_HEATBATH, mu, p, (uint32_t)k, s);
+                    gr.ops->update_batch(d, gr.count, gr.tiles[0], SUN_HEATBATH, mu, p, (uint32_t)k, b->block, b->xcd,
+                                         s);
         for (int k = 0; k < n_or; ++k)
             for (int mu = 0; mu < 4; ++mu)
                 for (int p = 0; p < 2; ++p)
-                    gr.ops->update_batch(d, gr.count, gr.tiles[0], SUN_OVERRELAX, mu, p, 0, s);
+                    gr.ops->update_batch(d, gr.count, gr.tiles[0], SUN_OVERRELAX, mu, p, 0, b->block, b->xcd, s);
         if (reunit) gr.ops->reunit_batch(d, gr.count, gr.tiles[2], s);
     }
     if (n_hb > 0) sun::launch_advance_steps(b->table, (int)b->chains.size(), n_hb, s);
     return launch_check("batch sweep");
+}
+
+// Assigns every chain its first tile in each grid kind (the phase grid in
+// tiles of the batch's block size) and uploads the table.  Synchronous.
+int upload_table(sun_batch_t b) {
+    for (auto& gr : b->groups) {
+        int t[4] = {0, 0, 0, 0};
+        for (int i = gr.first; i < gr.first + gr.count; ++i) {
+            sun::ChainDesc& c = b->host[i];
+            for (int k = 0; k < 4; ++k) c.tile0[k] = t[k];
+            t[0] += sun::half_blocks(c.g, b->block);
+            t[1] += sun::site_blocks(c.g);
+            t[2] += sun::link_blocks(c.g);
+            t[3] += sun::spatial_blocks(c.g);
+        }
+        for (int k = 0; k < 4; ++k) gr.tiles[k] = t[k];
+    }
+    return hip_check(hipMemcpy(b->table, b->host.data(), sizeof(sun::ChainDesc) * b->host.size(),
+                               hipMemcpyHostToDevice),
+                     "batch table upload");
 }
 
 int batch_plaquette_launches(sun_batch_t b, double* out, hipStream_t s) {
@@ -436,10 +478,9 @@ int sun_batch_create(int n, const sun_lattice_t* chains, const double* betas, co
     b->chains.assign(chains, chains + n);
     b->table = static_cast<sun::ChainDesc*>(table);
     // group by (Nc, dtype), keeping the caller's order inside a group
-    std::vector<sun::ChainDesc> host;
     for (int nc = 2; nc <= SUN_NC_MAX; ++nc)
         for (int dt = SUN_F32; dt <= SUN_F64; ++dt) {
-            sun_batch_s::Group gr{ops_for(nc, dt == SUN_F64), (int)host.size(), 0, {0, 0, 0, 0}};
+            sun_batch_s::Group gr{ops_for(nc, dt == SUN_F64), (int)b->host.size(), 0, {0, 0, 0, 0}};
             for (int i = 0; i < n; ++i) {
                 const sun_lattice_t h = chains[i];
                 if (h->nc != nc || h->dtype != dt) continue;
@@ -451,23 +492,14 @@ int sun_batch_create(int n, const sun_lattice_t* chains, const double* betas, co
                 c.k0 = (uint32_t)seeds[i];
                 c.k1 = (uint32_t)(seeds[i] >> 32);
                 c.step = h->step;
-                c.tile0[0] = gr.tiles[0];
-                c.tile0[1] = gr.tiles[1];
-                c.tile0[2] = gr.tiles[2];
-                c.tile0[3] = gr.tiles[3];
                 c.out_index = i;
-                gr.tiles[0] += sun::half_blocks(h->g);
-                gr.tiles[1] += sun::site_blocks(h->g);
-                gr.tiles[2] += sun::link_blocks(h->g);
-                gr.tiles[3] += sun::spatial_blocks(h->g);
-                host.push_back(c);
+                b->host.push_back(c);
                 ++gr.count;
             }
             if (gr.count) b->groups.push_back(gr);
         }
     for (int i = 0; i < n; ++i) b->step0.push_back(chains[i]->step);
-    if (int rc = hip_check(hipMemcpy(table, host.data(), sizeof(sun::ChainDesc) * host.size(), hipMemcpyHostToDevice),
-                           "batch table upload")) {
+    if (int rc = upload_table(b)) {
         delete b;
         return rc;
     }
@@ -531,6 +563,26 @@ int sun_batch_replay(sun_batch_t b, sun_stream_t stream) {
     if (int rc = hip_check(hipGraphLaunch(b->exec, as_stream(stream)), "hipGraphLaunch")) return rc;
     b->hb_steps_done += b->hb_per_replay;
     return SUN_OK;
+}
+
+int sun_batch_set_launch(sun_batch_t b, int block, int xcd) {
+    if (!b) return fail(SUN_EINVAL, "null batch");
+    if (!sun::valid_phase_block(block)) return fail(SUN_EINVAL, "block %d is not 64, 128 or 256", block);
+    // the table holds the device step counters: bring the host copy up to date first
+    for (size_t i = 0; i < b->host.size(); ++i)
+        b->host[i].step = b->step0[b->host[i].out_index] + b->hb_steps_done;
+    if (int rc = hip_check(hipDeviceSynchronize(), "hipDeviceSynchronize")) return rc;
+    b->block = block;
+    b->xcd = xcd ? 1 : 0;
+    if (b->exec) {
+        (void)hipGraphExecDestroy(b->exec);
+        b->exec = nullptr;
+    }
+    if (b->graph) {
+        (void)hipGraphDestroy(b->graph);
+        b->graph = nullptr;
+    }
+    return upload_table(b);
 }
 
 int sun_batch_sync(sun_batch_t b) {

@@ -215,11 +215,14 @@ __device__ __forceinline__ void update_any(T2<T>* __restrict__ U, const Geom& g,
         update_link<N, T, HB, MU>(U, g, par, h, beta, k0, k1, step);
 }
 
-// One checkerboard phase of one lattice.
-template <int N, typename T, bool HB, int MU>
-__global__ __launch_bounds__(kBlock) void k_update(T2<T>* __restrict__ U, Geom g, int par, T beta,
-                                                   uint32_t k0, uint32_t k1, uint32_t step) {
-    const int h = xcd_tile(blockIdx.x, gridDim.x) * kBlock + threadIdx.x;
+// One checkerboard phase of one lattice, BS work-items per workgroup; xcd
+// selects the XCD-aware workgroup order (a tuning choice that never changes
+// results: every link is computed by the same code whichever work-item runs it).
+template <int N, typename T, bool HB, int MU, int BS>
+__global__ __launch_bounds__(BS) void k_update(T2<T>* __restrict__ U, Geom g, int par, T beta, uint32_t k0,
+                                               uint32_t k1, uint32_t step, int xcd) {
+    const int tile = xcd ? xcd_tile(blockIdx.x, gridDim.x) : (int)blockIdx.x;
+    const int h = tile * BS + threadIdx.x;
     if (h >= g.Vh) return;
     update_any<N, T, HB, MU>(U, g, par, h, beta, k0, k1, step);
 }
@@ -247,13 +250,14 @@ __device__ __forceinline__ int find_chain(const ChainDesc* __restrict__ d, int n
     return lo;
 }
 
-template <int N, typename T, bool HB, int MU>
-__global__ __launch_bounds__(kBlock) void k_update_batch(const ChainDesc* __restrict__ d, int n, int par,
-                                                         uint32_t step_offset) {
-    const int tile = xcd_tile(blockIdx.x, gridDim.x);
+// Batched phase: tile0[TILE_HALF] counts tiles of BS work-items.
+template <int N, typename T, bool HB, int MU, int BS>
+__global__ __launch_bounds__(BS) void k_update_batch(const ChainDesc* __restrict__ d, int n, int par,
+                                                     uint32_t step_offset, int xcd) {
+    const int tile = xcd ? xcd_tile(blockIdx.x, gridDim.x) : (int)blockIdx.x;
     const int c = find_chain<TILE_HALF>(d, n, tile);
     const Geom g = d[c].g;
-    const int h = (tile - d[c].tile0[TILE_HALF]) * kBlock + threadIdx.x;
+    const int h = (tile - d[c].tile0[TILE_HALF]) * BS + threadIdx.x;
     if (h >= g.Vh || !((g.present >> MU) & 1)) return;
     update_any<N, T, HB, MU>((T2<T>*)d[c].links, g, par, h, (T)d[c].beta, d[c].k0, d[c].k1,
                              (uint32_t)(d[c].step + step_offset));
@@ -269,12 +273,13 @@ __global__ void k_advance_steps(ChainDesc* __restrict__ d, int n, int n_hb) {
 // ---------------------------------------------------------------------------
 // FP64 helpers for re-unitarization and diagnostics.
 // ---------------------------------------------------------------------------
-template <int N, typename T>
+// STREAM selects nontemporal accesses (for kernels that touch each link once).
+template <int N, typename T, bool STREAM = false>
 __device__ __forceinline__ Mat<N, double> load_link_f64(const T2<T>* __restrict__ U, int mu, int par, int h,
                                                         int Vh) {
     Mat<N, double> m;
     if constexpr (N == 2) {
-        const Quat<T> q = load_quat<T>(U, mu, par, h, Vh);
+        const Quat<T> q = STREAM ? load_quat_stream<T>(U, mu, par, h, Vh) : load_quat<T>(U, mu, par, h, Vh);
         m.re[0][0] = q.q[0];
         m.im[0][0] = q.q[3];
         m.re[0][1] = q.q[2];
@@ -284,7 +289,7 @@ __device__ __forceinline__ Mat<N, double> load_link_f64(const T2<T>* __restrict_
         m.re[1][1] = q.q[0];
         m.im[1][1] = -(double)q.q[3];
     } else {
-        const Mat<N, T> t = load_mat<N, T>(U, mu, par, h, Vh);
+        const Mat<N, T> t = STREAM ? load_mat_stream<N, T>(U, mu, par, h, Vh) : load_mat<N, T>(U, mu, par, h, Vh);
 SUN_MAT_UNROLL
         for (int i = 0; i < N; ++i)
 SUN_MAT_UNROLL
@@ -296,11 +301,15 @@ SUN_MAT_UNROLL
     return m;
 }
 
-template <int N, typename T>
+template <int N, typename T, bool STREAM = false>
 __device__ __forceinline__ void store_link_from_f64(T2<T>* __restrict__ U, int mu, int par, int h, int Vh,
                                                     const Mat<N, double>& m) {
     if constexpr (N == 2) {
-        store_quat<T>(U, mu, par, h, Vh, Quat<T>{{(T)m.re[0][0], (T)m.im[0][1], (T)m.re[0][1], (T)m.im[0][0]}});
+        const Quat<T> q{{(T)m.re[0][0], (T)m.im[0][1], (T)m.re[0][1], (T)m.im[0][0]}};
+        if (STREAM)
+            store_quat_stream<T>(U, mu, par, h, Vh, q);
+        else
+            store_quat<T>(U, mu, par, h, Vh, q);
     } else {
         Mat<N, T> t;
 SUN_MAT_UNROLL
@@ -310,7 +319,10 @@ SUN_MAT_UNROLL
                 t.re[i][j] = (T)m.re[i][j];
                 t.im[i][j] = (T)m.im[i][j];
             }
-        store_mat<N, T>(U, mu, par, h, Vh, t);
+        if (STREAM)
+            store_mat_stream<N, T>(U, mu, par, h, Vh, t);
+        else
+            store_mat<N, T>(U, mu, par, h, Vh, t);
     }
 }
 
@@ -487,10 +499,10 @@ __device__ __forceinline__ void reunit_link(T2<T>* __restrict__ U, const Geom& g
     if (id >= 4 * g.V) return;
     const LinkId l = link_of(g, id);
     if (!((g.present >> l.mu) & 1)) return;
-    Mat<N, double> M = load_link_f64<N, T>(U, l.mu, l.par, l.h, g.Vh);
+    Mat<N, double> M = load_link_f64<N, T, true>(U, l.mu, l.par, l.h, g.Vh);
     if (REPORT) unitarity_dev<N>(M, dev[0], dev[1]);
     reunit<N>(M);
-    store_link_from_f64<N, T>(U, l.mu, l.par, l.h, g.Vh, M);
+    store_link_from_f64<N, T, true>(U, l.mu, l.par, l.h, g.Vh, M);
 }
 
 template <int N, typename T, bool REPORT>
@@ -546,13 +558,17 @@ SUN_MAT_UNROLL
     return t;
 }
 
-// Sums ReTr P over the planes of site id (checkerboard order: parity, then h)
-// into acc = {planes without direction 3, planes with direction 3}.
+// Sums ReTr P over the planes of logical site s into acc = {planes without
+// direction 3, planes with direction 3}.  Work-items follow the logical site
+// order, so the +mu neighbours a site reads are a few work-items away.
 template <int N, typename T>
-__device__ __forceinline__ void plaquette_site(const T2<T>* __restrict__ U, const Geom& g, int id, double (&acc)[2]) {
-    if (id >= g.V) return;
-    const int par = id >= g.Vh ? 1 : 0;
-    const int h = id - par * g.Vh;
+__device__ __forceinline__ void plaquette_site(const T2<T>* __restrict__ U, const Geom& g, int s, double (&acc)[2]) {
+    if (s >= g.V) return;
+    const int q0 = s / g.L[0], x0 = s - q0 * g.L[0];
+    const int q1 = q0 / g.L[1], x1 = q0 - q1 * g.L[1];
+    const int q2 = q1 / g.L[2], x2 = q1 - q2 * g.L[2];
+    const int par = (x0 + x1 + x2 + q2) & 1;
+    const int h = s >> 1;
     const Site x = site_of(g, par, h);
     const int p = g.present;
 #define SUN_PLAQ(m, n, slot) \

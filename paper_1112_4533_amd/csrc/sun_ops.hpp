@@ -13,7 +13,13 @@ struct Ctx {
     void* links;
     Geom g;
     hipStream_t stream;
+    int block = 256;  // work-items per workgroup of the phase kernels (64, 128 or 256)
+    int xcd = 1;      // XCD-aware workgroup order for the phase kernels
 };
+
+// Launch shapes the phase kernels are instantiated for.
+constexpr int kPhaseBlocks[3] = {64, 128, 256};
+inline bool valid_phase_block(int b) { return b == 64 || b == 128 || b == 256; }
 
 struct Ops {
     // one checkerboard phase; kind 0 heatbath, 1 overrelaxation
@@ -31,7 +37,7 @@ struct Ops {
     // batches: d is a device table of n chains of this Nc and storage type;
     // tiles is the total tile count of the grid kind the call uses
     void (*update_batch)(const ChainDesc* d, int n, int tiles, int kind, int mu, int par, uint32_t step_offset,
-                         hipStream_t s);
+                         int block, int xcd, hipStream_t s);
     void (*reunit_batch)(const ChainDesc* d, int n, int tiles, hipStream_t s);
     void (*plaquette_batch)(const ChainDesc* d, int n, int tiles, double* out, hipStream_t s);
 };
@@ -41,6 +47,7 @@ inline int blocks_for(long long n) { return (int)((n + kLaunchBlock - 1) / kLaun
 inline int link_blocks(const Geom& g) { return blocks_for(4LL * g.V); }
 inline int site_blocks(const Geom& g) { return blocks_for(g.V); }
 inline int half_blocks(const Geom& g) { return blocks_for(g.Vh); }
+inline int half_blocks(const Geom& g, int bs) { return (g.Vh + bs - 1) / bs; }
 inline int spatial_blocks(const Geom& g) { return blocks_for(g.V / g.L[3]); }
 
 // f64 = 0: float storage, 1: double storage

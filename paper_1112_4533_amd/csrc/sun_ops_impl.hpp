@@ -12,26 +12,50 @@ struct OpsImpl {
 
     template <bool HB, int MU>
     static void update_mu(const Ctx& c, int par, T beta, uint32_t k0, uint32_t k1, uint32_t step) {
-        k_update<N, T, HB, MU><<<half_blocks(c.g), kBlock, 0, c.stream>>>((P*)c.links, c.g, par, beta, k0, k1, step);
+        P* u = (P*)c.links;
+        switch (c.block) {
+            case 64:
+                k_update<N, T, HB, MU, 64><<<half_blocks(c.g, 64), 64, 0, c.stream>>>(u, c.g, par, beta, k0, k1, step,
+                                                                                      c.xcd);
+                break;
+            case 128:
+                k_update<N, T, HB, MU, 128><<<half_blocks(c.g, 128), 128, 0, c.stream>>>(u, c.g, par, beta, k0, k1,
+                                                                                         step, c.xcd);
+                break;
+            default:
+                k_update<N, T, HB, MU, 256><<<half_blocks(c.g, 256), 256, 0, c.stream>>>(u, c.g, par, beta, k0, k1,
+                                                                                         step, c.xcd);
+                break;
+        }
+    }
+
+    template <bool HB, int BS>
+    static void update_batch_bs(const ChainDesc* d, int n, int tiles, int mu, int par, uint32_t off, int xcd,
+                                hipStream_t s) {
+        switch (mu) {
+            case 0: k_update_batch<N, T, HB, 0, BS><<<tiles, BS, 0, s>>>(d, n, par, off, xcd); break;
+            case 1: k_update_batch<N, T, HB, 1, BS><<<tiles, BS, 0, s>>>(d, n, par, off, xcd); break;
+            case 2: k_update_batch<N, T, HB, 2, BS><<<tiles, BS, 0, s>>>(d, n, par, off, xcd); break;
+            default: k_update_batch<N, T, HB, 3, BS><<<tiles, BS, 0, s>>>(d, n, par, off, xcd); break;
+        }
     }
 
     template <bool HB>
-    static void update_batch_kind(const ChainDesc* d, int n, int tiles, int mu, int par, uint32_t off,
-                                  hipStream_t s) {
-        switch (mu) {
-            case 0: k_update_batch<N, T, HB, 0><<<tiles, kBlock, 0, s>>>(d, n, par, off); break;
-            case 1: k_update_batch<N, T, HB, 1><<<tiles, kBlock, 0, s>>>(d, n, par, off); break;
-            case 2: k_update_batch<N, T, HB, 2><<<tiles, kBlock, 0, s>>>(d, n, par, off); break;
-            default: k_update_batch<N, T, HB, 3><<<tiles, kBlock, 0, s>>>(d, n, par, off); break;
+    static void update_batch_kind(const ChainDesc* d, int n, int tiles, int mu, int par, uint32_t off, int block,
+                                  int xcd, hipStream_t s) {
+        switch (block) {
+            case 64: update_batch_bs<HB, 64>(d, n, tiles, mu, par, off, xcd, s); break;
+            case 128: update_batch_bs<HB, 128>(d, n, tiles, mu, par, off, xcd, s); break;
+            default: update_batch_bs<HB, 256>(d, n, tiles, mu, par, off, xcd, s); break;
         }
     }
 
     static void update_batch(const ChainDesc* d, int n, int tiles, int kind, int mu, int par, uint32_t off,
-                             hipStream_t s) {
+                             int block, int xcd, hipStream_t s) {
         if (kind == 0)
-            update_batch_kind<true>(d, n, tiles, mu, par, off, s);
+            update_batch_kind<true>(d, n, tiles, mu, par, off, block, xcd, s);
         else
-            update_batch_kind<false>(d, n, tiles, mu, par, off, s);
+            update_batch_kind<false>(d, n, tiles, mu, par, off, block, xcd, s);
     }
 
     static void reunit_batch(const ChainDesc* d, int n, int tiles, hipStream_t s) {

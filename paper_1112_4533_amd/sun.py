@@ -62,6 +62,9 @@ def load():
         "sun_batch_capture": [vp, c_int, c_int, c_int, c_int, vp, vp],
         "sun_batch_replay": [vp, vp],
         "sun_batch_sync": [vp],
+        "sun_set_launch": [vp, c_int, c_int],
+        "sun_get_launch": [vp, ctypes.POINTER(c_int), ctypes.POINTER(c_int)],
+        "sun_batch_set_launch": [vp, c_int, c_int],
     }
     for name, args in sigs.items():
         f = getattr(L, name)
@@ -85,7 +88,8 @@ def exported_symbols():
                         "sun_unitarity", "sun_export", "sun_import", "sun_get_step", "sun_set_step",
                         "sun_profile", "sun_profile_read", "sun_sample_su2", "sun_last_error",
                         "sun_batch_bytes", "sun_batch_create", "sun_batch_sweep", "sun_batch_plaquette",
-                        "sun_batch_capture", "sun_batch_replay", "sun_batch_sync", "sun_batch_destroy")
+                        "sun_batch_capture", "sun_batch_replay", "sun_batch_sync", "sun_batch_destroy",
+                        "sun_set_launch", "sun_get_launch", "sun_batch_set_launch")
             if hasattr(L, n)]
 
 
@@ -204,6 +208,18 @@ class Lattice:
     def step(self, value):
         _check(load().sun_set_step(self._h, int(value)))
 
+    # -- launch shape (tuning only; results do not depend on it) ---------
+    LAUNCH_SHAPES = [(b, x) for b in (64, 128, 256) for x in (1, 0)]
+
+    def set_launch(self, block=256, xcd=1):
+        _check(load().sun_set_launch(self._h, int(block), int(xcd)))
+
+    @property
+    def launch(self):
+        b, x = ctypes.c_int(), ctypes.c_int()
+        _check(load().sun_get_launch(self._h, ctypes.byref(b), ctypes.byref(x)))
+        return b.value, x.value
+
     # -- event timing ----------------------------------------------------
     def profile(self, enable=True):
         _check(load().sun_profile(self._h, int(bool(enable))))
@@ -236,6 +252,9 @@ class Batch:
         _check(lib.sun_batch_create(n, handles, b, sd, _ptr(self.table), tb.value, ctypes.byref(h)))
         self._h = h
         self.n = n
+        self.betas = [float(x) for x in betas]
+        self.seeds = [int(x) for x in seeds]
+        self.launch = (256, 1)
         self.stream = torch.cuda.Stream(device=dev)   # graphs need a non-null stream
 
     def __del__(self):
@@ -270,6 +289,11 @@ class Batch:
 
     def sync(self):
         _check(load().sun_batch_sync(self._h))
+
+    def set_launch(self, block=256, xcd=1):
+        """Launch shape of the phase kernels; drops a captured graph."""
+        _check(load().sun_batch_set_launch(self._h, int(block), int(xcd)))
+        self.launch = (int(block), int(xcd))
 
 
 def sample_su2(alpha, seed, step=0, mu_sg=0, dtype="f64"):

@@ -75,4 +75,23 @@ def test_create_validates_buffers_without_touching_them(lib):
     assert lib.sun_sweep(h, 6.0, -1, 0, 1, 1, None) == -1
     assert lib.sun_plaquette(h, None, None) == -2
     assert lib.sun_profile_read(h, 9, None, None) == -1
+    # launch shapes: only the instantiated workgroup sizes
+    b, x = ctypes.c_int(), ctypes.c_int()
+    assert lib.sun_get_launch(h, ctypes.byref(b), ctypes.byref(x)) == 0 and (b.value, x.value) == (256, 1)
+    assert lib.sun_set_launch(h, 100, 1) == -1
+    assert lib.sun_set_launch(h, 64, 0) == 0
+    assert lib.sun_get_launch(h, ctypes.byref(b), ctypes.byref(x)) == 0 and (b.value, x.value) == (64, 0)
     lib.sun_lattice_destroy(h)
+
+
+def test_batch_argument_checks(lib):
+    tb = ctypes.c_size_t()
+    assert lib.sun_batch_bytes(0, ctypes.byref(tb)) == -1
+    assert lib.sun_batch_bytes(64, ctypes.byref(tb)) == 0 and tb.value >= 64 * 64
+    out = ctypes.c_void_p()
+    one = (ctypes.c_void_p * 1)(None)
+    d = (ctypes.c_double * 1)(1.0)
+    s = (ctypes.c_uint64 * 1)(1)
+    assert lib.sun_batch_create(1, one, d, s, ctypes.c_void_p(0x10000), tb.value, ctypes.byref(out)) == -1
+    assert lib.sun_batch_sweep(None, 1, 1, 1, None) == -1
+    assert lib.sun_batch_replay(None, None) == -1

@@ -497,3 +497,56 @@ def test_batch_eager_and_graph_agree_over_many_replays(gpu):
         torch.cuda.synchronize()
         for x, y in zip(a, g):
             assert torch.equal(x.links, y.links)
+
+
+# ---------------------------------------------------------------------------
+# Launch shapes and the autotuner
+# ---------------------------------------------------------------------------
+@pytest.mark.parametrize("nc,dtype", [(2, "f32"), (3, "f32"), (3, "f64"), (4, "f32")])
+def test_every_launch_shape_gives_the_same_bits(gpu, nc, dtype):
+    sun = gpu
+    L = (10, 6, 4, 6)
+    ref = None
+    for block, xcd in sun.Lattice.LAUNCH_SHAPES:
+        lat = gpu_lattice(sun, nc, L, dtype, hot=True, seed=8)
+        lat.set_launch(block, xcd)
+        assert lat.launch == (block, xcd)
+        lat.sweep(BETA[nc], 1, 2, seed=8)
+        lat.sweep(BETA[nc], 1, 2, seed=8)
+        torch.cuda.synchronize()
+        if ref is None:
+            ref = lat.links.clone()
+        else:
+            assert torch.equal(ref, lat.links), (block, xcd)
+
+
+def test_batch_launch_shapes_and_tuner(gpu, tmp_path, monkeypatch):
+    sun = gpu
+    from paper_1112_4533_amd import autotune
+    monkeypatch.setattr(autotune, "CACHE", str(tmp_path / "tune.json"))
+    spec = BATCH
+    ref = [gpu_lattice(sun, nc, L, dt, hot=True, seed=sd) for nc, L, dt, b, sd in spec]
+    rb = sun.Batch(ref, [c[3] for c in spec], [c[4] for c in spec])
+    rb.sweep(1, 2)
+    rb.sweep(1, 2)
+    for block, xcd in [(64, 0), (128, 1)]:
+        lats = [gpu_lattice(sun, nc, L, dt, hot=True, seed=sd) for nc, L, dt, b, sd in spec]
+        bt = sun.Batch(lats, [c[3] for c in spec], [c[4] for c in spec])
+        bt.set_launch(block, xcd)
+        bt.sweep(1, 2)
+        bt.capture(n_sweeps=1, n_hb=1, n_or=2)
+        bt.replay()
+        torch.cuda.synchronize()
+        for a, b in zip(ref, lats):
+            assert torch.equal(a.links, b.links), (block, xcd)
+    # the tuner works on clones: the chains' fields are unchanged by tuning
+    before = [l.links.clone() for l in ref]
+    block, xcd, times = autotune.tune_batch(rb)
+    assert (block, xcd) in sun.Lattice.LAUNCH_SHAPES and len(times) == 6
+    for a, b in zip(before, ref):
+        assert torch.equal(a, b.links)
+    lat = ref[1]
+    block, xcd, _ = autotune.tune_lattice(lat)
+    assert lat.launch == (block, xcd)
+    # a second call comes from the cache
+    assert autotune.tune_lattice(lat)[:2] == (block, xcd)
