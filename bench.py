@@ -25,8 +25,9 @@ METRIC = "link updates/sec + HBM GB/s (%roofline), SU(3) 32^4, batched FP32 vs p
 
 
 def link_bytes(nc, dtype):
-    reals = 4 if nc == 2 else 2 * nc * nc
-    return reals * (4 if dtype == "f32" else 8)
+    rows = 2 if dtype.endswith("r12") else nc
+    reals = 4 if nc == 2 else 2 * rows * nc
+    return reals * (4 if dtype.startswith("f32") else 8)
 
 
 def phase_bytes(nc, V, dtype):
@@ -191,6 +192,7 @@ def main():
     ap.add_argument("--cpu-sweeps", type=int, default=8, help="oracle sweeps in the CPU-baseline sample")
     ap.add_argument("--no-f64", action="store_true")
     ap.add_argument("--no-batch", action="store_true")
+    ap.add_argument("--no-two-row", action="store_true")
     ap.add_argument("--copy-calibration", type=float, default=0.0, metavar="GB",
                     help="only copy a GB-sized device buffer 5 times (the reference kernel for "
                          "scaling HBM byte counters), then exit")
@@ -211,11 +213,12 @@ def main():
               file=sys.stderr)
         sys.exit(2)
 
-    from paper_1112_4533_amd.workloads import SU3_32_F32, SU3_32_F64
+    from paper_1112_4533_amd.workloads import SU3_32_F32, SU3_32_F32_TWO_ROW, SU3_32_F64
 
     run = SU3_32_F32
     r32 = run_gpu(run, args.steps, args.warmup)
     r64 = None if args.no_f64 else run_gpu(SU3_32_F64, max(2, args.steps // 2), max(1, args.warmup // 2))
+    r12 = None if args.no_two_row else run_gpu(SU3_32_F32_TWO_ROW, args.steps, args.warmup)
 
     V = run.volume
     k_or = r32["kernels"]["overrelax"]
@@ -264,6 +267,20 @@ def main():
             "steps": max(2, args.steps // 2), "kernels": r64["kernels"], "plaquette": r64["plaquette"],
             "max_unitarity_dev_before_reunit": r64["unitarity_before_reunit"],
             "f32_over_f64": r32["updates_per_s"] / r64["updates_per_s"],
+        }
+    if r12:
+        k12 = r12["kernels"]["overrelax"]
+        pb12 = phase_bytes(run.nc, V, SU3_32_F32_TWO_ROW.dtype)
+        a12 = pb12 / (k12["avg_ms"] * 1e-3) / 1e9
+        line["two_row"] = {
+            "workload": SU3_32_F32_TWO_ROW.name, "value": r12["updates_per_s"], "unit": "link_updates/s",
+            "ms_per_step": r12["ms_per_step"],
+            "roofline": {"bound": "hbm", "kernel": "overrelaxation phase, two-row storage", "achieved": a12,
+                         "peak": PEAK_HBM_GBS, "unit": "GB/s", "frac": a12 / PEAK_HBM_GBS,
+                         "bytes_per_launch": pb12, "avg_launch_ms": k12["avg_ms"]},
+            "kernels": r12["kernels"], "plaquette": r12["plaquette"],
+            "max_unitarity_dev_before_reunit": r12["unitarity_before_reunit"],
+            "speedup_over_18_real": r12["updates_per_s"] / r32["updates_per_s"],
         }
     if not args.no_batch:
         line["batch"] = run_batch(max(4, args.steps), args.warmup, max(2, args.steps // 4))

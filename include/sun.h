@@ -49,9 +49,11 @@ enum {
     SUN_EUNSUP = -4  /* valid request this build does not implement */
 };
 
-/* Link storage precision.  Reductions, re-unitarization and the start
- * configuration are always computed in FP64. */
-enum { SUN_F32 = 0, SUN_F64 = 1 };
+/* Link storage.  Reductions, re-unitarization and the start configuration
+ * are always computed in FP64.  The TWO_ROW forms (SU(3) only, paper Sec. 3:
+ * 12 reals instead of 18) store rows 0 and 1 and rebuild row 2 as
+ * conj(row0 x row1) on every load, which cuts link traffic by a third. */
+enum { SUN_F32 = 0, SUN_F64 = 1, SUN_F32_TWO_ROW = 2, SUN_F64_TWO_ROW = 3 };
 
 /* Update kinds of one checkerboard phase (paper Sec. 3 kernel list). */
 enum { SUN_HEATBATH = 0, SUN_OVERRELAX = 1 };
@@ -66,7 +68,8 @@ int sun_lattice_bytes(int nc, const int L[4], int dtype, size_t *link_bytes,
                       size_t *scratch_bytes);
 
 /* Creates a handle over caller-owned device buffers (links: link_bytes,
- * scratch: scratch_bytes, both 256-byte aligned).  Nc in 2..SUN_NC_MAX.
+ * scratch: scratch_bytes, both 256-byte aligned).  Nc in 2..SUN_NC_MAX;
+ * SUN_EUNSUP for a TWO_ROW dtype with Nc != 3.
  * The field content is undefined until sun_init or sun_import. */
 int sun_lattice_create(int nc, const int L[4], int dtype, void *links, size_t link_bytes,
                        void *scratch, size_t scratch_bytes, sun_lattice_t *out);

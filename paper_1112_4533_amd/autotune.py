@@ -56,8 +56,7 @@ def _time(fn, reps):
 
 
 def lattice_key(lat):
-    dt = "f32" if lat.dtype == sun.F32 else "f64"
-    return f"{_arch()}:su{lat.nc}:{'x'.join(map(str, lat.L))}:{dt}"
+    return f"{_arch()}:su{lat.nc}:{'x'.join(map(str, lat.L))}:{sun.DTYPE_NAMES[lat.dtype]}"
 
 
 def tune_lattice(lat, reps=5, use_cache=True):
@@ -69,7 +68,7 @@ def tune_lattice(lat, reps=5, use_cache=True):
         block, xcd = cache[key]["block"], cache[key]["xcd"]
         lat.set_launch(block, xcd)
         return block, xcd, cache[key].get("ms", {})
-    clone = sun.Lattice(lat.nc, lat.L, "f32" if lat.dtype == sun.F32 else "f64", device=lat.links.device)
+    clone = sun.Lattice(lat.nc, lat.L, lat.dtype, device=lat.links.device)
     clone.links.copy_(lat.links)
     times = {}
     for block, xcd in sun.Lattice.LAUNCH_SHAPES:
@@ -85,7 +84,7 @@ def tune_lattice(lat, reps=5, use_cache=True):
 
 
 def batch_key(batch):
-    parts = [f"su{l.nc}:{'x'.join(map(str, l.L))}:{'f32' if l.dtype == sun.F32 else 'f64'}" for l in batch.lattices]
+    parts = [f"su{l.nc}:{'x'.join(map(str, l.L))}:{sun.DTYPE_NAMES[l.dtype]}" for l in batch.lattices]
     return f"{_arch()}:batch:" + ",".join(parts)
 
 
@@ -99,7 +98,7 @@ def tune_batch(batch, reps=3, use_cache=True):
         return cache[key]["block"], cache[key]["xcd"], cache[key].get("ms", {})
     clones = []
     for l in batch.lattices:
-        c = sun.Lattice(l.nc, l.L, "f32" if l.dtype == sun.F32 else "f64", device=l.links.device)
+        c = sun.Lattice(l.nc, l.L, l.dtype, device=l.links.device)
         c.links.copy_(l.links)
         clones.append(c)
     cb = sun.Batch(clones, batch.betas, batch.seeds)

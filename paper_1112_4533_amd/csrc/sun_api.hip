@@ -68,7 +68,13 @@ struct sun_lattice_s {
 
 namespace {
 
-const sun::Ops* ops_for(int nc, int f64) {
+// dtype bit 0: FP64 storage; bit 1: SU(3) two-row storage.
+inline int is_f64(int dtype) { return dtype & 1; }
+inline int is_two_row(int dtype) { return (dtype >> 1) & 1; }
+
+const sun::Ops* ops_for(int nc, int dtype) {
+    const int f64 = is_f64(dtype);
+    if (is_two_row(dtype)) return nc == 3 ? sun::ops_nc3_two_row(f64) : nullptr;
     switch (nc) {
         case 2: return sun::ops_nc2(f64);
         case 3: return sun::ops_nc3(f64);
@@ -84,7 +90,8 @@ const sun::Ops* ops_for(int nc, int f64) {
 int check_lattice(int nc, const int L[4], int dtype) {
     if (!L) return fail(SUN_EINVAL, "L is null");
     if (nc < 2 || nc > SUN_NC_MAX) return fail(SUN_EINVAL, "Nc = %d outside 2..%d", nc, SUN_NC_MAX);
-    if (dtype != SUN_F32 && dtype != SUN_F64) return fail(SUN_EINVAL, "dtype %d is neither SUN_F32 nor SUN_F64", dtype);
+    if (dtype < SUN_F32 || dtype > SUN_F64_TWO_ROW) return fail(SUN_EINVAL, "dtype %d is not a SUN_F* code", dtype);
+    if (is_two_row(dtype) && nc != 3) return fail(SUN_EUNSUP, "two-row storage exists for SU(3) only (Nc = %d)", nc);
     if (L[0] < 2 || (L[0] & 1)) return fail(SUN_EINVAL, "L[0] = %d must be even and >= 2", L[0]);
     long long V = 1;
     for (int mu = 0; mu < 4; ++mu) {
@@ -112,8 +119,9 @@ sun::Geom make_geom(const int L[4]) {
 }
 
 size_t link_bytes_of(int nc, const sun::Geom& g, int dtype) {
-    const size_t reals = (nc == 2) ? 4 : 2 * (size_t)nc * nc;
-    return reals * 4 * (size_t)g.V * (dtype == SUN_F64 ? 8 : 4);
+    const size_t rows = is_two_row(dtype) ? 2 : (size_t)nc;
+    const size_t reals = (nc == 2) ? 4 : 2 * rows * nc;
+    return reals * 4 * (size_t)g.V * (is_f64(dtype) ? 8 : 4);
 }
 
 size_t scratch_bytes_of(const sun::Geom& g) {
@@ -184,7 +192,7 @@ int sun_lattice_create(int nc, const int L[4], int dtype, void* links, size_t li
     h->g = g;
     h->links = links;
     h->scratch = static_cast<double*>(scratch);
-    h->ops = ops_for(nc, dtype == SUN_F64);
+    h->ops = ops_for(nc, dtype);
     *out = h;
     return SUN_OK;
 }
@@ -479,8 +487,9 @@ int sun_batch_create(int n, const sun_lattice_t* chains, const double* betas, co
     b->table = static_cast<sun::ChainDesc*>(table);
     // group by (Nc, dtype), keeping the caller's order inside a group
     for (int nc = 2; nc <= SUN_NC_MAX; ++nc)
-        for (int dt = SUN_F32; dt <= SUN_F64; ++dt) {
-            sun_batch_s::Group gr{ops_for(nc, dt == SUN_F64), (int)b->host.size(), 0, {0, 0, 0, 0}};
+        for (int dt = SUN_F32; dt <= SUN_F64_TWO_ROW; ++dt) {
+            if (is_two_row(dt) && nc != 3) continue;
+            sun_batch_s::Group gr{ops_for(nc, dt), (int)b->host.size(), 0, {0, 0, 0, 0}};
             for (int i = 0; i < n; ++i) {
                 const sun_lattice_t h = chains[i];
                 if (h->nc != nc || h->dtype != dt) continue;

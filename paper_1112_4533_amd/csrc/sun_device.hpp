@@ -322,34 +322,56 @@ struct Pair<double> {
 template <typename T>
 using T2 = typename Pair<T>::type;
 
-template <int N>
+// Stored rows R: R = N keeps the whole matrix; R = 2 with N = 3 keeps rows 0
+// and 1 (12 reals, the paper's Sec. 3 SU(3) parameterization) and rebuilds
+// row 2 = conj(row0 x row1) on every load (exact for SU(3)).
+template <int N, int R = N>
 struct Planes {
-    static constexpr int E = (N == 2) ? 2 : N * N;
+    static_assert(R == N || (N == 3 && R == 2), "only SU(3) has a two-row form");
+    static constexpr int E = (N == 2) ? 2 : R * N;
 };
 
-template <int N, typename T>
+template <int N, typename T, int R = N>
 __device__ __forceinline__ const T2<T>* plane0(const T2<T>* base, int mu, int par, int Vh) {
-    return base + (size_t)((mu * 2 + par) * Planes<N>::E) * (size_t)Vh;
+    return base + (size_t)((mu * 2 + par) * Planes<N, R>::E) * (size_t)Vh;
 }
 
+// Row 2 of an SU(3) matrix from rows 0 and 1: conj(row0 x row1).
 template <int N, typename T>
+__device__ __forceinline__ void third_row(Mat<N, T>& m) {
+    if constexpr (N == 3) {
+#pragma unroll
+        for (int c = 0; c < 3; ++c) {
+            const int a = (c + 1) % 3, b = (c + 2) % 3;
+            const T xr = m.re[0][a] * m.re[1][b] - m.im[0][a] * m.im[1][b] -
+                         (m.re[0][b] * m.re[1][a] - m.im[0][b] * m.im[1][a]);
+            const T xi = m.re[0][a] * m.im[1][b] + m.im[0][a] * m.re[1][b] -
+                         (m.re[0][b] * m.im[1][a] + m.im[0][b] * m.re[1][a]);
+            m.re[2][c] = xr;
+            m.im[2][c] = -xi;
+        }
+    }
+}
+
+template <int N, typename T, int R = N>
 __device__ __forceinline__ Mat<N, T> load_mat(const T2<T>* base, int mu, int par, int h, int Vh) {
-    const T2<T>* p = plane0<N, T>(base, mu, par, Vh) + h;
+    const T2<T>* p = plane0<N, T, R>(base, mu, par, Vh) + h;
     Mat<N, T> m;
 SUN_MAT_UNROLL
-    for (int e = 0; e < N * N; ++e) {
+    for (int e = 0; e < R * N; ++e) {
         const T2<T> v = p[(size_t)e * Vh];
         m.re[e / N][e % N] = v.x;
         m.im[e / N][e % N] = v.y;
     }
+    if constexpr (R < N) third_row(m);
     return m;
 }
 
-template <int N, typename T>
+template <int N, typename T, int R = N>
 __device__ __forceinline__ void store_mat(T2<T>* base, int mu, int par, int h, int Vh, const Mat<N, T>& m) {
-    T2<T>* p = const_cast<T2<T>*>(plane0<N, T>(base, mu, par, Vh)) + h;
+    T2<T>* p = const_cast<T2<T>*>(plane0<N, T, R>(base, mu, par, Vh)) + h;
 SUN_MAT_UNROLL
-    for (int e = 0; e < N * N; ++e) {
+    for (int e = 0; e < R * N; ++e) {
         T2<T> v;
         v.x = m.re[e / N][e % N];
         v.y = m.im[e / N][e % N];
@@ -389,24 +411,25 @@ __device__ __forceinline__ void store_stream(T2<T>* p, const T2<T>& a) {
     __builtin_nontemporal_store(v, reinterpret_cast<typename NativePair<T>::type*>(p));
 }
 
-template <int N, typename T>
+template <int N, typename T, int R = N>
 __device__ __forceinline__ Mat<N, T> load_mat_stream(const T2<T>* base, int mu, int par, int h, int Vh) {
-    const T2<T>* p = plane0<N, T>(base, mu, par, Vh) + h;
+    const T2<T>* p = plane0<N, T, R>(base, mu, par, Vh) + h;
     Mat<N, T> m;
 SUN_MAT_UNROLL
-    for (int e = 0; e < N * N; ++e) {
+    for (int e = 0; e < R * N; ++e) {
         const T2<T> v = load_stream<T>(p + (size_t)e * Vh);
         m.re[e / N][e % N] = v.x;
         m.im[e / N][e % N] = v.y;
     }
+    if constexpr (R < N) third_row(m);
     return m;
 }
 
-template <int N, typename T>
+template <int N, typename T, int R = N>
 __device__ __forceinline__ void store_mat_stream(T2<T>* base, int mu, int par, int h, int Vh, const Mat<N, T>& m) {
-    T2<T>* p = const_cast<T2<T>*>(plane0<N, T>(base, mu, par, Vh)) + h;
+    T2<T>* p = const_cast<T2<T>*>(plane0<N, T, R>(base, mu, par, Vh)) + h;
 SUN_MAT_UNROLL
-    for (int e = 0; e < N * N; ++e) {
+    for (int e = 0; e < R * N; ++e) {
         T2<T> v;
         v.x = m.re[e / N][e % N];
         v.y = m.im[e / N][e % N];

@@ -90,7 +90,7 @@ __global__ __launch_bounds__(kBlock) void k_finalize(const double* __restrict__ 
 //   U_nu(x+mu) U_mu(x+nu)^dag U_nu(x)^dag + U_nu(x+mu-nu)^dag U_mu(x-nu)^dag U_nu(x-nu)
 // so that ReTr(U_mu(x) A) is the sum of the plaquettes containing the link.
 // ---------------------------------------------------------------------------
-template <int N, typename T, int MU>
+template <int N, typename T, int R, int MU>
 __device__ __forceinline__ Mat<N, T> staple(const T2<T>* __restrict__ U, const Geom& g, const Site& x, int par,
                                             int h) {
     const int op = par ^ 1;
@@ -103,12 +103,12 @@ __device__ __forceinline__ Mat<N, T> staple(const T2<T>* __restrict__ U, const G
         const Site xpn = step_up(g, x, nu);
         const Site xmn = step_down(g, x, nu);
         const Site xpmn = step_down(g, xp, nu);
-        const Mat<N, T> m = mul_nd(load_mat<N, T>(U, nu, op, xp.s >> 1, g.Vh),
-                                   load_mat<N, T>(U, MU, op, xpn.s >> 1, g.Vh));
-        add_mul_nd(A, m, load_mat<N, T>(U, nu, par, h, g.Vh));
-        const Mat<N, T> l = mul_nn(load_mat<N, T>(U, MU, op, xmn.s >> 1, g.Vh),
-                                   load_mat<N, T>(U, nu, par, xpmn.s >> 1, g.Vh));
-        add_mul_dn(A, l, load_mat<N, T>(U, nu, op, xmn.s >> 1, g.Vh));
+        const Mat<N, T> m = mul_nd(load_mat<N, T, R>(U, nu, op, xp.s >> 1, g.Vh),
+                                   load_mat<N, T, R>(U, MU, op, xpn.s >> 1, g.Vh));
+        add_mul_nd(A, m, load_mat<N, T, R>(U, nu, par, h, g.Vh));
+        const Mat<N, T> l = mul_nn(load_mat<N, T, R>(U, MU, op, xmn.s >> 1, g.Vh),
+                                   load_mat<N, T, R>(U, nu, par, xpmn.s >> 1, g.Vh));
+        add_mul_dn(A, l, load_mat<N, T, R>(U, nu, op, xmn.s >> 1, g.Vh));
     }
     return A;
 }
@@ -154,12 +154,12 @@ __device__ __forceinline__ T unit_quat(const Quat<T>& p, Quat<T>& v) {
 // kept in registers and updated with U.  Shared by the single-lattice and the
 // batched kernels, so a chain gives the same bits either way.
 // ---------------------------------------------------------------------------
-template <int N, typename T, bool HB, int MU>
+template <int N, typename T, int R, bool HB, int MU>
 __device__ __forceinline__ void update_link(T2<T>* __restrict__ U, const Geom& g, int par, int h, T beta,
                                             uint32_t k0, uint32_t k1, uint32_t step) {
     const Site x = site_of(g, par, h);
-    const Mat<N, T> A = staple<N, T, MU>(U, g, x, par, h);
-    Mat<N, T> Ul = load_mat_stream<N, T>(U, MU, par, h, g.Vh);
+    const Mat<N, T> A = staple<N, T, R, MU>(U, g, x, par, h);
+    Mat<N, T> Ul = load_mat_stream<N, T, R>(U, MU, par, h, g.Vh);
     Mat<N, T> W = mul_nn(Ul, A);
     int sg = 0;
 SUN_MAT_UNROLL
@@ -182,7 +182,7 @@ SUN_MAT_UNROLL
             rows_left_mul(Ul, i, j, a);
             rows_left_mul(W, i, j, a);
         }
-    store_mat_stream<N, T>(U, MU, par, h, g.Vh, Ul);
+    store_mat_stream<N, T, R>(U, MU, par, h, g.Vh, Ul);
 }
 
 // The same for SU(2) in the 4-real parameterization (paper Sec. 2, Sec. 3).
@@ -206,25 +206,25 @@ __device__ __forceinline__ void update_link_su2(T2<T>* __restrict__ U, const Geo
     store_quat_stream<T>(U, MU, par, h, g.Vh, qmul(a, u));
 }
 
-template <int N, typename T, bool HB, int MU>
+template <int N, typename T, int R, bool HB, int MU>
 __device__ __forceinline__ void update_any(T2<T>* __restrict__ U, const Geom& g, int par, int h, T beta, uint32_t k0,
                                            uint32_t k1, uint32_t step) {
     if constexpr (N == 2)
         update_link_su2<T, HB, MU>(U, g, par, h, beta, k0, k1, step);
     else
-        update_link<N, T, HB, MU>(U, g, par, h, beta, k0, k1, step);
+        update_link<N, T, R, HB, MU>(U, g, par, h, beta, k0, k1, step);
 }
 
 // One checkerboard phase of one lattice, BS work-items per workgroup; xcd
 // selects the XCD-aware workgroup order (a tuning choice that never changes
 // results: every link is computed by the same code whichever work-item runs it).
-template <int N, typename T, bool HB, int MU, int BS>
+template <int N, typename T, int R, bool HB, int MU, int BS>
 __global__ __launch_bounds__(BS) void k_update(T2<T>* __restrict__ U, Geom g, int par, T beta, uint32_t k0,
                                                uint32_t k1, uint32_t step, int xcd) {
     const int tile = xcd ? xcd_tile(blockIdx.x, gridDim.x) : (int)blockIdx.x;
     const int h = tile * BS + threadIdx.x;
     if (h >= g.Vh) return;
-    update_any<N, T, HB, MU>(U, g, par, h, beta, k0, k1, step);
+    update_any<N, T, R, HB, MU>(U, g, par, h, beta, k0, k1, step);
 }
 
 // ---------------------------------------------------------------------------
@@ -251,7 +251,7 @@ __device__ __forceinline__ int find_chain(const ChainDesc* __restrict__ d, int n
 }
 
 // Batched phase: tile0[TILE_HALF] counts tiles of BS work-items.
-template <int N, typename T, bool HB, int MU, int BS>
+template <int N, typename T, int R, bool HB, int MU, int BS>
 __global__ __launch_bounds__(BS) void k_update_batch(const ChainDesc* __restrict__ d, int n, int par,
                                                      uint32_t step_offset, int xcd) {
     const int tile = xcd ? xcd_tile(blockIdx.x, gridDim.x) : (int)blockIdx.x;
@@ -259,7 +259,7 @@ __global__ __launch_bounds__(BS) void k_update_batch(const ChainDesc* __restrict
     const Geom g = d[c].g;
     const int h = (tile - d[c].tile0[TILE_HALF]) * BS + threadIdx.x;
     if (h >= g.Vh || !((g.present >> MU) & 1)) return;
-    update_any<N, T, HB, MU>((T2<T>*)d[c].links, g, par, h, (T)d[c].beta, d[c].k0, d[c].k1,
+    update_any<N, T, R, HB, MU>((T2<T>*)d[c].links, g, par, h, (T)d[c].beta, d[c].k0, d[c].k1,
                              (uint32_t)(d[c].step + step_offset));
 }
 
@@ -274,7 +274,7 @@ __global__ void k_advance_steps(ChainDesc* __restrict__ d, int n, int n_hb) {
 // FP64 helpers for re-unitarization and diagnostics.
 // ---------------------------------------------------------------------------
 // STREAM selects nontemporal accesses (for kernels that touch each link once).
-template <int N, typename T, bool STREAM = false>
+template <int N, typename T, int R, bool STREAM = false>
 __device__ __forceinline__ Mat<N, double> load_link_f64(const T2<T>* __restrict__ U, int mu, int par, int h,
                                                         int Vh) {
     Mat<N, double> m;
@@ -289,7 +289,7 @@ __device__ __forceinline__ Mat<N, double> load_link_f64(const T2<T>* __restrict_
         m.re[1][1] = q.q[0];
         m.im[1][1] = -(double)q.q[3];
     } else {
-        const Mat<N, T> t = STREAM ? load_mat_stream<N, T>(U, mu, par, h, Vh) : load_mat<N, T>(U, mu, par, h, Vh);
+        const Mat<N, T> t = STREAM ? load_mat_stream<N, T, R>(U, mu, par, h, Vh) : load_mat<N, T, R>(U, mu, par, h, Vh);
 SUN_MAT_UNROLL
         for (int i = 0; i < N; ++i)
 SUN_MAT_UNROLL
@@ -301,7 +301,7 @@ SUN_MAT_UNROLL
     return m;
 }
 
-template <int N, typename T, bool STREAM = false>
+template <int N, typename T, int R, bool STREAM = false>
 __device__ __forceinline__ void store_link_from_f64(T2<T>* __restrict__ U, int mu, int par, int h, int Vh,
                                                     const Mat<N, double>& m) {
     if constexpr (N == 2) {
@@ -320,9 +320,9 @@ SUN_MAT_UNROLL
                 t.im[i][j] = (T)m.im[i][j];
             }
         if (STREAM)
-            store_mat_stream<N, T>(U, mu, par, h, Vh, t);
+            store_mat_stream<N, T, R>(U, mu, par, h, Vh, t);
         else
-            store_mat<N, T>(U, mu, par, h, Vh, t);
+            store_mat<N, T, R>(U, mu, par, h, Vh, t);
     }
 }
 
@@ -494,33 +494,33 @@ __device__ __forceinline__ LinkId link_of(const Geom& g, int id) {
 // REPORT is a template flag (not a runtime one) so that the projection
 // compiles to the same instructions in every kernel that runs it: a chain in
 // a batch must get the same bits as the chain alone.
-template <int N, typename T, bool REPORT>
+template <int N, typename T, int R, bool REPORT>
 __device__ __forceinline__ void reunit_link(T2<T>* __restrict__ U, const Geom& g, int id, double (&dev)[2]) {
     if (id >= 4 * g.V) return;
     const LinkId l = link_of(g, id);
     if (!((g.present >> l.mu) & 1)) return;
-    Mat<N, double> M = load_link_f64<N, T, true>(U, l.mu, l.par, l.h, g.Vh);
+    Mat<N, double> M = load_link_f64<N, T, R, true>(U, l.mu, l.par, l.h, g.Vh);
     if (REPORT) unitarity_dev<N>(M, dev[0], dev[1]);
     reunit<N>(M);
-    store_link_from_f64<N, T, true>(U, l.mu, l.par, l.h, g.Vh, M);
+    store_link_from_f64<N, T, R, true>(U, l.mu, l.par, l.h, g.Vh, M);
 }
 
-template <int N, typename T, bool REPORT>
+template <int N, typename T, int R, bool REPORT>
 __global__ __launch_bounds__(kBlock) void k_reunit(T2<T>* __restrict__ U, Geom g, double* __restrict__ partial) {
     double dev[2] = {0.0, 0.0};
-    reunit_link<N, T, REPORT>(U, g, blockIdx.x * kBlock + threadIdx.x, dev);
+    reunit_link<N, T, R, REPORT>(U, g, blockIdx.x * kBlock + threadIdx.x, dev);
     if (REPORT) block_max<2>(dev, partial + 2 * (size_t)blockIdx.x);
 }
 
-template <int N, typename T>
+template <int N, typename T, int R>
 __global__ __launch_bounds__(kBlock) void k_reunit_batch(const ChainDesc* __restrict__ d, int n) {
     const int tile = blockIdx.x;
     const int c = find_chain<TILE_LINK>(d, n, tile);
     double dev[2] = {0.0, 0.0};
-    reunit_link<N, T, false>((T2<T>*)d[c].links, d[c].g, (tile - d[c].tile0[TILE_LINK]) * kBlock + threadIdx.x, dev);
+    reunit_link<N, T, R, false>((T2<T>*)d[c].links, d[c].g, (tile - d[c].tile0[TILE_LINK]) * kBlock + threadIdx.x, dev);
 }
 
-template <int N, typename T>
+template <int N, typename T, int R>
 __global__ __launch_bounds__(kBlock) void k_unitarity(const T2<T>* __restrict__ U, Geom g,
                                                       double* __restrict__ partial) {
     const int id = blockIdx.x * kBlock + threadIdx.x;
@@ -528,7 +528,7 @@ __global__ __launch_bounds__(kBlock) void k_unitarity(const T2<T>* __restrict__ 
     if (id < 4 * g.V) {
         const LinkId l = link_of(g, id);
         if ((g.present >> l.mu) & 1) {
-            const Mat<N, double> M = load_link_f64<N, T>(U, l.mu, l.par, l.h, g.Vh);
+            const Mat<N, double> M = load_link_f64<N, T, R>(U, l.mu, l.par, l.h, g.Vh);
             unitarity_dev<N>(M, dev[0], dev[1]);
         }
     }
@@ -540,15 +540,15 @@ __global__ __launch_bounds__(kBlock) void k_unitarity(const T2<T>* __restrict__ 
 // evaluated in FP64 from the stored links; per-block partial sums
 // {spatial planes, planes with direction 3}.
 // ---------------------------------------------------------------------------
-template <int N, typename T, int MU, int NU>
+template <int N, typename T, int R, int MU, int NU>
 __device__ __forceinline__ double re_tr_plaq(const T2<T>* __restrict__ U, const Geom& g, const Site& x, int par,
                                              int h) {
     const Site xm = step_up(g, x, MU), xn = step_up(g, x, NU);
     const int op = par ^ 1;
-    const Mat<N, double> a = mul_nn(load_link_f64<N, T>(U, MU, par, h, g.Vh),
-                                    load_link_f64<N, T>(U, NU, op, xm.s >> 1, g.Vh));
-    const Mat<N, double> b = mul_nd(a, load_link_f64<N, T>(U, MU, op, xn.s >> 1, g.Vh));
-    const Mat<N, double> un = load_link_f64<N, T>(U, NU, par, h, g.Vh);
+    const Mat<N, double> a = mul_nn(load_link_f64<N, T, R>(U, MU, par, h, g.Vh),
+                                    load_link_f64<N, T, R>(U, NU, op, xm.s >> 1, g.Vh));
+    const Mat<N, double> b = mul_nd(a, load_link_f64<N, T, R>(U, MU, op, xn.s >> 1, g.Vh));
+    const Mat<N, double> un = load_link_f64<N, T, R>(U, NU, par, h, g.Vh);
     // ReTr(b un^dag) = sum_ij Re(b_ij conj(un_ij))
     double t = 0.0;
 SUN_MAT_UNROLL
@@ -561,7 +561,7 @@ SUN_MAT_UNROLL
 // Sums ReTr P over the planes of logical site s into acc = {planes without
 // direction 3, planes with direction 3}.  Work-items follow the logical site
 // order, so the +mu neighbours a site reads are a few work-items away.
-template <int N, typename T>
+template <int N, typename T, int R>
 __device__ __forceinline__ void plaquette_site(const T2<T>* __restrict__ U, const Geom& g, int s, double (&acc)[2]) {
     if (s >= g.V) return;
     const int q0 = s / g.L[0], x0 = s - q0 * g.L[0];
@@ -572,7 +572,7 @@ __device__ __forceinline__ void plaquette_site(const T2<T>* __restrict__ U, cons
     const Site x = site_of(g, par, h);
     const int p = g.present;
 #define SUN_PLAQ(m, n, slot) \
-    if (((p >> m) & 1) && ((p >> n) & 1)) acc[slot] += re_tr_plaq<N, T, m, n>(U, g, x, par, h);
+    if (((p >> m) & 1) && ((p >> n) & 1)) acc[slot] += re_tr_plaq<N, T, R, m, n>(U, g, x, par, h);
     SUN_PLAQ(0, 1, 0)
     SUN_PLAQ(0, 2, 0)
     SUN_PLAQ(1, 2, 0)
@@ -582,24 +582,24 @@ __device__ __forceinline__ void plaquette_site(const T2<T>* __restrict__ U, cons
 #undef SUN_PLAQ
 }
 
-template <int N, typename T>
+template <int N, typename T, int R>
 __global__ __launch_bounds__(kBlock) void k_plaquette(const T2<T>* __restrict__ U, Geom g,
                                                       double* __restrict__ partial) {
     const int tile = xcd_tile(blockIdx.x, gridDim.x);
     double acc[2] = {0.0, 0.0};
-    plaquette_site<N, T>(U, g, tile * kBlock + threadIdx.x, acc);
+    plaquette_site<N, T, R>(U, g, tile * kBlock + threadIdx.x, acc);
     block_sum<2>(acc, partial + 2 * (size_t)tile);
 }
 
 // Batched plaquette: each chain's per-tile partials go to that chain's own
 // scratch at the same index the single-lattice kernel uses.
-template <int N, typename T>
+template <int N, typename T, int R>
 __global__ __launch_bounds__(kBlock) void k_plaquette_batch(const ChainDesc* __restrict__ d, int n) {
     const int tile = xcd_tile(blockIdx.x, gridDim.x);
     const int c = find_chain<TILE_SITE>(d, n, tile);
     const int local = tile - d[c].tile0[TILE_SITE];
     double acc[2] = {0.0, 0.0};
-    plaquette_site<N, T>((const T2<T>*)d[c].links, d[c].g, local * kBlock + threadIdx.x, acc);
+    plaquette_site<N, T, R>((const T2<T>*)d[c].links, d[c].g, local * kBlock + threadIdx.x, acc);
     block_sum<2>(acc, d[c].scratch + 2 * (size_t)local);
 }
 
@@ -662,7 +662,7 @@ __global__ __launch_bounds__(kBlock) void k_plaquette_final_batch(const ChainDes
 // ---------------------------------------------------------------------------
 // Polyakov loop along direction 3, FP64.
 // ---------------------------------------------------------------------------
-template <int N, typename T>
+template <int N, typename T, int R>
 __global__ __launch_bounds__(kBlock) void k_polyakov(const T2<T>* __restrict__ U, Geom g,
                                                      double* __restrict__ partial) {
     const int xs = blockIdx.x * kBlock + threadIdx.x;
@@ -682,7 +682,7 @@ __global__ __launch_bounds__(kBlock) void k_polyakov(const T2<T>* __restrict__ U
                 r = q;
             }
             st.s = s;
-            P = mul_nn(P, load_link_f64<N, T>(U, 3, parity_of(st), s >> 1, g.Vh));
+            P = mul_nn(P, load_link_f64<N, T, R>(U, 3, parity_of(st), s >> 1, g.Vh));
         }
 SUN_MAT_UNROLL
         for (int i = 0; i < N; ++i) {
@@ -697,7 +697,7 @@ SUN_MAT_UNROLL
 // Start configuration (paper Sec. 3): identity, or Haar links from a complex
 // Gaussian matrix (Box-Muller on Philox uniforms) re-unitarized in FP64.
 // ---------------------------------------------------------------------------
-template <int N, typename T>
+template <int N, typename T, int R>
 __global__ __launch_bounds__(kBlock) void k_init(T2<T>* __restrict__ U, Geom g, int hot, uint32_t k0,
                                                  uint32_t k1) {
     const int id = blockIdx.x * kBlock + threadIdx.x;
@@ -729,19 +729,19 @@ SUN_MAT_UNROLL
         }
         reunit<N>(M);
     }
-    store_link_from_f64<N, T>(U, l.mu, l.par, l.h, g.Vh, M);
+    store_link_from_f64<N, T, R>(U, l.mu, l.par, l.h, g.Vh, M);
 }
 
 // ---------------------------------------------------------------------------
 // Canonical FP64 field <-> SoA storage.
 // ---------------------------------------------------------------------------
-template <int N, typename T>
+template <int N, typename T, int R>
 __global__ __launch_bounds__(kBlock) void k_export(const T2<T>* __restrict__ U, Geom g, double* __restrict__ out) {
     const int id = blockIdx.x * kBlock + threadIdx.x;
     if (id >= 4 * g.V) return;
     const LinkId l = link_of(g, id);
     const int s = site_of(g, l.par, l.h).s;
-    const Mat<N, double> M = load_link_f64<N, T>(U, l.mu, l.par, l.h, g.Vh);
+    const Mat<N, double> M = load_link_f64<N, T, R>(U, l.mu, l.par, l.h, g.Vh);
     double* o = out + ((size_t)l.mu * g.V + s) * (2 * N * N);
 SUN_MAT_UNROLL
     for (int e = 0; e < N * N; ++e) {
@@ -750,7 +750,7 @@ SUN_MAT_UNROLL
     }
 }
 
-template <int N, typename T>
+template <int N, typename T, int R>
 __global__ __launch_bounds__(kBlock) void k_import(T2<T>* __restrict__ U, Geom g, const double* __restrict__ in) {
     const int id = blockIdx.x * kBlock + threadIdx.x;
     if (id >= 4 * g.V) return;
@@ -763,7 +763,7 @@ SUN_MAT_UNROLL
         M.re[e / N][e % N] = p[2 * e];
         M.im[e / N][e % N] = p[2 * e + 1];
     }
-    store_link_from_f64<N, T>(U, l.mu, l.par, l.h, g.Vh, M);
+    store_link_from_f64<N, T, R>(U, l.mu, l.par, l.h, g.Vh, M);
 }
 
 // ---------------------------------------------------------------------------

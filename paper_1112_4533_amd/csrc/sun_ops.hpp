@@ -58,6 +58,7 @@ const Ops* ops_nc5(int f64);
 const Ops* ops_nc6(int f64);
 const Ops* ops_nc7(int f64);
 const Ops* ops_nc8(int f64);
+const Ops* ops_nc3_two_row(int f64);  // SU(3), rows 0 and 1 stored
 
 void launch_finalize_max2(const double* partial, int nblk, double* out, hipStream_t s);
 void launch_finalize_sum2(const double* partial, int nblk, double* out, double scale, hipStream_t s);

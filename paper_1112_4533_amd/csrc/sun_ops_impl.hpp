@@ -6,7 +6,7 @@
 
 namespace sun {
 
-template <int N, typename T>
+template <int N, typename T, int R>
 struct OpsImpl {
     using P = T2<T>;
 
@@ -15,15 +15,15 @@ struct OpsImpl {
         P* u = (P*)c.links;
         switch (c.block) {
             case 64:
-                k_update<N, T, HB, MU, 64><<<half_blocks(c.g, 64), 64, 0, c.stream>>>(u, c.g, par, beta, k0, k1, step,
+                k_update<N, T, R, HB, MU, 64><<<half_blocks(c.g, 64), 64, 0, c.stream>>>(u, c.g, par, beta, k0, k1, step,
                                                                                       c.xcd);
                 break;
             case 128:
-                k_update<N, T, HB, MU, 128><<<half_blocks(c.g, 128), 128, 0, c.stream>>>(u, c.g, par, beta, k0, k1,
+                k_update<N, T, R, HB, MU, 128><<<half_blocks(c.g, 128), 128, 0, c.stream>>>(u, c.g, par, beta, k0, k1,
                                                                                          step, c.xcd);
                 break;
             default:
-                k_update<N, T, HB, MU, 256><<<half_blocks(c.g, 256), 256, 0, c.stream>>>(u, c.g, par, beta, k0, k1,
+                k_update<N, T, R, HB, MU, 256><<<half_blocks(c.g, 256), 256, 0, c.stream>>>(u, c.g, par, beta, k0, k1,
                                                                                          step, c.xcd);
                 break;
         }
@@ -33,10 +33,10 @@ struct OpsImpl {
     static void update_batch_bs(const ChainDesc* d, int n, int tiles, int mu, int par, uint32_t off, int xcd,
                                 hipStream_t s) {
         switch (mu) {
-            case 0: k_update_batch<N, T, HB, 0, BS><<<tiles, BS, 0, s>>>(d, n, par, off, xcd); break;
-            case 1: k_update_batch<N, T, HB, 1, BS><<<tiles, BS, 0, s>>>(d, n, par, off, xcd); break;
-            case 2: k_update_batch<N, T, HB, 2, BS><<<tiles, BS, 0, s>>>(d, n, par, off, xcd); break;
-            default: k_update_batch<N, T, HB, 3, BS><<<tiles, BS, 0, s>>>(d, n, par, off, xcd); break;
+            case 0: k_update_batch<N, T, R, HB, 0, BS><<<tiles, BS, 0, s>>>(d, n, par, off, xcd); break;
+            case 1: k_update_batch<N, T, R, HB, 1, BS><<<tiles, BS, 0, s>>>(d, n, par, off, xcd); break;
+            case 2: k_update_batch<N, T, R, HB, 2, BS><<<tiles, BS, 0, s>>>(d, n, par, off, xcd); break;
+            default: k_update_batch<N, T, R, HB, 3, BS><<<tiles, BS, 0, s>>>(d, n, par, off, xcd); break;
         }
     }
 
@@ -59,11 +59,11 @@ struct OpsImpl {
     }
 
     static void reunit_batch(const ChainDesc* d, int n, int tiles, hipStream_t s) {
-        k_reunit_batch<N, T><<<tiles, kBlock, 0, s>>>(d, n);
+        k_reunit_batch<N, T, R><<<tiles, kBlock, 0, s>>>(d, n);
     }
 
     static void plaquette_batch(const ChainDesc* d, int n, int tiles, double* out, hipStream_t s) {
-        k_plaquette_batch<N, T><<<tiles, kBlock, 0, s>>>(d, n);
+        k_plaquette_batch<N, T, R><<<tiles, kBlock, 0, s>>>(d, n);
         k_plaquette_final_batch<N><<<n, kBlock, 0, s>>>(d, n, out);
     }
 
@@ -86,28 +86,28 @@ struct OpsImpl {
     }
 
     static void init(const Ctx& c, int hot, uint32_t k0, uint32_t k1) {
-        k_init<N, T><<<link_blocks(c.g), kBlock, 0, c.stream>>>((P*)c.links, c.g, hot, k0, k1);
+        k_init<N, T, R><<<link_blocks(c.g), kBlock, 0, c.stream>>>((P*)c.links, c.g, hot, k0, k1);
     }
     static void reunit(const Ctx& c, double* partial) {
         if (partial)
-            k_reunit<N, T, true><<<link_blocks(c.g), kBlock, 0, c.stream>>>((P*)c.links, c.g, partial);
+            k_reunit<N, T, R, true><<<link_blocks(c.g), kBlock, 0, c.stream>>>((P*)c.links, c.g, partial);
         else
-            k_reunit<N, T, false><<<link_blocks(c.g), kBlock, 0, c.stream>>>((P*)c.links, c.g, nullptr);
+            k_reunit<N, T, R, false><<<link_blocks(c.g), kBlock, 0, c.stream>>>((P*)c.links, c.g, nullptr);
     }
     static void unitarity(const Ctx& c, double* partial) {
-        k_unitarity<N, T><<<link_blocks(c.g), kBlock, 0, c.stream>>>((const P*)c.links, c.g, partial);
+        k_unitarity<N, T, R><<<link_blocks(c.g), kBlock, 0, c.stream>>>((const P*)c.links, c.g, partial);
     }
     static void plaquette(const Ctx& c, double* partial) {
-        k_plaquette<N, T><<<site_blocks(c.g), kBlock, 0, c.stream>>>((const P*)c.links, c.g, partial);
+        k_plaquette<N, T, R><<<site_blocks(c.g), kBlock, 0, c.stream>>>((const P*)c.links, c.g, partial);
     }
     static void polyakov(const Ctx& c, double* partial) {
-        k_polyakov<N, T><<<spatial_blocks(c.g), kBlock, 0, c.stream>>>((const P*)c.links, c.g, partial);
+        k_polyakov<N, T, R><<<spatial_blocks(c.g), kBlock, 0, c.stream>>>((const P*)c.links, c.g, partial);
     }
     static void export_field(const Ctx& c, double* out) {
-        k_export<N, T><<<link_blocks(c.g), kBlock, 0, c.stream>>>((const P*)c.links, c.g, out);
+        k_export<N, T, R><<<link_blocks(c.g), kBlock, 0, c.stream>>>((const P*)c.links, c.g, out);
     }
     static void import_field(const Ctx& c, const double* in) {
-        k_import<N, T><<<link_blocks(c.g), kBlock, 0, c.stream>>>((P*)c.links, c.g, in);
+        k_import<N, T, R><<<link_blocks(c.g), kBlock, 0, c.stream>>>((P*)c.links, c.g, in);
     }
 
     static const Ops* table() {
@@ -123,6 +123,14 @@ struct OpsImpl {
 #define SUN_DEFINE_OPS(NC)                                                     \
     namespace sun {                                                            \
     const Ops* ops_nc##NC(int f64) {                                           \
-        return f64 ? OpsImpl<NC, double>::table() : OpsImpl<NC, float>::table(); \
+        return f64 ? OpsImpl<NC, double, NC>::table() : OpsImpl<NC, float, NC>::table(); \
     }                                                                          \
+    }
+
+// SU(3) with two stored rows (12 reals per link); row 2 = conj(row0 x row1).
+#define SUN_DEFINE_OPS_TWO_ROW()                                                \
+    namespace sun {                                                             \
+    const Ops* ops_nc3_two_row(int f64) {                                       \
+        return f64 ? OpsImpl<3, double, 2>::table() : OpsImpl<3, float, 2>::table(); \
+    }                                                                           \
     }

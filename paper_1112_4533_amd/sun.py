@@ -13,7 +13,8 @@ import torch
 _PKG = os.path.dirname(os.path.abspath(__file__))
 LIB_PATH = os.path.join(_PKG, "_lib", "libsun.so")
 
-F32, F64 = 0, 1
+F32, F64, F32_TWO_ROW, F64_TWO_ROW = 0, 1, 2, 3
+DTYPE_NAMES = {F32: "f32", F64: "f64", F32_TWO_ROW: "f32r12", F64_TWO_ROW: "f64r12"}
 HEATBATH, OVERRELAX = 0, 1
 KERNEL_IDS = {"heatbath": 0, "overrelax": 1, "reunit": 2, "plaquette": 3, "polyakov": 4}
 SUN_OK = 0
@@ -107,10 +108,18 @@ def _ptr(t):
 
 
 def _dtype_code(dtype):
-    if dtype in ("f32", "float32", torch.float32, F32):
+    """Link storage: "f32", "f64", or the SU(3) two-row forms "f32r12",
+    "f64r12" (also the integer codes)."""
+    if isinstance(dtype, int) and dtype in DTYPE_NAMES:
+        return dtype
+    if dtype in ("f32", "float32", torch.float32):
         return F32
-    if dtype in ("f64", "float64", torch.float64, F64):
+    if dtype in ("f64", "float64", torch.float64):
         return F64
+    if dtype == "f32r12":
+        return F32_TWO_ROW
+    if dtype == "f64r12":
+        return F64_TWO_ROW
     raise ValueError(f"unknown link dtype {dtype!r}")
 
 

@@ -40,6 +40,8 @@ SU3_16_HOT = Run("su3_16^4_hot_f32", 3, (16, 16, 16, 16), 6.0, True, "f32", 1, 4
 # SU(3) 32^4, beta 6.2, hot start, 1 HB + 4 OR, 100 sweeps, FP32 and FP64.
 SU3_32_F32 = Run("su3_32^4_hot_f32", 3, (32, 32, 32, 32), 6.2, True, "f32", 1, 4, 100)
 SU3_32_F64 = Run("su3_32^4_hot_f64", 3, (32, 32, 32, 32), 6.2, True, "f64", 1, 4, 100)
+# The same with SU(3) links stored as two rows (12 reals, FP32).
+SU3_32_F32_TWO_ROW = Run("su3_32^4_hot_f32_two_row", 3, (32, 32, 32, 32), 6.2, True, "f32r12", 1, 4, 100)
 
 
 def large_nc_runs(dtype="f32"):

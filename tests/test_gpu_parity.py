@@ -28,7 +28,7 @@ from stats import binned_mean_err
 
 pytestmark = pytest.mark.gpu
 
-TOL = {"f64": 1e-12, "f32": 1e-5}
+TOL = {"f64": 1e-12, "f32": 1e-5, "f64r12": 1e-12, "f32r12": 1e-5}
 FLIP_MARGIN = 1e-4
 
 
@@ -62,14 +62,14 @@ def compare_links(gpu_field, orc_field, dtype, margin=None, cond=None, what=""):
     scale = np.ones_like(d)
     if cond is not None:
         c = np.asarray(cond, dtype=np.float64)
-        scale = np.maximum(1.0, np.where(c > 0, c, 0.0) / (4.0 if dtype == "f64" else 2.0))
+        scale = np.maximum(1.0, np.where(c > 0, c, 0.0) / (2.0 if dtype.startswith("f32") else 4.0))
         ratio = d / (TOL[dtype] * scale)
         print(f"{what}: max |dU| {d.max():.2e}, max |dU| / tol {ratio.max():.3f}")
     bad = d > TOL[dtype] * scale
     if not bad.any():
         return 0
     idx = np.argwhere(bad)
-    if dtype == "f64" or margin is None:
+    if dtype.startswith("f64") or margin is None:
         mu, s = idx[0]
         raise AssertionError(f"{what}: {len(idx)} links out of tolerance, e.g. (mu={mu}, s={s}) "
                              f"|dU| = {d[mu, s]:.3e}, tol {TOL[dtype] * scale[mu, s]:.2e}")
@@ -128,15 +128,15 @@ def test_sampler_empty_input(gpu):
 # ---------------------------------------------------------------------------
 # Start configurations and the field round trip
 # ---------------------------------------------------------------------------
-@pytest.mark.parametrize("nc", [2, 3, 4, 5, 6, 8])
-@pytest.mark.parametrize("dtype", ["f64", "f32"])
+@pytest.mark.parametrize("nc,dtype", [(n, d) for n in (2, 3, 4, 5, 6, 8) for d in ("f64", "f32")]
+                         + [(3, "f64r12"), (3, "f32r12")])
 def test_hot_start_parity(gpu, nc, dtype):
     L = (4, 4, 2, 6)
     lat = gpu_lattice(gpu, nc, L, dtype, hot=True, seed=1234)
     got = to_np(lat.export())
     want = O.new_field(nc, L, hot=True, seed=1234)
     # one Gram-Schmidt pass over a Gaussian matrix: rounding ~ cond(M) * eps
-    tol = 1e-12 if dtype == "f64" else 1e-6
+    tol = 1e-12 if dtype.startswith("f64") else 1e-6
     assert np.abs(got - want).max() < tol
 
 
@@ -162,12 +162,12 @@ def test_export_import_roundtrip(gpu, nc):
 # ---------------------------------------------------------------------------
 # Observables on one and the same field
 # ---------------------------------------------------------------------------
-@pytest.mark.parametrize("nc", [2, 3, 4, 6, 8])
-@pytest.mark.parametrize("dtype", ["f64", "f32"])
+@pytest.mark.parametrize("nc,dtype", [(n, d) for n in (2, 3, 4, 6, 8) for d in ("f64", "f32")]
+                         + [(3, "f64r12"), (3, "f32r12")])
 def test_observables_parity(gpu, nc, dtype):
     L = (6, 4, 4, 8)      # V/2 = 384: a ragged second block
-    U = rounded(thermal_field(nc, L, BETA[nc]), dtype)
-    lat = gpu_lattice(gpu, nc, L, dtype, field=U)
+    lat = gpu_lattice(gpu, nc, L, dtype, field=thermal_field(nc, L, BETA[nc]))
+    U = to_np(lat.export())                 # the field as the GPU stores it
     np.testing.assert_allclose(to_np(lat.plaquette()), O.plaquette(U, nc, L), rtol=1e-13, atol=1e-15)
     pg = to_np(lat.polyakov())
     po = O.polyakov(U, nc, L)
@@ -198,20 +198,22 @@ def test_reunitarize_parity(gpu, nc):
 # Single checkerboard phases (links within a phase are independent, so a
 # phase compares every link without cascades)
 # ---------------------------------------------------------------------------
-@pytest.mark.parametrize("nc", [2, 3, 4, 6])
-@pytest.mark.parametrize("dtype", ["f64", "f32"])
+PHASE_CASES = [(nc, dt) for nc in (2, 3, 4, 6) for dt in ("f64", "f32")] + [(3, "f64r12"), (3, "f32r12")]
+
+
+@pytest.mark.parametrize("nc,dtype", PHASE_CASES)
 @pytest.mark.parametrize("kind", [0, 1])
 def test_phase_parity(gpu, nc, dtype, kind):
     L = (6, 4, 4, 8)
     beta = BETA[nc]
-    base = rounded(thermal_field(nc, L, beta), dtype)
+    base = thermal_field(nc, L, beta)
     flips = 0
     for mu in range(4):
         for par in range(2):
             lat = gpu_lattice(gpu, nc, L, dtype, field=base)
+            want = to_np(lat.export())          # the field as the GPU stores it
             lat.phase(kind, mu, par, beta, seed=99, step=7)
             got = to_np(lat.export())
-            want = base.copy()
             m, k = oracle_phase_diag(want, nc, L, kind, mu, par, beta, 99, 7)
             flips += compare_links(got, want, dtype, m, k, f"nc={nc} {dtype} kind={kind} mu={mu} p={par}")
     print(f"flips: {flips}")
@@ -267,7 +269,8 @@ def test_sweep_is_its_phase_sequence_bitwise(gpu, nc, dtype, n_hb, n_or):
 
 
 @pytest.mark.parametrize("nc,dtype,hot", [(2, "f64", False), (3, "f64", True), (4, "f64", True),
-                                          (3, "f32", True), (2, "f32", True)])
+                                          (3, "f32", True), (2, "f32", True), (3, "f32r12", True),
+                                          (3, "f64r12", True)])
 def test_sweep_trajectory_parity_phase_by_phase(gpu, nc, dtype, hot):
     """Two sweeps (1 HB + 2 OR) from a start configuration, every phase and
     the re-unitarization compared with the oracle applied to the GPU's own
@@ -383,9 +386,10 @@ def test_2d_su2_exact_plaquette_on_gpu(gpu):
 # ---------------------------------------------------------------------------
 # Full size, launch configuration of the benchmark (SU(3) 32^4 FP32)
 # ---------------------------------------------------------------------------
-def test_full_size_su3_32_phase_parity(gpu):
+@pytest.mark.parametrize("dtype", ["f32", "f32r12"])
+def test_full_size_su3_32_phase_parity(gpu, dtype):
     nc, L, beta = 3, (32, 32, 32, 32), 6.2
-    lat = gpu_lattice(gpu, nc, L, "f32", hot=True, seed=1234)
+    lat = gpu_lattice(gpu, nc, L, dtype, hot=True, seed=1234)
     base = to_np(lat.export())
     want = O.new_field(nc, L, hot=True, seed=1234)
     assert np.abs(base - want).max() < 1e-6
@@ -395,7 +399,7 @@ def test_full_size_su3_32_phase_parity(gpu):
     m2, k2 = oracle_phase_diag(base, nc, L, 0, 2, 0, beta, 1234, 0)
     m3, k3 = oracle_phase_diag(base, nc, L, 1, 3, 1, beta, 1234, 0)
     m2[3], k2[3] = m3[3], k3[3]
-    flips = compare_links(got, base, "f32", m2, k2, "32^4")
+    flips = compare_links(got, base, dtype, m2, k2, "32^4")
     print(f"32^4 flips: {flips}")
     np.testing.assert_allclose(to_np(lat.plaquette()), O.plaquette(base, nc, L), atol=2e-6)
 
