@@ -44,12 +44,14 @@ def step_bytes(nc, V, dtype, n_hb, n_or):
     return 8 * (n_hb + n_or) * phase_bytes(nc, V, dtype) + (8 * V + 4 * V + V) * lb
 
 
-def run_gpu(run, steps, warmup):
+def run_gpu(run, steps, warmup, tune=True):
     import torch
-    from paper_1112_4533_amd import sun
+    from paper_1112_4533_amd import autotune, sun
 
     lat = sun.Lattice(run.nc, run.L, run.dtype)
     lat.init(hot=run.hot, seed=run.seed)
+    if tune:
+        autotune.tune_lattice(lat, reps=3, use_cache=False)
     dev = lat.links.device
     plaq = torch.zeros(3, dtype=torch.float64, device=dev)
     poly = torch.zeros(2, dtype=torch.float64, device=dev)
@@ -88,6 +90,7 @@ def run_gpu(run, steps, warmup):
         "polyakov": poly.cpu().tolist(),
         "unitarity_before_reunit": drift.cpu().tolist(),
         "step_counter": lat.step,
+        "launch": {"heatbath": lat.get_launch(sun.HEATBATH), "overrelax": lat.get_launch(sun.OVERRELAX)},
     }
 
 
@@ -110,6 +113,8 @@ def run_batch(steps, warmup, f64_sweeps):
         lat.init(hot=True, seed=r.seed)
         lats.append(lat)
     bt = sun.Batch(lats, [r.beta for r in spec], [r.seed for r in spec])
+    from paper_1112_4533_amd import autotune
+    autotune.tune_batch(bt, reps=2, use_cache=False)
     plaq32 = torch.zeros((len(spec), 3), dtype=torch.float64, device="cuda")
     bt.capture(n_sweeps=1, n_hb=n_hb, n_or=n_or, reunit=True, plaq_out=plaq32)
     for _ in range(warmup):
@@ -151,7 +156,7 @@ def run_batch(steps, warmup, f64_sweeps):
     return {
         "chains": len(spec), "sites": total_sites,
         "fp32_batched_graph": {"value": upd32, "unit": "link_updates/s", "ms_per_sweep": 1e3 * dt32 / steps,
-                               "sweeps": steps},
+                               "sweeps": steps, "launch": {"heatbath": bt.launch[0], "overrelax": bt.launch[1]}},
         "fp64_per_chain_eager": {"value": upd64, "unit": "link_updates/s", "ms_per_sweep": 1e3 * dt64 / f64_sweeps,
                                  "sweeps": f64_sweeps},
         "speedup": upd32 / upd64,
@@ -255,6 +260,7 @@ def main():
         },
         "effective_GBps_whole_step": step_bytes(run.nc, V, run.dtype, run.n_hb, run.n_or) / (r32["ms_per_step"] * 1e-3) / 1e9,
         "kernels": r32["kernels"],
+        "launch": r32["launch"],
         "accuracy": {
             "plaquette": r32["plaquette"],
             "polyakov": r32["polyakov"],

@@ -128,12 +128,16 @@ int sun_import(sun_lattice_t h, const double *dev_canonical, sun_stream_t stream
 int sun_get_step(sun_lattice_t h, uint64_t *step);
 int sun_set_step(sun_lattice_t h, uint64_t step);
 
-/* Launch shape of the phase kernels: block work-items per workgroup (64,
- * 128 or 256; default 256) and the XCD-aware workgroup order (1, default) or
- * the plain order (0).  A tuning choice only: results are bitwise the same
- * for every shape. */
-int sun_set_launch(sun_lattice_t h, int block, int xcd);
-int sun_get_launch(sun_lattice_t h, int *block, int *xcd);
+/* Launch shape of the phase kernels of one update kind (SUN_HEATBATH,
+ * SUN_OVERRELAX, or -1 for both): block work-items per workgroup (64, 128 or
+ * 256), the XCD-aware workgroup order (1) or the plain order (0), and a cap
+ * on resident waves per CU (8, 12, 16, or 0 for none) enforced through the
+ * workgroups' LDS allocation: a phase's per-XCD working set exceeds the L2,
+ * so fewer resident waves raise the L2 hit rate.  Defaults: heatbath
+ * (256, 1, 0), overrelaxation (256, 1, 12).  A tuning choice only: results
+ * are bitwise the same for every shape. */
+int sun_set_launch(sun_lattice_t h, int kind, int block, int xcd, int waves);
+int sun_get_launch(sun_lattice_t h, int kind, int *block, int *xcd, int *waves);
 
 /* Per-kernel timing with HIP events recorded around each launch on the
  * launch stream.  kernel: 0 heatbath phase, 1 overrelaxation phase,
@@ -189,7 +193,7 @@ int sun_batch_replay(sun_batch_t b, sun_stream_t stream);
 
 /* Launch shape of the batch's phase kernels (as sun_set_launch).  Waits for
  * the device, rewrites the table, and drops any captured graph. */
-int sun_batch_set_launch(sun_batch_t b, int block, int xcd);
+int sun_batch_set_launch(sun_batch_t b, int kind, int block, int xcd, int waves);
 
 /* Writes the chains' advanced RNG step counters back to their handles. */
 int sun_batch_sync(sun_batch_t b);

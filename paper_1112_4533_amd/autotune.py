@@ -1,13 +1,16 @@
 """Launch-shape autotuner for the phase kernels.
 
-The phase kernels come in workgroup sizes of 64, 128 and 256 work-items and
-with the XCD-aware or the plain workgroup order.  Every shape computes the
-same bits, so the choice is a pure speed question; it depends on the lattice
-size (a small lattice needs small workgroups to occupy 256 CUs, a large one
-needs the XCD-aware order for L2 reuse).  The tuner times overrelaxation
-steps on a clone of the field (the chain itself is never touched), keeps the
-fastest shape, applies it, and remembers it in a JSON cache keyed by GPU
-architecture, Nc, extents and precision (or by the chain list of a batch).
+The phase kernels come in workgroup sizes of 64, 128 and 256 work-items, with
+the XCD-aware or the plain workgroup order, and with a cap of 8, 12, 16 or no
+limit on resident waves per CU.  Every shape computes the same bits, so the
+choice is a pure speed question, made separately for the heatbath and the
+overrelaxation kernels (the heatbath draws cost arithmetic, so it prefers
+more resident waves).  It depends on the lattice: a small lattice needs small
+workgroups to occupy 256 CUs, a large one the XCD-aware order and a wave cap
+for L2 reuse.  The tuner times heatbath-only and overrelaxation-only steps on
+a clone of the field (the chain itself is never touched), applies the
+fastest shape of each kind, and remembers the choice in a JSON cache keyed
+by GPU architecture, Nc, extents and storage (or by the chain list of a batch).
 """
 import json
 import os
@@ -55,32 +58,44 @@ def _time(fn, reps):
     return a.elapsed_time(b) / reps
 
 
+def _search(set_shape, step_hb, step_or, reps):
+    """Times every shape for each kind; returns ({kind: best shape}, timings)."""
+    best, times = {}, {}
+    for kind, step in ((sun.HEATBATH, step_hb), (sun.OVERRELAX, step_or)):
+        t = {}
+        for shape in sun.Lattice.LAUNCH_SHAPES:
+            set_shape(shape, kind)
+            t["/".join(map(str, shape))] = _time(step, reps)
+        key = min(t, key=t.get)
+        best[kind] = tuple(int(v) for v in key.split("/"))
+        times["heatbath" if kind == sun.HEATBATH else "overrelax"] = t
+    return best, times
+
+
 def lattice_key(lat):
     return f"{_arch()}:su{lat.nc}:{'x'.join(map(str, lat.L))}:{sun.DTYPE_NAMES[lat.dtype]}"
 
 
 def tune_lattice(lat, reps=5, use_cache=True):
-    """Picks and applies the fastest launch shape for `lat`; returns
-    (block, xcd, {shape: ms per overrelaxation step})."""
+    """Picks and applies the fastest launch shape of each update kind for
+    `lat`; returns ({kind: (block, xcd, waves)}, timings in ms per step)."""
     key = lattice_key(lat)
     cache = _load_cache() if use_cache else {}
     if key in cache:
-        block, xcd = cache[key]["block"], cache[key]["xcd"]
-        lat.set_launch(block, xcd)
-        return block, xcd, cache[key].get("ms", {})
+        best = {int(k): tuple(v) for k, v in cache[key]["shape"].items()}
+        for kind, shape in best.items():
+            lat.set_launch(*shape, kind=kind)
+        return best, cache[key].get("ms", {})
     clone = sun.Lattice(lat.nc, lat.L, lat.dtype, device=lat.links.device)
     clone.links.copy_(lat.links)
-    times = {}
-    for block, xcd in sun.Lattice.LAUNCH_SHAPES:
-        clone.set_launch(block, xcd)
-        times[f"{block}/{xcd}"] = _time(lambda: clone.sweep(1.0, 0, 1, seed=0, reunit=False), reps)
-    best = min(times, key=times.get)
-    block, xcd = (int(v) for v in best.split("/"))
-    lat.set_launch(block, xcd)
-    cache[key] = {"block": block, "xcd": xcd, "ms": times}
+    best, times = _search(lambda shape, kind: clone.set_launch(*shape, kind=kind),
+                          lambda: clone.phase_step(sun.HEATBATH), lambda: clone.phase_step(sun.OVERRELAX), reps)
+    for kind, shape in best.items():
+        lat.set_launch(*shape, kind=kind)
+    cache[key] = {"shape": {str(k): list(v) for k, v in best.items()}, "ms": times}
     if use_cache:
         _save_cache(cache)
-    return block, xcd, times
+    return best, times
 
 
 def batch_key(batch):
@@ -89,27 +104,26 @@ def batch_key(batch):
 
 
 def tune_batch(batch, reps=3, use_cache=True):
-    """Picks and applies the fastest launch shape for a batch (timed on a
-    clone of its chains); drops the batch's captured graph."""
+    """As tune_lattice for a batch (timed on a clone of its chains); drops
+    the batch's captured graph."""
     key = batch_key(batch)
     cache = _load_cache() if use_cache else {}
     if key in cache:
-        batch.set_launch(cache[key]["block"], cache[key]["xcd"])
-        return cache[key]["block"], cache[key]["xcd"], cache[key].get("ms", {})
+        best = {int(k): tuple(v) for k, v in cache[key]["shape"].items()}
+        for kind, shape in best.items():
+            batch.set_launch(*shape, kind=kind)
+        return best, cache[key].get("ms", {})
     clones = []
     for l in batch.lattices:
         c = sun.Lattice(l.nc, l.L, l.dtype, device=l.links.device)
         c.links.copy_(l.links)
         clones.append(c)
     cb = sun.Batch(clones, batch.betas, batch.seeds)
-    times = {}
-    for block, xcd in sun.Lattice.LAUNCH_SHAPES:
-        cb.set_launch(block, xcd)
-        times[f"{block}/{xcd}"] = _time(lambda: cb.sweep(0, 1, reunit=False), reps)
-    best = min(times, key=times.get)
-    block, xcd = (int(v) for v in best.split("/"))
-    batch.set_launch(block, xcd)
-    cache[key] = {"block": block, "xcd": xcd, "ms": times}
+    best, times = _search(lambda shape, kind: cb.set_launch(*shape, kind=kind),
+                          lambda: cb.sweep(1, 0, reunit=False), lambda: cb.sweep(0, 1, reunit=False), reps)
+    for kind, shape in best.items():
+        batch.set_launch(*shape, kind=kind)
+    cache[key] = {"shape": {str(k): list(v) for k, v in best.items()}, "ms": times}
     if use_cache:
         _save_cache(cache)
-    return block, xcd, times
+    return best, times

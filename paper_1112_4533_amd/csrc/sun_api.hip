@@ -59,11 +59,10 @@ struct sun_lattice_s {
     std::vector<hipEvent_t> pool;
     double total_ms[kKernels] = {};
     int64_t launches[kKernels] = {};
-    // launch shape of the phase kernels (sun_set_launch)
-    int block = 256;
-    int xcd = 1;
+    // launch shapes of the phase kernels (sun_set_launch)
+    sun::Shape shape[2] = {sun::Shape{256, 1, 0}, sun::Shape{256, 1, 12}};
 
-    sun::Ctx ctx(hipStream_t s) const { return sun::Ctx{links, g, s, block, xcd}; }
+    sun::Ctx ctx(hipStream_t s) const { return sun::Ctx{links, g, s, {shape[0], shape[1]}}; }
 };
 
 namespace {
@@ -131,6 +130,14 @@ size_t scratch_bytes_of(const sun::Geom& g) {
 }
 
 inline hipStream_t as_stream(sun_stream_t s) { return reinterpret_cast<hipStream_t>(s); }
+
+// kind: SUN_HEATBATH, SUN_OVERRELAX, or -1 for both.
+int check_shape(int kind, int block, int waves) {
+    if (kind < -1 || kind > 1) return fail(SUN_EINVAL, "kind %d is not -1, SUN_HEATBATH or SUN_OVERRELAX", kind);
+    if (!sun::valid_phase_block(block)) return fail(SUN_EINVAL, "block %d is not 64, 128 or 256", block);
+    if (!sun::valid_wave_cap(waves)) return fail(SUN_EINVAL, "wave cap %d is not 0, 8, 12 or 16", waves);
+    return SUN_OK;
+}
 
 // Records an event pair around one launch when profiling is on.
 struct Timed {
@@ -332,18 +339,20 @@ int sun_set_step(sun_lattice_t h, uint64_t step) {
     return SUN_OK;
 }
 
-int sun_set_launch(sun_lattice_t h, int block, int xcd) {
+int sun_set_launch(sun_lattice_t h, int kind, int block, int xcd, int waves) {
     if (!h) return fail(SUN_EINVAL, "null handle");
-    if (!sun::valid_phase_block(block)) return fail(SUN_EINVAL, "block %d is not 64, 128 or 256", block);
-    h->block = block;
-    h->xcd = xcd ? 1 : 0;
+    if (int rc = check_shape(kind, block, waves)) return rc;
+    for (int k = 0; k < 2; ++k)
+        if (kind < 0 || kind == k) h->shape[k] = sun::Shape{block, xcd ? 1 : 0, waves};
     return SUN_OK;
 }
 
-int sun_get_launch(sun_lattice_t h, int* block, int* xcd) {
-    if (!h || !block || !xcd) return fail(SUN_EINVAL, "null argument");
-    *block = h->block;
-    *xcd = h->xcd;
+int sun_get_launch(sun_lattice_t h, int kind, int* block, int* xcd, int* waves) {
+    if (!h || !block || !xcd || !waves) return fail(SUN_EINVAL, "null argument");
+    if (kind != SUN_HEATBATH && kind != SUN_OVERRELAX) return fail(SUN_EINVAL, "kind %d", kind);
+    *block = h->shape[kind].block;
+    *xcd = h->shape[kind].xcd;
+    *waves = h->shape[kind].waves;
     return SUN_OK;
 }
 
@@ -401,14 +410,13 @@ struct sun_batch_s {
     struct Group {
         const sun::Ops* ops;
         int first, count;      // range of the device table
-        int tiles[4];          // total tiles per grid kind
+        int tiles[5];          // total tiles per grid kind (see TileKind)
     };
     std::vector<sun_lattice_t> chains;  // in the caller's order
     std::vector<Group> groups;
     std::vector<sun::ChainDesc> host;   // host copy of the table
     sun::ChainDesc* table = nullptr;    // device
-    int block = 256;                    // launch shape of the phase kernels
-    int xcd = 1;
+    sun::Shape shape[2] = {sun::Shape{256, 1, 0}, sun::Shape{256, 1, 12}};  // per update kind
     uint64_t hb_steps_done = 0;         // heatbath steps run since creation (all chains alike)
     std::vector<uint64_t> step0;        // chain step counters at creation
     hipGraph_t graph = nullptr;
@@ -424,13 +432,14 @@ int batch_sweep_launches(sun_batch_t b, int n_hb, int n_or, int reunit, hipStrea
         for (int k = 0; k < n_hb; ++k)
             for (int mu = 0; mu < 4; ++mu)
                 for (int p = 0; p < 2; ++p)
-                    gr.ops->update_batch(d, gr.count, gr.tiles[0], SUN_HEATBATH, mu, p, (uint32_t)k, b->block, b->xcd,
-                                         s);
+                    gr.ops->update_batch(d, gr.count, gr.tiles[sun::TILE_HALF_HB], SUN_HEATBATH, mu, p, (uint32_t)k,
+                                         b->shape[SUN_HEATBATH], s);
         for (int k = 0; k < n_or; ++k)
             for (int mu = 0; mu < 4; ++mu)
                 for (int p = 0; p < 2; ++p)
-                    gr.ops->update_batch(d, gr.count, gr.tiles[0], SUN_OVERRELAX, mu, p, 0, b->block, b->xcd, s);
-        if (reunit) gr.ops->reunit_batch(d, gr.count, gr.tiles[2], s);
+                    gr.ops->update_batch(d, gr.count, gr.tiles[sun::TILE_HALF_OR], SUN_OVERRELAX, mu, p, 0,
+                                         b->shape[SUN_OVERRELAX], s);
+        if (reunit) gr.ops->reunit_batch(d, gr.count, gr.tiles[sun::TILE_LINK], s);
     }
     if (n_hb > 0) sun::launch_advance_steps(b->table, (int)b->chains.size(), n_hb, s);
     return launch_check("batch sweep");
@@ -440,16 +449,17 @@ int batch_sweep_launches(sun_batch_t b, int n_hb, int n_or, int reunit, hipStrea
 // tiles of the batch's block size) and uploads the table.  Synchronous.
 int upload_table(sun_batch_t b) {
     for (auto& gr : b->groups) {
-        int t[4] = {0, 0, 0, 0};
+        int t[5] = {0, 0, 0, 0, 0};
         for (int i = gr.first; i < gr.first + gr.count; ++i) {
             sun::ChainDesc& c = b->host[i];
-            for (int k = 0; k < 4; ++k) c.tile0[k] = t[k];
-            t[0] += sun::half_blocks(c.g, b->block);
-            t[1] += sun::site_blocks(c.g);
-            t[2] += sun::link_blocks(c.g);
-            t[3] += sun::spatial_blocks(c.g);
+            for (int k = 0; k < 5; ++k) c.tile0[k] = t[k];
+            t[sun::TILE_HALF_HB] += sun::half_blocks(c.g, b->shape[SUN_HEATBATH].block);
+            t[sun::TILE_SITE] += sun::site_blocks(c.g);
+            t[sun::TILE_LINK] += sun::link_blocks(c.g);
+            t[sun::TILE_SPATIAL] += sun::spatial_blocks(c.g);
+            t[sun::TILE_HALF_OR] += sun::half_blocks(c.g, b->shape[SUN_OVERRELAX].block);
         }
-        for (int k = 0; k < 4; ++k) gr.tiles[k] = t[k];
+        for (int k = 0; k < 5; ++k) gr.tiles[k] = t[k];
     }
     return hip_check(hipMemcpy(b->table, b->host.data(), sizeof(sun::ChainDesc) * b->host.size(),
                                hipMemcpyHostToDevice),
@@ -457,7 +467,8 @@ int upload_table(sun_batch_t b) {
 }
 
 int batch_plaquette_launches(sun_batch_t b, double* out, hipStream_t s) {
-    for (const auto& gr : b->groups) gr.ops->plaquette_batch(b->table + gr.first, gr.count, gr.tiles[1], out, s);
+    for (const auto& gr : b->groups)
+        gr.ops->plaquette_batch(b->table + gr.first, gr.count, gr.tiles[sun::TILE_SITE], out, s);
     return launch_check("batch plaquette");
 }
 
@@ -489,7 +500,7 @@ int sun_batch_create(int n, const sun_lattice_t* chains, const double* betas, co
     for (int nc = 2; nc <= SUN_NC_MAX; ++nc)
         for (int dt = SUN_F32; dt <= SUN_F64_TWO_ROW; ++dt) {
             if (is_two_row(dt) && nc != 3) continue;
-            sun_batch_s::Group gr{ops_for(nc, dt), (int)b->host.size(), 0, {0, 0, 0, 0}};
+            sun_batch_s::Group gr{ops_for(nc, dt), (int)b->host.size(), 0, {0, 0, 0, 0, 0}};
             for (int i = 0; i < n; ++i) {
                 const sun_lattice_t h = chains[i];
                 if (h->nc != nc || h->dtype != dt) continue;
@@ -574,15 +585,15 @@ int sun_batch_replay(sun_batch_t b, sun_stream_t stream) {
     return SUN_OK;
 }
 
-int sun_batch_set_launch(sun_batch_t b, int block, int xcd) {
+int sun_batch_set_launch(sun_batch_t b, int kind, int block, int xcd, int waves) {
     if (!b) return fail(SUN_EINVAL, "null batch");
-    if (!sun::valid_phase_block(block)) return fail(SUN_EINVAL, "block %d is not 64, 128 or 256", block);
+    if (int rc = check_shape(kind, block, waves)) return rc;
     // the table holds the device step counters: bring the host copy up to date first
     for (size_t i = 0; i < b->host.size(); ++i)
         b->host[i].step = b->step0[b->host[i].out_index] + b->hb_steps_done;
     if (int rc = hip_check(hipDeviceSynchronize(), "hipDeviceSynchronize")) return rc;
-    b->block = block;
-    b->xcd = xcd ? 1 : 0;
+    for (int k = 0; k < 2; ++k)
+        if (kind < 0 || kind == k) b->shape[k] = sun::Shape{block, xcd ? 1 : 0, waves};
     if (b->exec) {
         (void)hipGraphExecDestroy(b->exec);
         b->exec = nullptr;

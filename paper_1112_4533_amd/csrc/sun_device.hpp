@@ -68,7 +68,7 @@ struct Geom {
 
 // One chain of a batch (device-resident table entry): its field, its own
 // partials buffer, geometry, coupling, Philox key, RNG step counter, and the
-// first tile it occupies in batched grids over V/2, V, 4V and Vs items.
+// first tile it occupies in each batched grid.
 struct ChainDesc {
     void* links;
     double* scratch;     // the chain's own partials buffer
@@ -76,11 +76,12 @@ struct ChainDesc {
     double beta;
     uint32_t k0, k1;     // Philox key (seed)
     uint64_t step;       // RNG step counter
-    int tile0[4];        // first tile of the chain in grids over V/2, V, 4V and Vs items
+    int tile0[5];        // first tile of the chain in grids over V/2 (heatbath shape), V, 4V, Vs
+                         // and V/2 (overrelaxation shape) items
     int out_index;       // position of the chain in the caller's list (result slots)
 };
 
-enum TileKind { TILE_HALF = 0, TILE_SITE = 1, TILE_LINK = 2, TILE_SPATIAL = 3 };
+enum TileKind { TILE_HALF_HB = 0, TILE_SITE = 1, TILE_LINK = 2, TILE_SPATIAL = 3, TILE_HALF_OR = 4 };
 
 struct Site {
     int x[4];

@@ -9,13 +9,32 @@
 
 namespace sun {
 
+// Launch shape of a phase kernel.
+struct Shape {
+    int block = 256;  // work-items per workgroup (64, 128 or 256)
+    int xcd = 1;      // XCD-aware workgroup order
+    int waves = 0;    // resident waves per CU (0 = no cap)
+};
+
 struct Ctx {
     void* links;
     Geom g;
     hipStream_t stream;
-    int block = 256;  // work-items per workgroup of the phase kernels (64, 128 or 256)
-    int xcd = 1;      // XCD-aware workgroup order for the phase kernels
+    Shape shape[2];   // per update kind: heatbath, overrelaxation
 };
+
+// Dynamic LDS per workgroup that limits a CU to `waves` resident waves of
+// `block`-item workgroups (0 = no cap).  LDS per CU: 160 KiB on gfx950; the
+// size is kLdsPerCu / (blocks + 1/2) rounded down to 512 bytes, so that
+// `blocks` workgroups fit with room to spare and one more does not.
+constexpr int kLdsPerCu = 160 * 1024;
+inline int lds_for_wave_cap(int waves, int block) {
+    if (waves <= 0) return 0;
+    const int per_block = block / 64;
+    const int blocks = waves / per_block < 1 ? 1 : waves / per_block;
+    return (int)(2.0 * kLdsPerCu / (2 * blocks + 1)) & ~511;
+}
+inline bool valid_wave_cap(int w) { return w == 0 || w == 8 || w == 12 || w == 16; }
 
 // Launch shapes the phase kernels are instantiated for.
 constexpr int kPhaseBlocks[3] = {64, 128, 256};
@@ -37,7 +56,7 @@ struct Ops {
     // batches: d is a device table of n chains of this Nc and storage type;
     // tiles is the total tile count of the grid kind the call uses
     void (*update_batch)(const ChainDesc* d, int n, int tiles, int kind, int mu, int par, uint32_t step_offset,
-                         int block, int xcd, hipStream_t s);
+                         const Shape& shape, hipStream_t s);
     void (*reunit_batch)(const ChainDesc* d, int n, int tiles, hipStream_t s);
     void (*plaquette_batch)(const ChainDesc* d, int n, int tiles, double* out, hipStream_t s);
 };

@@ -13,49 +13,52 @@ struct OpsImpl {
     template <bool HB, int MU>
     static void update_mu(const Ctx& c, int par, T beta, uint32_t k0, uint32_t k1, uint32_t step) {
         P* u = (P*)c.links;
-        switch (c.block) {
+        const Shape& sh = c.shape[HB ? 0 : 1];
+        const int lds = lds_for_wave_cap(sh.waves, sh.block);
+        switch (sh.block) {
             case 64:
-                k_update<N, T, R, HB, MU, 64><<<half_blocks(c.g, 64), 64, 0, c.stream>>>(u, c.g, par, beta, k0, k1, step,
-                                                                                      c.xcd);
+                k_update<N, T, R, HB, MU, 64><<<half_blocks(c.g, 64), 64, lds, c.stream>>>(u, c.g, par, beta, k0, k1,
+                                                                                            step, sh.xcd);
                 break;
             case 128:
-                k_update<N, T, R, HB, MU, 128><<<half_blocks(c.g, 128), 128, 0, c.stream>>>(u, c.g, par, beta, k0, k1,
-                                                                                         step, c.xcd);
+                k_update<N, T, R, HB, MU, 128><<<half_blocks(c.g, 128), 128, lds, c.stream>>>(u, c.g, par, beta, k0,
+                                                                                              k1, step, sh.xcd);
                 break;
             default:
-                k_update<N, T, R, HB, MU, 256><<<half_blocks(c.g, 256), 256, 0, c.stream>>>(u, c.g, par, beta, k0, k1,
-                                                                                         step, c.xcd);
+                k_update<N, T, R, HB, MU, 256><<<half_blocks(c.g, 256), 256, lds, c.stream>>>(u, c.g, par, beta, k0,
+                                                                                              k1, step, sh.xcd);
                 break;
         }
     }
 
     template <bool HB, int BS>
     static void update_batch_bs(const ChainDesc* d, int n, int tiles, int mu, int par, uint32_t off, int xcd,
-                                hipStream_t s) {
+                                int lds, hipStream_t s) {
         switch (mu) {
-            case 0: k_update_batch<N, T, R, HB, 0, BS><<<tiles, BS, 0, s>>>(d, n, par, off, xcd); break;
-            case 1: k_update_batch<N, T, R, HB, 1, BS><<<tiles, BS, 0, s>>>(d, n, par, off, xcd); break;
-            case 2: k_update_batch<N, T, R, HB, 2, BS><<<tiles, BS, 0, s>>>(d, n, par, off, xcd); break;
-            default: k_update_batch<N, T, R, HB, 3, BS><<<tiles, BS, 0, s>>>(d, n, par, off, xcd); break;
+            case 0: k_update_batch<N, T, R, HB, 0, BS><<<tiles, BS, lds, s>>>(d, n, par, off, xcd); break;
+            case 1: k_update_batch<N, T, R, HB, 1, BS><<<tiles, BS, lds, s>>>(d, n, par, off, xcd); break;
+            case 2: k_update_batch<N, T, R, HB, 2, BS><<<tiles, BS, lds, s>>>(d, n, par, off, xcd); break;
+            default: k_update_batch<N, T, R, HB, 3, BS><<<tiles, BS, lds, s>>>(d, n, par, off, xcd); break;
         }
     }
 
     template <bool HB>
     static void update_batch_kind(const ChainDesc* d, int n, int tiles, int mu, int par, uint32_t off, int block,
-                                  int xcd, hipStream_t s) {
+                                  int xcd, int lds, hipStream_t s) {
         switch (block) {
-            case 64: update_batch_bs<HB, 64>(d, n, tiles, mu, par, off, xcd, s); break;
-            case 128: update_batch_bs<HB, 128>(d, n, tiles, mu, par, off, xcd, s); break;
-            default: update_batch_bs<HB, 256>(d, n, tiles, mu, par, off, xcd, s); break;
+            case 64: update_batch_bs<HB, 64>(d, n, tiles, mu, par, off, xcd, lds, s); break;
+            case 128: update_batch_bs<HB, 128>(d, n, tiles, mu, par, off, xcd, lds, s); break;
+            default: update_batch_bs<HB, 256>(d, n, tiles, mu, par, off, xcd, lds, s); break;
         }
     }
 
     static void update_batch(const ChainDesc* d, int n, int tiles, int kind, int mu, int par, uint32_t off,
-                             int block, int xcd, hipStream_t s) {
+                             const Shape& sh, hipStream_t s) {
+        const int lds = lds_for_wave_cap(sh.waves, sh.block);
         if (kind == 0)
-            update_batch_kind<true>(d, n, tiles, mu, par, off, block, xcd, s);
+            update_batch_kind<true>(d, n, tiles, mu, par, off, sh.block, sh.xcd, lds, s);
         else
-            update_batch_kind<false>(d, n, tiles, mu, par, off, block, xcd, s);
+            update_batch_kind<false>(d, n, tiles, mu, par, off, sh.block, sh.xcd, lds, s);
     }
 
     static void reunit_batch(const ChainDesc* d, int n, int tiles, hipStream_t s) {

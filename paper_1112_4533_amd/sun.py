@@ -63,9 +63,9 @@ def load():
         "sun_batch_capture": [vp, c_int, c_int, c_int, c_int, vp, vp],
         "sun_batch_replay": [vp, vp],
         "sun_batch_sync": [vp],
-        "sun_set_launch": [vp, c_int, c_int],
-        "sun_get_launch": [vp, ctypes.POINTER(c_int), ctypes.POINTER(c_int)],
-        "sun_batch_set_launch": [vp, c_int, c_int],
+        "sun_set_launch": [vp, c_int, c_int, c_int, c_int],
+        "sun_get_launch": [vp, c_int, ctypes.POINTER(c_int), ctypes.POINTER(c_int), ctypes.POINTER(c_int)],
+        "sun_batch_set_launch": [vp, c_int, c_int, c_int, c_int],
     }
     for name, args in sigs.items():
         f = getattr(L, name)
@@ -169,6 +169,13 @@ class Lattice:
         _check(load().sun_sweep(self._h, float(beta), int(n_hb), int(n_or), int(seed), int(bool(reunit)),
                                 _stream()))
 
+    def phase_step(self, kind, beta=1.0, seed=0, step=0):
+        """All eight phases (mu = 0..3, even then odd) of one update kind,
+        leaving the RNG step counter alone."""
+        for mu in range(4):
+            for p in range(2):
+                self.phase(kind, mu, p, beta, seed, step)
+
     def reunitarize(self, report=False):
         """Returns a device tensor {max|U^dag U - 1|, max|det - 1|} measured
         before the projection when report is true."""
@@ -218,16 +225,23 @@ class Lattice:
         _check(load().sun_set_step(self._h, int(value)))
 
     # -- launch shape (tuning only; results do not depend on it) ---------
-    LAUNCH_SHAPES = [(b, x) for b in (64, 128, 256) for x in (1, 0)]
+    # (work-items per workgroup, XCD-aware order, resident-wave cap per CU)
+    LAUNCH_SHAPES = [(b, x, w) for b in (64, 128, 256) for x in (1, 0) for w in (8, 12, 16, 0)]
 
-    def set_launch(self, block=256, xcd=1):
-        _check(load().sun_set_launch(self._h, int(block), int(xcd)))
+    def set_launch(self, block=256, xcd=1, waves=0, kind=-1):
+        """Launch shape of the heatbath (kind 0), overrelaxation (1) or both
+        (-1) phase kernels."""
+        _check(load().sun_set_launch(self._h, int(kind), int(block), int(xcd), int(waves)))
+
+    def get_launch(self, kind):
+        b, x, w = ctypes.c_int(), ctypes.c_int(), ctypes.c_int()
+        _check(load().sun_get_launch(self._h, int(kind), ctypes.byref(b), ctypes.byref(x), ctypes.byref(w)))
+        return b.value, x.value, w.value
 
     @property
     def launch(self):
-        b, x = ctypes.c_int(), ctypes.c_int()
-        _check(load().sun_get_launch(self._h, ctypes.byref(b), ctypes.byref(x)))
-        return b.value, x.value
+        """(heatbath shape, overrelaxation shape)."""
+        return self.get_launch(HEATBATH), self.get_launch(OVERRELAX)
 
     # -- event timing ----------------------------------------------------
     def profile(self, enable=True):
@@ -263,7 +277,7 @@ class Batch:
         self.n = n
         self.betas = [float(x) for x in betas]
         self.seeds = [int(x) for x in seeds]
-        self.launch = (256, 1)
+        self.launch = [(256, 1, 0), (256, 1, 12)]   # heatbath, overrelaxation
         self.stream = torch.cuda.Stream(device=dev)   # graphs need a non-null stream
 
     def __del__(self):
@@ -299,10 +313,12 @@ class Batch:
     def sync(self):
         _check(load().sun_batch_sync(self._h))
 
-    def set_launch(self, block=256, xcd=1):
-        """Launch shape of the phase kernels; drops a captured graph."""
-        _check(load().sun_batch_set_launch(self._h, int(block), int(xcd)))
-        self.launch = (int(block), int(xcd))
+    def set_launch(self, block=256, xcd=1, waves=0, kind=-1):
+        """Launch shape of the phase kernels (kind as Lattice.set_launch);
+        drops a captured graph."""
+        _check(load().sun_batch_set_launch(self._h, int(kind), int(block), int(xcd), int(waves)))
+        for k in ((HEATBATH, OVERRELAX) if kind < 0 else (kind,)):
+            self.launch[k] = (int(block), int(xcd), int(waves))
 
 
 def sample_su2(alpha, seed, step=0, mu_sg=0, dtype="f64"):

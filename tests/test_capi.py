@@ -42,11 +42,18 @@ def test_lattice_bytes(lib):
     assert rc == 0 and lb == 4 * 8 ** 4 * 4 * 8           # SU(2): 4 reals per link
     rc, lb, _ = _bytes(lib, 8, (12, 12, 12, 12), 1)
     assert rc == 0 and lb == 4 * 12 ** 4 * 128 * 8
+    # SU(3) two-row storage: 12 reals per link
+    rc, lb, _ = _bytes(lib, 3, (32, 32, 32, 32), 2)
+    assert rc == 0 and lb == 4 * 32 ** 4 * 12 * 4
+    rc, lb, _ = _bytes(lib, 3, (8, 8, 8, 8), 3)
+    assert rc == 0 and lb == 4 * 8 ** 4 * 12 * 8
+    for nc in (2, 4):
+        assert _bytes(lib, nc, (8, 8, 8, 8), 2)[0] == -4
 
 
 @pytest.mark.parametrize("nc,L,dtype", [
     (1, (8, 8, 8, 8), 0), (9, (8, 8, 8, 8), 0), (3, (7, 8, 8, 8), 0), (3, (1, 8, 8, 8), 0),
-    (3, (8, 8, 3, 8), 0), (3, (8, 8, 8, 8), 2), (3, (256, 256, 256, 256), 0)])
+    (3, (8, 8, 3, 8), 0), (3, (8, 8, 8, 8), 4), (3, (256, 256, 256, 256), 0)])
 def test_lattice_bytes_rejects(lib, nc, L, dtype):
     rc, _, _ = _bytes(lib, nc, L, dtype)
     assert rc == -1
@@ -76,11 +83,17 @@ def test_create_validates_buffers_without_touching_them(lib):
     assert lib.sun_plaquette(h, None, None) == -2
     assert lib.sun_profile_read(h, 9, None, None) == -1
     # launch shapes: only the instantiated workgroup sizes
-    b, x = ctypes.c_int(), ctypes.c_int()
-    assert lib.sun_get_launch(h, ctypes.byref(b), ctypes.byref(x)) == 0 and (b.value, x.value) == (256, 1)
-    assert lib.sun_set_launch(h, 100, 1) == -1
-    assert lib.sun_set_launch(h, 64, 0) == 0
-    assert lib.sun_get_launch(h, ctypes.byref(b), ctypes.byref(x)) == 0 and (b.value, x.value) == (64, 0)
+    b, x, w = ctypes.c_int(), ctypes.c_int(), ctypes.c_int()
+    get = lambda k: (lib.sun_get_launch(h, k, ctypes.byref(b), ctypes.byref(x), ctypes.byref(w)),
+                     b.value, x.value, w.value)
+    assert get(0) == (0, 256, 1, 0) and get(1) == (0, 256, 1, 12)
+    assert lib.sun_set_launch(h, -1, 100, 1, 8) == -1
+    assert lib.sun_set_launch(h, -1, 64, 1, 5) == -1
+    assert lib.sun_set_launch(h, 2, 64, 1, 8) == -1
+    assert lib.sun_set_launch(h, 1, 64, 0, 16) == 0
+    assert get(0) == (0, 256, 1, 0) and get(1) == (0, 64, 0, 16)
+    assert lib.sun_set_launch(h, -1, 128, 1, 8) == 0
+    assert get(0) == (0, 128, 1, 8) and get(1) == (0, 128, 1, 8)
     lib.sun_lattice_destroy(h)
 
 

@@ -511,17 +511,17 @@ def test_every_launch_shape_gives_the_same_bits(gpu, nc, dtype):
     sun = gpu
     L = (10, 6, 4, 6)
     ref = None
-    for block, xcd in sun.Lattice.LAUNCH_SHAPES:
+    for shape in sun.Lattice.LAUNCH_SHAPES:
         lat = gpu_lattice(sun, nc, L, dtype, hot=True, seed=8)
-        lat.set_launch(block, xcd)
-        assert lat.launch == (block, xcd)
+        lat.set_launch(*shape)
+        assert lat.launch == (shape, shape)
         lat.sweep(BETA[nc], 1, 2, seed=8)
         lat.sweep(BETA[nc], 1, 2, seed=8)
         torch.cuda.synchronize()
         if ref is None:
             ref = lat.links.clone()
         else:
-            assert torch.equal(ref, lat.links), (block, xcd)
+            assert torch.equal(ref, lat.links), shape
 
 
 def test_batch_launch_shapes_and_tuner(gpu, tmp_path, monkeypatch):
@@ -533,24 +533,29 @@ def test_batch_launch_shapes_and_tuner(gpu, tmp_path, monkeypatch):
     rb = sun.Batch(ref, [c[3] for c in spec], [c[4] for c in spec])
     rb.sweep(1, 2)
     rb.sweep(1, 2)
-    for block, xcd in [(64, 0), (128, 1)]:
+    for hb, orx in [((64, 0, 0), (128, 1, 12)), ((256, 1, 16), (64, 1, 8)), ((128, 0, 8), (256, 0, 0))]:
+        shape = (hb, orx)
         lats = [gpu_lattice(sun, nc, L, dt, hot=True, seed=sd) for nc, L, dt, b, sd in spec]
         bt = sun.Batch(lats, [c[3] for c in spec], [c[4] for c in spec])
-        bt.set_launch(block, xcd)
+        bt.set_launch(*hb, kind=0)
+        bt.set_launch(*orx, kind=1)
         bt.sweep(1, 2)
         bt.capture(n_sweeps=1, n_hb=1, n_or=2)
         bt.replay()
         torch.cuda.synchronize()
         for a, b in zip(ref, lats):
-            assert torch.equal(a.links, b.links), (block, xcd)
+            assert torch.equal(a.links, b.links), shape
     # the tuner works on clones: the chains' fields are unchanged by tuning
     before = [l.links.clone() for l in ref]
-    block, xcd, times = autotune.tune_batch(rb)
-    assert (block, xcd) in sun.Lattice.LAUNCH_SHAPES and len(times) == 6
+    best, times = autotune.tune_batch(rb, reps=1)
+    assert all(best[k] in sun.Lattice.LAUNCH_SHAPES for k in (0, 1))
+    assert len(times["heatbath"]) == len(times["overrelax"]) == len(sun.Lattice.LAUNCH_SHAPES)
     for a, b in zip(before, ref):
         assert torch.equal(a, b.links)
     lat = ref[1]
-    block, xcd, _ = autotune.tune_lattice(lat)
-    assert lat.launch == (block, xcd)
+    before = lat.links.clone()
+    best, _ = autotune.tune_lattice(lat, reps=1)
+    assert lat.launch == (best[0], best[1])
+    assert torch.equal(before, lat.links)
     # a second call comes from the cache
-    assert autotune.tune_lattice(lat)[:2] == (block, xcd)
+    assert autotune.tune_lattice(lat)[0] == best
