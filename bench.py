@@ -2,11 +2,13 @@
 """Throughput of the SU(3) Wilson-action checkerboard sweep on one MI355X.
 
 Workload: SU(3), 32^4 periodic lattice, beta = 6.2, Haar hot start, FP32 link
-storage with FP64 reductions and FP64 re-unitarization.  One step is one pass
+storage in the two-row form (12 reals per link, row 2 rebuilt on load) with
+FP64 reductions and FP64 re-unitarization.  One step is one pass
 of the whole hot path over the lattice: 1 heatbath step + 4 overrelaxation
 steps (each 4 directions x {even, odd} phases), re-unitarization (reporting
 the unitarity drift it removed), the plaquette (FP64) and the Polyakov loop.
-The same workload with FP64 link storage is timed beside it.
+The same workload with 18-real FP32 links, with FP64 links, and a batch of
+64 small independent chains replayed from a HIP graph are timed beside it.
 
 Prints one JSON line.  `value` is link updates per second (one update = one
 heatbath or overrelaxation visit of one link) with the field resident in HBM.
@@ -44,7 +46,46 @@ def step_bytes(nc, V, dtype, n_hb, n_or):
     return 8 * (n_hb + n_or) * phase_bytes(nc, V, dtype) + (8 * V + 4 * V + V) * lb
 
 
-def run_gpu(run, steps, warmup, tune=True):
+KERNEL_SOURCES = ["sun_device.hpp", "sun_kernels.hpp"]
+TRAFFIC_FILE = os.path.join(ROOT, "profiles", "traffic.json")
+
+
+def kernel_source_hash():
+    """Hash of the device code, so stored byte counters are used only while
+    the kernels they were taken on are unchanged."""
+    import hashlib
+    h = hashlib.sha256()
+    for f in KERNEL_SOURCES:
+        with open(os.path.join(ROOT, "paper_1112_4533_amd", "csrc", f), "rb") as fh:
+            h.update(fh.read())
+    return h.hexdigest()[:16]
+
+
+def stored_traffic(workload):
+    """HBM-side bytes per launch of the overrelaxation phase kernel from the
+    committed rocprofv3 FETCH_SIZE / WRITE_SIZE summary, or None when the
+    kernels changed after those counters were taken."""
+    try:
+        with open(TRAFFIC_FILE) as f:
+            t = json.load(f)
+    except (OSError, ValueError):
+        return None
+    e = t.get(workload)
+    if not e or e.get("source_hash") != kernel_source_hash():
+        return None
+    return e["read_bytes"] + e["write_bytes"]
+
+
+def roofline(run, r):
+    k = r["kernels"]["overrelax"]
+    per_launch = phase_bytes(run.nc, run.volume, run.dtype)
+    achieved = per_launch / (k["avg_ms"] * 1e-3) / 1e9
+    return {"bound": "hbm", "kernel": f"overrelaxation phase ({run.dtype} storage)", "achieved": achieved,
+            "peak": PEAK_HBM_GBS, "unit": "GB/s", "frac": achieved / PEAK_HBM_GBS,
+            "traffic": stored_traffic(run.name), "bytes_per_launch": per_launch, "avg_launch_ms": k["avg_ms"]}
+
+
+def run_gpu(run, steps, warmup, tune=False):
     import torch
     from paper_1112_4533_amd import autotune, sun
 
@@ -79,6 +120,12 @@ def run_gpu(run, steps, warmup, tune=True):
         ms, n = lat.profile_read(name)
         kernels[name] = {"avg_ms": ms / n if n else None, "launches": n}
     lat.profile(False)
+    # overrelaxation is microcanonical: the relative action change of one
+    # overrelaxation step (FP64 plaquettes before and after), untimed
+    p0 = lat.plaquette().cpu()
+    lat.sweep(run.beta, 0, 1, seed=run.seed, reunit=False)
+    p1 = lat.plaquette().cpu()
+    or_ds = float((p0[0] - p1[0]) / (1.0 - p0[0]))   # S is proportional to 1 - mean plaquette
     V = run.volume
     updates = steps * (run.n_hb + run.n_or) * 4 * V
     return {
@@ -90,11 +137,12 @@ def run_gpu(run, steps, warmup, tune=True):
         "polyakov": poly.cpu().tolist(),
         "unitarity_before_reunit": drift.cpu().tolist(),
         "step_counter": lat.step,
+        "or_dS_over_S": or_ds,
         "launch": {"heatbath": lat.get_launch(sun.HEATBATH), "overrelax": lat.get_launch(sun.OVERRELAX)},
     }
 
 
-def run_batch(steps, warmup, f64_sweeps):
+def run_batch(steps, warmup, f64_sweeps, tune=False):
     """The 64-chain batch (mixed SU(2)/SU(3), extents 8..20, per-chain beta
     and seed): FP32 links swept together from a captured graph (each replay
     is one sweep of every chain: 1 HB + 4 OR, re-unitarization, plaquettes),
@@ -113,8 +161,9 @@ def run_batch(steps, warmup, f64_sweeps):
         lat.init(hot=True, seed=r.seed)
         lats.append(lat)
     bt = sun.Batch(lats, [r.beta for r in spec], [r.seed for r in spec])
-    from paper_1112_4533_amd import autotune
-    autotune.tune_batch(bt, reps=2, use_cache=False)
+    if tune:
+        from paper_1112_4533_amd import autotune
+        autotune.tune_batch(bt, reps=2, use_cache=False)
     plaq32 = torch.zeros((len(spec), 3), dtype=torch.float64, device="cuda")
     bt.capture(n_sweeps=1, n_hb=n_hb, n_or=n_or, reunit=True, plaq_out=plaq32)
     for _ in range(warmup):
@@ -197,7 +246,10 @@ def main():
     ap.add_argument("--cpu-sweeps", type=int, default=8, help="oracle sweeps in the CPU-baseline sample")
     ap.add_argument("--no-f64", action="store_true")
     ap.add_argument("--no-batch", action="store_true")
-    ap.add_argument("--no-two-row", action="store_true")
+    ap.add_argument("--head", choices=["two_row", "eighteen"], default="two_row",
+                    help="SU(3) storage of the headline line (the other is reported beside it)")
+    ap.add_argument("--no-second", action="store_true", help="skip the other storage's leg")
+    ap.add_argument("--tune", action="store_true", help="autotune launch shapes before timing")
     ap.add_argument("--copy-calibration", type=float, default=0.0, metavar="GB",
                     help="only copy a GB-sized device buffer 5 times (the reference kernel for "
                          "scaling HBM byte counters), then exit")
@@ -220,78 +272,67 @@ def main():
 
     from paper_1112_4533_amd.workloads import SU3_32_F32, SU3_32_F32_TWO_ROW, SU3_32_F64
 
-    run = SU3_32_F32
-    r32 = run_gpu(run, args.steps, args.warmup)
+    # the headline is the faster FP32 storage of the same workload (two-row);
+    # --head eighteen makes the 18-real form the headline
+    head, other = ((SU3_32_F32_TWO_ROW, SU3_32_F32) if args.head == "two_row" else (SU3_32_F32, SU3_32_F32_TWO_ROW))
+    r_head = run_gpu(head, args.steps, args.warmup, tune=args.tune)
+    r18 = None if args.no_second else run_gpu(other, args.steps, args.warmup, tune=args.tune)
     r64 = None if args.no_f64 else run_gpu(SU3_32_F64, max(2, args.steps // 2), max(1, args.warmup // 2))
-    r12 = None if args.no_two_row else run_gpu(SU3_32_F32_TWO_ROW, args.steps, args.warmup)
 
-    V = run.volume
-    k_or = r32["kernels"]["overrelax"]
-    per_launch = phase_bytes(run.nc, V, run.dtype)
-    achieved = per_launch / (k_or["avg_ms"] * 1e-3) / 1e9
+    V = head.volume
     line = {
         "metric": METRIC,
-        "value": r32["updates_per_s"],
+        "value": r_head["updates_per_s"],
         "unit": "link_updates/s",
         "n_gpus": 1,
         "steps": args.steps,
         "warmup": args.warmup,
-        "ms_per_step": r32["ms_per_step"],
+        "ms_per_step": r_head["ms_per_step"],
         "higher_is_better": True,
         "scaling": "weak",
         "vs_baseline": None,
         "dtype": "f32",
         "data": "synthetic (Haar hot start from Philox, seed 1234)",
         "config": {
-            "workload": run.name, "nc": run.nc, "L": list(run.L), "beta": run.beta,
-            "n_hb": run.n_hb, "n_or": run.n_or, "reunit": "every sweep",
+            "workload": head.name, "nc": head.nc, "L": list(head.L), "beta": head.beta,
+            "n_hb": head.n_hb, "n_or": head.n_or, "reunit": "every sweep",
+            "storage": ("FP32, SU(3) two-row (12 reals per link, row 2 rebuilt on load)"
+                        if head.dtype.endswith("r12") else "FP32, full 3x3 (18 reals per link)"),
             "step": "sweep + reunitarize(drift) + plaquette + polyakov",
         },
-        "roofline": {
-            "bound": "hbm",
-            "kernel": "overrelaxation phase (k_update<3,float,OR>)",
-            "achieved": achieved,
-            "peak": PEAK_HBM_GBS,
-            "unit": "GB/s",
-            "frac": achieved / PEAK_HBM_GBS,
-            "traffic": None,
-            "bytes_per_launch": per_launch,
-            "avg_launch_ms": k_or["avg_ms"],
-        },
-        "effective_GBps_whole_step": step_bytes(run.nc, V, run.dtype, run.n_hb, run.n_or) / (r32["ms_per_step"] * 1e-3) / 1e9,
-        "kernels": r32["kernels"],
-        "launch": r32["launch"],
+        "roofline": roofline(head, r_head),
+        "effective_GBps_whole_step": step_bytes(head.nc, V, head.dtype, head.n_hb, head.n_or)
+        / (r_head["ms_per_step"] * 1e-3) / 1e9,
+        "kernels": r_head["kernels"],
+        "launch": r_head["launch"],
         "accuracy": {
-            "plaquette": r32["plaquette"],
-            "polyakov": r32["polyakov"],
-            "max_unitarity_dev_before_reunit": r32["unitarity_before_reunit"],
+            "plaquette": r_head["plaquette"],
+            "polyakov": r_head["polyakov"],
+            "max_unitarity_dev_before_reunit": r_head["unitarity_before_reunit"],
+            "overrelaxation_rel_action_change": r_head["or_dS_over_S"],
         },
     }
+    if r18:
+        line["eighteen_real" if args.head == "two_row" else "two_row"] = {
+            "workload": other.name, "value": r18["updates_per_s"], "unit": "link_updates/s",
+            "ms_per_step": r18["ms_per_step"], "roofline": roofline(other, r18), "kernels": r18["kernels"],
+            "launch": r18["launch"], "plaquette": r18["plaquette"],
+            "max_unitarity_dev_before_reunit": r18["unitarity_before_reunit"],
+            "overrelaxation_rel_action_change": r18["or_dS_over_S"],
+            "headline_over_this": r_head["updates_per_s"] / r18["updates_per_s"],
+        }
     if r64:
         line["fp64"] = {
-            "value": r64["updates_per_s"], "unit": "link_updates/s", "ms_per_step": r64["ms_per_step"],
-            "steps": max(2, args.steps // 2), "kernels": r64["kernels"], "plaquette": r64["plaquette"],
-            "max_unitarity_dev_before_reunit": r64["unitarity_before_reunit"],
-            "f32_over_f64": r32["updates_per_s"] / r64["updates_per_s"],
-        }
-    if r12:
-        k12 = r12["kernels"]["overrelax"]
-        pb12 = phase_bytes(run.nc, V, SU3_32_F32_TWO_ROW.dtype)
-        a12 = pb12 / (k12["avg_ms"] * 1e-3) / 1e9
-        line["two_row"] = {
-            "workload": SU3_32_F32_TWO_ROW.name, "value": r12["updates_per_s"], "unit": "link_updates/s",
-            "ms_per_step": r12["ms_per_step"],
-            "roofline": {"bound": "hbm", "kernel": "overrelaxation phase, two-row storage", "achieved": a12,
-                         "peak": PEAK_HBM_GBS, "unit": "GB/s", "frac": a12 / PEAK_HBM_GBS,
-                         "bytes_per_launch": pb12, "avg_launch_ms": k12["avg_ms"]},
-            "kernels": r12["kernels"], "plaquette": r12["plaquette"],
-            "max_unitarity_dev_before_reunit": r12["unitarity_before_reunit"],
-            "speedup_over_18_real": r12["updates_per_s"] / r32["updates_per_s"],
+            "workload": SU3_32_F64.name, "value": r64["updates_per_s"], "unit": "link_updates/s",
+            "ms_per_step": r64["ms_per_step"], "steps": max(2, args.steps // 2), "kernels": r64["kernels"],
+            "plaquette": r64["plaquette"], "max_unitarity_dev_before_reunit": r64["unitarity_before_reunit"],
+            "overrelaxation_rel_action_change": r64["or_dS_over_S"],
+            "fp32_over_fp64": r_head["updates_per_s"] / r64["updates_per_s"],
         }
     if not args.no_batch:
-        line["batch"] = run_batch(max(4, args.steps), args.warmup, max(2, args.steps // 4))
+        line["batch"] = run_batch(max(4, args.steps), args.warmup, max(2, args.steps // 4), tune=args.tune)
     if not args.no_cpu_baseline:
-        line["cpu_baseline"] = run_cpu_baseline(run, args.cpu_sweeps)
+        line["cpu_baseline"] = run_cpu_baseline(SU3_32_F32, args.cpu_sweeps)
     print(json.dumps(line), flush=True)
 
 
