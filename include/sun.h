@@ -130,14 +130,20 @@ int sun_set_step(sun_lattice_t h, uint64_t step);
 
 /* Launch shape of the phase kernels of one update kind (SUN_HEATBATH,
  * SUN_OVERRELAX, or -1 for both): block work-items per workgroup (64, 128 or
- * 256), the XCD-aware workgroup order (1) or the plain order (0), and a cap
- * on resident waves per CU (8, 12, 16, or 0 for none) enforced through the
- * workgroups' LDS allocation: a phase's per-XCD working set exceeds the L2,
- * so fewer resident waves raise the L2 hit rate.  Defaults: heatbath
- * (256, 1, 0), overrelaxation (256, 1, 12).  A tuning choice only: results
- * are bitwise the same for every shape. */
-int sun_set_launch(sun_lattice_t h, int kind, int block, int xcd, int waves);
-int sun_get_launch(sun_lattice_t h, int kind, int *block, int *xcd, int *waves);
+ * 256), the XCD-aware workgroup order (1) or the plain order (0), a cap on
+ * resident waves per CU (8, 12, 16, or 0 for none) enforced through the
+ * workgroups' LDS allocation (a phase's per-XCD working set exceeds the L2,
+ * so fewer resident waves raise the L2 hit rate), and the depth of the
+ * t-blocked tile walk (2, 4 or 8 time slices; 0 or 1 for the linear walk):
+ * the tiles of tblock consecutive time slices are walked together so that a
+ * phase re-reads its t-neighbours from L2.  The t-blocked walk applies where
+ * L_t is a multiple of tblock and an (x, y) plane holds a whole number of
+ * workgroups (L_x L_y / 2 a multiple of block); elsewhere the linear walk
+ * runs, and sun_get_launch reports the walk in effect (0 for linear).
+ * Defaults: heatbath (256, 1, 0, 4), overrelaxation (256, 1, 12, 4).  A
+ * tuning choice only: results are bitwise the same for every shape. */
+int sun_set_launch(sun_lattice_t h, int kind, int block, int xcd, int waves, int tblock);
+int sun_get_launch(sun_lattice_t h, int kind, int *block, int *xcd, int *waves, int *tblock);
 
 /* Per-kernel timing with HIP events recorded around each launch on the
  * launch stream.  kernel: 0 heatbath phase, 1 overrelaxation phase,
@@ -191,8 +197,9 @@ int sun_batch_capture(sun_batch_t b, int n_sweeps, int n_hb, int n_or, int reuni
                       sun_stream_t stream);
 int sun_batch_replay(sun_batch_t b, sun_stream_t stream);
 
-/* Launch shape of the batch's phase kernels (as sun_set_launch).  Waits for
- * the device, rewrites the table, and drops any captured graph. */
+/* Launch shape of the batch's phase kernels (as sun_set_launch, always with
+ * the linear tile walk).  Waits for the device, rewrites the table, and drops
+ * any captured graph. */
 int sun_batch_set_launch(sun_batch_t b, int kind, int block, int xcd, int waves);
 
 /* Writes the chains' advanced RNG step counters back to their handles. */

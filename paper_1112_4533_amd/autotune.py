@@ -1,8 +1,9 @@
 """Launch-shape autotuner for the phase kernels.
 
 The phase kernels come in workgroup sizes of 64, 128 and 256 work-items, with
-the XCD-aware or the plain workgroup order, and with a cap of 8, 12, 16 or no
-limit on resident waves per CU.  Every shape computes the same bits, so the
+the XCD-aware or the plain workgroup order, with a cap of 8, 12, 16 or no
+limit on resident waves per CU, and (single lattices) with the linear or a
+t-blocked tile walk of 2, 4 or 8 time slices.  Every shape computes the same bits, so the
 choice is a pure speed question, made separately for the heatbath and the
 overrelaxation kernels (the heatbath draws cost arithmetic, so it prefers
 more resident waves).  It depends on the lattice: a small lattice needs small
@@ -58,12 +59,12 @@ def _time(fn, reps):
     return a.elapsed_time(b) / reps
 
 
-def _search(set_shape, step_hb, step_or, reps):
+def _search(shapes, set_shape, step_hb, step_or, reps):
     """Times every shape for each kind; returns ({kind: best shape}, timings)."""
     best, times = {}, {}
     for kind, step in ((sun.HEATBATH, step_hb), (sun.OVERRELAX, step_or)):
         t = {}
-        for shape in sun.Lattice.LAUNCH_SHAPES:
+        for shape in shapes:
             set_shape(shape, kind)
             t["/".join(map(str, shape))] = _time(step, reps)
         key = min(t, key=t.get)
@@ -78,7 +79,8 @@ def lattice_key(lat):
 
 def tune_lattice(lat, reps=5, use_cache=True):
     """Picks and applies the fastest launch shape of each update kind for
-    `lat`; returns ({kind: (block, xcd, waves)}, timings in ms per step)."""
+    `lat`; returns ({kind: (block, xcd, waves, tblock)}, timings in ms per
+    step)."""
     key = lattice_key(lat)
     cache = _load_cache() if use_cache else {}
     if key in cache:
@@ -88,7 +90,13 @@ def tune_lattice(lat, reps=5, use_cache=True):
         return best, cache[key].get("ms", {})
     clone = sun.Lattice(lat.nc, lat.L, lat.dtype, device=lat.links.device)
     clone.links.copy_(lat.links)
-    best, times = _search(lambda shape, kind: clone.set_launch(*shape, kind=kind),
+    shapes = []                            # distinct shapes in effect on this lattice
+    for shape in sun.Lattice.LAUNCH_SHAPES:
+        clone.set_launch(*shape, kind=sun.OVERRELAX)
+        eff = clone.get_launch(sun.OVERRELAX)
+        if eff not in shapes:
+            shapes.append(eff)
+    best, times = _search(shapes, lambda shape, kind: clone.set_launch(*shape, kind=kind),
                           lambda: clone.phase_step(sun.HEATBATH), lambda: clone.phase_step(sun.OVERRELAX), reps)
     for kind, shape in best.items():
         lat.set_launch(*shape, kind=kind)
@@ -119,7 +127,7 @@ def tune_batch(batch, reps=3, use_cache=True):
         c.links.copy_(l.links)
         clones.append(c)
     cb = sun.Batch(clones, batch.betas, batch.seeds)
-    best, times = _search(lambda shape, kind: cb.set_launch(*shape, kind=kind),
+    best, times = _search(sun.Batch.LAUNCH_SHAPES, lambda shape, kind: cb.set_launch(*shape, kind=kind),
                           lambda: cb.sweep(1, 0, reunit=False), lambda: cb.sweep(0, 1, reunit=False), reps)
     for kind, shape in best.items():
         batch.set_launch(*shape, kind=kind)

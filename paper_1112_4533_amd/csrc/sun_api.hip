@@ -4,6 +4,8 @@
 // sun_kernels.hpp; this file only validates and launches.
 #include <hip/hip_runtime.h>
 
+#include <algorithm>
+
 #include <cstdarg>
 #include <cstdio>
 #include <cstring>
@@ -60,7 +62,7 @@ struct sun_lattice_s {
     double total_ms[kKernels] = {};
     int64_t launches[kKernels] = {};
     // launch shapes of the phase kernels (sun_set_launch)
-    sun::Shape shape[2] = {sun::Shape{256, 1, 0}, sun::Shape{256, 1, 12}};
+    sun::Shape shape[2] = {sun::Shape{256, 1, 0, 4}, sun::Shape{256, 1, 12, 4}};
 
     sun::Ctx ctx(hipStream_t s) const { return sun::Ctx{links, g, s, {shape[0], shape[1]}}; }
 };
@@ -124,7 +126,7 @@ size_t link_bytes_of(int nc, const sun::Geom& g, int dtype) {
 }
 
 size_t scratch_bytes_of(const sun::Geom& g) {
-    const int nblk = sun::link_blocks(g);  // the largest partial array
+    const int nblk = std::max(sun::link_blocks(g), sun::plaquette_tiles(g));  // the largest partial array
     const size_t b = 2 * sizeof(double) * (size_t)nblk;
     return (b + 255) & ~(size_t)255;
 }
@@ -132,10 +134,11 @@ size_t scratch_bytes_of(const sun::Geom& g) {
 inline hipStream_t as_stream(sun_stream_t s) { return reinterpret_cast<hipStream_t>(s); }
 
 // kind: SUN_HEATBATH, SUN_OVERRELAX, or -1 for both.
-int check_shape(int kind, int block, int waves) {
+int check_shape(int kind, int block, int waves, int tblock = 0) {
     if (kind < -1 || kind > 1) return fail(SUN_EINVAL, "kind %d is not -1, SUN_HEATBATH or SUN_OVERRELAX", kind);
     if (!sun::valid_phase_block(block)) return fail(SUN_EINVAL, "block %d is not 64, 128 or 256", block);
     if (!sun::valid_wave_cap(waves)) return fail(SUN_EINVAL, "wave cap %d is not 0, 8, 12 or 16", waves);
+    if (!sun::valid_tblock(tblock)) return fail(SUN_EINVAL, "time block %d is not 0, 1, 2, 4 or 8", tblock);
     return SUN_OK;
 }
 
@@ -285,7 +288,7 @@ int sun_plaquette(sun_lattice_t h, double* dev_out3, sun_stream_t stream) {
             if (((h->g.present >> mu) & 1) && ((h->g.present >> nu) & 1)) (nu == 3 ? n_tm : n_sp)++;
     const double norm = (double)h->nc * (double)h->g.V;
     h->ops->plaquette(h->ctx(s), h->scratch);
-    sun::launch_plaquette_final(h->scratch, sun::site_blocks(h->g), dev_out3, norm * n_sp, norm * n_tm,
+    sun::launch_plaquette_final(h->scratch, sun::plaquette_tiles(h->g), dev_out3, norm * n_sp, norm * n_tm,
                                 norm * (n_sp + n_tm), s);
     if (int rc = launch_check("plaquette")) return rc;
     return t.done();
@@ -339,20 +342,21 @@ int sun_set_step(sun_lattice_t h, uint64_t step) {
     return SUN_OK;
 }
 
-int sun_set_launch(sun_lattice_t h, int kind, int block, int xcd, int waves) {
+int sun_set_launch(sun_lattice_t h, int kind, int block, int xcd, int waves, int tblock) {
     if (!h) return fail(SUN_EINVAL, "null handle");
-    if (int rc = check_shape(kind, block, waves)) return rc;
+    if (int rc = check_shape(kind, block, waves, tblock)) return rc;
     for (int k = 0; k < 2; ++k)
-        if (kind < 0 || kind == k) h->shape[k] = sun::Shape{block, xcd ? 1 : 0, waves};
+        if (kind < 0 || kind == k) h->shape[k] = sun::Shape{block, xcd ? 1 : 0, waves, tblock > 1 ? tblock : 0};
     return SUN_OK;
 }
 
-int sun_get_launch(sun_lattice_t h, int kind, int* block, int* xcd, int* waves) {
-    if (!h || !block || !xcd || !waves) return fail(SUN_EINVAL, "null argument");
+int sun_get_launch(sun_lattice_t h, int kind, int* block, int* xcd, int* waves, int* tblock) {
+    if (!h || !block || !xcd || !waves || !tblock) return fail(SUN_EINVAL, "null argument");
     if (kind != SUN_HEATBATH && kind != SUN_OVERRELAX) return fail(SUN_EINVAL, "kind %d", kind);
     *block = h->shape[kind].block;
     *xcd = h->shape[kind].xcd;
     *waves = h->shape[kind].waves;
+    *tblock = sun::walk_for(h->g, h->shape[kind]).tb;
     return SUN_OK;
 }
 
@@ -454,7 +458,7 @@ int upload_table(sun_batch_t b) {
             sun::ChainDesc& c = b->host[i];
             for (int k = 0; k < 5; ++k) c.tile0[k] = t[k];
             t[sun::TILE_HALF_HB] += sun::half_blocks(c.g, b->shape[SUN_HEATBATH].block);
-            t[sun::TILE_SITE] += sun::site_blocks(c.g);
+            t[sun::TILE_SITE] += sun::plaquette_tiles(c.g);
             t[sun::TILE_LINK] += sun::link_blocks(c.g);
             t[sun::TILE_SPATIAL] += sun::spatial_blocks(c.g);
             t[sun::TILE_HALF_OR] += sun::half_blocks(c.g, b->shape[SUN_OVERRELAX].block);

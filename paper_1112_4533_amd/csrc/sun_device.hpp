@@ -146,6 +146,36 @@ __device__ __forceinline__ int xcd_tile(int b, int nblk) {
     return x * q + (x < r ? x : r) + b / kXcds;
 }
 
+// Order in which a phase walks its tiles.  With tb > 1 the tiles of one
+// (z, t) plane (tpp of them) are taken for tb consecutive t first, then the
+// next z, then the next block of tb time slices: the t-neighbour planes a
+// phase re-reads are then 2 tiles apart instead of a whole time slice, so
+// they are still in L2 when the neighbouring tile asks for them.  The host
+// sets tb > 1 only where a plane holds a whole number of tiles and tb
+// divides L_t, which makes the walk a permutation of the tiles.
+struct Walk {
+    int xcd;  // XCD-aware workgroup order
+    int tb;   // time slices per block of the walk (0 or 1: linear walk)
+    int tpp;  // tiles per (z, t) plane
+    int lz;   // L_z
+};
+
+// Tiles of the plaquette grid (256-item workgroups): both parities of every
+// checkerboard tile.
+__host__ __device__ __forceinline__ int plaquette_tiles(const Geom& g) { return 2 * ((g.Vh + 255) / 256); }
+
+__device__ __forceinline__ int walk_tile(int b, int nblk, const Walk& w) {
+    const int q = w.xcd ? xcd_tile(b, nblk) : b;
+    if (w.tb <= 1) return q;
+    const int i = q % w.tpp;
+    int rest = q / w.tpp;
+    const int ti = rest % w.tb;
+    rest /= w.tb;
+    const int z = rest % w.lz;
+    const int blk = rest / w.lz;
+    return i + w.tpp * (z + w.lz * (blk * w.tb + ti));
+}
+
 // ---------------------------------------------------------------------------
 // Register matrices.
 // ---------------------------------------------------------------------------
@@ -174,6 +204,20 @@ SUN_MAT_UNROLL
         }
 }
 
+// Fused multiply-add, one rounding.  The products below are written as
+// chains of these so that a complex multiply-add costs four VALU operations.
+__device__ __forceinline__ float fmadd(float a, float b, float c) { return __builtin_fmaf(a, b, c); }
+__device__ __forceinline__ double fmadd(double a, double b, double c) { return __builtin_fma(a, b, c); }
+
+// (r, m) += (ar + i ai)(br + i bi)
+template <typename T>
+__device__ __forceinline__ void cmac(T& r, T& m, T ar, T ai, T br, T bi) {
+    r = fmadd(ar, br, r);
+    r = fmadd(-ai, bi, r);
+    m = fmadd(ar, bi, m);
+    m = fmadd(ai, br, m);
+}
+
 // c = a b
 template <int N, typename T>
 __device__ __forceinline__ Mat<N, T> mul_nn(const Mat<N, T>& a, const Mat<N, T>& b) {
@@ -184,10 +228,7 @@ SUN_MAT_UNROLL
         for (int j = 0; j < N; ++j) {
             T r = T(0), m = T(0);
 SUN_MAT_UNROLL
-            for (int k = 0; k < N; ++k) {
-                r += a.re[i][k] * b.re[k][j] - a.im[i][k] * b.im[k][j];
-                m += a.re[i][k] * b.im[k][j] + a.im[i][k] * b.re[k][j];
-            }
+            for (int k = 0; k < N; ++k) cmac(r, m, a.re[i][k], a.im[i][k], b.re[k][j], b.im[k][j]);
             c.re[i][j] = r;
             c.im[i][j] = m;
         }
@@ -204,10 +245,7 @@ SUN_MAT_UNROLL
         for (int j = 0; j < N; ++j) {
             T r = T(0), m = T(0);
 SUN_MAT_UNROLL
-            for (int k = 0; k < N; ++k) {
-                r += a.re[i][k] * b.re[j][k] + a.im[i][k] * b.im[j][k];
-                m += a.im[i][k] * b.re[j][k] - a.re[i][k] * b.im[j][k];
-            }
+            for (int k = 0; k < N; ++k) cmac(r, m, a.re[i][k], a.im[i][k], b.re[j][k], -b.im[j][k]);
             c.re[i][j] = r;
             c.im[i][j] = m;
         }
@@ -221,27 +259,26 @@ SUN_MAT_UNROLL
     for (int i = 0; i < N; ++i)
 SUN_MAT_UNROLL
         for (int j = 0; j < N; ++j) {
-            T r = T(0), m = T(0);
+            T r = acc.re[i][j], m = acc.im[i][j];
 SUN_MAT_UNROLL
-            for (int k = 0; k < N; ++k) {
-                r += a.re[k][i] * b.re[k][j] + a.im[k][i] * b.im[k][j];
-                m += a.re[k][i] * b.im[k][j] - a.im[k][i] * b.re[k][j];
-            }
-            acc.re[i][j] += r;
-            acc.im[i][j] += m;
+            for (int k = 0; k < N; ++k) cmac(r, m, a.re[k][i], -a.im[k][i], b.re[k][j], b.im[k][j]);
+            acc.re[i][j] = r;
+            acc.im[i][j] = m;
         }
 }
 
 // acc += a b^dag
 template <int N, typename T>
 __device__ __forceinline__ void add_mul_nd(Mat<N, T>& acc, const Mat<N, T>& a, const Mat<N, T>& b) {
-    const Mat<N, T> c = mul_nd(a, b);
 SUN_MAT_UNROLL
     for (int i = 0; i < N; ++i)
 SUN_MAT_UNROLL
         for (int j = 0; j < N; ++j) {
-            acc.re[i][j] += c.re[i][j];
-            acc.im[i][j] += c.im[i][j];
+            T r = acc.re[i][j], m = acc.im[i][j];
+SUN_MAT_UNROLL
+            for (int k = 0; k < N; ++k) cmac(r, m, a.re[i][k], a.im[i][k], b.re[j][k], -b.im[j][k]);
+            acc.re[i][j] = r;
+            acc.im[i][j] = m;
         }
 }
 
@@ -258,10 +295,10 @@ struct Quat {
 template <typename T>
 __device__ __forceinline__ Quat<T> qmul(const Quat<T>& a, const Quat<T>& b) {
     Quat<T> c;
-    c.q[0] = a.q[0] * b.q[0] - a.q[1] * b.q[1] - a.q[2] * b.q[2] - a.q[3] * b.q[3];
-    c.q[1] = a.q[0] * b.q[1] + b.q[0] * a.q[1] - (a.q[2] * b.q[3] - a.q[3] * b.q[2]);
-    c.q[2] = a.q[0] * b.q[2] + b.q[0] * a.q[2] - (a.q[3] * b.q[1] - a.q[1] * b.q[3]);
-    c.q[3] = a.q[0] * b.q[3] + b.q[0] * a.q[3] - (a.q[1] * b.q[2] - a.q[2] * b.q[1]);
+    c.q[0] = fmadd(-a.q[3], b.q[3], fmadd(-a.q[2], b.q[2], fmadd(-a.q[1], b.q[1], a.q[0] * b.q[0])));
+    c.q[1] = fmadd(a.q[3], b.q[2], fmadd(-a.q[2], b.q[3], fmadd(b.q[0], a.q[1], a.q[0] * b.q[1])));
+    c.q[2] = fmadd(a.q[1], b.q[3], fmadd(-a.q[3], b.q[1], fmadd(b.q[0], a.q[2], a.q[0] * b.q[2])));
+    c.q[3] = fmadd(a.q[2], b.q[1], fmadd(-a.q[1], b.q[2], fmadd(b.q[0], a.q[3], a.q[0] * b.q[3])));
     return c;
 }
 
@@ -295,10 +332,10 @@ __device__ __forceinline__ void rows_left_mul(Mat<N, T>& M, int i, int j, const 
 SUN_MAT_UNROLL
     for (int c = 0; c < N; ++c) {
         const T xr = M.re[i][c], xi = M.im[i][c], yr = M.re[j][c], yi = M.im[j][c];
-        M.re[i][c] = a.q[0] * xr - a.q[3] * xi + a.q[2] * yr - a.q[1] * yi;
-        M.im[i][c] = a.q[0] * xi + a.q[3] * xr + a.q[2] * yi + a.q[1] * yr;
-        M.re[j][c] = -a.q[2] * xr - a.q[1] * xi + a.q[0] * yr + a.q[3] * yi;
-        M.im[j][c] = -a.q[2] * xi + a.q[1] * xr + a.q[0] * yi - a.q[3] * yr;
+        M.re[i][c] = fmadd(-a.q[1], yi, fmadd(a.q[2], yr, fmadd(-a.q[3], xi, a.q[0] * xr)));
+        M.im[i][c] = fmadd(a.q[1], yr, fmadd(a.q[2], yi, fmadd(a.q[3], xr, a.q[0] * xi)));
+        M.re[j][c] = fmadd(a.q[3], yi, fmadd(a.q[0], yr, fmadd(-a.q[1], xi, -a.q[2] * xr)));
+        M.im[j][c] = fmadd(-a.q[3], yr, fmadd(a.q[0], yi, fmadd(a.q[1], xr, -a.q[2] * xi)));
     }
 }
 
@@ -344,10 +381,14 @@ __device__ __forceinline__ void third_row(Mat<N, T>& m) {
 #pragma unroll
         for (int c = 0; c < 3; ++c) {
             const int a = (c + 1) % 3, b = (c + 2) % 3;
-            const T xr = m.re[0][a] * m.re[1][b] - m.im[0][a] * m.im[1][b] -
-                         (m.re[0][b] * m.re[1][a] - m.im[0][b] * m.im[1][a]);
-            const T xi = m.re[0][a] * m.im[1][b] + m.im[0][a] * m.re[1][b] -
-                         (m.re[0][b] * m.im[1][a] + m.im[0][b] * m.re[1][a]);
+            // (row0 x row1)_c = r0a r1b - r0b r1a, complex
+            T xr = m.re[0][a] * m.re[1][b], xi = m.re[0][a] * m.im[1][b];
+            xr = fmadd(-m.im[0][a], m.im[1][b], xr);
+            xi = fmadd(m.im[0][a], m.re[1][b], xi);
+            xr = fmadd(-m.re[0][b], m.re[1][a], xr);
+            xi = fmadd(-m.re[0][b], m.im[1][a], xi);
+            xr = fmadd(m.im[0][b], m.im[1][a], xr);
+            xi = fmadd(-m.im[0][b], m.re[1][a], xi);
             m.re[2][c] = xr;
             m.im[2][c] = -xi;
         }

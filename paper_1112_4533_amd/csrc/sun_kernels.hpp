@@ -11,6 +11,7 @@
 namespace sun {
 
 constexpr int kBlock = 256;  // 4 wave64 per workgroup
+static_assert(kBlock == 256, "plaquette_tiles counts 256-item workgroups");
 constexpr int kWaves = kBlock / 64;
 
 // ---------------------------------------------------------------------------
@@ -90,46 +91,66 @@ __global__ __launch_bounds__(kBlock) void k_finalize(const double* __restrict__ 
 //   U_nu(x+mu) U_mu(x+nu)^dag U_nu(x)^dag + U_nu(x+mu-nu)^dag U_mu(x-nu)^dag U_nu(x-nu)
 // so that ReTr(U_mu(x) A) is the sum of the plaquettes containing the link.
 // ---------------------------------------------------------------------------
+// One direction's two staples, added to A.  The direction is a template
+// parameter so that the whole staple is straight-line code: neighbour
+// coordinates and plane offsets are compile-time, and the scheduler can issue
+// the loads of later directions ahead of the arithmetic of earlier ones.
+template <int N, typename T, int R, int MU, int NU>
+__device__ __forceinline__ void staple_dir(Mat<N, T>& A, const T2<T>* __restrict__ U, const Geom& g, const Site& x,
+                                           const Site& xp, int par, int h) {
+    if constexpr (NU != MU) {
+        if (!((g.present >> NU) & 1)) return;
+        const int op = par ^ 1;
+        const Site xpn = step_up(g, x, NU);
+        const Site xmn = step_down(g, x, NU);
+        const Site xpmn = step_down(g, xp, NU);
+        const Mat<N, T> m = mul_nd(load_mat<N, T, R>(U, NU, op, xp.s >> 1, g.Vh),
+                                   load_mat<N, T, R>(U, MU, op, xpn.s >> 1, g.Vh));
+        add_mul_nd(A, m, load_mat<N, T, R>(U, NU, par, h, g.Vh));
+        const Mat<N, T> l = mul_nn(load_mat<N, T, R>(U, MU, op, xmn.s >> 1, g.Vh),
+                                   load_mat<N, T, R>(U, NU, par, xpmn.s >> 1, g.Vh));
+        add_mul_dn(A, l, load_mat<N, T, R>(U, NU, op, xmn.s >> 1, g.Vh));
+    }
+}
+
 template <int N, typename T, int R, int MU>
 __device__ __forceinline__ Mat<N, T> staple(const T2<T>* __restrict__ U, const Geom& g, const Site& x, int par,
                                             int h) {
-    const int op = par ^ 1;
     const Site xp = step_up(g, x, MU);
     Mat<N, T> A;
     set_zero(A);
-#pragma unroll
-    for (int nu = 0; nu < 4; ++nu) {
-        if (nu == MU || !((g.present >> nu) & 1)) continue;
-        const Site xpn = step_up(g, x, nu);
-        const Site xmn = step_down(g, x, nu);
-        const Site xpmn = step_down(g, xp, nu);
-        const Mat<N, T> m = mul_nd(load_mat<N, T, R>(U, nu, op, xp.s >> 1, g.Vh),
-                                   load_mat<N, T, R>(U, MU, op, xpn.s >> 1, g.Vh));
-        add_mul_nd(A, m, load_mat<N, T, R>(U, nu, par, h, g.Vh));
-        const Mat<N, T> l = mul_nn(load_mat<N, T, R>(U, MU, op, xmn.s >> 1, g.Vh),
-                                   load_mat<N, T, R>(U, nu, par, xpmn.s >> 1, g.Vh));
-        add_mul_dn(A, l, load_mat<N, T, R>(U, nu, op, xmn.s >> 1, g.Vh));
-    }
+    staple_dir<N, T, R, MU, 0>(A, U, g, x, xp, par, h);
+    staple_dir<N, T, R, MU, 1>(A, U, g, x, xp, par, h);
+    staple_dir<N, T, R, MU, 2>(A, U, g, x, xp, par, h);
+    staple_dir<N, T, R, MU, 3>(A, U, g, x, xp, par, h);
     return A;
+}
+
+template <typename T, int MU, int NU>
+__device__ __forceinline__ void staple_dir_su2(Quat<T>& A, const T2<T>* __restrict__ U, const Geom& g, const Site& x,
+                                               const Site& xp, int par, int h) {
+    if constexpr (NU != MU) {
+        if (!((g.present >> NU) & 1)) return;
+        const int op = par ^ 1;
+        const Site xpn = step_up(g, x, NU);
+        const Site xmn = step_down(g, x, NU);
+        const Site xpmn = step_down(g, xp, NU);
+        const Quat<T> m = qmul(load_quat<T>(U, NU, op, xp.s >> 1, g.Vh), qconj(load_quat<T>(U, MU, op, xpn.s >> 1, g.Vh)));
+        qadd(A, qmul(m, qconj(load_quat<T>(U, NU, par, h, g.Vh))));
+        const Quat<T> l = qmul(load_quat<T>(U, MU, op, xmn.s >> 1, g.Vh), load_quat<T>(U, NU, par, xpmn.s >> 1, g.Vh));
+        qadd(A, qmul(qconj(l), load_quat<T>(U, NU, op, xmn.s >> 1, g.Vh)));
+    }
 }
 
 template <typename T, int MU>
 __device__ __forceinline__ Quat<T> staple_su2(const T2<T>* __restrict__ U, const Geom& g, const Site& x, int par,
                                               int h) {
-    const int op = par ^ 1;
     const Site xp = step_up(g, x, MU);
     Quat<T> A{{T(0), T(0), T(0), T(0)}};
-#pragma unroll
-    for (int nu = 0; nu < 4; ++nu) {
-        if (nu == MU || !((g.present >> nu) & 1)) continue;
-        const Site xpn = step_up(g, x, nu);
-        const Site xmn = step_down(g, x, nu);
-        const Site xpmn = step_down(g, xp, nu);
-        const Quat<T> m = qmul(load_quat<T>(U, nu, op, xp.s >> 1, g.Vh), qconj(load_quat<T>(U, MU, op, xpn.s >> 1, g.Vh)));
-        qadd(A, qmul(m, qconj(load_quat<T>(U, nu, par, h, g.Vh))));
-        const Quat<T> l = qmul(load_quat<T>(U, MU, op, xmn.s >> 1, g.Vh), load_quat<T>(U, nu, par, xpmn.s >> 1, g.Vh));
-        qadd(A, qmul(qconj(l), load_quat<T>(U, nu, op, xmn.s >> 1, g.Vh)));
-    }
+    staple_dir_su2<T, MU, 0>(A, U, g, x, xp, par, h);
+    staple_dir_su2<T, MU, 1>(A, U, g, x, xp, par, h);
+    staple_dir_su2<T, MU, 2>(A, U, g, x, xp, par, h);
+    staple_dir_su2<T, MU, 3>(A, U, g, x, xp, par, h);
     return A;
 }
 
@@ -228,8 +249,8 @@ __device__ __forceinline__ void update_any(T2<T>* __restrict__ U, const Geom& g,
 
 template <int N, typename T, int R, bool HB, int MU, int BS>
 __global__ __launch_bounds__(BS) void k_update(T2<T>* __restrict__ U, Geom g, int par, T beta, uint32_t k0,
-                                               uint32_t k1, uint32_t step, int xcd) {
-    const int tile = xcd ? xcd_tile(blockIdx.x, gridDim.x) : (int)blockIdx.x;
+                                               uint32_t k1, uint32_t step, Walk walk) {
+    const int tile = walk_tile(blockIdx.x, gridDim.x, walk);
     const int h = tile * BS + threadIdx.x;
     if (h >= g.Vh) return;
     update_any<N, T, R, HB, MU>(U, g, par, h, beta, k0, k1, step);
@@ -567,17 +588,30 @@ SUN_MAT_UNROLL
     return t;
 }
 
-// Sums ReTr P over the planes of logical site s into acc = {planes without
-// direction 3, planes with direction 3}.  Work-items follow the logical site
-// order, so the +mu neighbours a site reads are a few work-items away.
+// Tile q of the plaquette grid covers parity q & 1 of checkerboard tile
+// walk(q >> 1): the two parities of one stretch of sites share their
+// neighbour links, and the t-blocked walk (4 time slices, where a plane holds
+// whole tiles) keeps the t-neighbours of a tile in L2.  The walk depends on
+// the geometry alone, so a chain's plaquette has the same bits alone and in a
+// batch.
+__device__ __forceinline__ void plaquette_tile(const Geom& g, int q, int& par, int& h) {
+    Walk w{0, 0, 1, 1};
+    const int plane_h = g.L[0] * g.L[1] / 2;
+    if (plane_h % kBlock == 0 && g.L[3] % 4 == 0) {
+        w.tb = 4;
+        w.tpp = plane_h / kBlock;
+        w.lz = g.L[2];
+    }
+    par = q & 1;
+    h = walk_tile(q >> 1, plaquette_tiles(g) >> 1, w) * kBlock + (int)threadIdx.x;
+}
+
+// Sums ReTr P over the planes of site (par, h) into acc = {planes without
+// direction 3, planes with direction 3}.
 template <int N, typename T, int R>
-__device__ __forceinline__ void plaquette_site(const T2<T>* __restrict__ U, const Geom& g, int s, double (&acc)[2]) {
-    if (s >= g.V) return;
-    const int q0 = s / g.L[0], x0 = s - q0 * g.L[0];
-    const int q1 = q0 / g.L[1], x1 = q0 - q1 * g.L[1];
-    const int q2 = q1 / g.L[2], x2 = q1 - q2 * g.L[2];
-    const int par = (x0 + x1 + x2 + q2) & 1;
-    const int h = s >> 1;
+__device__ __forceinline__ void plaquette_site(const T2<T>* __restrict__ U, const Geom& g, int par, int h,
+                                               double (&acc)[2]) {
+    if (h >= g.Vh) return;
     const Site x = site_of(g, par, h);
     const int p = g.present;
 #define SUN_PLAQ(m, n, slot) \
@@ -591,13 +625,16 @@ __device__ __forceinline__ void plaquette_site(const T2<T>* __restrict__ U, cons
 #undef SUN_PLAQ
 }
 
+// Grid: plaquette_tiles(g) workgroups; partial[2 q .. 2 q + 1] per tile q.
 template <int N, typename T, int R>
 __global__ __launch_bounds__(kBlock) void k_plaquette(const T2<T>* __restrict__ U, Geom g,
                                                       double* __restrict__ partial) {
-    const int tile = xcd_tile(blockIdx.x, gridDim.x);
+    const int q = xcd_tile(blockIdx.x, gridDim.x);
+    int par, h;
+    plaquette_tile(g, q, par, h);
     double acc[2] = {0.0, 0.0};
-    plaquette_site<N, T, R>(U, g, tile * kBlock + threadIdx.x, acc);
-    block_sum<2>(acc, partial + 2 * (size_t)tile);
+    plaquette_site<N, T, R>(U, g, par, h, acc);
+    block_sum<2>(acc, partial + 2 * (size_t)q);
 }
 
 // Batched plaquette: each chain's per-tile partials go to that chain's own
@@ -607,8 +644,10 @@ __global__ __launch_bounds__(kBlock) void k_plaquette_batch(const ChainDesc* __r
     const int tile = xcd_tile(blockIdx.x, gridDim.x);
     const int c = find_chain<TILE_SITE>(d, n, tile);
     const int local = tile - d[c].tile0[TILE_SITE];
+    int par, h;
+    plaquette_tile(d[c].g, local, par, h);
     double acc[2] = {0.0, 0.0};
-    plaquette_site<N, T, R>((const T2<T>*)d[c].links, d[c].g, local * kBlock + threadIdx.x, acc);
+    plaquette_site<N, T, R>((const T2<T>*)d[c].links, d[c].g, par, h, acc);
     block_sum<2>(acc, d[c].scratch + 2 * (size_t)local);
 }
 
@@ -664,8 +703,7 @@ __global__ __launch_bounds__(kBlock) void k_plaquette_final_batch(const ChainDes
     if (c >= n) return;
     double sp, tm, all;
     plaquette_norms<N>(d[c].g, sp, tm, all);
-    plaquette_final<2>(d[c].scratch, (d[c].g.V + kBlock - 1) / kBlock, out + 3 * (size_t)d[c].out_index, sp, tm,
-                       all);
+    plaquette_final<2>(d[c].scratch, plaquette_tiles(d[c].g), out + 3 * (size_t)d[c].out_index, sp, tm, all);
 }
 
 // ---------------------------------------------------------------------------

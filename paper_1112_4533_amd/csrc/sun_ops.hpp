@@ -14,7 +14,22 @@ struct Shape {
     int block = 256;  // work-items per workgroup (64, 128 or 256)
     int xcd = 1;      // XCD-aware workgroup order
     int waves = 0;    // resident waves per CU (0 = no cap)
+    int tblock = 0;   // time slices per block of the tile walk (0: linear)
 };
+
+// The walk of a single lattice's phase for a shape; falls back to the linear
+// walk where the t-blocked one is not a permutation of the tiles.
+inline Walk walk_for(const Geom& g, const Shape& sh) {
+    Walk w{sh.xcd, 0, 1, 1};
+    const long long plane_h = (long long)g.L[0] * g.L[1] / 2;
+    if (sh.tblock > 1 && plane_h % sh.block == 0 && g.L[3] % sh.tblock == 0) {
+        w.tb = sh.tblock;
+        w.tpp = (int)(plane_h / sh.block);
+        w.lz = g.L[2];
+    }
+    return w;
+}
+inline bool valid_tblock(int t) { return t == 0 || t == 1 || t == 2 || t == 4 || t == 8; }
 
 struct Ctx {
     void* links;
@@ -47,7 +62,7 @@ struct Ops {
     // partial: 2 doubles per block of link_blocks(g), or null
     void (*reunit)(const Ctx&, double* partial);
     void (*unitarity)(const Ctx&, double* partial);
-    // partial: 2 doubles per block of site_blocks(g)
+    // partial: 2 doubles per tile of plaquette_tiles(g)
     void (*plaquette)(const Ctx&, double* partial);
     // partial: 2 doubles per block of spatial_blocks(g)
     void (*polyakov)(const Ctx&, double* partial);
@@ -64,7 +79,6 @@ struct Ops {
 constexpr int kLaunchBlock = 256;
 inline int blocks_for(long long n) { return (int)((n + kLaunchBlock - 1) / kLaunchBlock); }
 inline int link_blocks(const Geom& g) { return blocks_for(4LL * g.V); }
-inline int site_blocks(const Geom& g) { return blocks_for(g.V); }
 inline int half_blocks(const Geom& g) { return blocks_for(g.Vh); }
 inline int half_blocks(const Geom& g, int bs) { return (g.Vh + bs - 1) / bs; }
 inline int spatial_blocks(const Geom& g) { return blocks_for(g.V / g.L[3]); }

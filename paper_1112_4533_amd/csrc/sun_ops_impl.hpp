@@ -15,18 +15,19 @@ struct OpsImpl {
         P* u = (P*)c.links;
         const Shape& sh = c.shape[HB ? 0 : 1];
         const int lds = lds_for_wave_cap(sh.waves, sh.block);
+        const Walk w = walk_for(c.g, sh);
         switch (sh.block) {
             case 64:
                 k_update<N, T, R, HB, MU, 64><<<half_blocks(c.g, 64), 64, lds, c.stream>>>(u, c.g, par, beta, k0, k1,
-                                                                                            step, sh.xcd);
+                                                                                            step, w);
                 break;
             case 128:
                 k_update<N, T, R, HB, MU, 128><<<half_blocks(c.g, 128), 128, lds, c.stream>>>(u, c.g, par, beta, k0,
-                                                                                              k1, step, sh.xcd);
+                                                                                              k1, step, w);
                 break;
             default:
                 k_update<N, T, R, HB, MU, 256><<<half_blocks(c.g, 256), 256, lds, c.stream>>>(u, c.g, par, beta, k0,
-                                                                                              k1, step, sh.xcd);
+                                                                                              k1, step, w);
                 break;
         }
     }
@@ -101,7 +102,7 @@ struct OpsImpl {
         k_unitarity<N, T, R><<<link_blocks(c.g), kBlock, 0, c.stream>>>((const P*)c.links, c.g, partial);
     }
     static void plaquette(const Ctx& c, double* partial) {
-        k_plaquette<N, T, R><<<site_blocks(c.g), kBlock, 0, c.stream>>>((const P*)c.links, c.g, partial);
+        k_plaquette<N, T, R><<<plaquette_tiles(c.g), kBlock, 0, c.stream>>>((const P*)c.links, c.g, partial);
     }
     static void polyakov(const Ctx& c, double* partial) {
         k_polyakov<N, T, R><<<spatial_blocks(c.g), kBlock, 0, c.stream>>>((const P*)c.links, c.g, partial);

@@ -63,8 +63,9 @@ def load():
         "sun_batch_capture": [vp, c_int, c_int, c_int, c_int, vp, vp],
         "sun_batch_replay": [vp, vp],
         "sun_batch_sync": [vp],
-        "sun_set_launch": [vp, c_int, c_int, c_int, c_int],
-        "sun_get_launch": [vp, c_int, ctypes.POINTER(c_int), ctypes.POINTER(c_int), ctypes.POINTER(c_int)],
+        "sun_set_launch": [vp, c_int, c_int, c_int, c_int, c_int],
+        "sun_get_launch": [vp, c_int, ctypes.POINTER(c_int), ctypes.POINTER(c_int), ctypes.POINTER(c_int),
+                           ctypes.POINTER(c_int)],
         "sun_batch_set_launch": [vp, c_int, c_int, c_int, c_int],
     }
     for name, args in sigs.items():
@@ -225,18 +226,22 @@ class Lattice:
         _check(load().sun_set_step(self._h, int(value)))
 
     # -- launch shape (tuning only; results do not depend on it) ---------
-    # (work-items per workgroup, XCD-aware order, resident-wave cap per CU)
-    LAUNCH_SHAPES = [(b, x, w) for b in (64, 128, 256) for x in (1, 0) for w in (8, 12, 16, 0)]
+    # (work-items per workgroup, XCD-aware order, resident-wave cap per CU,
+    #  time slices per block of the tile walk)
+    LAUNCH_SHAPES = [(b, x, w, t) for b in (64, 128, 256) for x in (1, 0) for w in (8, 12, 16, 0)
+                     for t in (0, 2, 4, 8)]
 
-    def set_launch(self, block=256, xcd=1, waves=0, kind=-1):
+    def set_launch(self, block=256, xcd=1, waves=0, tblock=0, kind=-1):
         """Launch shape of the heatbath (kind 0), overrelaxation (1) or both
         (-1) phase kernels."""
-        _check(load().sun_set_launch(self._h, int(kind), int(block), int(xcd), int(waves)))
+        _check(load().sun_set_launch(self._h, int(kind), int(block), int(xcd), int(waves), int(tblock)))
 
     def get_launch(self, kind):
-        b, x, w = ctypes.c_int(), ctypes.c_int(), ctypes.c_int()
-        _check(load().sun_get_launch(self._h, int(kind), ctypes.byref(b), ctypes.byref(x), ctypes.byref(w)))
-        return b.value, x.value, w.value
+        """(block, xcd, waves, tblock in effect) of one update kind."""
+        b, x, w, t = ctypes.c_int(), ctypes.c_int(), ctypes.c_int(), ctypes.c_int()
+        _check(load().sun_get_launch(self._h, int(kind), ctypes.byref(b), ctypes.byref(x), ctypes.byref(w),
+                                     ctypes.byref(t)))
+        return b.value, x.value, w.value, t.value
 
     @property
     def launch(self):
@@ -259,6 +264,10 @@ class Batch:
     The lattices keep their fields; while the batch is in use they should be
     driven only through it (sync() hands the step counters back)."""
 
+    # (work-items per workgroup, XCD-aware order, resident-wave cap per CU);
+    # batches always walk their tiles linearly
+    LAUNCH_SHAPES = [(b, x, w) for b in (64, 128, 256) for x in (1, 0) for w in (8, 12, 16, 0)]
+
     def __init__(self, lattices, betas, seeds):
         self.lattices = list(lattices)
         n = len(self.lattices)
@@ -277,7 +286,7 @@ class Batch:
         self.n = n
         self.betas = [float(x) for x in betas]
         self.seeds = [int(x) for x in seeds]
-        self.launch = [(256, 1, 0), (256, 1, 12)]   # heatbath, overrelaxation
+        self.launch = [(256, 1, 0), (256, 1, 12)]   # heatbath, overrelaxation (block, xcd, waves)
         self.stream = torch.cuda.Stream(device=dev)   # graphs need a non-null stream
 
     def __del__(self):

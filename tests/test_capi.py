@@ -82,18 +82,37 @@ def test_create_validates_buffers_without_touching_them(lib):
     assert lib.sun_sweep(h, 6.0, -1, 0, 1, 1, None) == -1
     assert lib.sun_plaquette(h, None, None) == -2
     assert lib.sun_profile_read(h, 9, None, None) == -1
-    # launch shapes: only the instantiated workgroup sizes
-    b, x, w = ctypes.c_int(), ctypes.c_int(), ctypes.c_int()
-    get = lambda k: (lib.sun_get_launch(h, k, ctypes.byref(b), ctypes.byref(x), ctypes.byref(w)),
-                     b.value, x.value, w.value)
-    assert get(0) == (0, 256, 1, 0) and get(1) == (0, 256, 1, 12)
-    assert lib.sun_set_launch(h, -1, 100, 1, 8) == -1
-    assert lib.sun_set_launch(h, -1, 64, 1, 5) == -1
-    assert lib.sun_set_launch(h, 2, 64, 1, 8) == -1
-    assert lib.sun_set_launch(h, 1, 64, 0, 16) == 0
-    assert get(0) == (0, 256, 1, 0) and get(1) == (0, 64, 0, 16)
-    assert lib.sun_set_launch(h, -1, 128, 1, 8) == 0
-    assert get(0) == (0, 128, 1, 8) and get(1) == (0, 128, 1, 8)
+    # launch shapes: only the instantiated workgroup sizes, wave caps and walks
+    b, x, w, t = ctypes.c_int(), ctypes.c_int(), ctypes.c_int(), ctypes.c_int()
+    get = lambda k: (lib.sun_get_launch(h, k, ctypes.byref(b), ctypes.byref(x), ctypes.byref(w), ctypes.byref(t)),
+                     b.value, x.value, w.value, t.value)
+    # (a 4^4 plane holds 8 checkerboard sites: the default t-blocked walk
+    # falls back to the linear one and reports 0)
+    assert get(0) == (0, 256, 1, 0, 0) and get(1) == (0, 256, 1, 12, 0)
+    assert lib.sun_set_launch(h, -1, 100, 1, 8, 0) == -1
+    assert lib.sun_set_launch(h, -1, 64, 1, 5, 0) == -1
+    assert lib.sun_set_launch(h, 2, 64, 1, 8, 0) == -1
+    assert lib.sun_set_launch(h, -1, 64, 1, 8, 3) == -1
+    assert lib.sun_set_launch(h, 1, 64, 0, 16, 0) == 0
+    assert get(0) == (0, 256, 1, 0, 0) and get(1) == (0, 64, 0, 16, 0)
+    assert lib.sun_set_launch(h, -1, 128, 1, 8, 0) == 0
+    assert get(0) == (0, 128, 1, 8, 0) and get(1) == (0, 128, 1, 8, 0)
+    assert lib.sun_get_launch(h, 0, None, None, None, None) == -1
+    # a 4^4 plane holds 8 checkerboard sites: no whole workgroup, linear walk
+    assert lib.sun_set_launch(h, -1, 64, 1, 0, 4) == 0
+    assert get(1) == (0, 64, 1, 0, 0)
+    lib.sun_lattice_destroy(h)
+    # the t-blocked walk needs L_t % tblock == 0 and L_x L_y / 2 % block == 0
+    L2 = (16, 16, 4, 8)
+    rc, lb, sb = _bytes(lib, 3, L2, 0)
+    assert lib.sun_lattice_create(3, (ctypes.c_int * 4)(*L2), 0, ctypes.c_void_p(0x10000), lb,
+                                  ctypes.c_void_p(0x20000), sb, ctypes.byref(h)) == 0
+    assert get(0) == (0, 256, 1, 0, 0)           # 128 sites per plane: no whole 256-item tile
+    assert lib.sun_set_launch(h, -1, 128, 1, 0, 4) == 0
+    assert get(0) == (0, 128, 1, 0, 4) and get(1) == (0, 128, 1, 0, 4)
+    for block, tb, want in [(64, 4, 4), (128, 8, 8), (128, 2, 2), (256, 4, 0), (64, 1, 0), (64, 0, 0)]:
+        assert lib.sun_set_launch(h, 1, block, 1, 12, tb) == 0
+        assert get(1) == (0, block, 1, 12, want), (block, tb)
     lib.sun_lattice_destroy(h)
 
 
