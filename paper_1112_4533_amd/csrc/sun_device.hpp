@@ -282,6 +282,71 @@ SUN_MAT_UNROLL
         }
 }
 
+// Partial products for SU(3) staple terms (3x3; only the named rows or
+// columns of the result are written).
+
+// rows 0, 1 of a b^dag (reads rows 0, 1 of a)
+template <typename T>
+__device__ __forceinline__ Mat<3, T> mul_nd_rows2(const Mat<3, T>& a, const Mat<3, T>& b) {
+    Mat<3, T> c;
+#pragma unroll
+    for (int i = 0; i < 2; ++i)
+#pragma unroll
+        for (int j = 0; j < 3; ++j) {
+            T r = T(0), m = T(0);
+#pragma unroll
+            for (int k = 0; k < 3; ++k) cmac(r, m, a.re[i][k], a.im[i][k], b.re[j][k], -b.im[j][k]);
+            c.re[i][j] = r;
+            c.im[i][j] = m;
+        }
+    return c;
+}
+
+// columns 0, 1 of a b (reads columns 0, 1 of b)
+template <typename T>
+__device__ __forceinline__ Mat<3, T> mul_nn_cols2(const Mat<3, T>& a, const Mat<3, T>& b) {
+    Mat<3, T> c;
+#pragma unroll
+    for (int i = 0; i < 3; ++i)
+#pragma unroll
+        for (int j = 0; j < 2; ++j) {
+            T r = T(0), m = T(0);
+#pragma unroll
+            for (int k = 0; k < 3; ++k) cmac(r, m, a.re[i][k], a.im[i][k], b.re[k][j], b.im[k][j]);
+            c.re[i][j] = r;
+            c.im[i][j] = m;
+        }
+    return c;
+}
+
+// rows 0, 1 of a^dag b (reads columns 0, 1 of a)
+template <typename T>
+__device__ __forceinline__ Mat<3, T> mul_dn_rows2(const Mat<3, T>& a, const Mat<3, T>& b) {
+    Mat<3, T> c;
+#pragma unroll
+    for (int i = 0; i < 2; ++i)
+#pragma unroll
+        for (int j = 0; j < 3; ++j) {
+            T r = T(0), m = T(0);
+#pragma unroll
+            for (int k = 0; k < 3; ++k) cmac(r, m, a.re[k][i], -a.im[k][i], b.re[k][j], b.im[k][j]);
+            c.re[i][j] = r;
+            c.im[i][j] = m;
+        }
+    return c;
+}
+
+template <int N, typename T>
+__device__ __forceinline__ void add_to(Mat<N, T>& acc, const Mat<N, T>& a) {
+SUN_MAT_UNROLL
+    for (int i = 0; i < N; ++i)
+SUN_MAT_UNROLL
+        for (int j = 0; j < N; ++j) {
+            acc.re[i][j] += a.re[i][j];
+            acc.im[i][j] += a.im[i][j];
+        }
+}
+
 // ---------------------------------------------------------------------------
 // Quaternions: q <-> [[q0 + i q3, q2 + i q1], [-q2 + i q1, q0 - i q3]]
 // (paper Sec. 2, U = a0 + i a.sigma).  Product:
@@ -375,23 +440,26 @@ __device__ __forceinline__ const T2<T>* plane0(const T2<T>* base, int mu, int pa
 }
 
 // Row 2 of an SU(3) matrix from rows 0 and 1: conj(row0 x row1).
+template <typename T>
+__device__ __forceinline__ void third_row_entry(Mat<3, T>& m, int c) {
+    const int a = (c + 1) % 3, b = (c + 2) % 3;
+    // (row0 x row1)_c = r0a r1b - r0b r1a, complex
+    T xr = m.re[0][a] * m.re[1][b], xi = m.re[0][a] * m.im[1][b];
+    xr = fmadd(-m.im[0][a], m.im[1][b], xr);
+    xi = fmadd(m.im[0][a], m.re[1][b], xi);
+    xr = fmadd(-m.re[0][b], m.re[1][a], xr);
+    xi = fmadd(-m.re[0][b], m.im[1][a], xi);
+    xr = fmadd(m.im[0][b], m.im[1][a], xr);
+    xi = fmadd(-m.im[0][b], m.re[1][a], xi);
+    m.re[2][c] = xr;
+    m.im[2][c] = -xi;
+}
+
 template <int N, typename T>
 __device__ __forceinline__ void third_row(Mat<N, T>& m) {
     if constexpr (N == 3) {
 #pragma unroll
-        for (int c = 0; c < 3; ++c) {
-            const int a = (c + 1) % 3, b = (c + 2) % 3;
-            // (row0 x row1)_c = r0a r1b - r0b r1a, complex
-            T xr = m.re[0][a] * m.re[1][b], xi = m.re[0][a] * m.im[1][b];
-            xr = fmadd(-m.im[0][a], m.im[1][b], xr);
-            xi = fmadd(m.im[0][a], m.re[1][b], xi);
-            xr = fmadd(-m.re[0][b], m.re[1][a], xr);
-            xi = fmadd(-m.re[0][b], m.im[1][a], xi);
-            xr = fmadd(m.im[0][b], m.im[1][a], xr);
-            xi = fmadd(-m.im[0][b], m.re[1][a], xi);
-            m.re[2][c] = xr;
-            m.im[2][c] = -xi;
-        }
+        for (int c = 0; c < 3; ++c) third_row_entry<T>(m, c);
     }
 }
 
@@ -406,6 +474,40 @@ SUN_MAT_UNROLL
         m.im[e / N][e % N] = v.y;
     }
     if constexpr (R < N) third_row(m);
+    return m;
+}
+
+// Rows 0 and 1 of an SU(3) link (row 2 left unset), either storage.
+template <typename T, int R>
+__device__ __forceinline__ Mat<3, T> load_rows01(const T2<T>* base, int mu, int par, int h, int Vh) {
+    const T2<T>* p = plane0<3, T, R>(base, mu, par, Vh) + h;
+    Mat<3, T> m;
+#pragma unroll
+    for (int e = 0; e < 6; ++e) {
+        const T2<T> v = p[(size_t)e * Vh];
+        m.re[e / 3][e % 3] = v.x;
+        m.im[e / 3][e % 3] = v.y;
+    }
+    return m;
+}
+
+// Columns 0 and 1 of an SU(3) link (entry (2, 2) left unset): the two-row
+// form rebuilds only those two entries of row 2.
+template <typename T, int R>
+__device__ __forceinline__ Mat<3, T> load_cols01(const T2<T>* base, int mu, int par, int h, int Vh) {
+    Mat<3, T> m = load_rows01<T, R>(base, mu, par, h, Vh);
+    if constexpr (R == 3) {
+        const T2<T>* p = plane0<3, T, 3>(base, mu, par, Vh) + h;
+#pragma unroll
+        for (int e = 6; e < 8; ++e) {
+            const T2<T> v = p[(size_t)e * Vh];
+            m.re[2][e - 6] = v.x;
+            m.im[2][e - 6] = v.y;
+        }
+    } else {
+        third_row_entry<T>(m, 0);
+        third_row_entry<T>(m, 1);
+    }
     return m;
 }
 
