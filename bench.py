@@ -85,6 +85,9 @@ def roofline(run, r):
             "traffic": stored_traffic(run.name), "bytes_per_launch": per_launch, "avg_launch_ms": k["avg_ms"]}
 
 
+PROFILE_EVERY = 5
+
+
 def run_gpu(run, steps, warmup, tune=False):
     import torch
     from paper_1112_4533_amd import autotune, sun
@@ -108,7 +111,12 @@ def run_gpu(run, steps, warmup, tune=False):
     for _ in range(warmup):
         step()
     torch.cuda.synchronize()
-    lat.profile(True)
+    # HIP events bracket one launch in PROFILE_EVERY of each kernel kind in
+    # the timed region (a period coprime to the 8 phases of an update step,
+    # so every direction and parity is sampled); an event pair costs a few
+    # microseconds of stream time, and timing every launch would slow the
+    # step by about a tenth
+    lat.profile(True, every=PROFILE_EVERY)
     torch.cuda.synchronize()
     t0 = time.perf_counter()
     for _ in range(steps):

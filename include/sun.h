@@ -145,12 +145,17 @@ int sun_set_step(sun_lattice_t h, uint64_t step);
 int sun_set_launch(sun_lattice_t h, int kind, int block, int xcd, int waves, int tblock);
 int sun_get_launch(sun_lattice_t h, int kind, int *block, int *xcd, int *waves, int *tblock);
 
-/* Per-kernel timing with HIP events recorded around each launch on the
- * launch stream.  kernel: 0 heatbath phase, 1 overrelaxation phase,
- * 2 re-unitarization, 3 plaquette, 4 Polyakov loop.  sun_profile(h, 1)
- * clears and starts recording; sun_profile_read synchronizes the recorded
- * events and returns the summed milliseconds and the launch count. */
-int sun_profile(sun_lattice_t h, int enable);
+/* Per-kernel timing with HIP events recorded around launches on the launch
+ * stream.  kernel: 0 heatbath phase, 1 overrelaxation phase,
+ * 2 re-unitarization, 3 plaquette, 4 Polyakov loop.  sun_profile(h, every)
+ * clears the totals and, for every > 0, brackets one launch in `every` of
+ * each kernel kind with an event pair (1: every launch; a period coprime to
+ * the 8 phases of an update step samples all directions and parities);
+ * every = 0 stops recording.  An event pair costs a few microseconds of
+ * stream time, so sampling keeps timed runs close to unprofiled ones.
+ * sun_profile_read synchronizes the recorded events and returns the summed
+ * milliseconds and the number of launches recorded. */
+int sun_profile(sun_lattice_t h, int every);
 int sun_profile_read(sun_lattice_t h, int kernel, double *total_ms, int64_t *launches);
 
 /* The SU(2) heatbath draw alone (paper Sec. 2, SU(2) heatbath), for tests:

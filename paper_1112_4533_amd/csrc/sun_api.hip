@@ -53,6 +53,8 @@ struct sun_lattice_s {
     const sun::Ops* ops = nullptr;
     // event timing
     bool profiling = false;
+    int profile_every = 1;           // record one launch in this many per kernel kind
+    int64_t seen[kKernels] = {};     // launches issued since profiling started
     struct Pending {
         int kernel;
         hipEvent_t a, b;
@@ -149,8 +151,11 @@ struct Timed {
     hipStream_t s;
     hipEvent_t a = nullptr, b = nullptr;
     int rc = SUN_OK;
+    bool on = false;
     Timed(sun_lattice_s* h_, int k, hipStream_t s_) : h(h_), kernel(k), s(s_) {
         if (!h->profiling) return;
+        if (h->seen[k]++ % h->profile_every != 0) return;
+        on = true;
         for (hipEvent_t* e : {&a, &b}) {
             if (!h->pool.empty()) {
                 *e = h->pool.back();
@@ -162,7 +167,7 @@ struct Timed {
         rc = hip_check(hipEventRecord(a, s), "hipEventRecord");
     }
     int done() {
-        if (!h->profiling || rc != SUN_OK) return rc;
+        if (!on || rc != SUN_OK) return rc;
         rc = hip_check(hipEventRecord(b, s), "hipEventRecord");
         if (rc == SUN_OK) h->pending.push_back({kernel, a, b});
         return rc;
@@ -360,8 +365,9 @@ int sun_get_launch(sun_lattice_t h, int kind, int* block, int* xcd, int* waves, 
     return SUN_OK;
 }
 
-int sun_profile(sun_lattice_t h, int enable) {
+int sun_profile(sun_lattice_t h, int every) {
     if (!h) return fail(SUN_EINVAL, "null handle");
+    if (every < 0) return fail(SUN_EINVAL, "profile sampling period %d", every);
     for (auto& p : h->pending) {
         if (int rc = hip_check(hipEventSynchronize(p.b), "hipEventSynchronize")) return rc;
         h->pool.push_back(p.a);
@@ -371,8 +377,10 @@ int sun_profile(sun_lattice_t h, int enable) {
     for (int k = 0; k < kKernels; ++k) {
         h->total_ms[k] = 0.0;
         h->launches[k] = 0;
+        h->seen[k] = 0;
     }
-    h->profiling = enable != 0;
+    h->profiling = every != 0;
+    h->profile_every = every > 0 ? every : 1;
     return SUN_OK;
 }
 

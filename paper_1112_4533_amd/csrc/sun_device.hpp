@@ -30,8 +30,10 @@ __device__ __forceinline__ U4 philox(uint32_t c0, uint32_t c1, uint32_t c2, uint
                                      uint32_t k1) {
 #pragma unroll
     for (int r = 0; r < 10; ++r) {
-        const uint32_t lo0 = 0xD2511F53u * c0, hi0 = __umulhi(0xD2511F53u, c0);
-        const uint32_t lo1 = 0xCD9E8D57u * c2, hi1 = __umulhi(0xCD9E8D57u, c2);
+        // one 32 x 32 -> 64-bit product gives both halves in one instruction
+        const uint64_t p0 = (uint64_t)0xD2511F53u * c0, p1 = (uint64_t)0xCD9E8D57u * c2;
+        const uint32_t lo0 = (uint32_t)p0, hi0 = (uint32_t)(p0 >> 32);
+        const uint32_t lo1 = (uint32_t)p1, hi1 = (uint32_t)(p1 >> 32);
         const uint32_t n0 = hi1 ^ c1 ^ k0, n2 = hi0 ^ c3 ^ k1;
         c0 = n0;
         c1 = lo1;
@@ -635,6 +637,16 @@ __device__ __forceinline__ double d_sin(double x) { return sin(x); }
 __device__ __forceinline__ float d_sqrt(float x) { return sqrtf(x); }
 __device__ __forceinline__ double d_sqrt(double x) { return sqrt(x); }
 
+// The SU(2) draw in FP32 uses the hardware logarithm and cosine/sine
+// (relative error ~1e-7, far inside the FP32 comparison tolerance); the FP64
+// draw keeps the correctly rounded routines.
+__device__ __forceinline__ float draw_log(float x) { return __logf(x); }
+__device__ __forceinline__ double draw_log(double x) { return log(x); }
+__device__ __forceinline__ float draw_cos(float x) { return __cosf(x); }
+__device__ __forceinline__ double draw_cos(double x) { return cos(x); }
+__device__ __forceinline__ float draw_sin(float x) { return __sinf(x); }
+__device__ __forceinline__ double draw_sin(double x) { return sin(x); }
+
 template <typename T>
 struct Const {
     static constexpr T two_pi = T(6.283185307179586476925286766559);
@@ -671,8 +683,8 @@ __device__ __forceinline__ int sample_su2(T alpha, uint32_t k0, uint32_t k1, uin
                 break;
             }
         } else {
-            const T c = d_cos(Const<T>::two_pi * r1);
-            const T lam2 = -(d_log(r0) + c * c * d_log(r2)) / (T(2) * alpha);
+            const T c = draw_cos(Const<T>::two_pi * r1);
+            const T lam2 = -(draw_log(r0) + c * c * draw_log(r2)) / (T(2) * alpha);
             const T rhs = T(1) - lam2;
             if (r3 * r3 <= rhs) {
                 x0 = T(1) - T(2) * lam2;
@@ -688,8 +700,8 @@ __device__ __forceinline__ int sample_su2(T alpha, uint32_t k0, uint32_t k1, uin
     const T sin_t = d_sqrt(T(1) - cos_t * cos_t);
     const T phi = Const<T>::two_pi * uniform<T>(d.w[1]);
     x.q[0] = x0;
-    x.q[1] = rad * sin_t * d_cos(phi);
-    x.q[2] = rad * sin_t * d_sin(phi);
+    x.q[1] = rad * sin_t * draw_cos(phi);
+    x.q[2] = rad * sin_t * draw_sin(phi);
     x.q[3] = rad * cos_t;
     return hit + 1;
 }

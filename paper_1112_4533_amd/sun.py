@@ -249,8 +249,10 @@ class Lattice:
         return self.get_launch(HEATBATH), self.get_launch(OVERRELAX)
 
     # -- event timing ----------------------------------------------------
-    def profile(self, enable=True):
-        _check(load().sun_profile(self._h, int(bool(enable))))
+    def profile(self, enable=True, every=1):
+        """Starts (or with enable=False stops) event timing of one launch in
+        `every` per kernel kind; clears the totals."""
+        _check(load().sun_profile(self._h, int(every) if enable else 0))
 
     def profile_read(self, kernel):
         ms, n = ctypes.c_double(), ctypes.c_int64()

@@ -82,6 +82,7 @@ def test_create_validates_buffers_without_touching_them(lib):
     assert lib.sun_sweep(h, 6.0, -1, 0, 1, 1, None) == -1
     assert lib.sun_plaquette(h, None, None) == -2
     assert lib.sun_profile_read(h, 9, None, None) == -1
+    assert lib.sun_profile(h, -1) == -1
     # launch shapes: only the instantiated workgroup sizes, wave caps and walks
     b, x, w, t = ctypes.c_int(), ctypes.c_int(), ctypes.c_int(), ctypes.c_int()
     get = lambda k: (lib.sun_get_launch(h, k, ctypes.byref(b), ctypes.byref(x), ctypes.byref(w), ctypes.byref(t)),

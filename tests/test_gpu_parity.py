@@ -438,7 +438,15 @@ def test_profile_counts_launches(gpu):
     ms_or, n_or = lat.profile_read("overrelax")
     assert (n_hb, n_or) == (8, 32) and ms_hb > 0 and ms_or > 0
     assert lat.profile_read("reunit")[1] == 1 and lat.profile_read("plaquette")[1] == 1
+    # sampled: launches 0, 5, 10, ... of each kind are timed
+    lat.profile(True, every=5)
+    lat.sweep(6.0, 1, 4, seed=1)
+    lat.sweep(6.0, 1, 4, seed=1)
+    assert lat.profile_read("heatbath")[1] == 4 and lat.profile_read("overrelax")[1] == 13
+    assert lat.profile_read("reunit")[1] == 1
     lat.profile(False)
+    lat.sweep(6.0, 1, 4, seed=1)
+    assert lat.profile_read("overrelax")[1] == 0
 
 
 def test_rejects_bad_arguments(gpu):
