@@ -128,7 +128,9 @@ size_t link_bytes_of(int nc, const sun::Geom& g, int dtype) {
 }
 
 size_t scratch_bytes_of(const sun::Geom& g) {
-    const int nblk = std::max(sun::link_blocks(g), sun::plaquette_tiles(g));  // the largest partial array
+    // the largest partial array: per link block, per plaquette tile, or per
+    // Polyakov workgroup (at least 32 spatial sites each)
+    const int nblk = std::max({sun::link_blocks(g), sun::plaquette_tiles(g), (g.V / g.L[3] + 31) / 32});
     const size_t b = 2 * sizeof(double) * (size_t)nblk;
     return (b + 255) & ~(size_t)255;
 }
@@ -306,8 +308,8 @@ int sun_polyakov(sun_lattice_t h, double* dev_out2, sun_stream_t stream) {
     Timed t(h, 4, s);
     if (t.rc) return t.rc;
     const double Vs = (double)(h->g.V / h->g.L[3]);
-    h->ops->polyakov(h->ctx(s), h->scratch);
-    sun::launch_finalize_sum2(h->scratch, sun::spatial_blocks(h->g), dev_out2, 1.0 / (h->nc * Vs), s);
+    const int nblk = h->ops->polyakov(h->ctx(s), h->scratch);
+    sun::launch_finalize_sum2(h->scratch, nblk, dev_out2, 1.0 / (h->nc * Vs), s);
     if (int rc = launch_check("polyakov")) return rc;
     return t.done();
 }

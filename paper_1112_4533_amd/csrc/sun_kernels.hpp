@@ -442,8 +442,8 @@ template <int N>
 __device__ __forceinline__ void normalize_row(Mat<N, double>& M, int i) {
     double s = 0.0;
 SUN_MAT_UNROLL
-    for (int c = 0; c < N; ++c) s += M.re[i][c] * M.re[i][c] + M.im[i][c] * M.im[i][c];
-    const double inv = 1.0 / sqrt(s);
+    for (int c = 0; c < N; ++c) s = fmadd(M.im[i][c], M.im[i][c], fmadd(M.re[i][c], M.re[i][c], s));
+    const double inv = rsqrt(s);
 SUN_MAT_UNROLL
     for (int c = 0; c < N; ++c) {
         M.re[i][c] *= inv;
@@ -469,30 +469,15 @@ SUN_MAT_UNROLL
             for (int k = 0; k < i; ++k) {
                 double pr = 0.0, pi = 0.0;  // <r_k, r_i> = sum conj(r_k) r_i
 SUN_MAT_UNROLL
-                for (int c = 0; c < N; ++c) {
-                    pr += M.re[k][c] * M.re[i][c] + M.im[k][c] * M.im[i][c];
-                    pi += M.re[k][c] * M.im[i][c] - M.im[k][c] * M.re[i][c];
-                }
+                for (int c = 0; c < N; ++c) cmac(pr, pi, M.re[k][c], -M.im[k][c], M.re[i][c], M.im[i][c]);
+                // r_i -= <r_k, r_i> r_k
 SUN_MAT_UNROLL
-                for (int c = 0; c < N; ++c) {
-                    M.re[i][c] -= pr * M.re[k][c] - pi * M.im[k][c];
-                    M.im[i][c] -= pr * M.im[k][c] + pi * M.re[k][c];
-                }
+                for (int c = 0; c < N; ++c) cmac(M.re[i][c], M.im[i][c], -pr, -pi, M.re[k][c], M.im[k][c]);
             }
             normalize_row<N>(M, i);
         }
         if constexpr (N == 3) {
-            // row 2 = conj(row0 x row1)
-#pragma unroll
-            for (int c = 0; c < 3; ++c) {
-                const int a = (c + 1) % 3, b = (c + 2) % 3;
-                const double xr = M.re[0][a] * M.re[1][b] - M.im[0][a] * M.im[1][b] -
-                                  (M.re[0][b] * M.re[1][a] - M.im[0][b] * M.im[1][a]);
-                const double xi = M.re[0][a] * M.im[1][b] + M.im[0][a] * M.re[1][b] -
-                                  (M.re[0][b] * M.im[1][a] + M.im[0][b] * M.re[1][a]);
-                M.re[2][c] = xr;
-                M.im[2][c] = -xi;
-            }
+            third_row(M);  // row 2 = conj(row0 x row1)
         } else {
             double dr, di;
             det_lu<N>(M, dr, di);
@@ -508,25 +493,38 @@ SUN_MAT_UNROLL
     }
 }
 
-// {max_ij |(U^dag U - 1)_ij|, |det U - 1|}
+// det of a 3x3 matrix by cofactors of row 2.
+__device__ __forceinline__ void det3(const Mat<3, double>& m, double& dr, double& di) {
+    Mat<3, double> c = m;
+    third_row(c);  // row 2 of c = conj(row0 x row1); det = sum_c m[2][c] (row0 x row1)_c
+    dr = 0.0;
+    di = 0.0;
+#pragma unroll
+    for (int k = 0; k < 3; ++k) cmac(dr, di, m.re[2][k], m.im[2][k], c.re[2][k], -c.im[2][k]);
+}
+
+// {max_ij |(U^dag U - 1)_ij|, |det U - 1|}.  U^dag U - 1 is Hermitian, so
+// its upper triangle holds every modulus; the maximum is taken over squared
+// moduli and rooted once.
 template <int N>
 __device__ __forceinline__ void unitarity_dev(const Mat<N, double>& M, double& du, double& dd) {
-    du = 0.0;
+    double du2 = 0.0;
 SUN_MAT_UNROLL
     for (int i = 0; i < N; ++i)
 SUN_MAT_UNROLL
-        for (int j = 0; j < N; ++j) {
+        for (int j = i; j < N; ++j) {
             double r = (i == j) ? -1.0 : 0.0, m = 0.0;
 SUN_MAT_UNROLL
-            for (int k = 0; k < N; ++k) {
-                r += M.re[k][i] * M.re[k][j] + M.im[k][i] * M.im[k][j];
-                m += M.re[k][i] * M.im[k][j] - M.im[k][i] * M.re[k][j];
-            }
-            du = fmax(du, sqrt(r * r + m * m));
+            for (int k = 0; k < N; ++k) cmac(r, m, M.re[k][i], -M.im[k][i], M.re[k][j], M.im[k][j]);
+            du2 = fmax(du2, fmadd(m, m, r * r));
         }
+    du = sqrt(du2);
     double dr, di;
-    det_lu<N>(M, dr, di);
-    dd = sqrt((dr - 1.0) * (dr - 1.0) + di * di);
+    if constexpr (N == 3)
+        det3(M, dr, di);
+    else
+        det_lu<N>(M, dr, di);
+    dd = sqrt(fmadd(di, di, (dr - 1.0) * (dr - 1.0)));
 }
 
 // Link id in [0, 4V): mu-major, then parity, then checkerboard index.
@@ -735,16 +733,36 @@ __global__ __launch_bounds__(kBlock) void k_plaquette_final_batch(const ChainDes
 // ---------------------------------------------------------------------------
 // Polyakov loop along direction 3, FP64.
 // ---------------------------------------------------------------------------
+// Time segments per spatial site: the product along t is split into S
+// consecutive stretches multiplied by S work-items, whose S partial products
+// are then multiplied in order through LDS (FP64, 2 N^2 doubles per item).
+template <int N>
+constexpr int polyakov_segments() {
+    return N <= 3 ? 8 : (N == 4 ? 4 : 1);
+}
+template <int N>
+__host__ __device__ inline int polyakov_blocks(const Geom& g) {
+    constexpr int sites = kBlock / polyakov_segments<N>();
+    return (g.V / g.L[3] + sites - 1) / sites;
+}
+
+// Work-item (seg, j) of a workgroup multiplies U_3 along its time stretch at
+// spatial site blockIdx.x * (kBlock / S) + j; lanes of one segment take
+// consecutive spatial sites, so each load instruction reads consecutive links.
 template <int N, typename T, int R>
 __global__ __launch_bounds__(kBlock) void k_polyakov(const T2<T>* __restrict__ U, Geom g,
                                                      double* __restrict__ partial) {
-    const int xs = blockIdx.x * kBlock + threadIdx.x;
+    constexpr int S = polyakov_segments<N>();
+    constexpr int SITES = kBlock / S;
+    const int seg = threadIdx.x / SITES, j = threadIdx.x - seg * SITES;
+    const int xs = blockIdx.x * SITES + j;
     const int Vs = g.V / g.L[3];
-    double tr[2] = {0.0, 0.0};
-    if (xs < Vs) {
-        Mat<N, double> P;
-        set_identity(P);
-        for (int t = 0; t < g.L[3]; ++t) {
+    const bool live = xs < Vs;
+    Mat<N, double> P;
+    set_identity(P);
+    if (live) {
+        const int t0 = seg * g.L[3] / S, t1 = (seg + 1) * g.L[3] / S;
+        for (int t = t0; t < t1; ++t) {
             const int s = xs + t * Vs;
             Site st;
             int r = s;
@@ -757,6 +775,31 @@ __global__ __launch_bounds__(kBlock) void k_polyakov(const T2<T>* __restrict__ U
             st.s = s;
             P = mul_nn(P, load_link_f64<N, T, R>(U, 3, parity_of(st), s >> 1, g.Vh));
         }
+    }
+    double tr[2] = {0.0, 0.0};
+    if constexpr (S > 1) {
+        __shared__ double part[S][2 * N * N][SITES];
+        if (seg > 0) {
+SUN_MAT_UNROLL
+            for (int e = 0; e < N * N; ++e) {
+                part[seg][2 * e][j] = P.re[e / N][e % N];
+                part[seg][2 * e + 1][j] = P.im[e / N][e % N];
+            }
+        }
+        __syncthreads();
+        if (seg == 0 && live) {
+            for (int k = 1; k < S; ++k) {
+                Mat<N, double> Q;
+SUN_MAT_UNROLL
+                for (int e = 0; e < N * N; ++e) {
+                    Q.re[e / N][e % N] = part[k][2 * e][j];
+                    Q.im[e / N][e % N] = part[k][2 * e + 1][j];
+                }
+                P = mul_nn(P, Q);
+            }
+        }
+    }
+    if (seg == 0 && live) {
 SUN_MAT_UNROLL
         for (int i = 0; i < N; ++i) {
             tr[0] += P.re[i][i];

@@ -64,8 +64,8 @@ struct Ops {
     void (*unitarity)(const Ctx&, double* partial);
     // partial: 2 doubles per tile of plaquette_tiles(g)
     void (*plaquette)(const Ctx&, double* partial);
-    // partial: 2 doubles per block of spatial_blocks(g)
-    void (*polyakov)(const Ctx&, double* partial);
+    // partial: 2 doubles per block; returns the block count
+    int (*polyakov)(const Ctx&, double* partial);
     void (*export_field)(const Ctx&, double* out);
     void (*import_field)(const Ctx&, const double* in);
     // batches: d is a device table of n chains of this Nc and storage type;

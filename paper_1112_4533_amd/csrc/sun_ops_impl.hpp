@@ -104,8 +104,10 @@ struct OpsImpl {
     static void plaquette(const Ctx& c, double* partial) {
         k_plaquette<N, T, R><<<plaquette_tiles(c.g), kBlock, 0, c.stream>>>((const P*)c.links, c.g, partial);
     }
-    static void polyakov(const Ctx& c, double* partial) {
-        k_polyakov<N, T, R><<<spatial_blocks(c.g), kBlock, 0, c.stream>>>((const P*)c.links, c.g, partial);
+    static int polyakov(const Ctx& c, double* partial) {
+        const int nblk = polyakov_blocks<N>(c.g);
+        k_polyakov<N, T, R><<<nblk, kBlock, 0, c.stream>>>((const P*)c.links, c.g, partial);
+        return nblk;
     }
     static void export_field(const Ctx& c, double* out) {
         k_export<N, T, R><<<link_blocks(c.g), kBlock, 0, c.stream>>>((const P*)c.links, c.g, out);
