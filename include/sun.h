@@ -52,14 +52,33 @@ enum {
 /* Link storage.  Reductions, re-unitarization and the start configuration
  * are always computed in FP64.  The TWO_ROW forms (SU(3) only, paper Sec. 3:
  * 12 reals instead of 18) store rows 0 and 1 and rebuild row 2 as
- * conj(row0 x row1) on every load, which cuts link traffic by a third. */
-enum { SUN_F32 = 0, SUN_F64 = 1, SUN_F32_TWO_ROW = 2, SUN_F64_TWO_ROW = 3 };
+ * conj(row0 x row1) on every load, which cuts link traffic by a third.
+ *
+ * Nc <= SUN_NC_MAX_REGISTER runs one link per work-item with the link
+ * matrices in registers and the field split into planes by (direction,
+ * parity, matrix entry).  Larger Nc (paper Sec. 4: up to 32 in single and
+ * 16 in double precision at 8^4) runs the generic path of one 64-lane
+ * workgroup per link, matrices in LDS and the entries of each link
+ * contiguous in memory; SUN_F32 and SUN_F64 select it by themselves there,
+ * and the WIDE codes select it for any 4 <= Nc <= 32 (for comparisons with
+ * the register path).  Its FP64 form needs 5 Nc^2 x 16 bytes of LDS per
+ * workgroup and so stops at Nc = 28 (SUN_EUNSUP beyond).  Launch shapes do
+ * not apply to it, and batches do not accept it. */
+enum {
+    SUN_F32 = 0,
+    SUN_F64 = 1,
+    SUN_F32_TWO_ROW = 2,
+    SUN_F64_TWO_ROW = 3,
+    SUN_F32_WIDE = 4,
+    SUN_F64_WIDE = 5
+};
 
 /* Update kinds of one checkerboard phase (paper Sec. 3 kernel list). */
 enum { SUN_HEATBATH = 0, SUN_OVERRELAX = 1 };
 
-/* Largest Nc this build instantiates. */
-#define SUN_NC_MAX 8
+/* Largest Nc of the register path, and of the build. */
+#define SUN_NC_MAX_REGISTER 8
+#define SUN_NC_MAX 32
 
 /* Bytes of device memory a lattice needs: the link field (SoA planes split by
  * direction, parity and matrix element) and the scratch buffer used by the
@@ -69,7 +88,8 @@ int sun_lattice_bytes(int nc, const int L[4], int dtype, size_t *link_bytes,
 
 /* Creates a handle over caller-owned device buffers (links: link_bytes,
  * scratch: scratch_bytes, both 256-byte aligned).  Nc in 2..SUN_NC_MAX;
- * SUN_EUNSUP for a TWO_ROW dtype with Nc != 3.
+ * SUN_EUNSUP for a TWO_ROW dtype with Nc != 3, a WIDE dtype with Nc < 4, or
+ * FP64 on the workgroup-per-link path with Nc > 28.
  * The field content is undefined until sun_init or sun_import. */
 int sun_lattice_create(int nc, const int L[4], int dtype, void *links, size_t link_bytes,
                        void *scratch, size_t scratch_bytes, sun_lattice_t *out);
@@ -181,7 +201,8 @@ typedef struct sun_batch_s *sun_batch_t;
 /* Device bytes of the descriptor table of an n-chain batch. */
 int sun_batch_bytes(int n, size_t *table_bytes);
 
-/* Creates a batch over n existing lattice handles (which must outlive it).
+/* Creates a batch over n existing lattice handles (which must outlive it);
+ * SUN_EUNSUP if one of them runs the workgroup-per-link path.
  * betas, seeds: host arrays of n values.  table: caller-owned device memory
  * of sun_batch_bytes() bytes, 256-byte aligned; it is written once here with
  * a synchronous copy. */

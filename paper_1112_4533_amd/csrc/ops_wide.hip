@@ -1,0 +1,65 @@
+// ops_wide.hip -- launchers of the large-Nc kernels (one workgroup per link;
+// Nc is a run-time argument, the LDS size follows it).
+#include "sun_ops.hpp"
+#include "sun_wide.hpp"
+
+namespace sun {
+
+template <typename T>
+struct OpsWide {
+    using P = T2<T>;
+    static constexpr int f64 = sizeof(T) == 8;
+
+    static void update(const Ctx& c, int kind, int mu, int par, double beta, uint32_t k0, uint32_t k1, uint32_t step) {
+        const size_t lds = wide_update_lds(c.nc, f64);
+        wide::k_update<T><<<c.g.Vh, wide::kLanes, lds, c.stream>>>((P*)c.links, c.g, c.nc, mu, par, kind == 0 ? 1 : 0,
+                                                                   (T)beta, k0, k1, step);
+    }
+    static void init(const Ctx& c, int hot, uint32_t k0, uint32_t k1) {
+        wide::k_init<T><<<4 * c.g.V, wide::kLanes, wide::fp64_lds(c.nc, 2), c.stream>>>((P*)c.links, c.g, c.nc, hot, k0,
+                                                                                        k1);
+    }
+    static int reunit(const Ctx& c, double* partial) {
+        const size_t lds = wide::fp64_lds(c.nc, 2);
+        if (partial)
+            wide::k_reunit<T, true><<<4 * c.g.V, wide::kLanes, lds, c.stream>>>((P*)c.links, c.g, c.nc, partial);
+        else
+            wide::k_reunit<T, false><<<4 * c.g.V, wide::kLanes, lds, c.stream>>>((P*)c.links, c.g, c.nc, nullptr);
+        return 4 * c.g.V;
+    }
+    static int unitarity(const Ctx& c, double* partial) {
+        wide::k_unitarity<T><<<4 * c.g.V, wide::kLanes, wide::fp64_lds(c.nc, 2), c.stream>>>((const P*)c.links, c.g,
+                                                                                             c.nc, partial);
+        return 4 * c.g.V;
+    }
+    static int plaquette(const Ctx& c, double* partial) {
+        wide::k_plaquette<T><<<c.g.V, wide::kLanes, wide::fp64_lds(c.nc, 3), c.stream>>>((const P*)c.links, c.g, c.nc,
+                                                                                         partial);
+        return c.g.V;
+    }
+    static int polyakov(const Ctx& c, double* partial) {
+        const int Vs = c.g.V / c.g.L[3];
+        wide::k_polyakov<T><<<Vs, wide::kLanes, wide::fp64_lds(c.nc, 3), c.stream>>>((const P*)c.links, c.g, c.nc,
+                                                                                     partial);
+        return Vs;
+    }
+    static int entry_blocks(const Ctx& c) {
+        return (int)((4LL * c.g.V * c.nc * c.nc + 255) / 256);
+    }
+    static void export_field(const Ctx& c, double* out) {
+        wide::k_export<T><<<entry_blocks(c), 256, 0, c.stream>>>((const P*)c.links, c.g, c.nc, out);
+    }
+    static void import_field(const Ctx& c, const double* in) {
+        wide::k_import<T><<<entry_blocks(c), 256, 0, c.stream>>>((P*)c.links, c.g, c.nc, in);
+    }
+
+    static const Ops* table() {
+        static const Ops ops = {&update, &init, &reunit, &unitarity, &plaquette, &polyakov, &export_field,
+                                &import_field, nullptr, nullptr, nullptr};
+        return &ops;
+    }
+};
+
+const Ops* ops_wide(int f64) { return f64 ? OpsWide<double>::table() : OpsWide<float>::table(); }
+
+}  // namespace sun

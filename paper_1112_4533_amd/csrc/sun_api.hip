@@ -66,17 +66,20 @@ struct sun_lattice_s {
     // launch shapes of the phase kernels (sun_set_launch)
     sun::Shape shape[2] = {sun::Shape{256, 1, 0, 4}, sun::Shape{256, 1, 12, 4}};
 
-    sun::Ctx ctx(hipStream_t s) const { return sun::Ctx{links, g, s, {shape[0], shape[1]}}; }
+    sun::Ctx ctx(hipStream_t s) const { return sun::Ctx{links, g, s, {shape[0], shape[1]}, nc}; }
 };
 
 namespace {
 
-// dtype bit 0: FP64 storage; bit 1: SU(3) two-row storage.
+// dtype bit 0: FP64 storage; bit 1: SU(3) two-row storage; bit 2: the
+// workgroup-per-link path (also taken by every Nc above the register path's).
 inline int is_f64(int dtype) { return dtype & 1; }
 inline int is_two_row(int dtype) { return (dtype >> 1) & 1; }
+inline bool is_wide(int nc, int dtype) { return ((dtype >> 2) & 1) || nc > SUN_NC_MAX_REGISTER; }
 
 const sun::Ops* ops_for(int nc, int dtype) {
     const int f64 = is_f64(dtype);
+    if (is_wide(nc, dtype)) return sun::ops_wide(f64);
     if (is_two_row(dtype)) return nc == 3 ? sun::ops_nc3_two_row(f64) : nullptr;
     switch (nc) {
         case 2: return sun::ops_nc2(f64);
@@ -93,8 +96,14 @@ const sun::Ops* ops_for(int nc, int dtype) {
 int check_lattice(int nc, const int L[4], int dtype) {
     if (!L) return fail(SUN_EINVAL, "L is null");
     if (nc < 2 || nc > SUN_NC_MAX) return fail(SUN_EINVAL, "Nc = %d outside 2..%d", nc, SUN_NC_MAX);
-    if (dtype < SUN_F32 || dtype > SUN_F64_TWO_ROW) return fail(SUN_EINVAL, "dtype %d is not a SUN_F* code", dtype);
+    if (dtype < SUN_F32 || dtype > SUN_F64_WIDE) return fail(SUN_EINVAL, "dtype %d is not a SUN_F* code", dtype);
     if (is_two_row(dtype) && nc != 3) return fail(SUN_EUNSUP, "two-row storage exists for SU(3) only (Nc = %d)", nc);
+    if (is_wide(nc, dtype)) {
+        if (nc < 4) return fail(SUN_EUNSUP, "the workgroup-per-link path starts at Nc = 4 (Nc = %d)", nc);
+        if (sun::wide_update_lds(nc, is_f64(dtype)) > sun::kWideLdsMax)
+            return fail(SUN_EUNSUP, "Nc = %d in FP64 needs %zu bytes of LDS per workgroup (limit %zu)", nc,
+                        sun::wide_update_lds(nc, 1), sun::kWideLdsMax);
+    }
     if (L[0] < 2 || (L[0] & 1)) return fail(SUN_EINVAL, "L[0] = %d must be even and >= 2", L[0]);
     long long V = 1;
     for (int mu = 0; mu < 4; ++mu) {
@@ -127,10 +136,12 @@ size_t link_bytes_of(int nc, const sun::Geom& g, int dtype) {
     return reals * 4 * (size_t)g.V * (is_f64(dtype) ? 8 : 4);
 }
 
-size_t scratch_bytes_of(const sun::Geom& g) {
+size_t scratch_bytes_of(const sun::Geom& g, bool wide) {
     // the largest partial array: per link block, per plaquette tile, or per
-    // Polyakov workgroup (at least 32 spatial sites each)
-    const int nblk = std::max({sun::link_blocks(g), sun::plaquette_tiles(g), (g.V / g.L[3] + 31) / 32});
+    // Polyakov workgroup (at least 32 spatial sites each); the wide path
+    // reduces per link
+    const int nblk = wide ? 4 * g.V
+                          : std::max({sun::link_blocks(g), sun::plaquette_tiles(g), (g.V / g.L[3] + 31) / 32});
     const size_t b = 2 * sizeof(double) * (size_t)nblk;
     return (b + 255) & ~(size_t)255;
 }
@@ -186,7 +197,7 @@ int sun_lattice_bytes(int nc, const int L[4], int dtype, size_t* link_bytes, siz
     if (int rc = check_lattice(nc, L, dtype)) return rc;
     const sun::Geom g = make_geom(L);
     if (link_bytes) *link_bytes = link_bytes_of(nc, g, dtype);
-    if (scratch_bytes) *scratch_bytes = scratch_bytes_of(g);
+    if (scratch_bytes) *scratch_bytes = scratch_bytes_of(g, is_wide(nc, dtype));
     return SUN_OK;
 }
 
@@ -198,9 +209,9 @@ int sun_lattice_create(int nc, const int L[4], int dtype, void* links, size_t li
     const sun::Geom g = make_geom(L);
     if (!links || link_bytes < link_bytes_of(nc, g, dtype))
         return fail(SUN_ESIZE, "link buffer %p of %zu bytes, need %zu", links, link_bytes, link_bytes_of(nc, g, dtype));
-    if (!scratch || scratch_bytes < scratch_bytes_of(g))
-        return fail(SUN_ESIZE, "scratch buffer %p of %zu bytes, need %zu", scratch, scratch_bytes,
-                    scratch_bytes_of(g));
+    const size_t need_scratch = scratch_bytes_of(g, is_wide(nc, dtype));
+    if (!scratch || scratch_bytes < need_scratch)
+        return fail(SUN_ESIZE, "scratch buffer %p of %zu bytes, need %zu", scratch, scratch_bytes, need_scratch);
     if (((uintptr_t)links & 255) || ((uintptr_t)scratch & 255))
         return fail(SUN_EINVAL, "buffers must be 256-byte aligned");
     auto* h = new sun_lattice_s;
@@ -254,8 +265,8 @@ int sun_phase(sun_lattice_t h, int kind, int mu, int parity, double beta, uint64
 static int run_reunit(sun_lattice_t h, double* dev_out2, hipStream_t s) {
     Timed t(h, 2, s);
     if (t.rc) return t.rc;
-    h->ops->reunit(h->ctx(s), dev_out2 ? h->scratch : nullptr);
-    if (dev_out2) sun::launch_finalize_max2(h->scratch, sun::link_blocks(h->g), dev_out2, s);
+    const int nblk = h->ops->reunit(h->ctx(s), dev_out2 ? h->scratch : nullptr);
+    if (dev_out2) sun::launch_finalize_max2(h->scratch, nblk, dev_out2, s);
     if (int rc = launch_check("reunitarize")) return rc;
     return t.done();
 }
@@ -294,9 +305,8 @@ int sun_plaquette(sun_lattice_t h, double* dev_out3, sun_stream_t stream) {
         for (int nu = mu + 1; nu < 4; ++nu)
             if (((h->g.present >> mu) & 1) && ((h->g.present >> nu) & 1)) (nu == 3 ? n_tm : n_sp)++;
     const double norm = (double)h->nc * (double)h->g.V;
-    h->ops->plaquette(h->ctx(s), h->scratch);
-    sun::launch_plaquette_final(h->scratch, sun::plaquette_tiles(h->g), dev_out3, norm * n_sp, norm * n_tm,
-                                norm * (n_sp + n_tm), s);
+    const int nblk = h->ops->plaquette(h->ctx(s), h->scratch);
+    sun::launch_plaquette_final(h->scratch, nblk, dev_out3, norm * n_sp, norm * n_tm, norm * (n_sp + n_tm), s);
     if (int rc = launch_check("plaquette")) return rc;
     return t.done();
 }
@@ -318,8 +328,8 @@ int sun_unitarity(sun_lattice_t h, double* dev_out2, sun_stream_t stream) {
     if (!h) return fail(SUN_EINVAL, "null handle");
     if (!dev_out2) return fail(SUN_ESIZE, "dev_out2 is null");
     const hipStream_t s = as_stream(stream);
-    h->ops->unitarity(h->ctx(s), h->scratch);
-    sun::launch_finalize_max2(h->scratch, sun::link_blocks(h->g), dev_out2, s);
+    const int nblk = h->ops->unitarity(h->ctx(s), h->scratch);
+    sun::launch_finalize_max2(h->scratch, nblk, dev_out2, s);
     return launch_check("unitarity");
 }
 
@@ -505,13 +515,17 @@ int sun_batch_create(int n, const sun_lattice_t* chains, const double* betas, co
     if (!chains || !betas || !seeds) return fail(SUN_EINVAL, "null chain, beta or seed array");
     if (!table || table_bytes < need) return fail(SUN_ESIZE, "table of %zu bytes, need %zu", table_bytes, need);
     if ((uintptr_t)table & 255) return fail(SUN_EINVAL, "table must be 256-byte aligned");
-    for (int i = 0; i < n; ++i)
+    for (int i = 0; i < n; ++i) {
         if (!chains[i]) return fail(SUN_EINVAL, "chain %d is null", i);
+        if (is_wide(chains[i]->nc, chains[i]->dtype))
+            return fail(SUN_EUNSUP, "chain %d uses the workgroup-per-link path (Nc = %d), which batches do not run", i,
+                        chains[i]->nc);
+    }
     auto* b = new sun_batch_s;
     b->chains.assign(chains, chains + n);
     b->table = static_cast<sun::ChainDesc*>(table);
     // group by (Nc, dtype), keeping the caller's order inside a group
-    for (int nc = 2; nc <= SUN_NC_MAX; ++nc)
+    for (int nc = 2; nc <= SUN_NC_MAX_REGISTER; ++nc)
         for (int dt = SUN_F32; dt <= SUN_F64_TWO_ROW; ++dt) {
             if (is_two_row(dt) && nc != 3) continue;
             sun_batch_s::Group gr{ops_for(nc, dt), (int)b->host.size(), 0, {0, 0, 0, 0, 0}};

@@ -661,48 +661,66 @@ constexpr int kMaxAttempts = 64;
 // for alpha < 1.7, Kennedy-Pendleton above.  Returns the attempt count, or 0
 // when kMaxAttempts draws were rejected (the caller then skips the step).
 // ---------------------------------------------------------------------------
+// One attempt of the x0 draw from the four uniforms of counter word `hit`:
+// returns whether it is accepted, with x0 and the radius sqrt(1 - x0^2).
+// em = expm1(-2 alpha) is the Creutz branch's loop invariant.
 template <typename T>
-__device__ __forceinline__ int sample_su2(T alpha, uint32_t k0, uint32_t k1, uint32_t site, uint32_t step,
-                                          uint32_t mu_sg, Quat<T>& x) {
-    T x0 = T(1), rad = T(0);
-    int hit = 0;
-    bool ok = false;
-    const bool creutz = alpha < Const<T>::switch_alpha;
-    // expm1(-2 alpha) is loop invariant
-    const T em = creutz ? d_expm1(T(-2) * alpha) : T(0);
-    for (; hit < kMaxAttempts; ++hit) {
-        const U4 r = philox(site, step, mu_sg, (RNG_ATTEMPT << 24) | (uint32_t)hit, k0, k1);
-        const T r0 = uniform<T>(r.w[0]), r1 = uniform<T>(r.w[1]);
-        const T r2 = uniform<T>(r.w[2]), r3 = uniform<T>(r.w[3]);
-        if (creutz) {
-            x0 = (alpha == T(0)) ? T(2) * r0 - T(1) : T(1) + d_log1p((T(1) - r0) * em) / alpha;
-            const T rhs = T(1) - x0 * x0;
-            if (r1 * r1 <= rhs) {
-                rad = d_sqrt(rhs);
-                ok = true;
-                break;
-            }
-        } else {
-            const T c = draw_cos(Const<T>::two_pi * r1);
-            const T lam2 = -(draw_log(r0) + c * c * draw_log(r2)) / (T(2) * alpha);
-            const T rhs = T(1) - lam2;
-            if (r3 * r3 <= rhs) {
-                x0 = T(1) - T(2) * lam2;
-                rad = T(2) * d_sqrt(lam2) * d_sqrt(rhs);
-                ok = true;
-                break;
-            }
+__device__ __forceinline__ bool su2_attempt(T alpha, bool creutz, T em, const U4& r, T& x0, T& rad) {
+    const T r0 = uniform<T>(r.w[0]), r1 = uniform<T>(r.w[1]);
+    const T r2 = uniform<T>(r.w[2]), r3 = uniform<T>(r.w[3]);
+    if (creutz) {
+        x0 = (alpha == T(0)) ? T(2) * r0 - T(1) : T(1) + d_log1p((T(1) - r0) * em) / alpha;
+        const T rhs = T(1) - x0 * x0;
+        if (r1 * r1 <= rhs) {
+            rad = d_sqrt(rhs);
+            return true;
+        }
+    } else {
+        const T c = draw_cos(Const<T>::two_pi * r1);
+        const T lam2 = -(draw_log(r0) + c * c * draw_log(r2)) / (T(2) * alpha);
+        const T rhs = T(1) - lam2;
+        if (r3 * r3 <= rhs) {
+            x0 = T(1) - T(2) * lam2;
+            rad = T(2) * d_sqrt(lam2) * d_sqrt(rhs);
+            return true;
         }
     }
-    if (!ok) return 0;
+    return false;
+}
+
+// (x1, x2, x3) uniform on the sphere of radius rad.
+template <typename T>
+__device__ __forceinline__ Quat<T> su2_direction(T x0, T rad, uint32_t k0, uint32_t k1, uint32_t site, uint32_t step,
+                                                 uint32_t mu_sg) {
     const U4 d = philox(site, step, mu_sg, RNG_DIRECTION << 24, k0, k1);
     const T cos_t = T(1) - T(2) * uniform<T>(d.w[0]);
     const T sin_t = d_sqrt(T(1) - cos_t * cos_t);
     const T phi = Const<T>::two_pi * uniform<T>(d.w[1]);
+    Quat<T> x;
     x.q[0] = x0;
     x.q[1] = rad * sin_t * draw_cos(phi);
     x.q[2] = rad * sin_t * draw_sin(phi);
     x.q[3] = rad * cos_t;
+    return x;
+}
+
+template <typename T>
+__device__ __forceinline__ int sample_su2(T alpha, uint32_t k0, uint32_t k1, uint32_t site, uint32_t step,
+                                          uint32_t mu_sg, Quat<T>& x) {
+    T x0 = T(1), rad = T(0);
+    const bool creutz = alpha < Const<T>::switch_alpha;
+    const T em = creutz ? d_expm1(T(-2) * alpha) : T(0);  // loop invariant
+    int hit = 0;
+    bool ok = false;
+    for (; hit < kMaxAttempts; ++hit) {
+        const U4 r = philox(site, step, mu_sg, (RNG_ATTEMPT << 24) | (uint32_t)hit, k0, k1);
+        if (su2_attempt(alpha, creutz, em, r, x0, rad)) {
+            ok = true;
+            break;
+        }
+    }
+    if (!ok) return 0;
+    x = su2_direction(x0, rad, k0, k1, site, step, mu_sg);
     return hit + 1;
 }
 

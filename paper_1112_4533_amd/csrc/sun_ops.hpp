@@ -36,6 +36,7 @@ struct Ctx {
     Geom g;
     hipStream_t stream;
     Shape shape[2];   // per update kind: heatbath, overrelaxation
+    int nc;
 };
 
 // Dynamic LDS per workgroup that limits a CU to `waves` resident waves of
@@ -59,11 +60,11 @@ struct Ops {
     // one checkerboard phase; kind 0 heatbath, 1 overrelaxation
     void (*update)(const Ctx&, int kind, int mu, int par, double beta, uint32_t k0, uint32_t k1, uint32_t step);
     void (*init)(const Ctx&, int hot, uint32_t k0, uint32_t k1);
-    // partial: 2 doubles per block of link_blocks(g), or null
-    void (*reunit)(const Ctx&, double* partial);
-    void (*unitarity)(const Ctx&, double* partial);
-    // partial: 2 doubles per tile of plaquette_tiles(g)
-    void (*plaquette)(const Ctx&, double* partial);
+    // reductions write 2 doubles per workgroup into partial and return the
+    // workgroup count (reunit: partial may be null, then nothing is reported)
+    int (*reunit)(const Ctx&, double* partial);
+    int (*unitarity)(const Ctx&, double* partial);
+    int (*plaquette)(const Ctx&, double* partial);
     // partial: 2 doubles per block; returns the block count
     int (*polyakov)(const Ctx&, double* partial);
     void (*export_field)(const Ctx&, double* out);
@@ -92,6 +93,11 @@ const Ops* ops_nc6(int f64);
 const Ops* ops_nc7(int f64);
 const Ops* ops_nc8(int f64);
 const Ops* ops_nc3_two_row(int f64);  // SU(3), rows 0 and 1 stored
+const Ops* ops_wide(int f64);         // 4 <= Nc <= 32, one workgroup per link, link-major
+
+// Dynamic LDS of the wide phase kernel, and whether it fits a workgroup.
+constexpr size_t kWideLdsMax = 64 * 1024;
+inline size_t wide_update_lds(int nc, int f64) { return (size_t)5 * nc * nc * (f64 ? 16 : 8); }
 
 void launch_finalize_max2(const double* partial, int nblk, double* out, hipStream_t s);
 void launch_finalize_sum2(const double* partial, int nblk, double* out, double scale, hipStream_t s);

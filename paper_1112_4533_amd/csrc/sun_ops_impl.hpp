@@ -92,17 +92,20 @@ struct OpsImpl {
     static void init(const Ctx& c, int hot, uint32_t k0, uint32_t k1) {
         k_init<N, T, R><<<link_blocks(c.g), kBlock, 0, c.stream>>>((P*)c.links, c.g, hot, k0, k1);
     }
-    static void reunit(const Ctx& c, double* partial) {
+    static int reunit(const Ctx& c, double* partial) {
         if (partial)
             k_reunit<N, T, R, true><<<link_blocks(c.g), kBlock, 0, c.stream>>>((P*)c.links, c.g, partial);
         else
             k_reunit<N, T, R, false><<<link_blocks(c.g), kBlock, 0, c.stream>>>((P*)c.links, c.g, nullptr);
+        return link_blocks(c.g);
     }
-    static void unitarity(const Ctx& c, double* partial) {
+    static int unitarity(const Ctx& c, double* partial) {
         k_unitarity<N, T, R><<<link_blocks(c.g), kBlock, 0, c.stream>>>((const P*)c.links, c.g, partial);
+        return link_blocks(c.g);
     }
-    static void plaquette(const Ctx& c, double* partial) {
+    static int plaquette(const Ctx& c, double* partial) {
         k_plaquette<N, T, R><<<plaquette_tiles(c.g), kBlock, 0, c.stream>>>((const P*)c.links, c.g, partial);
+        return plaquette_tiles(c.g);
     }
     static int polyakov(const Ctx& c, double* partial) {
         const int nblk = polyakov_blocks<N>(c.g);

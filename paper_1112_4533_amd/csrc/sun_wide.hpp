@@ -1,0 +1,572 @@
+// sun_wide.hpp -- SU(Nc) for large Nc (4 <= Nc <= 32): one 64-lane
+// workgroup per link (paper Sec. 3, generic SU(Nc) code; Sec. 4, the
+// large-Nc runs at 8^4).
+//
+// At large Nc a link no longer fits in one work-item's registers (Nc = 32 is
+// 2048 reals), so a workgroup of one wavefront owns one link: the matrices of
+// the update live in LDS, every product is spread over the lanes element by
+// element, and the SU(2) subgroup steps (Nc(Nc-1)/2 of them, sequential by
+// definition) update two rows with one lane per column.  Links are stored
+// link-major (the Nc^2 complex entries of one link are contiguous), so the
+// workgroup reads a link with unit stride.  Operands that enter a product
+// daggered are transposed while they are copied into LDS, so that every
+// product reads one operand by broadcast and the other with unit stride.
+//
+// The arithmetic is that of the register kernels: the same closing staple,
+// W = U A, the lexicographic subgroup order, the quaternion projection, the
+// same Philox counters, and an SU(2) draw whose 64 attempts are evaluated one
+// per lane, the first accepted one winning (which is the sequential draw's
+// result).  Reductions and re-unitarization are FP64.
+#pragma once
+
+#include "sun_kernels.hpp"
+
+namespace sun {
+namespace wide {
+
+constexpr int kLanes = 64;
+static_assert(kMaxAttempts == kLanes, "one SU(2) attempt per lane");
+constexpr int kNcMin = 4, kNcMax = 32;
+
+// Buffers (n x n complex) a kernel keeps in LDS, and the Nc limit they imply
+// for a 64 KiB workgroup allocation.
+constexpr int kUpdateBuffers = 5;
+
+template <typename T>
+__host__ __device__ inline size_t update_lds(int n) {
+    return (size_t)kUpdateBuffers * n * n * sizeof(T2<T>);
+}
+__host__ __device__ inline size_t fp64_lds(int n, int buffers) { return (size_t)buffers * n * n * sizeof(double2); }
+
+template <typename T>
+__device__ __forceinline__ T2<T> cpx(T re, T im) {
+    T2<T> v;
+    v.x = re;
+    v.y = im;
+    return v;
+}
+
+// Link-major storage: link (mu, parity, h) is n^2 consecutive entries.
+template <typename T>
+__device__ __forceinline__ const T2<T>* link_at(const T2<T>* U, int n2, int mu, int par, int h, int Vh) {
+    return U + ((size_t)(mu * 2 + par) * Vh + h) * n2;
+}
+
+// dst (LDS, type D) = src or src^dag (global, type S), converted.
+template <typename D, typename S>
+__device__ __forceinline__ void lds_load(T2<D>* dst, const T2<S>* src, int n, bool dag) {
+    const int n2 = n * n;
+    for (int e = threadIdx.x; e < n2; e += kLanes) {
+        const T2<S> v = src[e];
+        if (dag) {
+            const int i = e / n, j = e - i * n;
+            dst[j * n + i] = cpx<D>((D)v.x, -(D)v.y);
+        } else {
+            dst[e] = cpx<D>((D)v.x, (D)v.y);
+        }
+    }
+}
+
+// C = A B, or C += A B (C distinct from A and B).
+template <typename T>
+__device__ __forceinline__ void lds_mm(T2<T>* C, const T2<T>* A, const T2<T>* B, int n, bool acc) {
+    const int n2 = n * n;
+    for (int e = threadIdx.x; e < n2; e += kLanes) {
+        const int i = e / n, j = e - i * n;
+        T r = acc ? C[e].x : T(0), m = acc ? C[e].y : T(0);
+        const T2<T>* a = A + i * n;
+        for (int k = 0; k < n; ++k) {
+            const T2<T> x = a[k], y = B[k * n + j];
+            cmac(r, m, x.x, x.y, y.x, y.y);
+        }
+        C[e] = cpx<T>(r, m);
+    }
+}
+
+// Wave reductions with a fixed butterfly order (deterministic).
+__device__ __forceinline__ double wave_sum(double v) {
+#pragma unroll
+    for (int off = 32; off > 0; off >>= 1) v += __shfl_xor(v, off, kLanes);
+    return v;
+}
+__device__ __forceinline__ double wave_max(double v) {
+#pragma unroll
+    for (int off = 32; off > 0; off >>= 1) v = fmax(v, __shfl_xor(v, off, kLanes));
+    return v;
+}
+
+// The SU(2) draw with attempt `hit` on lane `hit`; the lowest accepting lane
+// wins.  Returns false (skip the step) when all 64 attempts are rejected.
+template <typename T>
+__device__ __forceinline__ bool sample_su2_lanes(T alpha, uint32_t k0, uint32_t k1, uint32_t site, uint32_t step,
+                                                 uint32_t mu_sg, Quat<T>& x) {
+    const bool creutz = alpha < Const<T>::switch_alpha;
+    const T em = creutz ? d_expm1(T(-2) * alpha) : T(0);
+    const uint32_t hit = threadIdx.x;
+    const U4 r = philox(site, step, mu_sg, (RNG_ATTEMPT << 24) | hit, k0, k1);
+    T x0 = T(1), rad = T(0);
+    const bool ok = su2_attempt(alpha, creutz, em, r, x0, rad);
+    const unsigned long long mask = __ballot(ok);
+    if (mask == 0ull) return false;
+    const int first = __ffsll(mask) - 1;
+    x0 = __shfl(x0, first, kLanes);
+    rad = __shfl(rad, first, kLanes);
+    x = su2_direction(x0, rad, k0, k1, site, step, mu_sg);
+    return true;
+}
+
+// Rows i, j of M (LDS), column c, left-multiplied by the 2x2 form of a.
+template <typename T>
+__device__ __forceinline__ void rows_left_mul_col(T2<T>* M, int n, int i, int j, int c, const Quat<T>& a) {
+    const T2<T> x = M[i * n + c], y = M[j * n + c];
+    M[i * n + c] = cpx<T>(fmadd(-a.q[1], y.y, fmadd(a.q[2], y.x, fmadd(-a.q[3], x.y, a.q[0] * x.x))),
+                          fmadd(a.q[1], y.x, fmadd(a.q[2], y.y, fmadd(a.q[3], x.x, a.q[0] * x.y))));
+    M[j * n + c] = cpx<T>(fmadd(a.q[3], y.y, fmadd(a.q[0], y.x, fmadd(-a.q[1], x.y, -a.q[2] * x.x))),
+                          fmadd(-a.q[3], y.x, fmadd(a.q[0], y.y, fmadd(a.q[1], x.x, -a.q[2] * x.y))));
+}
+
+// ---------------------------------------------------------------------------
+// One checkerboard phase: workgroup h updates U_mu(x), x = site h of parity
+// par.  LDS: U, A (staple), B0, B1 (neighbour links), Tm (product).
+// ---------------------------------------------------------------------------
+template <typename T>
+__global__ __launch_bounds__(kLanes) void k_update(T2<T>* __restrict__ U, Geom g, int n, int mu, int par, int hb,
+                                                   T beta, uint32_t k0, uint32_t k1, uint32_t step) {
+    extern __shared__ double4 smem_update[];
+    const int n2 = n * n;
+    T2<T>* Us = reinterpret_cast<T2<T>*>(smem_update);
+    T2<T>* A = Us + n2;
+    T2<T>* B0 = A + n2;
+    T2<T>* B1 = B0 + n2;
+    T2<T>* Tm = B1 + n2;
+    const int h = blockIdx.x;
+    const int Vh = g.Vh;
+    const Site x = site_of(g, par, h);
+    const Site xp = step_up(g, x, mu);
+    const int op = par ^ 1;
+
+    lds_load<T, T>(Us, link_at<T>(U, n2, mu, par, h, Vh), n, false);
+    for (int e = threadIdx.x; e < n2; e += kLanes) A[e] = cpx<T>(T(0), T(0));
+    for (int nu = 0; nu < 4; ++nu) {
+        if (nu == mu || !((g.present >> nu) & 1)) continue;
+        const Site xpn = step_up(g, x, nu), xmn = step_down(g, x, nu), xpmn = step_down(g, xp, nu);
+        // upper staple U_nu(x+mu) U_mu(x+nu)^dag U_nu(x)^dag
+        lds_load<T, T>(B0, link_at<T>(U, n2, nu, op, xp.s >> 1, Vh), n, false);
+        lds_load<T, T>(B1, link_at<T>(U, n2, mu, op, xpn.s >> 1, Vh), n, true);
+        __syncthreads();
+        lds_mm<T>(Tm, B0, B1, n, false);
+        __syncthreads();
+        lds_load<T, T>(B0, link_at<T>(U, n2, nu, par, h, Vh), n, true);
+        __syncthreads();
+        lds_mm<T>(A, Tm, B0, n, true);
+        __syncthreads();
+        // lower staple U_nu(x+mu-nu)^dag U_mu(x-nu)^dag U_nu(x-nu)
+        lds_load<T, T>(B0, link_at<T>(U, n2, nu, par, xpmn.s >> 1, Vh), n, true);
+        lds_load<T, T>(B1, link_at<T>(U, n2, mu, op, xmn.s >> 1, Vh), n, true);
+        __syncthreads();
+        lds_mm<T>(Tm, B0, B1, n, false);
+        __syncthreads();
+        lds_load<T, T>(B0, link_at<T>(U, n2, nu, op, xmn.s >> 1, Vh), n, false);
+        __syncthreads();
+        lds_mm<T>(A, Tm, B0, n, true);
+        __syncthreads();
+    }
+    __syncthreads();
+    T2<T>* W = B0;  // W = U A
+    lds_mm<T>(W, Us, A, n, false);
+    __syncthreads();
+
+    const int lane = threadIdx.x;
+    uint32_t sg = 0;
+    for (int i = 0; i < n; ++i)
+        for (int j = i + 1; j < n; ++j, ++sg) {
+            const T2<T> wii = W[i * n + i], wij = W[i * n + j], wji = W[j * n + i], wjj = W[j * n + j];
+            Quat<T> p;
+            p.q[0] = T(0.5) * (wii.x + wjj.x);
+            p.q[3] = T(0.5) * (wii.y - wjj.y);
+            p.q[2] = T(0.5) * (wij.x - wji.x);
+            p.q[1] = T(0.5) * (wij.y + wji.y);
+            Quat<T> v;
+            const T k = unit_quat(p, v);
+            Quat<T> a;
+            bool apply = true;
+            if (hb) {
+                const T alpha = T(2) * beta * k / T(n);
+                Quat<T> xs;
+                apply = sample_su2_lanes<T>(alpha, k0, k1, (uint32_t)x.s, step, ((uint32_t)mu << 16) | sg, xs);
+                if (apply) a = qmul(xs, qconj(v));
+            } else {
+                const Quat<T> vc = qconj(v);
+                a = qmul(vc, vc);
+            }
+            __syncthreads();  // every lane has read the block before rows i, j change
+            if (apply) {
+                if (lane < n)
+                    rows_left_mul_col<T>(Us, n, i, j, lane, a);
+                else if (lane >= 32 && lane - 32 < n)
+                    rows_left_mul_col<T>(W, n, i, j, lane - 32, a);
+            }
+            __syncthreads();
+        }
+    T2<T>* dst = const_cast<T2<T>*>(link_at<T>(U, n2, mu, par, h, Vh));
+    for (int e = threadIdx.x; e < n2; e += kLanes) dst[e] = Us[e];
+}
+
+// ---------------------------------------------------------------------------
+// FP64 helpers on an LDS matrix whose column c belongs to lane c (n <= 32).
+// ---------------------------------------------------------------------------
+
+// det by LU with partial pivoting (the first largest pivot), destroying D.
+__device__ __forceinline__ void lds_det(double2* D, int n, double& dr, double& di) {
+    const int c = threadIdx.x;
+    dr = 1.0;
+    di = 0.0;
+    for (int col = 0; col < n; ++col) {
+        __syncthreads();
+        int piv = col;
+        double best = 0.0;
+        if (c == 0) {
+            best = D[col * n + col].x * D[col * n + col].x + D[col * n + col].y * D[col * n + col].y;
+            for (int r = col + 1; r < n; ++r) {
+                const double a = D[r * n + col].x * D[r * n + col].x + D[r * n + col].y * D[r * n + col].y;
+                if (a > best) {
+                    best = a;
+                    piv = r;
+                }
+            }
+        }
+        piv = __shfl(piv, 0, kLanes);
+        best = __shfl(best, 0, kLanes);
+        if (best == 0.0) {
+            dr = di = 0.0;
+            return;
+        }
+        if (piv != col) {
+            if (c < n) {
+                const double2 t = D[col * n + c];
+                D[col * n + c] = D[piv * n + c];
+                D[piv * n + c] = t;
+            }
+            dr = -dr;
+            di = -di;
+        }
+        __syncthreads();
+        const double pr = D[col * n + col].x, pi = D[col * n + col].y;
+        const double nr = dr * pr - di * pi, ni = dr * pi + di * pr;
+        dr = nr;
+        di = ni;
+        const double inv = 1.0 / (pr * pr + pi * pi);
+        for (int r = col + 1; r < n; ++r) {
+            const double2 m = D[r * n + col];
+            const double fr = (m.x * pr + m.y * pi) * inv;
+            const double fi = (m.y * pr - m.x * pi) * inv;
+            if (c >= col && c < n) {
+                const double2 u = D[col * n + c];
+                double2 w = D[r * n + c];
+                w.x -= fr * u.x - fi * u.y;
+                w.y -= fr * u.y + fi * u.x;
+                D[r * n + c] = w;
+            }
+        }
+    }
+}
+
+// {max_ij |(M^dag M - 1)_ij|, |det M - 1|}; D is a work buffer.
+__device__ __forceinline__ void lds_unitarity(const double2* M, double2* D, int n, double& du, double& dd) {
+    const int n2 = n * n;
+    double du2 = 0.0;
+    for (int e = threadIdx.x; e < n2; e += kLanes) {
+        const int i = e / n, j = e - i * n;
+        if (j < i) continue;  // Hermitian: the upper triangle has every modulus
+        double r = (i == j) ? -1.0 : 0.0, m = 0.0;
+        for (int k = 0; k < n; ++k) {
+            const double2 a = M[k * n + i], b = M[k * n + j];
+            cmac(r, m, a.x, -a.y, b.x, b.y);
+        }
+        du2 = fmax(du2, fmadd(m, m, r * r));
+    }
+    du = sqrt(wave_max(du2));
+    for (int e = threadIdx.x; e < n2; e += kLanes) D[e] = M[e];
+    double dr, di;
+    lds_det(D, n, dr, di);
+    dd = sqrt(fmadd(di, di, (dr - 1.0) * (dr - 1.0)));
+}
+
+// Gram-Schmidt on all rows (lane c owns column c), then the last row times
+// conj(det)/|det| (paper Sec. 2, re-unitarization; Nc > 3).
+__device__ __forceinline__ void lds_reunit(double2* M, double2* D, int n) {
+    const int c = threadIdx.x;
+    const bool own = c < n;
+    for (int i = 0; i < n; ++i) {
+        for (int k = 0; k < i; ++k) {
+            double pr = 0.0, pi = 0.0;  // <r_k, r_i>
+            if (own) {
+                const double2 a = M[k * n + c], b = M[i * n + c];
+                cmac(pr, pi, a.x, -a.y, b.x, b.y);
+            }
+            pr = wave_sum(pr);
+            pi = wave_sum(pi);
+            if (own) {
+                const double2 a = M[k * n + c];
+                double2 b = M[i * n + c];
+                cmac(b.x, b.y, -pr, -pi, a.x, a.y);
+                M[i * n + c] = b;
+            }
+        }
+        double s = 0.0;
+        if (own) s = fmadd(M[i * n + c].y, M[i * n + c].y, M[i * n + c].x * M[i * n + c].x);
+        const double inv = rsqrt(wave_sum(s));
+        if (own) {
+            M[i * n + c].x *= inv;
+            M[i * n + c].y *= inv;
+        }
+    }
+    __syncthreads();
+    for (int e = threadIdx.x; e < n * n; e += kLanes) D[e] = M[e];
+    double dr, di;
+    lds_det(D, n, dr, di);
+    const double mod = sqrt(dr * dr + di * di);
+    const double cr = dr / mod, ci = -di / mod;
+    if (own) {
+        const double2 r = M[(n - 1) * n + c];
+        M[(n - 1) * n + c] = make_double2(r.x * cr - r.y * ci, r.x * ci + r.y * cr);
+    }
+    __syncthreads();
+}
+
+// Link id in [0, 4V) -> (mu, parity, h), as the register kernels number them.
+__device__ __forceinline__ void link_id(const Geom& g, int id, int& mu, int& par, int& h) {
+    mu = id / g.V;
+    const int rem = id - mu * g.V;
+    par = rem >= g.Vh ? 1 : 0;
+    h = rem - par * g.Vh;
+}
+
+// Re-unitarization of link blockIdx.x; with REPORT the deviation found before
+// the projection goes to partial[2 id], [2 id + 1].  LDS: M, D (FP64).
+template <typename T, bool REPORT>
+__global__ __launch_bounds__(kLanes) void k_reunit(T2<T>* __restrict__ U, Geom g, int n,
+                                                   double* __restrict__ partial) {
+    extern __shared__ double4 smem_reunit[];
+    const int n2 = n * n;
+    double2* M = reinterpret_cast<double2*>(smem_reunit);
+    double2* D = M + n2;
+    const int id = blockIdx.x;
+    int mu, par, h;
+    link_id(g, id, mu, par, h);
+    double du = 0.0, dd = 0.0;
+    if ((g.present >> mu) & 1) {
+        const T2<T>* src = link_at<T>(U, n2, mu, par, h, g.Vh);
+        lds_load<double, T>(M, src, n, false);
+        __syncthreads();
+        if (REPORT) lds_unitarity(M, D, n, du, dd);
+        __syncthreads();
+        lds_reunit(M, D, n);
+        T2<T>* dst = const_cast<T2<T>*>(src);
+        for (int e = threadIdx.x; e < n2; e += kLanes) dst[e] = cpx<T>((T)M[e].x, (T)M[e].y);
+    }
+    if (REPORT && threadIdx.x == 0) {
+        partial[2 * (size_t)id] = du;
+        partial[2 * (size_t)id + 1] = dd;
+    }
+}
+
+template <typename T>
+__global__ __launch_bounds__(kLanes) void k_unitarity(const T2<T>* __restrict__ U, Geom g, int n,
+                                                      double* __restrict__ partial) {
+    extern __shared__ double4 smem_unit[];
+    const int n2 = n * n;
+    double2* M = reinterpret_cast<double2*>(smem_unit);
+    double2* D = M + n2;
+    const int id = blockIdx.x;
+    int mu, par, h;
+    link_id(g, id, mu, par, h);
+    double du = 0.0, dd = 0.0;
+    if ((g.present >> mu) & 1) {
+        lds_load<double, T>(M, link_at<T>(U, n2, mu, par, h, g.Vh), n, false);
+        __syncthreads();
+        lds_unitarity(M, D, n, du, dd);
+    }
+    if (threadIdx.x == 0) {
+        partial[2 * (size_t)id] = du;
+        partial[2 * (size_t)id + 1] = dd;
+    }
+}
+
+// Start configuration of link blockIdx.x: identity, or a Haar draw (Gaussian
+// entries from Box-Muller on the same Philox counters as the register
+// kernels, then re-unitarization).  LDS: M, D.
+template <typename T>
+__global__ __launch_bounds__(kLanes) void k_init(T2<T>* __restrict__ U, Geom g, int n, int hot, uint32_t k0,
+                                                 uint32_t k1) {
+    extern __shared__ double4 smem_init[];
+    const int n2 = n * n;
+    double2* M = reinterpret_cast<double2*>(smem_init);
+    double2* D = M + n2;
+    const int id = blockIdx.x;
+    int mu, par, h;
+    link_id(g, id, mu, par, h);
+    if (hot && ((g.present >> mu) & 1)) {
+        const uint32_t s = (uint32_t)site_of(g, par, h).s;
+        // call q gives the Gaussians of entries 2q and 2q + 1
+        for (int q = threadIdx.x; 2 * q < n2; q += kLanes) {
+            const U4 r = philox(s, 0xFFFFFFFFu, (uint32_t)mu << 16, (RNG_HOTSTART << 24) | (uint32_t)q, k0, k1);
+#pragma unroll
+            for (int p = 0; p < 2; ++p) {
+                const double rad = sqrt(-2.0 * log(uniform<double>(r.w[2 * p])));
+                const double ang = Const<double>::two_pi * uniform<double>(r.w[2 * p + 1]);
+                if (2 * q + p < n2) M[2 * q + p] = make_double2(rad * cos(ang), rad * sin(ang));
+            }
+        }
+        __syncthreads();
+        lds_reunit(M, D, n);
+    } else {
+        for (int e = threadIdx.x; e < n2; e += kLanes) {
+            const int i = e / n;
+            M[e] = make_double2(i * n + i == e ? 1.0 : 0.0, 0.0);
+        }
+        __syncthreads();
+    }
+    T2<T>* dst = const_cast<T2<T>*>(link_at<T>(U, n2, mu, par, h, g.Vh));
+    for (int e = threadIdx.x; e < n2; e += kLanes) dst[e] = cpx<T>((T)M[e].x, (T)M[e].y);
+}
+
+// Plaquettes of site blockIdx.x (logical order): partial[2 s] = sum over the
+// planes without direction 3, partial[2 s + 1] = with direction 3, FP64.
+// ReTr(U_mu(x) U_nu(x+mu) U_mu(x+nu)^dag U_nu(x)^dag) = Re sum_ij A_ij conj(B_ij)
+// with A = U_mu(x) U_nu(x+mu), B = U_nu(x) U_mu(x+nu).  LDS: A, X, Y.
+template <typename T>
+__global__ __launch_bounds__(kLanes) void k_plaquette(const T2<T>* __restrict__ U, Geom g, int n,
+                                                      double* __restrict__ partial) {
+    extern __shared__ double4 smem_plaq[];
+    const int n2 = n * n;
+    double2* A = reinterpret_cast<double2*>(smem_plaq);
+    double2* X = A + n2;
+    double2* Y = X + n2;
+    const int s = blockIdx.x;
+    Site x;
+    {
+        int r = s;
+#pragma unroll
+        for (int m = 0; m < 4; ++m) {
+            const int q = r / g.L[m];
+            x.x[m] = r - q * g.L[m];
+            r = q;
+        }
+        x.s = s;
+    }
+    const int par = parity_of(x), op = par ^ 1, h = s >> 1;
+    double acc[2] = {0.0, 0.0};
+    for (int mu = 0; mu < 4; ++mu)
+        for (int nu = mu + 1; nu < 4; ++nu) {
+            if (!((g.present >> mu) & 1) || !((g.present >> nu) & 1)) continue;
+            const Site xm = step_up(g, x, mu), xn = step_up(g, x, nu);
+            lds_load<double, T>(X, link_at<T>(U, n2, mu, par, h, g.Vh), n, false);
+            lds_load<double, T>(Y, link_at<T>(U, n2, nu, op, xm.s >> 1, g.Vh), n, false);
+            __syncthreads();
+            lds_mm<double>(A, X, Y, n, false);
+            __syncthreads();
+            lds_load<double, T>(X, link_at<T>(U, n2, nu, par, h, g.Vh), n, false);
+            lds_load<double, T>(Y, link_at<T>(U, n2, mu, op, xn.s >> 1, g.Vh), n, false);
+            __syncthreads();
+            double t = 0.0;
+            for (int e = threadIdx.x; e < n2; e += kLanes) {
+                const int i = e / n, j = e - i * n;
+                double br = 0.0, bi = 0.0;
+                for (int k = 0; k < n; ++k) {
+                    const double2 a = X[i * n + k], b = Y[k * n + j];
+                    cmac(br, bi, a.x, a.y, b.x, b.y);
+                }
+                t = fmadd(A[e].y, bi, fmadd(A[e].x, br, t));
+            }
+            acc[nu == 3 ? 1 : 0] += wave_sum(t);
+            __syncthreads();
+        }
+    if (threadIdx.x == 0) {
+        partial[2 * (size_t)s] = acc[0];
+        partial[2 * (size_t)s + 1] = acc[1];
+    }
+}
+
+// Polyakov loop at spatial site blockIdx.x: Tr prod_t U_3(x, t), FP64.
+// LDS: P, X, Tm.
+template <typename T>
+__global__ __launch_bounds__(kLanes) void k_polyakov(const T2<T>* __restrict__ U, Geom g, int n,
+                                                     double* __restrict__ partial) {
+    extern __shared__ double4 smem_poly[];
+    const int n2 = n * n;
+    double2* P = reinterpret_cast<double2*>(smem_poly);
+    double2* X = P + n2;
+    double2* Tm = X + n2;
+    const int xs = blockIdx.x;
+    const int Vs = g.V / g.L[3];
+    for (int e = threadIdx.x; e < n2; e += kLanes) {
+        const int i = e / n;
+        P[e] = make_double2(i * n + i == e ? 1.0 : 0.0, 0.0);
+    }
+    for (int t = 0; t < g.L[3]; ++t) {
+        const int s = xs + t * Vs;
+        Site st;
+        int r = s;
+#pragma unroll
+        for (int m = 0; m < 4; ++m) {
+            const int q = r / g.L[m];
+            st.x[m] = r - q * g.L[m];
+            r = q;
+        }
+        st.s = s;
+        lds_load<double, T>(X, link_at<T>(U, n2, 3, parity_of(st), s >> 1, g.Vh), n, false);
+        __syncthreads();
+        lds_mm<double>(Tm, P, X, n, false);
+        __syncthreads();
+        double2* tmp = P;
+        P = Tm;
+        Tm = tmp;
+    }
+    double tr = 0.0, ti = 0.0;
+    for (int i = threadIdx.x; i < n; i += kLanes) {
+        tr += P[i * n + i].x;
+        ti += P[i * n + i].y;
+    }
+    tr = wave_sum(tr);
+    ti = wave_sum(ti);
+    if (threadIdx.x == 0) {
+        partial[2 * (size_t)xs] = tr;
+        partial[2 * (size_t)xs + 1] = ti;
+    }
+}
+
+// Canonical FP64 field [mu][s][i][j] (re, im) <-> link-major storage; one
+// work-item per complex entry.
+template <typename T>
+__global__ __launch_bounds__(256) void k_export(const T2<T>* __restrict__ U, Geom g, int n,
+                                                double* __restrict__ out) {
+    const int n2 = n * n;
+    const long long idx = (long long)blockIdx.x * 256 + threadIdx.x;
+    if (idx >= 4LL * g.V * n2) return;
+    const int id = (int)(idx / n2), e = (int)(idx - (long long)id * n2);
+    int mu, par, h;
+    link_id(g, id, mu, par, h);
+    const int s = site_of(g, par, h).s;
+    const T2<T> v = link_at<T>(U, n2, mu, par, h, g.Vh)[e];
+    double* o = out + (((size_t)mu * g.V + s) * n2 + e) * 2;
+    o[0] = (double)v.x;
+    o[1] = (double)v.y;
+}
+
+template <typename T>
+__global__ __launch_bounds__(256) void k_import(T2<T>* __restrict__ U, Geom g, int n, const double* __restrict__ in) {
+    const int n2 = n * n;
+    const long long idx = (long long)blockIdx.x * 256 + threadIdx.x;
+    if (idx >= 4LL * g.V * n2) return;
+    const int id = (int)(idx / n2), e = (int)(idx - (long long)id * n2);
+    int mu, par, h;
+    link_id(g, id, mu, par, h);
+    const int s = site_of(g, par, h).s;
+    const double* p = in + (((size_t)mu * g.V + s) * n2 + e) * 2;
+    T2<T>* dst = const_cast<T2<T>*>(link_at<T>(U, n2, mu, par, h, g.Vh));
+    dst[e] = cpx<T>((T)p[0], (T)p[1]);
+}
+
+}  // namespace wide
+}  // namespace sun

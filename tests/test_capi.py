@@ -49,11 +49,19 @@ def test_lattice_bytes(lib):
     assert rc == 0 and lb == 4 * 8 ** 4 * 12 * 8
     for nc in (2, 4):
         assert _bytes(lib, nc, (8, 8, 8, 8), 2)[0] == -4
+    # the workgroup-per-link path: Nc^2 complex entries per link, one FP64
+    # partial pair per link in the scratch buffer
+    for nc, dt, size in [(9, 0, 4), (16, 1, 8), (32, 0, 4), (4, 4, 4), (8, 5, 8), (28, 1, 8)]:
+        rc, lb, sb = _bytes(lib, nc, (8, 8, 8, 8), dt)
+        assert rc == 0 and lb == 4 * 8 ** 4 * 2 * nc * nc * size, (nc, dt)
+        assert sb >= 16 * 4 * 8 ** 4, (nc, dt)
+    for nc, dt in [(3, 4), (2, 5), (29, 1), (32, 5)]:    # below Nc = 4, or past the FP64 LDS limit
+        assert _bytes(lib, nc, (8, 8, 8, 8), dt)[0] == -4, (nc, dt)
 
 
 @pytest.mark.parametrize("nc,L,dtype", [
-    (1, (8, 8, 8, 8), 0), (9, (8, 8, 8, 8), 0), (3, (7, 8, 8, 8), 0), (3, (1, 8, 8, 8), 0),
-    (3, (8, 8, 3, 8), 0), (3, (8, 8, 8, 8), 4), (3, (256, 256, 256, 256), 0)])
+    (1, (8, 8, 8, 8), 0), (33, (8, 8, 8, 8), 0), (3, (7, 8, 8, 8), 0), (3, (1, 8, 8, 8), 0),
+    (3, (8, 8, 3, 8), 0), (3, (8, 8, 8, 8), 6), (3, (8, 8, 8, 8), -1), (3, (256, 256, 256, 256), 0)])
 def test_lattice_bytes_rejects(lib, nc, L, dtype):
     rc, _, _ = _bytes(lib, nc, L, dtype)
     assert rc == -1
@@ -126,5 +134,15 @@ def test_batch_argument_checks(lib):
     d = (ctypes.c_double * 1)(1.0)
     s = (ctypes.c_uint64 * 1)(1)
     assert lib.sun_batch_create(1, one, d, s, ctypes.c_void_p(0x10000), tb.value, ctypes.byref(out)) == -1
+    # a lattice on the workgroup-per-link path is refused before anything runs
+    L = (ctypes.c_int * 4)(4, 4, 2, 2)
+    lb, sb = ctypes.c_size_t(), ctypes.c_size_t()
+    assert lib.sun_lattice_bytes(9, L, 0, ctypes.byref(lb), ctypes.byref(sb)) == 0
+    h = ctypes.c_void_p()
+    assert lib.sun_lattice_create(9, L, 0, ctypes.c_void_p(0x100000), lb.value, ctypes.c_void_p(0x200000), sb.value,
+                                  ctypes.byref(h)) == 0
+    wide = (ctypes.c_void_p * 1)(h.value)
+    assert lib.sun_batch_create(1, wide, d, s, ctypes.c_void_p(0x10000), tb.value, ctypes.byref(out)) == -4
+    lib.sun_lattice_destroy(h)
     assert lib.sun_batch_sweep(None, 1, 1, 1, None) == -1
     assert lib.sun_batch_replay(None, None) == -1

@@ -28,77 +28,8 @@ from stats import binned_mean_err
 
 pytestmark = pytest.mark.gpu
 
-TOL = {"f64": 1e-12, "f32": 1e-5, "f64r12": 1e-12, "f32r12": 1e-5}
-FLIP_MARGIN = 1e-4
-
-
-def to_np(t):
-    torch.cuda.synchronize()
-    return t.detach().cpu().numpy()
-
-
-def gpu_lattice(sun, nc, L, dtype, field=None, hot=True, seed=1234):
-    lat = sun.Lattice(nc, L, dtype)
-    if field is None:
-        lat.init(hot=hot, seed=seed)
-    else:
-        lat.import_(torch.from_numpy(field))
-    return lat
-
-
-def rounded(field, dtype):
-    """The field as the GPU stores it (FP32 rounding of each real)."""
-    if dtype == "f64":
-        return field.copy()
-    r = field.real.astype(np.float32).astype(np.float64)
-    i = field.imag.astype(np.float32).astype(np.float64)
-    return r + 1j * i
-
-
-def compare_links(gpu_field, orc_field, dtype, margin=None, cond=None, what=""):
-    """Link-by-link comparison; margin and cond are (4, V) arrays from the
-    oracle's phase diagnostics (entries < 0: link not updated)."""
-    d = np.abs(gpu_field - orc_field).reshape(4, gpu_field.shape[1], -1).max(axis=2)
-    scale = np.ones_like(d)
-    if cond is not None:
-        c = np.asarray(cond, dtype=np.float64)
-        scale = np.maximum(1.0, np.where(c > 0, c, 0.0) / (2.0 if dtype.startswith("f32") else 4.0))
-        ratio = d / (TOL[dtype] * scale)
-        print(f"{what}: max |dU| {d.max():.2e}, max |dU| / tol {ratio.max():.3f}")
-    bad = d > TOL[dtype] * scale
-    if not bad.any():
-        return 0
-    idx = np.argwhere(bad)
-    if dtype.startswith("f64") or margin is None:
-        mu, s = idx[0]
-        raise AssertionError(f"{what}: {len(idx)} links out of tolerance, e.g. (mu={mu}, s={s}) "
-                             f"|dU| = {d[mu, s]:.3e}, tol {TOL[dtype] * scale[mu, s]:.2e}")
-    m = np.where(np.asarray(margin) < 0, np.inf, margin)
-    for mu, s in idx:
-        assert m[mu][s] < FLIP_MARGIN, (
-            f"{what}: link (mu={mu}, s={s}) differs by {d[mu, s]:.3e} with decision margin {m[mu][s]:.3e}")
-    assert len(idx) <= max(3, 1e-4 * d.size), f"{what}: {len(idx)} flipped links"
-    return len(idx)
-
-
-def oracle_phase_diag(field, nc, L, kind, mu, par, beta, seed, step):
-    """Runs the oracle phase in place; returns (4, V) margin and conditioning maps."""
-    margin, _, cond = O.phase(field, nc, L, kind, mu, par, beta, seed, step, want_margin=True)
-    mfull = np.full((4, field.shape[1]), -1.0)
-    cfull = np.full((4, field.shape[1]), -1.0)
-    mfull[mu] = margin
-    cfull[mu] = cond
-    return mfull, cfull
-
-
-def thermal_field(nc, L, beta, sweeps=2, seed=77):
-    U = O.new_field(nc, L, hot=True, seed=seed)
-    for k in range(sweeps):
-        O.sweep(U, nc, L, beta, 1, 1, seed, k)
-    return U
-
-
-BETA = {2: 2.3, 3: 6.0, 4: 11.1, 5: 17.3, 6: 24.98, 7: 34.0, 8: 44.4}
+from gpu_common import (BETA, FLIP_MARGIN, TOL, compare_links, gpu_lattice, oracle_phase_diag, rounded,
+                        thermal_field, to_np)
 
 
 # ---------------------------------------------------------------------------
@@ -454,7 +385,9 @@ def test_rejects_bad_arguments(gpu):
     with pytest.raises(sun.SunError):
         sun.Lattice(3, (8, 7, 8, 8))
     with pytest.raises(sun.SunError):
-        sun.Lattice(9, (8, 8, 8, 8))
+        sun.Lattice(33, (8, 8, 8, 8))
+    with pytest.raises(sun.SunError):
+        sun.Lattice(29, (8, 8, 8, 8), "f64")      # past the FP64 LDS limit of the wide path
     lat = gpu_lattice(sun, 3, (4, 4, 4, 4), "f32")
     with pytest.raises(sun.SunError):
         lat.phase(0, 4, 0, 6.0, 1, 0)

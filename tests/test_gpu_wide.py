@@ -1,0 +1,150 @@
+"""GPU parity of the large-Nc path (one workgroup per link, link-major
+storage) against the FP64 oracle, for 4 <= Nc <= 32.
+
+The tolerances are those of test_gpu_parity (FP64 1e-12, FP32 1e-5, scaled
+by the update's conditioning, FP32 decision flips near their threshold
+counted), widened where the oracle itself is sensitive: one link update is a
+chain of Nc (Nc - 1) / 2 subgroup steps (496 at Nc = 32), each dividing by
+its own k, so rounding compounds along the chain.  The oracle's phase is run
+a second time with its input perturbed at the storage precision's rounding
+level (1e-7 FP32, 1e-15 FP64), and a link may differ by up to 100 times the
+change that perturbation makes to it.  A decision that the perturbation
+flips counts as sensitive in the same way."""
+import numpy as np
+import pytest
+import torch
+
+import oracle as O
+from gpu_common import (beta_for, compare_links, gpu_lattice, oracle_phase_diag, rounded, thermal_field, to_np,
+                        twin_spread)
+
+pytestmark = pytest.mark.gpu
+
+SMALL = (4, 4, 2, 2)      # V/2 = 32 links per phase
+REL = {"f32": 1e-7, "f64": 1e-15}   # input perturbation of the oracle twin
+
+
+@pytest.mark.parametrize("nc,dtype", [(4, "f64w"), (4, "f32w"), (9, "f64"), (9, "f32"), (16, "f64"),
+                                      (16, "f32"), (28, "f64"), (32, "f32")])
+def test_wide_hot_start_parity(gpu, nc, dtype):
+    L = (4, 2, 2, 2)
+    lat = gpu_lattice(gpu, nc, L, dtype, hot=True, seed=1234)
+    got = to_np(lat.export())
+    want = O.new_field(nc, L, hot=True, seed=1234)
+    # Gram-Schmidt of an Nc x Nc Gaussian matrix: rounding ~ cond(M) eps
+    tol = 1e-11 if dtype.startswith("f64") else 1e-6
+    assert np.abs(got - want).max() < tol
+
+
+@pytest.mark.parametrize("nc", [4, 10])
+def test_wide_cold_start_exact(gpu, nc):
+    lat = gpu_lattice(gpu, nc, (4, 4, 2, 2), "f32w", hot=False)
+    assert np.array_equal(to_np(lat.plaquette()), [1.0, 1.0, 1.0])
+    assert np.array_equal(to_np(lat.polyakov()), [1.0, 0.0])
+    assert np.array_equal(to_np(lat.unitarity()), [0.0, 0.0])
+
+
+@pytest.mark.parametrize("nc,dtype", [(5, "f64w"), (12, "f32"), (12, "f64")])
+def test_wide_roundtrip(gpu, nc, dtype):
+    L = (4, 2, 2, 2)
+    U = O.new_field(nc, L, hot=True, seed=5)
+    lat = gpu_lattice(gpu, nc, L, dtype, field=U)
+    assert np.array_equal(to_np(lat.export()), rounded(U, dtype))
+
+
+@pytest.mark.parametrize("nc,dtype", [(4, "f64w"), (9, "f64"), (9, "f32"), (16, "f64")])
+def test_wide_observables_parity(gpu, nc, dtype):
+    L = (4, 2, 2, 4)
+    lat = gpu_lattice(gpu, nc, L, dtype, field=thermal_field(nc, L, beta_for(nc), sweeps=1))
+    U = to_np(lat.export())
+    np.testing.assert_allclose(to_np(lat.plaquette()), O.plaquette(U, nc, L), rtol=1e-13, atol=1e-15)
+    pg = to_np(lat.polyakov())
+    assert abs(complex(pg[0], pg[1]) - O.polyakov(U, nc, L)) < 1e-13
+    np.testing.assert_allclose(to_np(lat.unitarity()), O.unitarity(U, nc, L), rtol=1e-6, atol=1e-14)
+
+
+@pytest.mark.parametrize("nc", [4, 9, 16])
+def test_wide_reunitarize_parity(gpu, nc):
+    L = (4, 2, 2, 2)
+    rng = np.random.default_rng(nc)
+    U = O.new_field(nc, L, hot=True, seed=9)
+    U = U + 1e-3 * (rng.standard_normal(U.shape) + 1j * rng.standard_normal(U.shape))
+    lat = gpu_lattice(gpu, nc, L, "f64" if nc > 8 else "f64w", field=U)
+    before = to_np(lat.reunitarize(report=True))
+    after = to_np(lat.export())
+    np.testing.assert_allclose(before, O.unitarity(U, nc, L), rtol=1e-10)
+    O.reunitarize(U, nc, L)
+    assert np.abs(after - U).max() < 1e-12
+    assert to_np(lat.unitarity()).max() < 1e-13
+
+
+PHASES = [(0, 0, 0), (0, 3, 1), (1, 1, 1), (1, 2, 0)]   # (kind, mu, parity)
+
+
+@pytest.mark.parametrize("nc,dtype", [(4, "f64w"), (4, "f32w"), (5, "f64w"), (9, "f64"), (9, "f32"),
+                                      (16, "f64"), (16, "f32"), (24, "f64"), (32, "f32")])
+def test_wide_phase_parity(gpu, nc, dtype):
+    beta = beta_for(nc)
+    base = thermal_field(nc, SMALL, beta, sweeps=1) if nc <= 16 else O.new_field(nc, SMALL, hot=True, seed=21)
+    lat = gpu_lattice(gpu, nc, SMALL, dtype, field=base)
+    flips = 0
+    for kind, mu, par in PHASES:
+        before = to_np(lat.export())               # the GPU's own input field
+        lat.phase(kind, mu, par, beta, seed=77, step=3)
+        got = to_np(lat.export())
+        sp = twin_spread(before, nc, SMALL, kind, mu, par, beta, 77, 3, rel=REL[dtype[:3]])
+        want = before.copy()
+        m, k = oracle_phase_diag(want, nc, SMALL, kind, mu, par, beta, 77, 3)
+        flips += compare_links(got, want, dtype, m, k, f"nc={nc} {dtype} kind={kind} mu={mu} p={par}", spread=sp)
+    print(f"flips: {flips}")
+
+
+def test_wide_su32_8x4_phase_parity(gpu):
+    """The paper's largest single-precision case: SU(32) on 8^4."""
+    nc, L, beta = 32, (8, 8, 8, 8), 6.2
+    lat = gpu_lattice(gpu, nc, L, "f32", hot=True, seed=1234)
+    base = to_np(lat.export())
+    lat.phase(0, 1, 0, beta, seed=1234, step=0)
+    got = to_np(lat.export())
+    sp = twin_spread(base, nc, L, 0, 1, 0, beta, 1234, 0, rel=REL["f32"])
+    m, k = oracle_phase_diag(base, nc, L, 0, 1, 0, beta, 1234, 0)
+    flips = compare_links(got, base, "f32", m, k, "SU(32) 8^4 heatbath", spread=sp)
+    print(f"flips: {flips}")
+
+
+@pytest.mark.parametrize("nc", [4, 6, 8])
+def test_wide_agrees_with_register_path(gpu, nc):
+    """The two implementations of Nc <= 8 draw the same random numbers: a
+    heatbath and an overrelaxation phase agree to FP64 rounding."""
+    L = (4, 4, 2, 2)
+    U = thermal_field(nc, L, beta_for(nc), sweeps=1)
+    a = gpu_lattice(gpu, nc, L, "f64", field=U)
+    b = gpu_lattice(gpu, nc, L, "f64w", field=U)
+    for lat in (a, b):
+        lat.phase(0, 2, 1, beta_for(nc), seed=5, step=1)
+        lat.phase(1, 0, 0, beta_for(nc), seed=5, step=1)
+    assert np.abs(to_np(a.export()) - to_np(b.export())).max() < 1e-11
+    np.testing.assert_allclose(to_np(a.plaquette()), to_np(b.plaquette()), rtol=1e-13)
+
+
+def test_wide_sweep_is_its_phase_sequence(gpu):
+    nc, L = 10, (4, 4, 2, 2)
+    beta = beta_for(nc)
+    a = gpu_lattice(gpu, nc, L, "f32", hot=True, seed=4)
+    b = gpu_lattice(gpu, nc, L, "f32", hot=True, seed=4)
+    a.sweep(beta, 1, 2, seed=4)
+    for kind, steps in ((0, 1), (1, 2)):
+        for _ in range(steps):
+            for mu in range(4):
+                for par in range(2):
+                    b.phase(kind, mu, par, beta, seed=4, step=0)
+    b.reunitarize()
+    assert torch.equal(a.links, b.links)
+    assert a.step == 1
+
+
+def test_wide_rejected_by_batches(gpu):
+    sun = gpu
+    lat = gpu_lattice(sun, 9, (4, 4, 2, 2), "f32")
+    with pytest.raises(sun.SunError):
+        sun.Batch([lat], [6.0], [1])
