@@ -245,6 +245,73 @@ def run_cpu_baseline(run, sweeps):
     }
 
 
+PEAK_FP32_TFLOPS = 78.6          # MI355X vector FP32 without packed instructions (= the FP64 rate)
+PEAK_FP64_TFLOPS = 78.6
+NC_SCAN = {"f32": (4, 5, 6, 8, 10, 12, 16, 20, 24, 28, 32), "f64": (4, 5, 6, 8, 10, 12, 16, 20, 24, 28)}
+
+
+def wide_update_flops(nc):
+    """Algorithmic flops of one link update on the large-Nc path: 12 staple
+    products and W = U A (8 Nc^3 each), and per subgroup two rows of U and W
+    times a 2x2 complex matrix (32 flops per column and matrix)."""
+    return 13 * 8 * nc ** 3 + (nc * (nc - 1) // 2) * 2 * 32 * nc
+
+
+def run_nc_scan(reps, warmup):
+    """Time per iteration (1 heatbath + 1 overrelaxation step + re-unitarization,
+    the paper's large-Nc protocol) on 8^4 at beta 6.2, hot start, for the
+    register path (Nc <= 4) and the workgroup-per-link path (Nc >= 4), and a
+    least-squares cubic fit of the latter's time in Nc."""
+    import numpy as np
+    import torch
+    from paper_1112_4533_amd import sun
+
+    L, beta = (8, 8, 8, 8), 6.2
+    V = 8 ** 4
+    rows, fits = [], {}
+    for prec, ncs in NC_SCAN.items():
+        for nc in ncs:
+            paths = (["register"] if nc <= sun.NC_MAX_REGISTER else []) + ["wide"]
+            for path in paths:
+                dtype = prec if path == "register" or nc > sun.NC_MAX_REGISTER else prec + "w"
+                lat = sun.Lattice(nc, L, dtype)
+                lat.init(hot=True, seed=1234)
+                for _ in range(warmup):
+                    lat.sweep(beta, 1, 1, seed=1234)
+                torch.cuda.synchronize()
+                lat.profile(True)
+                a, b = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+                a.record()
+                for _ in range(reps):
+                    lat.sweep(beta, 1, 1, seed=1234)
+                b.record()
+                b.synchronize()
+                ms = a.elapsed_time(b) / reps
+                kern = {k: lat.profile_read(k) for k in ("heatbath", "overrelax", "reunit")}
+                lat.profile(False)
+                row = {"nc": nc, "precision": prec, "path": path, "ms_per_iteration": ms,
+                       "link_updates_per_s": 2 * 4 * V / (ms * 1e-3),
+                       "kernel_avg_ms": {k: (t / n if n else None) for k, (t, n) in kern.items()}}
+                if path == "wide":
+                    t_or = row["kernel_avg_ms"]["overrelax"]
+                    fl = wide_update_flops(nc) * V / 2
+                    peak = PEAK_FP32_TFLOPS if prec == "f32" else PEAK_FP64_TFLOPS
+                    row["overrelax_tflops"] = fl / (t_or * 1e-3) / 1e12
+                    row["overrelax_frac_of_peak"] = row["overrelax_tflops"] / peak
+                rows.append(row)
+                print(json.dumps(row), flush=True)
+                del lat
+        w = [(r["nc"], r["ms_per_iteration"]) for r in rows if r["precision"] == prec and r["path"] == "wide"]
+        x = np.array([n for n, _ in w], dtype=float)
+        y = np.array([t for _, t in w])
+        c = np.polyfit(x, y, 3)
+        fits[prec] = {"ms_cubic_coeffs_high_to_low": c.tolist(),
+                      "max_rel_residual": float(np.max(np.abs(np.polyval(c, x) - y) / y)),
+                      "cubic_share_at_max_nc": float(c[0] * x[-1] ** 3 / y[-1])}
+    return {"nc_scan": {"lattice": "8^4", "beta": beta, "iteration": "1 HB + 1 OR + re-unitarization",
+                        "rows": rows, "fit": fits}}
+
+
 def main():
     ap = argparse.ArgumentParser(description=__doc__, formatter_class=argparse.RawDescriptionHelpFormatter)
     ap.add_argument("--gpus", type=int, default=1)
@@ -261,7 +328,12 @@ def main():
     ap.add_argument("--copy-calibration", type=float, default=0.0, metavar="GB",
                     help="only copy a GB-sized device buffer 5 times (the reference kernel for "
                          "scaling HBM byte counters), then exit")
+    ap.add_argument("--nc-scan", action="store_true",
+                    help="only time one iteration against Nc (4..32) on 8^4 and fit a cubic, then exit")
     args = ap.parse_args()
+    if args.nc_scan:
+        print(json.dumps(run_nc_scan(max(1, args.steps // 10), max(1, args.warmup // 3))), flush=True)
+        return
     if args.copy_calibration > 0:
         import torch
         n = int(args.copy_calibration * 1e9) // 4

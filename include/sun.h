@@ -56,12 +56,12 @@ enum {
  *
  * Nc <= SUN_NC_MAX_REGISTER runs one link per work-item with the link
  * matrices in registers and the field split into planes by (direction,
- * parity, matrix entry).  Larger Nc (paper Sec. 4: up to 32 in single and
- * 16 in double precision at 8^4) runs the generic path of one 64-lane
+ * parity, matrix entry).  Larger Nc (the paper's generic SU(Nc) code, Sec. 4:
+ * up to 32 in single and 16 in double precision at 8^4) runs one 64-lane
  * workgroup per link, matrices in LDS and the entries of each link
  * contiguous in memory; SUN_F32 and SUN_F64 select it by themselves there,
- * and the WIDE codes select it for any 4 <= Nc <= 32 (for comparisons with
- * the register path).  Its FP64 form needs 5 Nc^2 x 16 bytes of LDS per
+ * and the WIDE codes select it at Nc = 4 too (for comparisons with the
+ * register path).  Its FP64 form needs 5 Nc^2 x 16 bytes of LDS per
  * workgroup and so stops at Nc = 28 (SUN_EUNSUP beyond).  Launch shapes do
  * not apply to it, and batches do not accept it. */
 enum {
@@ -77,7 +77,7 @@ enum {
 enum { SUN_HEATBATH = 0, SUN_OVERRELAX = 1 };
 
 /* Largest Nc of the register path, and of the build. */
-#define SUN_NC_MAX_REGISTER 8
+#define SUN_NC_MAX_REGISTER 4
 #define SUN_NC_MAX 32
 
 /* Bytes of device memory a lattice needs: the link field (SoA planes split by

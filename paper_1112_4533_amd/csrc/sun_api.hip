@@ -85,10 +85,6 @@ const sun::Ops* ops_for(int nc, int dtype) {
         case 2: return sun::ops_nc2(f64);
         case 3: return sun::ops_nc3(f64);
         case 4: return sun::ops_nc4(f64);
-        case 5: return sun::ops_nc5(f64);
-        case 6: return sun::ops_nc6(f64);
-        case 7: return sun::ops_nc7(f64);
-        case 8: return sun::ops_nc8(f64);
         default: return nullptr;
     }
 }

@@ -7,12 +7,9 @@
 #include <stdint.h>
 
 // Loops over matrix indices are fully unrolled, so that register-array
-// indices are compile-time constants.  Large-Nc translation units define
-// SUN_MAT_UNROLL to _Pragma("unroll 1") first: their matrices spill anyway and
-// full unrolling only multiplies compile time.
-#ifndef SUN_MAT_UNROLL
+// indices are compile-time constants (the register path runs Nc <= 4; larger
+// Nc keeps its matrices in LDS, sun_wide.hpp).
 #define SUN_MAT_UNROLL _Pragma("unroll")
-#endif
 
 namespace sun {
 

@@ -88,12 +88,8 @@ inline int spatial_blocks(const Geom& g) { return blocks_for(g.V / g.L[3]); }
 const Ops* ops_nc2(int f64);
 const Ops* ops_nc3(int f64);
 const Ops* ops_nc4(int f64);
-const Ops* ops_nc5(int f64);
-const Ops* ops_nc6(int f64);
-const Ops* ops_nc7(int f64);
-const Ops* ops_nc8(int f64);
 const Ops* ops_nc3_two_row(int f64);  // SU(3), rows 0 and 1 stored
-const Ops* ops_wide(int f64);         // 4 <= Nc <= 32, one workgroup per link, link-major
+const Ops* ops_wide(int f64);         // 4 <= Nc <= 32: one workgroup per link, link-major storage
 
 // Dynamic LDS of the wide phase kernel, and whether it fits a workgroup.
 constexpr size_t kWideLdsMax = 64 * 1024;

@@ -16,7 +16,7 @@ LIB_PATH = os.path.join(_PKG, "_lib", "libsun.so")
 F32, F64, F32_TWO_ROW, F64_TWO_ROW, F32_WIDE, F64_WIDE = 0, 1, 2, 3, 4, 5
 DTYPE_NAMES = {F32: "f32", F64: "f64", F32_TWO_ROW: "f32r12", F64_TWO_ROW: "f64r12", F32_WIDE: "f32w",
                F64_WIDE: "f64w"}
-NC_MAX_REGISTER, NC_MAX = 8, 32
+NC_MAX_REGISTER, NC_MAX = 4, 32
 HEATBATH, OVERRELAX = 0, 1
 KERNEL_IDS = {"heatbath": 0, "overrelax": 1, "reunit": 2, "plaquette": 3, "polyakov": 4}
 SUN_OK = 0
@@ -113,7 +113,7 @@ def _ptr(t):
 def _dtype_code(dtype):
     """Link storage: "f32", "f64", the SU(3) two-row forms "f32r12",
     "f64r12", or "f32w", "f64w" for the workgroup-per-link path at any
-    Nc >= 4 (which "f32" / "f64" select by themselves above Nc = 8); also the
+    Nc >= 4 (which "f32" / "f64" select by themselves above Nc = 4); also the
     integer codes."""
     if isinstance(dtype, int) and dtype in DTYPE_NAMES:
         return dtype

@@ -24,7 +24,7 @@ SMALL = (4, 4, 2, 2)      # V/2 = 32 links per phase
 REL = {"f32": 1e-7, "f64": 1e-15}   # input perturbation of the oracle twin
 
 
-@pytest.mark.parametrize("nc,dtype", [(4, "f64w"), (4, "f32w"), (9, "f64"), (9, "f32"), (16, "f64"),
+@pytest.mark.parametrize("nc,dtype", [(4, "f64w"), (4, "f32w"), (5, "f32"), (9, "f64"), (9, "f32"), (16, "f64"),
                                       (16, "f32"), (28, "f64"), (32, "f32")])
 def test_wide_hot_start_parity(gpu, nc, dtype):
     L = (4, 2, 2, 2)
@@ -112,9 +112,9 @@ def test_wide_su32_8x4_phase_parity(gpu):
     print(f"flips: {flips}")
 
 
-@pytest.mark.parametrize("nc", [4, 6, 8])
+@pytest.mark.parametrize("nc", [4])
 def test_wide_agrees_with_register_path(gpu, nc):
-    """The two implementations of Nc <= 8 draw the same random numbers: a
+    """The two implementations of SU(4) draw the same random numbers: a
     heatbath and an overrelaxation phase agree to FP64 rounding."""
     L = (4, 4, 2, 2)
     U = thermal_field(nc, L, beta_for(nc), sweeps=1)
