@@ -260,8 +260,9 @@ def wide_update_flops(nc):
 def run_nc_scan(reps, warmup):
     """Time per iteration (1 heatbath + 1 overrelaxation step + re-unitarization,
     the paper's large-Nc protocol) on 8^4 at beta 6.2, hot start, for the
-    register path (Nc <= 4) and the workgroup-per-link path (Nc >= 4), and a
-    least-squares cubic fit of the latter's time in Nc."""
+    register path (Nc <= 4) and the workgroup-per-link path (Nc >= 4), a
+    cubic fit of the latter's time in Nc (least squares in relative error),
+    and the log-log slope of each kernel's time from Nc = 16 up."""
     import numpy as np
     import torch
     from paper_1112_4533_amd import sun
@@ -301,13 +302,19 @@ def run_nc_scan(reps, warmup):
                 rows.append(row)
                 print(json.dumps(row), flush=True)
                 del lat
-        w = [(r["nc"], r["ms_per_iteration"]) for r in rows if r["precision"] == prec and r["path"] == "wide"]
-        x = np.array([n for n, _ in w], dtype=float)
-        y = np.array([t for _, t in w])
-        c = np.polyfit(x, y, 3)
+        w = [r for r in rows if r["precision"] == prec and r["path"] == "wide"]
+        x = np.array([r["nc"] for r in w], dtype=float)
+        y = np.array([r["ms_per_iteration"] for r in w])
+        c = np.polyfit(x, y, 3, w=1.0 / y)          # least squares in relative error
+        slopes = {}
+        for k in ("heatbath", "overrelax", "reunit"):
+            t = np.array([r["kernel_avg_ms"][k] for r in w])
+            lo = int(np.searchsorted(x, 16))
+            slopes[k] = float(np.log(t[-1] / t[lo]) / np.log(x[-1] / x[lo]))
         fits[prec] = {"ms_cubic_coeffs_high_to_low": c.tolist(),
                       "max_rel_residual": float(np.max(np.abs(np.polyval(c, x) - y) / y)),
-                      "cubic_share_at_max_nc": float(c[0] * x[-1] ** 3 / y[-1])}
+                      "cubic_share_at_max_nc": float(c[0] * x[-1] ** 3 / y[-1]),
+                      "loglog_slope_nc16_to_max": slopes}
     return {"nc_scan": {"lattice": "8^4", "beta": beta, "iteration": "1 HB + 1 OR + re-unitarization",
                         "rows": rows, "fit": fits}}
 
