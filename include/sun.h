@@ -61,9 +61,9 @@ enum {
  * workgroup per link, matrices in LDS and the entries of each link
  * contiguous in memory; SUN_F32 and SUN_F64 select it by themselves there,
  * and the WIDE codes select it at Nc = 4 too (for comparisons with the
- * register path).  Its FP64 form needs 5 Nc^2 x 16 bytes of LDS per
- * workgroup and so stops at Nc = 28 (SUN_EUNSUP beyond).  Launch shapes do
- * not apply to it, and batches do not accept it. */
+ * register path).  Its update keeps 4 Nc^2 complex entries in LDS (64 KiB
+ * at Nc = 32 in FP64).  Launch shapes do not apply to it, and batches do
+ * not accept it. */
 enum {
     SUN_F32 = 0,
     SUN_F64 = 1,
@@ -88,8 +88,7 @@ int sun_lattice_bytes(int nc, const int L[4], int dtype, size_t *link_bytes,
 
 /* Creates a handle over caller-owned device buffers (links: link_bytes,
  * scratch: scratch_bytes, both 256-byte aligned).  Nc in 2..SUN_NC_MAX;
- * SUN_EUNSUP for a TWO_ROW dtype with Nc != 3, a WIDE dtype with Nc < 4, or
- * FP64 on the workgroup-per-link path with Nc > 28.
+ * SUN_EUNSUP for a TWO_ROW dtype with Nc != 3 or a WIDE dtype with Nc < 4.
  * The field content is undefined until sun_init or sun_import. */
 int sun_lattice_create(int nc, const int L[4], int dtype, void *links, size_t link_bytes,
                        void *scratch, size_t scratch_bytes, sun_lattice_t *out);

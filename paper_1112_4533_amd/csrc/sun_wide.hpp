@@ -28,9 +28,8 @@ constexpr int kLanes = 64;
 static_assert(kMaxAttempts == kLanes, "one SU(2) attempt per lane");
 constexpr int kNcMin = 4, kNcMax = 32;
 
-// Buffers (n x n complex) a kernel keeps in LDS, and the Nc limit they imply
-// for a 64 KiB workgroup allocation.
-constexpr int kUpdateBuffers = 5;
+// Buffers (n x n complex) the phase kernel keeps in LDS.
+constexpr int kUpdateBuffers = 4;
 
 template <typename T>
 __host__ __device__ inline size_t update_lds(int n) {
@@ -127,15 +126,15 @@ __device__ __forceinline__ void rows_left_mul_col(T2<T>* M, int n, int i, int j,
 
 // ---------------------------------------------------------------------------
 // One checkerboard phase: workgroup h updates U_mu(x), x = site h of parity
-// par.  LDS: U, A (staple), B0, B1 (neighbour links), Tm (product).
+// par.  LDS: A (staple), B0, B1 (neighbour links), Tm (product); after the
+// staple, B1 holds U and Tm holds W = U A.
 // ---------------------------------------------------------------------------
 template <typename T>
 __global__ __launch_bounds__(kLanes) void k_update(T2<T>* __restrict__ U, Geom g, int n, int mu, int par, int hb,
                                                    T beta, uint32_t k0, uint32_t k1, uint32_t step) {
     extern __shared__ double4 smem_update[];
     const int n2 = n * n;
-    T2<T>* Us = reinterpret_cast<T2<T>*>(smem_update);
-    T2<T>* A = Us + n2;
+    T2<T>* A = reinterpret_cast<T2<T>*>(smem_update);
     T2<T>* B0 = A + n2;
     T2<T>* B1 = B0 + n2;
     T2<T>* Tm = B1 + n2;
@@ -145,7 +144,6 @@ __global__ __launch_bounds__(kLanes) void k_update(T2<T>* __restrict__ U, Geom g
     const Site xp = step_up(g, x, mu);
     const int op = par ^ 1;
 
-    lds_load<T, T>(Us, link_at<T>(U, n2, mu, par, h, Vh), n, false);
     for (int e = threadIdx.x; e < n2; e += kLanes) A[e] = cpx<T>(T(0), T(0));
     for (int nu = 0; nu < 4; ++nu) {
         if (nu == mu || !((g.present >> nu) & 1)) continue;
@@ -171,8 +169,10 @@ __global__ __launch_bounds__(kLanes) void k_update(T2<T>* __restrict__ U, Geom g
         lds_mm<T>(A, Tm, B0, n, true);
         __syncthreads();
     }
+    T2<T>* Us = B1;
+    lds_load<T, T>(Us, link_at<T>(U, n2, mu, par, h, Vh), n, false);
     __syncthreads();
-    T2<T>* W = B0;  // W = U A
+    T2<T>* W = Tm;  // W = U A
     lds_mm<T>(W, Us, A, n, false);
     __syncthreads();
 

@@ -51,11 +51,11 @@ def test_lattice_bytes(lib):
         assert _bytes(lib, nc, (8, 8, 8, 8), 2)[0] == -4
     # the workgroup-per-link path: Nc^2 complex entries per link, one FP64
     # partial pair per link in the scratch buffer
-    for nc, dt, size in [(5, 0, 4), (9, 0, 4), (16, 1, 8), (32, 0, 4), (4, 4, 4), (8, 5, 8), (28, 1, 8)]:
+    for nc, dt, size in [(5, 0, 4), (9, 0, 4), (16, 1, 8), (32, 0, 4), (4, 4, 4), (8, 5, 8), (32, 1, 8), (29, 5, 8)]:
         rc, lb, sb = _bytes(lib, nc, (8, 8, 8, 8), dt)
         assert rc == 0 and lb == 4 * 8 ** 4 * 2 * nc * nc * size, (nc, dt)
         assert sb >= 16 * 4 * 8 ** 4, (nc, dt)
-    for nc, dt in [(3, 4), (2, 5), (29, 1), (32, 5)]:    # below Nc = 4, or past the FP64 LDS limit
+    for nc, dt in [(3, 4), (2, 5)]:    # the workgroup-per-link path starts at Nc = 4
         assert _bytes(lib, nc, (8, 8, 8, 8), dt)[0] == -4, (nc, dt)
 
 

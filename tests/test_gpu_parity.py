@@ -386,8 +386,6 @@ def test_rejects_bad_arguments(gpu):
         sun.Lattice(3, (8, 7, 8, 8))
     with pytest.raises(sun.SunError):
         sun.Lattice(33, (8, 8, 8, 8))
-    with pytest.raises(sun.SunError):
-        sun.Lattice(29, (8, 8, 8, 8), "f64")      # past the FP64 LDS limit of the wide path
     lat = gpu_lattice(sun, 3, (4, 4, 4, 4), "f32")
     with pytest.raises(sun.SunError):
         lat.phase(0, 4, 0, 6.0, 1, 0)
