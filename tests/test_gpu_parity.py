@@ -132,6 +132,24 @@ def test_reunitarize_parity(gpu, nc):
 PHASE_CASES = [(nc, dt) for nc in (2, 3, 4, 6) for dt in ("f64", "f32")] + [(3, "f64r12"), (3, "f32r12")]
 
 
+@pytest.mark.parametrize("nc,dtype,L", [(3, "f32r12", (6, 4, 1, 4)), (2, "f64", (4, 1, 4, 4)), (4, "f32", (4, 4, 4, 1))])
+def test_phase_parity_3d(gpu, nc, dtype, L):
+    """3D lattices (one absent direction): every phase of both kinds."""
+    beta = BETA[nc]
+    base = O.new_field(nc, L, hot=True, seed=17)
+    for kind in (0, 1):
+        for mu in range(4):
+            lat = gpu_lattice(gpu, nc, L, dtype, field=base)
+            want = to_np(lat.export())
+            lat.phase(kind, mu, 1, beta, seed=5, step=1)
+            got = to_np(lat.export())
+            if L[mu] == 1:      # absent direction: nothing to update
+                assert np.array_equal(got, want)
+                continue
+            m, k = oracle_phase_diag(want, nc, L, kind, mu, 1, beta, 5, 1)
+            compare_links(got, want, dtype, m, k, f"3D nc={nc} {dtype} kind={kind} mu={mu}")
+
+
 @pytest.mark.parametrize("nc,dtype", PHASE_CASES)
 @pytest.mark.parametrize("kind", [0, 1])
 def test_phase_parity(gpu, nc, dtype, kind):

@@ -148,3 +148,27 @@ def test_wide_rejected_by_batches(gpu):
     lat = gpu_lattice(sun, 9, (4, 4, 2, 2), "f32")
     with pytest.raises(sun.SunError):
         sun.Batch([lat], [6.0], [1])
+
+
+@pytest.mark.parametrize("nc,dtype,L", [(5, "f64", (4, 4, 1, 4)), (9, "f32", (4, 2, 4, 1))])
+def test_wide_absent_direction(gpu, nc, dtype, L):
+    """3D lattices: links of the absent direction stay the identity, the
+    staple has four terms, and the observables normalise over the planes
+    that exist."""
+    beta = beta_for(nc)
+    base = O.new_field(nc, L, hot=True, seed=31)
+    lat = gpu_lattice(gpu, nc, L, dtype, field=base)
+    for kind, mu, par in [(0, 0, 1), (1, 1, 0), (0, 3 if L[3] > 1 else 2, 0)]:
+        before = to_np(lat.export())
+        lat.phase(kind, mu, par, beta, seed=3, step=2)
+        got = to_np(lat.export())
+        sp = twin_spread(before, nc, L, kind, mu, par, beta, 3, 2, rel=REL[dtype[:3]])
+        want = before.copy()
+        m, k = oracle_phase_diag(want, nc, L, kind, mu, par, beta, 3, 2)
+        compare_links(got, want, dtype, m, k, f"3D nc={nc} kind={kind} mu={mu}", spread=sp)
+    U = to_np(lat.export())
+    absent = [d for d in range(4) if L[d] == 1][0]
+    assert np.array_equal(U[absent], np.broadcast_to(np.eye(nc), U[absent].shape))
+    np.testing.assert_allclose(to_np(lat.plaquette()), O.plaquette(U, nc, L), rtol=1e-13, atol=1e-15)
+    pg = to_np(lat.polyakov())
+    assert abs(complex(pg[0], pg[1]) - O.polyakov(U, nc, L)) < 1e-13
