@@ -85,7 +85,7 @@ def roofline(run, r):
             "traffic": stored_traffic(run.name), "bytes_per_launch": per_launch, "avg_launch_ms": k["avg_ms"]}
 
 
-PROFILE_EVERY = 5
+PROFILE_EVERY = 9
 
 
 def run_gpu(run, steps, warmup, tune=False):

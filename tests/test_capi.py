@@ -18,7 +18,12 @@ def declared():
 
 @pytest.fixture(scope="module")
 def lib():
-    from paper_1112_4533_amd import sun
+    """The library, built first if nothing is built (these tests make no
+    GPU calls)."""
+    import os
+    from paper_1112_4533_amd import build, sun
+    if not os.path.exists(sun.LIB_PATH):
+        build.build()
     return sun.load()
 
 
