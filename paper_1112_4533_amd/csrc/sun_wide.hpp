@@ -223,20 +223,35 @@ __device__ __forceinline__ void lds_det(double2* D, int n, double& dr, double& d
     di = 0.0;
     for (int col = 0; col < n; ++col) {
         __syncthreads();
+        // pivot: the largest |D[r][col]|^2 over r >= col, the lowest r among
+        // equals -- a scan by lane 0 for small n, a wave argmax otherwise
+        // (the same choice: the scan keeps the first strict maximum)
         int piv = col;
-        double best = 0.0;
-        if (c == 0) {
-            best = D[col * n + col].x * D[col * n + col].x + D[col * n + col].y * D[col * n + col].y;
-            for (int r = col + 1; r < n; ++r) {
-                const double a = D[r * n + col].x * D[r * n + col].x + D[r * n + col].y * D[r * n + col].y;
-                if (a > best) {
-                    best = a;
-                    piv = r;
+        double best = -1.0;
+        if (n <= 8) {
+            if (c == 0)
+                for (int r = col; r < n; ++r) {
+                    const double a = D[r * n + col].x * D[r * n + col].x + D[r * n + col].y * D[r * n + col].y;
+                    if (a > best) {
+                        best = a;
+                        piv = r;
+                    }
+                }
+            piv = __shfl(piv, 0, kLanes);
+            best = __shfl(best, 0, kLanes);
+        } else {
+            piv = c;
+            if (c >= col && c < n) best = D[c * n + col].x * D[c * n + col].x + D[c * n + col].y * D[c * n + col].y;
+#pragma unroll
+            for (int off = 32; off > 0; off >>= 1) {
+                const double ob = __shfl_xor(best, off, kLanes);
+                const int op = __shfl_xor(piv, off, kLanes);
+                if (ob > best || (ob == best && op < piv)) {
+                    best = ob;
+                    piv = op;
                 }
             }
         }
-        piv = __shfl(piv, 0, kLanes);
-        best = __shfl(best, 0, kLanes);
         if (best == 0.0) {
             dr = di = 0.0;
             return;
@@ -292,34 +307,48 @@ __device__ __forceinline__ void lds_unitarity(const double2* M, double2* D, int 
     dd = sqrt(fmadd(di, di, (dr - 1.0) * (dr - 1.0)));
 }
 
-// Gram-Schmidt on all rows (lane c owns column c), then the last row times
-// conj(det)/|det| (paper Sec. 2, re-unitarization; Nc > 3).
+// Gram-Schmidt on all rows, then the last row times conj(det)/|det| (paper
+// Sec. 2, re-unitarization; Nc > 3).  Each row is orthogonalized against the
+// earlier ones by classical Gram-Schmidt applied twice (as stable as the
+// modified form): lane k forms <r_k, r_i> from LDS, then lane c subtracts
+// every projection from column c of r_i, so a row costs two barriers per pass
+// instead of a chain of wave reductions per projection.  D (first n entries)
+// holds the projections.
 __device__ __forceinline__ void lds_reunit(double2* M, double2* D, int n) {
-    const int c = threadIdx.x;
-    const bool own = c < n;
+    const int lane = threadIdx.x;
+    const bool own = lane < n;
+    double2* P = D;
     for (int i = 0; i < n; ++i) {
-        for (int k = 0; k < i; ++k) {
-            double pr = 0.0, pi = 0.0;  // <r_k, r_i>
-            if (own) {
-                const double2 a = M[k * n + c], b = M[i * n + c];
-                cmac(pr, pi, a.x, -a.y, b.x, b.y);
+        for (int pass = 0; pass < 2 && i > 0; ++pass) {
+            if (lane < i) {
+                double pr = 0.0, pi = 0.0;  // <r_lane, r_i>, columns taken from a
+                int c = lane % n;            // lane-dependent start: no bank conflicts
+                for (int t = 0; t < n; ++t) {
+                    const double2 a = M[lane * n + c], b = M[i * n + c];
+                    cmac(pr, pi, a.x, -a.y, b.x, b.y);
+                    c = (c + 1 == n) ? 0 : c + 1;
+                }
+                P[lane] = make_double2(pr, pi);
             }
-            pr = wave_sum(pr);
-            pi = wave_sum(pi);
+            __syncthreads();
             if (own) {
-                const double2 a = M[k * n + c];
-                double2 b = M[i * n + c];
-                cmac(b.x, b.y, -pr, -pi, a.x, a.y);
-                M[i * n + c] = b;
+                double2 b = M[i * n + lane];
+                for (int k = 0; k < i; ++k) {
+                    const double2 p = P[k], a = M[k * n + lane];
+                    cmac(b.x, b.y, -p.x, -p.y, a.x, a.y);
+                }
+                M[i * n + lane] = b;
             }
+            __syncthreads();
         }
         double s = 0.0;
-        if (own) s = fmadd(M[i * n + c].y, M[i * n + c].y, M[i * n + c].x * M[i * n + c].x);
+        if (own) s = fmadd(M[i * n + lane].y, M[i * n + lane].y, M[i * n + lane].x * M[i * n + lane].x);
         const double inv = rsqrt(wave_sum(s));
         if (own) {
-            M[i * n + c].x *= inv;
-            M[i * n + c].y *= inv;
+            M[i * n + lane].x *= inv;
+            M[i * n + lane].y *= inv;
         }
+        __syncthreads();
     }
     __syncthreads();
     for (int e = threadIdx.x; e < n * n; e += kLanes) D[e] = M[e];
@@ -328,8 +357,8 @@ __device__ __forceinline__ void lds_reunit(double2* M, double2* D, int n) {
     const double mod = sqrt(dr * dr + di * di);
     const double cr = dr / mod, ci = -di / mod;
     if (own) {
-        const double2 r = M[(n - 1) * n + c];
-        M[(n - 1) * n + c] = make_double2(r.x * cr - r.y * ci, r.x * ci + r.y * cr);
+        const double2 r = M[(n - 1) * n + lane];
+        M[(n - 1) * n + lane] = make_double2(r.x * cr - r.y * ci, r.x * ci + r.y * cr);
     }
     __syncthreads();
 }
