@@ -685,11 +685,10 @@ __device__ __forceinline__ bool su2_attempt(T alpha, bool creutz, T em, const U4
     return false;
 }
 
-// (x1, x2, x3) uniform on the sphere of radius rad.
+// (x1, x2, x3) uniform on the sphere of radius rad, from the direction
+// draw's Philox words d.
 template <typename T>
-__device__ __forceinline__ Quat<T> su2_direction(T x0, T rad, uint32_t k0, uint32_t k1, uint32_t site, uint32_t step,
-                                                 uint32_t mu_sg) {
-    const U4 d = philox(site, step, mu_sg, RNG_DIRECTION << 24, k0, k1);
+__device__ __forceinline__ Quat<T> su2_direction(T x0, T rad, const U4& d) {
     const T cos_t = T(1) - T(2) * uniform<T>(d.w[0]);
     const T sin_t = d_sqrt(T(1) - cos_t * cos_t);
     const T phi = Const<T>::two_pi * uniform<T>(d.w[1]);
@@ -717,7 +716,7 @@ __device__ __forceinline__ int sample_su2(T alpha, uint32_t k0, uint32_t k1, uin
         }
     }
     if (!ok) return 0;
-    x = su2_direction(x0, rad, k0, k1, site, step, mu_sg);
+    x = su2_direction(x0, rad, philox(site, step, mu_sg, RNG_DIRECTION << 24, k0, k1));
     return hit + 1;
 }
 

@@ -102,7 +102,10 @@ __device__ __forceinline__ bool sample_su2_lanes(T alpha, uint32_t k0, uint32_t 
     const bool creutz = alpha < Const<T>::switch_alpha;
     const T em = creutz ? d_expm1(T(-2) * alpha) : T(0);
     const uint32_t hit = threadIdx.x;
+    // the direction draw does not depend on the attempts: both generators
+    // run side by side
     const U4 r = philox(site, step, mu_sg, (RNG_ATTEMPT << 24) | hit, k0, k1);
+    const U4 d = philox(site, step, mu_sg, RNG_DIRECTION << 24, k0, k1);
     T x0 = T(1), rad = T(0);
     const bool ok = su2_attempt(alpha, creutz, em, r, x0, rad);
     const unsigned long long mask = __ballot(ok);
@@ -110,7 +113,7 @@ __device__ __forceinline__ bool sample_su2_lanes(T alpha, uint32_t k0, uint32_t 
     const int first = __ffsll(mask) - 1;
     x0 = __shfl(x0, first, kLanes);
     rad = __shfl(rad, first, kLanes);
-    x = su2_direction(x0, rad, k0, k1, site, step, mu_sg);
+    x = su2_direction(x0, rad, d);
     return true;
 }
 
