@@ -66,7 +66,10 @@ struct sun_lattice_s {
     // launch shapes of the phase kernels (sun_set_launch)
     sun::Shape shape[2] = {sun::Shape{256, 1, 0, 4}, sun::Shape{256, 1, 12, 4}};
 
-    sun::Ctx ctx(hipStream_t s) const { return sun::Ctx{links, g, s, {shape[0], shape[1]}, nc}; }
+    size_t link_bytes = 0;
+    sun::Ctx ctx(hipStream_t s) const {
+        return sun::Ctx{links, g, s, {shape[0], shape[1]}, nc, link_bytes > sun::kMallBytes ? 1 : 0};
+    }
 };
 
 namespace {
@@ -215,6 +218,7 @@ int sun_lattice_create(int nc, const int L[4], int dtype, void* links, size_t li
     h->dtype = dtype;
     h->g = g;
     h->links = links;
+    h->link_bytes = link_bytes_of(nc, g, dtype);
     h->scratch = static_cast<double*>(scratch);
     h->ops = ops_for(nc, dtype);
     *out = h;

@@ -200,12 +200,12 @@ __device__ __forceinline__ T unit_quat(const Quat<T>& p, Quat<T>& v) {
 // kept in registers and updated with U.  Shared by the single-lattice and the
 // batched kernels, so a chain gives the same bits either way.
 // ---------------------------------------------------------------------------
-template <int N, typename T, int R, bool HB, int MU>
+template <int N, typename T, int R, bool HB, int MU, bool NT>
 __device__ __forceinline__ void update_link(T2<T>* __restrict__ U, const Geom& g, int par, int h, T beta,
                                             uint32_t k0, uint32_t k1, uint32_t step) {
     const Site x = site_of(g, par, h);
     const Mat<N, T> A = staple<N, T, R, MU>(U, g, x, par, h);
-    Mat<N, T> Ul = load_mat_stream<N, T, R>(U, MU, par, h, g.Vh);
+    Mat<N, T> Ul = NT ? load_mat_stream<N, T, R>(U, MU, par, h, g.Vh) : load_mat<N, T, R>(U, MU, par, h, g.Vh);
     Mat<N, T> W = mul_nn(Ul, A);
     int sg = 0;
 SUN_MAT_UNROLL
@@ -228,16 +228,19 @@ SUN_MAT_UNROLL
             rows_left_mul(Ul, i, j, a);
             rows_left_mul(W, i, j, a);
         }
-    store_mat_stream<N, T, R>(U, MU, par, h, g.Vh, Ul);
+    if constexpr (NT)
+        store_mat_stream<N, T, R>(U, MU, par, h, g.Vh, Ul);
+    else
+        store_mat<N, T, R>(U, MU, par, h, g.Vh, Ul);
 }
 
 // The same for SU(2) in the 4-real parameterization (paper Sec. 2, Sec. 3).
-template <typename T, bool HB, int MU>
+template <typename T, bool HB, int MU, bool NT>
 __device__ __forceinline__ void update_link_su2(T2<T>* __restrict__ U, const Geom& g, int par, int h, T beta,
                                                 uint32_t k0, uint32_t k1, uint32_t step) {
     const Site x = site_of(g, par, h);
     const Quat<T> A = staple_su2<T, MU>(U, g, x, par, h);
-    const Quat<T> u = load_quat_stream<T>(U, MU, par, h, g.Vh);
+    const Quat<T> u = NT ? load_quat_stream<T>(U, MU, par, h, g.Vh) : load_quat<T>(U, MU, par, h, g.Vh);
     Quat<T> v;
     const T k = unit_quat(qmul(u, A), v);
     Quat<T> a;
@@ -249,16 +252,24 @@ __device__ __forceinline__ void update_link_su2(T2<T>* __restrict__ U, const Geo
         const Quat<T> vc = qconj(v);
         a = qmul(vc, vc);
     }
-    store_quat_stream<T>(U, MU, par, h, g.Vh, qmul(a, u));
+    if constexpr (NT)
+        store_quat_stream<T>(U, MU, par, h, g.Vh, qmul(a, u));
+    else
+        store_quat<T>(U, MU, par, h, g.Vh, qmul(a, u));
 }
 
-template <int N, typename T, int R, bool HB, int MU>
+// NT: nontemporal access to the updated link, for a field larger than the
+// Infinity Cache (the link is then not re-read soon enough to stay cached);
+// a field that fits keeps it cached for the next phase, which reads it.  A
+// compile-time choice: as a run-time branch it kept the plain loads from
+// being scheduled early.
+template <int N, typename T, int R, bool HB, int MU, bool NT>
 __device__ __forceinline__ void update_any(T2<T>* __restrict__ U, const Geom& g, int par, int h, T beta, uint32_t k0,
                                            uint32_t k1, uint32_t step) {
     if constexpr (N == 2)
-        update_link_su2<T, HB, MU>(U, g, par, h, beta, k0, k1, step);
+        update_link_su2<T, HB, MU, NT>(U, g, par, h, beta, k0, k1, step);
     else
-        update_link<N, T, R, HB, MU>(U, g, par, h, beta, k0, k1, step);
+        update_link<N, T, R, HB, MU, NT>(U, g, par, h, beta, k0, k1, step);
 }
 
 // One checkerboard phase of one lattice, BS work-items per workgroup; xcd
@@ -272,13 +283,13 @@ __device__ __forceinline__ void update_any(T2<T>* __restrict__ U, const Geom& g,
 // reserves per workgroup; the kernels never touch it (a reference to a
 // dynamic LDS array costs them a scratch spill).
 
-template <int N, typename T, int R, bool HB, int MU, int BS>
+template <int N, typename T, int R, bool HB, int MU, int BS, bool NT>
 __global__ __launch_bounds__(BS) void k_update(T2<T>* __restrict__ U, Geom g, int par, T beta, uint32_t k0,
                                                uint32_t k1, uint32_t step, Walk walk) {
     const int tile = walk_tile(blockIdx.x, gridDim.x, walk);
     const int h = tile * BS + threadIdx.x;
     if (h >= g.Vh) return;
-    update_any<N, T, R, HB, MU>(U, g, par, h, beta, k0, k1, step);
+    update_any<N, T, R, HB, MU, NT>(U, g, par, h, beta, k0, k1, step);
 }
 
 // ---------------------------------------------------------------------------
@@ -314,8 +325,8 @@ __global__ __launch_bounds__(BS) void k_update_batch(const ChainDesc* __restrict
     const Geom g = d[c].g;
     const int h = (tile - d[c].tile0[KIND]) * BS + threadIdx.x;
     if (h >= g.Vh || !((g.present >> MU) & 1)) return;
-    update_any<N, T, R, HB, MU>((T2<T>*)d[c].links, g, par, h, (T)d[c].beta, d[c].k0, d[c].k1,
-                             (uint32_t)(d[c].step + step_offset));
+    update_any<N, T, R, HB, MU, false>((T2<T>*)d[c].links, g, par, h, (T)d[c].beta, d[c].k0, d[c].k1,
+                                    (uint32_t)(d[c].step + step_offset));
 }
 
 // Advances every chain's RNG step counter after a sweep of n_hb heatbath steps.
@@ -548,20 +559,30 @@ __device__ __forceinline__ LinkId link_of(const Geom& g, int id) {
 // compiles to the same instructions in every kernel that runs it: a chain in
 // a batch must get the same bits as the chain alone.
 template <int N, typename T, int R, bool REPORT>
-__device__ __forceinline__ void reunit_link(T2<T>* __restrict__ U, const Geom& g, int id, double (&dev)[2]) {
+__device__ __forceinline__ void reunit_link(T2<T>* __restrict__ U, const Geom& g, int id, double (&dev)[2],
+                                            bool nt) {
     if (id >= 4 * g.V) return;
     const LinkId l = link_of(g, id);
     if (!((g.present >> l.mu) & 1)) return;
-    Mat<N, double> M = load_link_f64<N, T, R, true>(U, l.mu, l.par, l.h, g.Vh);
+    Mat<N, double> M;
+    if (nt)
+        M = load_link_f64<N, T, R, true>(U, l.mu, l.par, l.h, g.Vh);
+    else
+        M = load_link_f64<N, T, R, false>(U, l.mu, l.par, l.h, g.Vh);
     if (REPORT) unitarity_dev<N>(M, dev[0], dev[1]);
     reunit<N>(M);
-    store_link_from_f64<N, T, R, true>(U, l.mu, l.par, l.h, g.Vh, M);
+    if (nt)
+        store_link_from_f64<N, T, R, true>(U, l.mu, l.par, l.h, g.Vh, M);
+    else
+        store_link_from_f64<N, T, R, false>(U, l.mu, l.par, l.h, g.Vh, M);
 }
 
+// nt as for the phase kernels.
 template <int N, typename T, int R, bool REPORT>
-__global__ __launch_bounds__(kBlock) void k_reunit(T2<T>* __restrict__ U, Geom g, double* __restrict__ partial) {
+__global__ __launch_bounds__(kBlock) void k_reunit(T2<T>* __restrict__ U, Geom g, double* __restrict__ partial,
+                                                   int nt) {
     double dev[2] = {0.0, 0.0};
-    reunit_link<N, T, R, REPORT>(U, g, blockIdx.x * kBlock + threadIdx.x, dev);
+    reunit_link<N, T, R, REPORT>(U, g, blockIdx.x * kBlock + threadIdx.x, dev, nt != 0);
     if (REPORT) block_max<2>(dev, partial + 2 * (size_t)blockIdx.x);
 }
 
@@ -570,7 +591,8 @@ __global__ __launch_bounds__(kBlock) void k_reunit_batch(const ChainDesc* __rest
     const int tile = blockIdx.x;
     const int c = find_chain<TILE_LINK>(d, n, tile);
     double dev[2] = {0.0, 0.0};
-    reunit_link<N, T, R, false>((T2<T>*)d[c].links, d[c].g, (tile - d[c].tile0[TILE_LINK]) * kBlock + threadIdx.x, dev);
+    reunit_link<N, T, R, false>((T2<T>*)d[c].links, d[c].g, (tile - d[c].tile0[TILE_LINK]) * kBlock + threadIdx.x, dev,
+                                false);
 }
 
 template <int N, typename T, int R>

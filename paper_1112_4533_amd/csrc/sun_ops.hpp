@@ -37,7 +37,12 @@ struct Ctx {
     hipStream_t stream;
     Shape shape[2];   // per update kind: heatbath, overrelaxation
     int nc;
+    int nt;           // nontemporal access to updated links (field larger than the Infinity Cache)
 };
+
+// Infinity Cache (MALL) of an MI355X: a field at most this large stays cached
+// between phases.
+constexpr size_t kMallBytes = 256ull << 20;
 
 // Dynamic LDS per workgroup that limits a CU to `waves` resident waves of
 // `block`-item workgroups (0 = no cap).  LDS per CU: 160 KiB on gfx950; the

@@ -10,25 +10,27 @@ template <int N, typename T, int R>
 struct OpsImpl {
     using P = T2<T>;
 
+    template <bool HB, int MU, int BS>
+    static void update_bs(const Ctx& c, int par, T beta, uint32_t k0, uint32_t k1, uint32_t step, int lds,
+                          const Walk& w) {
+        P* u = (P*)c.links;
+        if (c.nt)
+            k_update<N, T, R, HB, MU, BS, true><<<half_blocks(c.g, BS), BS, lds, c.stream>>>(u, c.g, par, beta, k0, k1,
+                                                                                             step, w);
+        else
+            k_update<N, T, R, HB, MU, BS, false><<<half_blocks(c.g, BS), BS, lds, c.stream>>>(u, c.g, par, beta, k0,
+                                                                                              k1, step, w);
+    }
+
     template <bool HB, int MU>
     static void update_mu(const Ctx& c, int par, T beta, uint32_t k0, uint32_t k1, uint32_t step) {
-        P* u = (P*)c.links;
         const Shape& sh = c.shape[HB ? 0 : 1];
         const int lds = lds_for_wave_cap(sh.waves, sh.block);
         const Walk w = walk_for(c.g, sh);
         switch (sh.block) {
-            case 64:
-                k_update<N, T, R, HB, MU, 64><<<half_blocks(c.g, 64), 64, lds, c.stream>>>(u, c.g, par, beta, k0, k1,
-                                                                                            step, w);
-                break;
-            case 128:
-                k_update<N, T, R, HB, MU, 128><<<half_blocks(c.g, 128), 128, lds, c.stream>>>(u, c.g, par, beta, k0,
-                                                                                              k1, step, w);
-                break;
-            default:
-                k_update<N, T, R, HB, MU, 256><<<half_blocks(c.g, 256), 256, lds, c.stream>>>(u, c.g, par, beta, k0,
-                                                                                              k1, step, w);
-                break;
+            case 64: update_bs<HB, MU, 64>(c, par, beta, k0, k1, step, lds, w); break;
+            case 128: update_bs<HB, MU, 128>(c, par, beta, k0, k1, step, lds, w); break;
+            default: update_bs<HB, MU, 256>(c, par, beta, k0, k1, step, lds, w); break;
         }
     }
 
@@ -94,9 +96,9 @@ struct OpsImpl {
     }
     static int reunit(const Ctx& c, double* partial) {
         if (partial)
-            k_reunit<N, T, R, true><<<link_blocks(c.g), kBlock, 0, c.stream>>>((P*)c.links, c.g, partial);
+            k_reunit<N, T, R, true><<<link_blocks(c.g), kBlock, 0, c.stream>>>((P*)c.links, c.g, partial, c.nt);
         else
-            k_reunit<N, T, R, false><<<link_blocks(c.g), kBlock, 0, c.stream>>>((P*)c.links, c.g, nullptr);
+            k_reunit<N, T, R, false><<<link_blocks(c.g), kBlock, 0, c.stream>>>((P*)c.links, c.g, nullptr, c.nt);
         return link_blocks(c.g);
     }
     static int unitarity(const Ctx& c, double* partial) {
