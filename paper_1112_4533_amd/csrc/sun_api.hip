@@ -67,8 +67,9 @@ struct sun_lattice_s {
     sun::Shape shape[2] = {sun::Shape{256, 1, 0, 4}, sun::Shape{256, 1, 12, 4}};
 
     size_t link_bytes = 0;
+    uint64_t phases_run = 0;  // alternates the walk direction of successive phases
     sun::Ctx ctx(hipStream_t s) const {
-        return sun::Ctx{links, g, s, {shape[0], shape[1]}, nc, link_bytes > sun::kMallBytes ? 1 : 0};
+        return sun::Ctx{links, g, s, {shape[0], shape[1]}, nc, link_bytes > sun::kPlainAccessMaxBytes ? 1 : 0, 0};
     }
 };
 
@@ -248,7 +249,9 @@ static int run_phase(sun_lattice_t h, int kind, int mu, int parity, double beta,
     if (!((h->g.present >> mu) & 1)) return SUN_OK;  // absent direction: nothing to update
     Timed t(h, kind == SUN_HEATBATH ? 0 : 1, s);
     if (t.rc) return t.rc;
-    h->ops->update(h->ctx(s), kind, mu, parity, beta, (uint32_t)seed, (uint32_t)(seed >> 32), (uint32_t)step);
+    sun::Ctx c = h->ctx(s);
+    c.rev = (int)(h->phases_run++ & 1);
+    h->ops->update(c, kind, mu, parity, beta, (uint32_t)seed, (uint32_t)(seed >> 32), (uint32_t)step);
     if (int rc = launch_check(kind == SUN_HEATBATH ? "heatbath phase" : "overrelaxation phase")) return rc;
     return t.done();
 }

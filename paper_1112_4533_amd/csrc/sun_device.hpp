@@ -157,14 +157,19 @@ struct Walk {
     int tb;   // time slices per block of the walk (0 or 1: linear walk)
     int tpp;  // tiles per (z, t) plane
     int lz;   // L_z
+    int rev;  // walk the tiles in reverse order
 };
 
 // Tiles of the plaquette grid (256-item workgroups): both parities of every
 // checkerboard tile.
 __host__ __device__ __forceinline__ int plaquette_tiles(const Geom& g) { return 2 * ((g.Vh + 255) / 256); }
 
+// Consecutive phases walk in opposite directions (rev): a phase then starts
+// where the previous one ended, on the links most recently brought into the
+// Infinity Cache, which matters once the field is larger than that cache.
 __device__ __forceinline__ int walk_tile(int b, int nblk, const Walk& w) {
-    const int q = w.xcd ? xcd_tile(b, nblk) : b;
+    const int q0 = w.xcd ? xcd_tile(b, nblk) : b;
+    const int q = w.rev ? nblk - 1 - q0 : q0;
     if (w.tb <= 1) return q;
     const int i = q % w.tpp;
     int rest = q / w.tpp;

@@ -640,7 +640,7 @@ SUN_MAT_UNROLL
 // the geometry alone, so a chain's plaquette has the same bits alone and in a
 // batch.
 __device__ __forceinline__ void plaquette_tile(const Geom& g, int q, int& par, int& h) {
-    Walk w{0, 0, 1, 1};
+    Walk w{0, 0, 1, 1, 0};
     const int plane_h = g.L[0] * g.L[1] / 2;
     if (plane_h % kBlock == 0 && g.L[3] % 4 == 0) {
         w.tb = 4;

@@ -20,7 +20,7 @@ struct Shape {
 // The walk of a single lattice's phase for a shape; falls back to the linear
 // walk where the t-blocked one is not a permutation of the tiles.
 inline Walk walk_for(const Geom& g, const Shape& sh) {
-    Walk w{sh.xcd, 0, 1, 1};
+    Walk w{sh.xcd, 0, 1, 1, 0};
     const long long plane_h = (long long)g.L[0] * g.L[1] / 2;
     if (sh.tblock > 1 && plane_h % sh.block == 0 && g.L[3] % sh.tblock == 0) {
         w.tb = sh.tblock;
@@ -37,12 +37,15 @@ struct Ctx {
     hipStream_t stream;
     Shape shape[2];   // per update kind: heatbath, overrelaxation
     int nc;
-    int nt;           // nontemporal access to updated links (field larger than the Infinity Cache)
+    int nt;           // nontemporal access to updated links (field well above the Infinity Cache)
+    int rev;          // this phase walks its tiles in reverse order
 };
 
-// Infinity Cache (MALL) of an MI355X: a field at most this large stays cached
-// between phases.
-constexpr size_t kMallBytes = 256ull << 20;
+// Infinity Cache (MALL) of an MI355X is 256 MB.  Updated links keep plain
+// (cached) access up to 1.25 x that size: measured on 32^4 SU(3), a 302 MB
+// field ran 3.6% faster with plain access, 402 and 604 MB fields 1-2% faster
+// with nontemporal access (with alternating walk directions).
+constexpr size_t kPlainAccessMaxBytes = 320ull << 20;
 
 // Dynamic LDS per workgroup that limits a CU to `waves` resident waves of
 // `block`-item workgroups (0 = no cap).  LDS per CU: 160 KiB on gfx950; the

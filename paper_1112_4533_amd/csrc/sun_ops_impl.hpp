@@ -26,7 +26,8 @@ struct OpsImpl {
     static void update_mu(const Ctx& c, int par, T beta, uint32_t k0, uint32_t k1, uint32_t step) {
         const Shape& sh = c.shape[HB ? 0 : 1];
         const int lds = lds_for_wave_cap(sh.waves, sh.block);
-        const Walk w = walk_for(c.g, sh);
+        Walk w = walk_for(c.g, sh);
+        w.rev = c.rev;
         switch (sh.block) {
             case 64: update_bs<HB, MU, 64>(c, par, beta, k0, k1, step, lds, w); break;
             case 128: update_bs<HB, MU, 128>(c, par, beta, k0, k1, step, lds, w); break;
