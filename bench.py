@@ -8,7 +8,9 @@ of the whole hot path over the lattice: 1 heatbath step + 4 overrelaxation
 steps (each 4 directions x {even, odd} phases), re-unitarization (reporting
 the unitarity drift it removed), the plaquette (FP64) and the Polyakov loop.
 The same workload with 18-real FP32 links, with FP64 links, and a batch of
-64 small independent chains replayed from a HIP graph are timed beside it.
+64 small independent chains replayed from a HIP graph are timed beside it,
+and (untimed) the FP32-storage chain is compared with the FP64 chain of the
+same seed, sweep by sweep.
 
 Prints one JSON line.  `value` is link updates per second (one update = one
 heatbath or overrelaxation visit of one link) with the field resident in HBM.
@@ -148,6 +150,40 @@ def run_gpu(run, steps, warmup, tune=False):
         "or_dS_over_S": or_ds,
         "launch": {"heatbath": lat.get_launch(sun.HEATBATH), "overrelax": lat.get_launch(sun.OVERRELAX)},
     }
+
+
+def run_precision(run, sweeps):
+    """Precision pattern: the same chain (seed, hot start, beta, schedule)
+    with `run`'s FP32 storage and with FP64 links, untimed.  Reports both
+    plaquettes after each sweep and their difference: the drift that FP32
+    storage introduces (the two chains start from the same FP64 Haar field,
+    one rounded to FP32, and part once a heatbath acceptance test falls on
+    the other side of its threshold)."""
+    import torch
+    from paper_1112_4533_amd import sun
+
+    out = {"sweeps": sweeps, "storage": [run.dtype, "f64"]}
+    plaqs, devs = [], []
+    for dtype in (run.dtype, "f64"):
+        lat = sun.Lattice(run.nc, run.L, dtype)
+        lat.init(hot=run.hot, seed=run.seed)
+        dev = lat.links.device
+        drift = torch.zeros(2, dtype=torch.float64, device=dev)
+        lib, stream = sun.load(), sun._stream()
+        p, d = [], []
+        for _ in range(sweeps):
+            lat.sweep(run.beta, run.n_hb, run.n_or, seed=run.seed, reunit=False)
+            sun._check(lib.sun_reunitarize(lat._h, sun._ptr(drift), stream))
+            p.append(float(lat.plaquette().cpu()[0]))
+            d.append(float(drift.cpu()[0]))
+        plaqs.append(p)
+        devs.append(max(d))
+        del lat
+        torch.cuda.empty_cache()
+    out["plaquette_fp32_storage"], out["plaquette_fp64"] = plaqs
+    out["plaquette_diff"] = [a - b for a, b in zip(*plaqs)]
+    out["max_unitarity_dev_before_reunit"] = {run.dtype: devs[0], "f64": devs[1]}
+    return out
 
 
 def run_batch(steps, warmup, f64_sweeps, tune=False):
@@ -328,6 +364,8 @@ def main():
     ap.add_argument("--cpu-sweeps", type=int, default=8, help="oracle sweeps in the CPU-baseline sample")
     ap.add_argument("--no-f64", action="store_true")
     ap.add_argument("--no-batch", action="store_true")
+    ap.add_argument("--precision-sweeps", type=int, default=6,
+                    help="sweeps of the untimed FP32-storage vs FP64 chain comparison")
     ap.add_argument("--head", choices=["two_row", "eighteen"], default="two_row",
                     help="SU(3) storage of the headline line (the other is reported beside it)")
     ap.add_argument("--no-second", action="store_true", help="skip the other storage's leg")
@@ -416,6 +454,8 @@ def main():
             "overrelaxation_rel_action_change": r64["or_dS_over_S"],
             "fp32_over_fp64": r_head["updates_per_s"] / r64["updates_per_s"],
         }
+    if not args.no_f64:
+        line["precision"] = run_precision(head, args.precision_sweeps)
     if not args.no_batch:
         line["batch"] = run_batch(max(4, args.steps), args.warmup, max(2, args.steps // 4), tune=args.tune)
     if not args.no_cpu_baseline:

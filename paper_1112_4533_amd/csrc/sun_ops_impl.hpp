@@ -70,7 +70,7 @@ struct OpsImpl {
     }
 
     static void plaquette_batch(const ChainDesc* d, int n, int tiles, double* out, hipStream_t s) {
-        k_plaquette_batch<N, T, R><<<tiles, kBlock, 0, s>>>(d, n);
+        k_plaquette_batch<N, T, R><<<tiles, kBlock, lds_for_wave_cap(kPlaquetteWaveCap, kBlock), s>>>(d, n);
         k_plaquette_final_batch<N><<<n, kBlock, 0, s>>>(d, n, out);
     }
 
@@ -107,7 +107,8 @@ struct OpsImpl {
         return link_blocks(c.g);
     }
     static int plaquette(const Ctx& c, double* partial) {
-        k_plaquette<N, T, R><<<plaquette_tiles(c.g), kBlock, 0, c.stream>>>((const P*)c.links, c.g, partial);
+        k_plaquette<N, T, R><<<plaquette_tiles(c.g), kBlock, lds_for_wave_cap(kPlaquetteWaveCap, kBlock),
+                               c.stream>>>((const P*)c.links, c.g, partial);
         return plaquette_tiles(c.g);
     }
     static int polyakov(const Ctx& c, double* partial) {
