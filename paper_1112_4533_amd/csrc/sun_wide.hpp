@@ -51,35 +51,117 @@ __device__ __forceinline__ const T2<T>* link_at(const T2<T>* U, int n2, int mu, 
     return U + ((size_t)(mu * 2 + par) * Vh + h) * n2;
 }
 
-// dst (LDS, type D) = src or src^dag (global, type S), converted.
+// dst (LDS, type D) = src or src^dag (global, type S), converted.  Each
+// lane issues the global loads of kLoadBatch entries before it stores any,
+// so a link costs a few load latencies instead of one per entry.
+constexpr int kLoadBatch = 8;
+
 template <typename D, typename S>
 __device__ __forceinline__ void lds_load(T2<D>* dst, const T2<S>* src, int n, bool dag) {
     const int n2 = n * n;
-    for (int e = threadIdx.x; e < n2; e += kLanes) {
-        const T2<S> v = src[e];
-        if (dag) {
-            const int i = e / n, j = e - i * n;
-            dst[j * n + i] = cpx<D>((D)v.x, -(D)v.y);
-        } else {
-            dst[e] = cpx<D>((D)v.x, (D)v.y);
+    if (n2 <= kLanes) {  // one entry per lane
+        const int e = threadIdx.x;
+        if (e < n2) {
+            const T2<S> v = src[e];
+            if (dag) {
+                const int i = e / n, j = e - i * n;
+                dst[j * n + i] = cpx<D>((D)v.x, -(D)v.y);
+            } else {
+                dst[e] = cpx<D>((D)v.x, (D)v.y);
+            }
+        }
+        return;
+    }
+    for (int e0 = threadIdx.x; e0 < n2; e0 += kLoadBatch * kLanes) {
+        T2<S> v[kLoadBatch];
+#pragma unroll
+        for (int c = 0; c < kLoadBatch; ++c) {
+            const int e = e0 + c * kLanes;
+            if (e < n2) v[c] = src[e];
+        }
+#pragma unroll
+        for (int c = 0; c < kLoadBatch; ++c) {
+            const int e = e0 + c * kLanes;
+            if (e >= n2) break;
+            if (dag) {
+                const int i = e / n, j = e - i * n;
+                dst[j * n + i] = cpx<D>((D)v[c].x, -(D)v[c].y);
+            } else {
+                dst[e] = cpx<D>((D)v[c].x, (D)v[c].y);
+            }
         }
     }
 }
 
-// C = A B, or C += A B (C distinct from A and B).
+// C = A B, or C += A B (C distinct from A and B; n <= 32).  With g = 64 / n
+// row groups, lane l < g n owns column j = l mod n and rows i0, i0 + g, ...
+// (i0 = l / n), which it takes R at a time: each B_kj it reads serves R rows,
+// and the n lanes of a row group read the same A_ik (an LDS broadcast).  A
+// block that runs past the lane's last row repeats that row and does not
+// store it, so the k loop has no lane-dependent branch.  Every entry is the
+// sum over k = 0 .. n-1 in increasing k, with the same complex multiply-add
+// as the plain triple loop.
+template <typename T, int R>
+__device__ __forceinline__ void lds_mm_rows(T2<T>* C, const T2<T>* A, const T2<T>* B, int n, bool acc, int g, int j,
+                                            int i0, int cnt) {
+    for (int t0 = 0; t0 < cnt; t0 += R) {
+        int row[R];
+        T r[R], m[R];
+#pragma unroll
+        for (int t = 0; t < R; ++t) {
+            const int tt = t0 + t < cnt ? t0 + t : cnt - 1;
+            row[t] = (i0 + g * tt) * n;
+            r[t] = T(0);
+            m[t] = T(0);
+            if (acc) {
+                const T2<T> c = C[row[t] + j];
+                r[t] = c.x;
+                m[t] = c.y;
+            }
+        }
+        // four k per pass, their LDS reads issued together
+        int k = 0;
+        for (; k + 4 <= n; k += 4) {
+            T2<T> y[4], x[4][R];
+#pragma unroll
+            for (int q = 0; q < 4; ++q) {
+                y[q] = B[(k + q) * n + j];
+#pragma unroll
+                for (int t = 0; t < R; ++t) x[q][t] = A[row[t] + k + q];
+            }
+#pragma unroll
+            for (int q = 0; q < 4; ++q)
+#pragma unroll
+                for (int t = 0; t < R; ++t) cmac(r[t], m[t], x[q][t].x, x[q][t].y, y[q].x, y[q].y);
+        }
+        for (; k < n; ++k) {
+            const T2<T> y = B[k * n + j];
+#pragma unroll
+            for (int t = 0; t < R; ++t) {
+                const T2<T> x = A[row[t] + k];
+                cmac(r[t], m[t], x.x, x.y, y.x, y.y);
+            }
+        }
+#pragma unroll
+        for (int t = 0; t < R; ++t)
+            if (t0 + t < cnt) C[row[t] + j] = cpx<T>(r[t], m[t]);
+    }
+}
+
 template <typename T>
 __device__ __forceinline__ void lds_mm(T2<T>* C, const T2<T>* A, const T2<T>* B, int n, bool acc) {
-    const int n2 = n * n;
-    for (int e = threadIdx.x; e < n2; e += kLanes) {
-        const int i = e / n, j = e - i * n;
-        T r = acc ? C[e].x : T(0), m = acc ? C[e].y : T(0);
-        const T2<T>* a = A + i * n;
-        for (int k = 0; k < n; ++k) {
-            const T2<T> x = a[k], y = B[k * n + j];
-            cmac(r, m, x.x, x.y, y.x, y.y);
-        }
-        C[e] = cpx<T>(r, m);
-    }
+    const int g = kLanes / n;
+    const int lane = threadIdx.x;
+    if (lane >= g * n) return;
+    const int j = lane % n, i0 = lane / n;
+    const int cnt = (n - i0 + g - 1) / g;   // rows i0 + g t < n of this lane
+    const int most = (n + g - 1) / g;       // rows of lane 0, the most of any lane
+    if (most >= 4)
+        lds_mm_rows<T, 4>(C, A, B, n, acc, g, j, i0, cnt);
+    else if (most >= 2)
+        lds_mm_rows<T, 2>(C, A, B, n, acc, g, j, i0, cnt);
+    else
+        lds_mm_rows<T, 1>(C, A, B, n, acc, g, j, i0, cnt);
 }
 
 // Wave reductions with a fixed butterfly order (deterministic).
@@ -96,23 +178,45 @@ __device__ __forceinline__ double wave_max(double v) {
 
 // The SU(2) draw with attempt `hit` on lane `hit`; the lowest accepting lane
 // wins.  Returns false (skip the step) when all 64 attempts are rejected.
+// v on lane `lane` (uniform across the wave), read with readlane.
+__device__ __forceinline__ float lane_value(float v, int lane) {
+    return __builtin_bit_cast(float, __builtin_amdgcn_readlane(__builtin_bit_cast(int, v), lane));
+}
+__device__ __forceinline__ double lane_value(double v, int lane) {
+    const unsigned long long u = __builtin_bit_cast(unsigned long long, v);
+    const unsigned lo = (unsigned)__builtin_amdgcn_readlane((int)(u & 0xffffffffu), lane);
+    const unsigned hi = (unsigned)__builtin_amdgcn_readlane((int)(u >> 32), lane);
+    return __builtin_bit_cast(double, ((unsigned long long)hi << 32) | lo);
+}
+
+// The Philox words of subgroup mu_sg: this lane's attempt (hit = lane) and
+// the direction draw.  They depend on the counter alone, not on the field,
+// so the update computes them one subgroup ahead.
+struct SubgroupWords {
+    U4 r, d;
+};
+
+__device__ __forceinline__ SubgroupWords subgroup_words(uint32_t k0, uint32_t k1, uint32_t site, uint32_t step,
+                                                        uint32_t mu_sg) {
+    SubgroupWords w;
+    w.r = philox(site, step, mu_sg, (RNG_ATTEMPT << 24) | (uint32_t)threadIdx.x, k0, k1);
+    w.d = philox(site, step, mu_sg, RNG_DIRECTION << 24, k0, k1);
+    return w;
+}
+
 template <typename T>
-__device__ __forceinline__ bool sample_su2_lanes(T alpha, uint32_t k0, uint32_t k1, uint32_t site, uint32_t step,
-                                                 uint32_t mu_sg, Quat<T>& x) {
+__device__ __forceinline__ bool sample_su2_lanes(T alpha, const SubgroupWords& w, Quat<T>& x) {
     const bool creutz = alpha < Const<T>::switch_alpha;
     const T em = creutz ? d_expm1(T(-2) * alpha) : T(0);
-    const uint32_t hit = threadIdx.x;
-    // the direction draw does not depend on the attempts: both generators
-    // run side by side
-    const U4 r = philox(site, step, mu_sg, (RNG_ATTEMPT << 24) | hit, k0, k1);
-    const U4 d = philox(site, step, mu_sg, RNG_DIRECTION << 24, k0, k1);
+    const U4& r = w.r;
+    const U4& d = w.d;
     T x0 = T(1), rad = T(0);
     const bool ok = su2_attempt(alpha, creutz, em, r, x0, rad);
     const unsigned long long mask = __ballot(ok);
     if (mask == 0ull) return false;
-    const int first = __ffsll(mask) - 1;
-    x0 = __shfl(x0, first, kLanes);
-    rad = __shfl(rad, first, kLanes);
+    const int first = __ffsll(mask) - 1;  // the same on every lane
+    x0 = lane_value(x0, first);
+    rad = lane_value(rad, first);
     x = su2_direction(x0, rad, d);
     return true;
 }
@@ -180,6 +284,9 @@ __global__ __launch_bounds__(kLanes) void k_update(T2<T>* __restrict__ U, Geom g
     __syncthreads();
 
     const int lane = threadIdx.x;
+    const uint32_t mu_hi = (uint32_t)mu << 16;
+    SubgroupWords words{};
+    if (hb) words = subgroup_words(k0, k1, (uint32_t)x.s, step, mu_hi);
     uint32_t sg = 0;
     for (int i = 0; i < n; ++i)
         for (int j = i + 1; j < n; ++j, ++sg) {
@@ -196,8 +303,9 @@ __global__ __launch_bounds__(kLanes) void k_update(T2<T>* __restrict__ U, Geom g
             if (hb) {
                 const T alpha = T(2) * beta * k / T(n);
                 Quat<T> xs;
-                apply = sample_su2_lanes<T>(alpha, k0, k1, (uint32_t)x.s, step, ((uint32_t)mu << 16) | sg, xs);
+                apply = sample_su2_lanes<T>(alpha, words, xs);
                 if (apply) a = qmul(xs, qconj(v));
+                words = subgroup_words(k0, k1, (uint32_t)x.s, step, mu_hi | (sg + 1));
             } else {
                 const Quat<T> vc = qconj(v);
                 a = qmul(vc, vc);
