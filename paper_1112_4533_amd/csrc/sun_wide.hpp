@@ -176,8 +176,6 @@ __device__ __forceinline__ double wave_max(double v) {
     return v;
 }
 
-// The SU(2) draw with attempt `hit` on lane `hit`; the lowest accepting lane
-// wins.  Returns false (skip the step) when all 64 attempts are rejected.
 // v on lane `lane` (uniform across the wave), read with readlane.
 __device__ __forceinline__ float lane_value(float v, int lane) {
     return __builtin_bit_cast(float, __builtin_amdgcn_readlane(__builtin_bit_cast(int, v), lane));
@@ -204,6 +202,8 @@ __device__ __forceinline__ SubgroupWords subgroup_words(uint32_t k0, uint32_t k1
     return w;
 }
 
+// The SU(2) draw with attempt `hit` on lane `hit`; the lowest accepting lane
+// wins.  Returns false (skip the step) when all 64 attempts are rejected.
 template <typename T>
 __device__ __forceinline__ bool sample_su2_lanes(T alpha, const SubgroupWords& w, Quat<T>& x) {
     const bool creutz = alpha < Const<T>::switch_alpha;
@@ -221,10 +221,11 @@ __device__ __forceinline__ bool sample_su2_lanes(T alpha, const SubgroupWords& w
     return true;
 }
 
-// Rows i, j of M (LDS), column c, left-multiplied by the 2x2 form of a.
+// Rows i, j of M (LDS), column c, left-multiplied by the 2x2 form of a,
+// given their current entries x = M_ic and y = M_jc.
 template <typename T>
-__device__ __forceinline__ void rows_left_mul_col(T2<T>* M, int n, int i, int j, int c, const Quat<T>& a) {
-    const T2<T> x = M[i * n + c], y = M[j * n + c];
+__device__ __forceinline__ void rows_left_mul_col(T2<T>* M, int n, int i, int j, int c, const Quat<T>& a,
+                                                  const T2<T>& x, const T2<T>& y) {
     M[i * n + c] = cpx<T>(fmadd(-a.q[1], y.y, fmadd(a.q[2], y.x, fmadd(-a.q[3], x.y, a.q[0] * x.x))),
                           fmadd(a.q[1], y.x, fmadd(a.q[2], y.y, fmadd(a.q[3], x.x, a.q[0] * x.y))));
     M[j * n + c] = cpx<T>(fmadd(a.q[3], y.y, fmadd(a.q[0], y.x, fmadd(-a.q[1], x.y, -a.q[2] * x.x))),
@@ -287,10 +288,22 @@ __global__ __launch_bounds__(kLanes) void k_update(T2<T>* __restrict__ U, Geom g
     const uint32_t mu_hi = (uint32_t)mu << 16;
     SubgroupWords words{};
     if (hb) words = subgroup_words(k0, k1, (uint32_t)x.s, step, mu_hi);
+    // The workgroup is one wavefront, and a wavefront's LDS operations
+    // complete in the order it issues them: a read issued after a write sees
+    // it, whichever lane wrote, and a write issued after a read leaves that
+    // read's value alone.  So the subgroup steps need only compiler ordering
+    // (a wavefront-scope fence), not a wait for every LDS round trip, and each
+    // lane reads its entries of rows i and j together with the 2x2 block.
+    // Lanes 0..31 own column lane of U, lanes 32..63 column lane - 32 of W.
+    T2<T>* const M = lane < 32 ? Us : W;
+    const int col = lane & 31;
+    const bool owner = col < n;
+    const int c = owner ? col : 0;
     uint32_t sg = 0;
     for (int i = 0; i < n; ++i)
         for (int j = i + 1; j < n; ++j, ++sg) {
             const T2<T> wii = W[i * n + i], wij = W[i * n + j], wji = W[j * n + i], wjj = W[j * n + j];
+            const T2<T> mi = M[i * n + c], mj = M[j * n + c];
             Quat<T> p;
             p.q[0] = T(0.5) * (wii.x + wjj.x);
             p.q[3] = T(0.5) * (wii.y - wjj.y);
@@ -310,15 +323,10 @@ __global__ __launch_bounds__(kLanes) void k_update(T2<T>* __restrict__ U, Geom g
                 const Quat<T> vc = qconj(v);
                 a = qmul(vc, vc);
             }
-            __syncthreads();  // every lane has read the block before rows i, j change
-            if (apply) {
-                if (lane < n)
-                    rows_left_mul_col<T>(Us, n, i, j, lane, a);
-                else if (lane >= 32 && lane - 32 < n)
-                    rows_left_mul_col<T>(W, n, i, j, lane - 32, a);
-            }
-            __syncthreads();
+            if (apply && owner) rows_left_mul_col<T>(M, n, i, j, c, a, mi, mj);
+            __builtin_amdgcn_fence(__ATOMIC_SEQ_CST, "wavefront");
         }
+    __syncthreads();
     T2<T>* dst = const_cast<T2<T>*>(link_at<T>(U, n2, mu, par, h, Vh));
     for (int e = threadIdx.x; e < n2; e += kLanes) dst[e] = Us[e];
 }
