@@ -176,6 +176,14 @@ __device__ __forceinline__ double wave_max(double v) {
     return v;
 }
 
+// Every kernel here runs one wavefront per workgroup, and a wavefront's LDS
+// operations complete in the order it issues them: a read issued after a
+// write sees it, whichever lane wrote, and a write issued after a read leaves
+// that read's value alone.  Steps that hand LDS data between lanes therefore
+// need only compiler ordering (a wavefront-scope fence), not a wait for the
+// LDS round trip that a workgroup barrier implies.
+__device__ __forceinline__ void wave_lds_order() { __builtin_amdgcn_fence(__ATOMIC_SEQ_CST, "wavefront"); }
+
 // v on lane `lane` (uniform across the wave), read with readlane.
 __device__ __forceinline__ float lane_value(float v, int lane) {
     return __builtin_bit_cast(float, __builtin_amdgcn_readlane(__builtin_bit_cast(int, v), lane));
@@ -187,37 +195,59 @@ __device__ __forceinline__ double lane_value(double v, int lane) {
     return __builtin_bit_cast(double, ((unsigned long long)hi << 32) | lo);
 }
 
-// The Philox words of subgroup mu_sg: this lane's attempt (hit = lane) and
-// the direction draw.  They depend on the counter alone, not on the field,
-// so the update computes them one subgroup ahead.
-struct SubgroupWords {
-    U4 r, d;
+// SU(2) draws of the subgroup steps, eight subgroups per pair of Philox
+// passes.  The hybrid sampler accepts an attempt with probability at least
+// about 0.71, so the first few attempts almost always decide: lane l holds
+// the words of attempt l mod 8 of subgroup sg0 + l / 8, and lanes l hold the
+// direction words of subgroup sg0 + l mod 8.  A draw whose first eight
+// attempts all reject (about 5e-5 of draws) runs attempts 8 .. 63 one per
+// lane.  Either way the draw takes the lowest accepting attempt of the
+// counter-based stream, as the sequential sampler does.
+constexpr int kSgBatch = 8;                    // subgroups per batch
+constexpr int kFirstHits = kLanes / kSgBatch;  // attempts per subgroup in a batch
+
+struct DrawBatch {
+    U4 att;  // attempt (lane mod 8) of subgroup sg0 + lane / 8
+    U4 dir;  // direction words of subgroup sg0 + lane mod 8
 };
 
-__device__ __forceinline__ SubgroupWords subgroup_words(uint32_t k0, uint32_t k1, uint32_t site, uint32_t step,
-                                                        uint32_t mu_sg) {
-    SubgroupWords w;
-    w.r = philox(site, step, mu_sg, (RNG_ATTEMPT << 24) | (uint32_t)threadIdx.x, k0, k1);
-    w.d = philox(site, step, mu_sg, RNG_DIRECTION << 24, k0, k1);
-    return w;
+__device__ __forceinline__ DrawBatch draw_batch(uint32_t k0, uint32_t k1, uint32_t site, uint32_t step,
+                                                uint32_t mu_hi, uint32_t sg0) {
+    const uint32_t l = threadIdx.x;
+    DrawBatch b;
+    b.att = philox(site, step, mu_hi | (sg0 + l / kFirstHits), (RNG_ATTEMPT << 24) | (l % kFirstHits), k0, k1);
+    b.dir = philox(site, step, mu_hi | (sg0 + l % kSgBatch), RNG_DIRECTION << 24, k0, k1);
+    return b;
 }
 
-// The SU(2) draw with attempt `hit` on lane `hit`; the lowest accepting lane
-// wins.  Returns false (skip the step) when all 64 attempts are rejected.
+__device__ __forceinline__ U4 lane_words(const U4& w, int lane) {
+    U4 r;
+#pragma unroll
+    for (int q = 0; q < 4; ++q) r.w[q] = (uint32_t)__builtin_amdgcn_readlane((int)w.w[q], lane);
+    return r;
+}
+
+// The draw of subgroup mu_sg, slot s = mu_sg mod 8 of batch b.  Returns false
+// (skip the step) when all kMaxAttempts attempts are rejected.
 template <typename T>
-__device__ __forceinline__ bool sample_su2_lanes(T alpha, const SubgroupWords& w, Quat<T>& x) {
+__device__ __forceinline__ bool sample_su2_lanes(T alpha, const DrawBatch& b, int s, uint32_t k0, uint32_t k1,
+                                                 uint32_t site, uint32_t step, uint32_t mu_sg, Quat<T>& x) {
     const bool creutz = alpha < Const<T>::switch_alpha;
     const T em = creutz ? d_expm1(T(-2) * alpha) : T(0);
-    const U4& r = w.r;
-    const U4& d = w.d;
     T x0 = T(1), rad = T(0);
-    const bool ok = su2_attempt(alpha, creutz, em, r, x0, rad);
-    const unsigned long long mask = __ballot(ok);
-    if (mask == 0ull) return false;
+    bool ok = su2_attempt(alpha, creutz, em, b.att, x0, rad);
+    unsigned long long mask = __ballot(ok) & (0xFFull << (kFirstHits * s));
+    if (mask == 0ull) {
+        const uint32_t hit = threadIdx.x + kFirstHits;
+        const U4 r = philox(site, step, mu_sg, (RNG_ATTEMPT << 24) | hit, k0, k1);
+        ok = hit < (uint32_t)kMaxAttempts && su2_attempt(alpha, creutz, em, r, x0, rad);
+        mask = __ballot(ok);
+        if (mask == 0ull) return false;
+    }
     const int first = __ffsll(mask) - 1;  // the same on every lane
     x0 = lane_value(x0, first);
     rad = lane_value(rad, first);
-    x = su2_direction(x0, rad, d);
+    x = su2_direction(x0, rad, lane_words(b.dir, s));
     return true;
 }
 
@@ -286,15 +316,10 @@ __global__ __launch_bounds__(kLanes) void k_update(T2<T>* __restrict__ U, Geom g
 
     const int lane = threadIdx.x;
     const uint32_t mu_hi = (uint32_t)mu << 16;
-    SubgroupWords words{};
-    if (hb) words = subgroup_words(k0, k1, (uint32_t)x.s, step, mu_hi);
-    // The workgroup is one wavefront, and a wavefront's LDS operations
-    // complete in the order it issues them: a read issued after a write sees
-    // it, whichever lane wrote, and a write issued after a read leaves that
-    // read's value alone.  So the subgroup steps need only compiler ordering
-    // (a wavefront-scope fence), not a wait for every LDS round trip, and each
-    // lane reads its entries of rows i and j together with the 2x2 block.
-    // Lanes 0..31 own column lane of U, lanes 32..63 column lane - 32 of W.
+    DrawBatch batch{};
+    // The subgroup steps are ordered by wave_lds_order, and each lane reads
+    // its entries of rows i and j together with the 2x2 block.  Lanes 0..31
+    // own column lane of U, lanes 32..63 column lane - 32 of W.
     T2<T>* const M = lane < 32 ? Us : W;
     const int col = lane & 31;
     const bool owner = col < n;
@@ -314,17 +339,18 @@ __global__ __launch_bounds__(kLanes) void k_update(T2<T>* __restrict__ U, Geom g
             Quat<T> a;
             bool apply = true;
             if (hb) {
+                const int slot = (int)(sg % kSgBatch);
+                if (slot == 0) batch = draw_batch(k0, k1, (uint32_t)x.s, step, mu_hi, sg);
                 const T alpha = T(2) * beta * k / T(n);
                 Quat<T> xs;
-                apply = sample_su2_lanes<T>(alpha, words, xs);
+                apply = sample_su2_lanes<T>(alpha, batch, slot, k0, k1, (uint32_t)x.s, step, mu_hi | sg, xs);
                 if (apply) a = qmul(xs, qconj(v));
-                words = subgroup_words(k0, k1, (uint32_t)x.s, step, mu_hi | (sg + 1));
             } else {
                 const Quat<T> vc = qconj(v);
                 a = qmul(vc, vc);
             }
             if (apply && owner) rows_left_mul_col<T>(M, n, i, j, c, a, mi, mj);
-            __builtin_amdgcn_fence(__ATOMIC_SEQ_CST, "wavefront");
+            wave_lds_order();
         }
     __syncthreads();
     T2<T>* dst = const_cast<T2<T>*>(link_at<T>(U, n2, mu, par, h, Vh));
@@ -341,7 +367,7 @@ __device__ __forceinline__ void lds_det(double2* D, int n, double& dr, double& d
     dr = 1.0;
     di = 0.0;
     for (int col = 0; col < n; ++col) {
-        __syncthreads();
+        wave_lds_order();
         // pivot: the largest |D[r][col]|^2 over r >= col, the lowest r among
         // equals -- a scan by lane 0 for small n, a wave argmax otherwise
         // (the same choice: the scan keeps the first strict maximum)
@@ -384,7 +410,7 @@ __device__ __forceinline__ void lds_det(double2* D, int n, double& dr, double& d
             dr = -dr;
             di = -di;
         }
-        __syncthreads();
+        wave_lds_order();
         const double pr = D[col * n + col].x, pi = D[col * n + col].y;
         const double nr = dr * pr - di * pi, ni = dr * pi + di * pr;
         dr = nr;
@@ -430,8 +456,8 @@ __device__ __forceinline__ void lds_unitarity(const double2* M, double2* D, int 
 // Sec. 2, re-unitarization; Nc > 3).  Each row is orthogonalized against the
 // earlier ones by classical Gram-Schmidt applied twice (as stable as the
 // modified form): lane k forms <r_k, r_i> from LDS, then lane c subtracts
-// every projection from column c of r_i, so a row costs two barriers per pass
-// instead of a chain of wave reductions per projection.  D (first n entries)
+// every projection from column c of r_i, so a row costs two LDS hand-offs per
+// pass instead of a chain of wave reductions per projection.  D (first n entries)
 // holds the projections.
 __device__ __forceinline__ void lds_reunit(double2* M, double2* D, int n) {
     const int lane = threadIdx.x;
@@ -442,6 +468,7 @@ __device__ __forceinline__ void lds_reunit(double2* M, double2* D, int n) {
             if (lane < i) {
                 double pr = 0.0, pi = 0.0;  // <r_lane, r_i>, columns taken from a
                 int c = lane % n;            // lane-dependent start: no bank conflicts
+#pragma unroll 4
                 for (int t = 0; t < n; ++t) {
                     const double2 a = M[lane * n + c], b = M[i * n + c];
                     cmac(pr, pi, a.x, -a.y, b.x, b.y);
@@ -449,16 +476,17 @@ __device__ __forceinline__ void lds_reunit(double2* M, double2* D, int n) {
                 }
                 P[lane] = make_double2(pr, pi);
             }
-            __syncthreads();
+            wave_lds_order();
             if (own) {
                 double2 b = M[i * n + lane];
+#pragma unroll 4
                 for (int k = 0; k < i; ++k) {
                     const double2 p = P[k], a = M[k * n + lane];
                     cmac(b.x, b.y, -p.x, -p.y, a.x, a.y);
                 }
                 M[i * n + lane] = b;
             }
-            __syncthreads();
+            wave_lds_order();
         }
         double s = 0.0;
         if (own) s = fmadd(M[i * n + lane].y, M[i * n + lane].y, M[i * n + lane].x * M[i * n + lane].x);
@@ -467,9 +495,8 @@ __device__ __forceinline__ void lds_reunit(double2* M, double2* D, int n) {
             M[i * n + lane].x *= inv;
             M[i * n + lane].y *= inv;
         }
-        __syncthreads();
+        wave_lds_order();
     }
-    __syncthreads();
     for (int e = threadIdx.x; e < n * n; e += kLanes) D[e] = M[e];
     double dr, di;
     lds_det(D, n, dr, di);
