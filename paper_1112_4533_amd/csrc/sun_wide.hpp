@@ -206,36 +206,72 @@ __device__ __forceinline__ double lane_value(double v, int lane) {
 constexpr int kSgBatch = 8;                    // subgroups per batch
 constexpr int kFirstHits = kLanes / kSgBatch;  // attempts per subgroup in a batch
 
+// What a batch keeps per lane: the uniforms of its attempt that the two
+// samplers test (r0, r1, r3) and the Kennedy-Pendleton log term
+// -(log r0 + cos^2(2 pi r1) log r2), which does not depend on alpha; and the
+// direction of subgroup sg0 + lane mod 8 as cos/sin of its polar angle and
+// of its azimuth.  Only the alpha-dependent remainder of a draw is left on
+// the sequential chain of subgroup steps.
+template <typename T>
 struct DrawBatch {
-    U4 att;  // attempt (lane mod 8) of subgroup sg0 + lane / 8
-    U4 dir;  // direction words of subgroup sg0 + lane mod 8
+    T r0, r1, r3, kp;
+    T cos_t, sin_t, cos_p, sin_p;
 };
 
-__device__ __forceinline__ DrawBatch draw_batch(uint32_t k0, uint32_t k1, uint32_t site, uint32_t step,
-                                                uint32_t mu_hi, uint32_t sg0) {
+template <typename T>
+__device__ __forceinline__ DrawBatch<T> draw_batch(uint32_t k0, uint32_t k1, uint32_t site, uint32_t step,
+                                                   uint32_t mu_hi, uint32_t sg0) {
     const uint32_t l = threadIdx.x;
-    DrawBatch b;
-    b.att = philox(site, step, mu_hi | (sg0 + l / kFirstHits), (RNG_ATTEMPT << 24) | (l % kFirstHits), k0, k1);
-    b.dir = philox(site, step, mu_hi | (sg0 + l % kSgBatch), RNG_DIRECTION << 24, k0, k1);
+    const U4 a = philox(site, step, mu_hi | (sg0 + l / kFirstHits), (RNG_ATTEMPT << 24) | (l % kFirstHits), k0, k1);
+    const U4 d = philox(site, step, mu_hi | (sg0 + l % kSgBatch), RNG_DIRECTION << 24, k0, k1);
+    DrawBatch<T> b;
+    b.r0 = uniform<T>(a.w[0]);
+    b.r1 = uniform<T>(a.w[1]);
+    const T r2 = uniform<T>(a.w[2]);
+    b.r3 = uniform<T>(a.w[3]);
+    const T c = draw_cos(Const<T>::two_pi * b.r1);
+    b.kp = -(draw_log(b.r0) + c * c * draw_log(r2));
+    b.cos_t = T(1) - T(2) * uniform<T>(d.w[0]);
+    b.sin_t = d_sqrt(T(1) - b.cos_t * b.cos_t);
+    const T phi = Const<T>::two_pi * uniform<T>(d.w[1]);
+    b.cos_p = draw_cos(phi);
+    b.sin_p = draw_sin(phi);
     return b;
 }
 
-__device__ __forceinline__ U4 lane_words(const U4& w, int lane) {
-    U4 r;
-#pragma unroll
-    for (int q = 0; q < 4; ++q) r.w[q] = (uint32_t)__builtin_amdgcn_readlane((int)w.w[q], lane);
-    return r;
+// One attempt from a batch's precomputed terms: the same tests and results
+// as su2_attempt on the attempt's Philox words.
+template <typename T>
+__device__ __forceinline__ bool su2_attempt_batched(T alpha, bool creutz, T em, const DrawBatch<T>& b, T& x0,
+                                                    T& rad) {
+    if (creutz) {
+        x0 = (alpha == T(0)) ? T(2) * b.r0 - T(1) : T(1) + d_log1p((T(1) - b.r0) * em) / alpha;
+        const T rhs = T(1) - x0 * x0;
+        if (b.r1 * b.r1 <= rhs) {
+            rad = d_sqrt(rhs);
+            return true;
+        }
+    } else {
+        const T lam2 = b.kp / (T(2) * alpha);
+        const T rhs = T(1) - lam2;
+        if (b.r3 * b.r3 <= rhs) {
+            x0 = T(1) - T(2) * lam2;
+            rad = T(2) * d_sqrt(lam2) * d_sqrt(rhs);
+            return true;
+        }
+    }
+    return false;
 }
 
 // The draw of subgroup mu_sg, slot s = mu_sg mod 8 of batch b.  Returns false
 // (skip the step) when all kMaxAttempts attempts are rejected.
 template <typename T>
-__device__ __forceinline__ bool sample_su2_lanes(T alpha, const DrawBatch& b, int s, uint32_t k0, uint32_t k1,
+__device__ __forceinline__ bool sample_su2_lanes(T alpha, const DrawBatch<T>& b, int s, uint32_t k0, uint32_t k1,
                                                  uint32_t site, uint32_t step, uint32_t mu_sg, Quat<T>& x) {
     const bool creutz = alpha < Const<T>::switch_alpha;
     const T em = creutz ? d_expm1(T(-2) * alpha) : T(0);
     T x0 = T(1), rad = T(0);
-    bool ok = su2_attempt(alpha, creutz, em, b.att, x0, rad);
+    bool ok = su2_attempt_batched(alpha, creutz, em, b, x0, rad);
     unsigned long long mask = __ballot(ok) & (0xFFull << (kFirstHits * s));
     if (mask == 0ull) {
         const uint32_t hit = threadIdx.x + kFirstHits;
@@ -247,7 +283,12 @@ __device__ __forceinline__ bool sample_su2_lanes(T alpha, const DrawBatch& b, in
     const int first = __ffsll(mask) - 1;  // the same on every lane
     x0 = lane_value(x0, first);
     rad = lane_value(rad, first);
-    x = su2_direction(x0, rad, lane_words(b.dir, s));
+    const T cos_t = lane_value(b.cos_t, s), sin_t = lane_value(b.sin_t, s);
+    const T cos_p = lane_value(b.cos_p, s), sin_p = lane_value(b.sin_p, s);
+    x.q[0] = x0;
+    x.q[1] = rad * sin_t * cos_p;
+    x.q[2] = rad * sin_t * sin_p;
+    x.q[3] = rad * cos_t;
     return true;
 }
 
@@ -316,7 +357,7 @@ __global__ __launch_bounds__(kLanes) void k_update(T2<T>* __restrict__ U, Geom g
 
     const int lane = threadIdx.x;
     const uint32_t mu_hi = (uint32_t)mu << 16;
-    DrawBatch batch{};
+    DrawBatch<T> batch{};
     // The subgroup steps are ordered by wave_lds_order, and each lane reads
     // its entries of rows i and j together with the 2x2 block.  Lanes 0..31
     // own column lane of U, lanes 32..63 column lane - 32 of W.
@@ -340,7 +381,7 @@ __global__ __launch_bounds__(kLanes) void k_update(T2<T>* __restrict__ U, Geom g
             bool apply = true;
             if (hb) {
                 const int slot = (int)(sg % kSgBatch);
-                if (slot == 0) batch = draw_batch(k0, k1, (uint32_t)x.s, step, mu_hi, sg);
+                if (slot == 0) batch = draw_batch<T>(k0, k1, (uint32_t)x.s, step, mu_hi, sg);
                 const T alpha = T(2) * beta * k / T(n);
                 Quat<T> xs;
                 apply = sample_su2_lanes<T>(alpha, batch, slot, k0, k1, (uint32_t)x.s, step, mu_hi | sg, xs);
