@@ -665,13 +665,14 @@ constexpr int kMaxAttempts = 64;
 // ---------------------------------------------------------------------------
 // One attempt of the x0 draw from the four uniforms of counter word `hit`:
 // returns whether it is accepted, with x0 and the radius sqrt(1 - x0^2).
-// em = expm1(-2 alpha) is the Creutz branch's loop invariant.
+// em = expm1(-2 alpha) and ia = 1 / alpha (0 for alpha = 0) are the draw's
+// loop invariants, so an attempt divides by nothing.
 template <typename T>
-__device__ __forceinline__ bool su2_attempt(T alpha, bool creutz, T em, const U4& r, T& x0, T& rad) {
+__device__ __forceinline__ bool su2_attempt(T alpha, T ia, bool creutz, T em, const U4& r, T& x0, T& rad) {
     const T r0 = uniform<T>(r.w[0]), r1 = uniform<T>(r.w[1]);
     const T r2 = uniform<T>(r.w[2]), r3 = uniform<T>(r.w[3]);
     if (creutz) {
-        x0 = (alpha == T(0)) ? T(2) * r0 - T(1) : T(1) + d_log1p((T(1) - r0) * em) / alpha;
+        x0 = (alpha == T(0)) ? T(2) * r0 - T(1) : T(1) + d_log1p((T(1) - r0) * em) * ia;
         const T rhs = T(1) - x0 * x0;
         if (r1 * r1 <= rhs) {
             rad = d_sqrt(rhs);
@@ -679,7 +680,7 @@ __device__ __forceinline__ bool su2_attempt(T alpha, bool creutz, T em, const U4
         }
     } else {
         const T c = draw_cos(Const<T>::two_pi * r1);
-        const T lam2 = -(draw_log(r0) + c * c * draw_log(r2)) / (T(2) * alpha);
+        const T lam2 = -(draw_log(r0) + c * c * draw_log(r2)) * (T(0.5) * ia);
         const T rhs = T(1) - lam2;
         if (r3 * r3 <= rhs) {
             x0 = T(1) - T(2) * lam2;
@@ -710,12 +711,13 @@ __device__ __forceinline__ int sample_su2(T alpha, uint32_t k0, uint32_t k1, uin
                                           uint32_t mu_sg, Quat<T>& x) {
     T x0 = T(1), rad = T(0);
     const bool creutz = alpha < Const<T>::switch_alpha;
-    const T em = creutz ? d_expm1(T(-2) * alpha) : T(0);  // loop invariant
+    const T em = creutz ? d_expm1(T(-2) * alpha) : T(0);  // loop invariants
+    const T ia = alpha > T(0) ? T(1) / alpha : T(0);
     int hit = 0;
     bool ok = false;
     for (; hit < kMaxAttempts; ++hit) {
         const U4 r = philox(site, step, mu_sg, (RNG_ATTEMPT << 24) | (uint32_t)hit, k0, k1);
-        if (su2_attempt(alpha, creutz, em, r, x0, rad)) {
+        if (su2_attempt(alpha, ia, creutz, em, r, x0, rad)) {
             ok = true;
             break;
         }

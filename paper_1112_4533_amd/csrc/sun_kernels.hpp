@@ -207,6 +207,7 @@ __device__ __forceinline__ void update_link(T2<T>* __restrict__ U, const Geom& g
     const Mat<N, T> A = staple<N, T, R, MU>(U, g, x, par, h);
     Mat<N, T> Ul = NT ? load_mat_stream<N, T, R>(U, MU, par, h, g.Vh) : load_mat<N, T, R>(U, MU, par, h, g.Vh);
     Mat<N, T> W = mul_nn(Ul, A);
+    const T cb = T(2) * beta / T(N);  // alpha = 2 beta k / N
     int sg = 0;
 SUN_MAT_UNROLL
     for (int i = 0; i < N; ++i)
@@ -216,7 +217,7 @@ SUN_MAT_UNROLL
             const T k = unit_quat(block_quat(W, i, j), v);
             Quat<T> a;
             if (HB) {
-                const T alpha = T(2) * beta * k / T(N);
+                const T alpha = cb * k;
                 Quat<T> xs;
                 if (!sample_su2<T>(alpha, k0, k1, (uint32_t)x.s, step, ((uint32_t)MU << 16) | (uint32_t)sg, xs))
                     continue;

@@ -242,17 +242,17 @@ __device__ __forceinline__ DrawBatch<T> draw_batch(uint32_t k0, uint32_t k1, uin
 // One attempt from a batch's precomputed terms: the same tests and results
 // as su2_attempt on the attempt's Philox words.
 template <typename T>
-__device__ __forceinline__ bool su2_attempt_batched(T alpha, bool creutz, T em, const DrawBatch<T>& b, T& x0,
+__device__ __forceinline__ bool su2_attempt_batched(T alpha, T ia, bool creutz, T em, const DrawBatch<T>& b, T& x0,
                                                     T& rad) {
     if (creutz) {
-        x0 = (alpha == T(0)) ? T(2) * b.r0 - T(1) : T(1) + d_log1p((T(1) - b.r0) * em) / alpha;
+        x0 = (alpha == T(0)) ? T(2) * b.r0 - T(1) : T(1) + d_log1p((T(1) - b.r0) * em) * ia;
         const T rhs = T(1) - x0 * x0;
         if (b.r1 * b.r1 <= rhs) {
             rad = d_sqrt(rhs);
             return true;
         }
     } else {
-        const T lam2 = b.kp / (T(2) * alpha);
+        const T lam2 = b.kp * (T(0.5) * ia);
         const T rhs = T(1) - lam2;
         if (b.r3 * b.r3 <= rhs) {
             x0 = T(1) - T(2) * lam2;
@@ -270,13 +270,14 @@ __device__ __forceinline__ bool sample_su2_lanes(T alpha, const DrawBatch<T>& b,
                                                  uint32_t site, uint32_t step, uint32_t mu_sg, Quat<T>& x) {
     const bool creutz = alpha < Const<T>::switch_alpha;
     const T em = creutz ? d_expm1(T(-2) * alpha) : T(0);
+    const T ia = alpha > T(0) ? T(1) / alpha : T(0);
     T x0 = T(1), rad = T(0);
-    bool ok = su2_attempt_batched(alpha, creutz, em, b, x0, rad);
+    bool ok = su2_attempt_batched(alpha, ia, creutz, em, b, x0, rad);
     unsigned long long mask = __ballot(ok) & (0xFFull << (kFirstHits * s));
     if (mask == 0ull) {
         const uint32_t hit = threadIdx.x + kFirstHits;
         const U4 r = philox(site, step, mu_sg, (RNG_ATTEMPT << 24) | hit, k0, k1);
-        ok = hit < (uint32_t)kMaxAttempts && su2_attempt(alpha, creutz, em, r, x0, rad);
+        ok = hit < (uint32_t)kMaxAttempts && su2_attempt(alpha, ia, creutz, em, r, x0, rad);
         mask = __ballot(ok);
         if (mask == 0ull) return false;
     }
@@ -358,6 +359,7 @@ __global__ __launch_bounds__(kLanes) void k_update(T2<T>* __restrict__ U, Geom g
     const int lane = threadIdx.x;
     const uint32_t mu_hi = (uint32_t)mu << 16;
     DrawBatch<T> batch{};
+    const T cb = T(2) * beta / T(n);  // alpha = 2 beta k / n
     // The subgroup steps are ordered by wave_lds_order, and each lane reads
     // its entries of rows i and j together with the 2x2 block.  Lanes 0..31
     // own column lane of U, lanes 32..63 column lane - 32 of W.
@@ -382,7 +384,7 @@ __global__ __launch_bounds__(kLanes) void k_update(T2<T>* __restrict__ U, Geom g
             if (hb) {
                 const int slot = (int)(sg % kSgBatch);
                 if (slot == 0) batch = draw_batch<T>(k0, k1, (uint32_t)x.s, step, mu_hi, sg);
-                const T alpha = T(2) * beta * k / T(n);
+                const T alpha = cb * k;
                 Quat<T> xs;
                 apply = sample_su2_lanes<T>(alpha, batch, slot, k0, k1, (uint32_t)x.s, step, mu_hi | sg, xs);
                 if (apply) a = qmul(xs, qconj(v));
