@@ -159,8 +159,9 @@ int sun_set_step(sun_lattice_t h, uint64_t step);
  * L_t is a multiple of tblock and an (x, y) plane holds a whole number of
  * workgroups (L_x L_y / 2 a multiple of block); elsewhere the linear walk
  * runs, and sun_get_launch reports the walk in effect (0 for linear).
- * Defaults: heatbath (256, 1, 0, 4), overrelaxation (256, 1, 12, 4).  A
- * tuning choice only: results are bitwise the same for every shape. */
+ * Defaults: heatbath (256, 1, 16, 4); overrelaxation (256, 1, 12, 4) for
+ * links of at most 48 bytes, (256, 1, 8, 4) for larger ones.  A tuning
+ * choice only: results are bitwise the same for every shape. */
 int sun_set_launch(sun_lattice_t h, int kind, int block, int xcd, int waves, int tblock);
 int sun_get_launch(sun_lattice_t h, int kind, int *block, int *xcd, int *waves, int *tblock);
 

@@ -102,13 +102,14 @@ def test_create_validates_buffers_without_touching_them(lib):
                      b.value, x.value, w.value, t.value)
     # (a 4^4 plane holds 8 checkerboard sites: the default t-blocked walk
     # falls back to the linear one and reports 0)
-    assert get(0) == (0, 256, 1, 0, 0) and get(1) == (0, 256, 1, 12, 0)
+    # (18-real FP32 links, 72 bytes: the overrelaxation default caps at 8)
+    assert get(0) == (0, 256, 1, 16, 0) and get(1) == (0, 256, 1, 8, 0)
     assert lib.sun_set_launch(h, -1, 100, 1, 8, 0) == -1
     assert lib.sun_set_launch(h, -1, 64, 1, 5, 0) == -1
     assert lib.sun_set_launch(h, 2, 64, 1, 8, 0) == -1
     assert lib.sun_set_launch(h, -1, 64, 1, 8, 3) == -1
     assert lib.sun_set_launch(h, 1, 64, 0, 16, 0) == 0
-    assert get(0) == (0, 256, 1, 0, 0) and get(1) == (0, 64, 0, 16, 0)
+    assert get(0) == (0, 256, 1, 16, 0) and get(1) == (0, 64, 0, 16, 0)
     assert lib.sun_set_launch(h, -1, 128, 1, 8, 0) == 0
     assert get(0) == (0, 128, 1, 8, 0) and get(1) == (0, 128, 1, 8, 0)
     assert lib.sun_get_launch(h, 0, None, None, None, None) == -1
@@ -121,7 +122,7 @@ def test_create_validates_buffers_without_touching_them(lib):
     rc, lb, sb = _bytes(lib, 3, L2, 0)
     assert lib.sun_lattice_create(3, (ctypes.c_int * 4)(*L2), 0, ctypes.c_void_p(0x10000), lb,
                                   ctypes.c_void_p(0x20000), sb, ctypes.byref(h)) == 0
-    assert get(0) == (0, 256, 1, 0, 0)           # 128 sites per plane: no whole 256-item tile
+    assert get(0) == (0, 256, 1, 16, 0)          # 128 sites per plane: no whole 256-item tile
     assert lib.sun_set_launch(h, -1, 128, 1, 0, 4) == 0
     assert get(0) == (0, 128, 1, 0, 4) and get(1) == (0, 128, 1, 0, 4)
     for block, tb, want in [(64, 4, 4), (128, 8, 8), (128, 2, 2), (256, 4, 0), (64, 1, 0), (64, 0, 0)]:
