@@ -61,7 +61,7 @@ enum {
  * workgroup per link, matrices in LDS and the entries of each link
  * contiguous in memory; SUN_F32 and SUN_F64 select it by themselves there,
  * and the WIDE codes select it at Nc = 4 too (for comparisons with the
- * register path).  Its update keeps 4 Nc^2 complex entries in LDS (64 KiB
+ * register path).  Its update keeps 3 Nc^2 complex entries in LDS (48 KiB
  * at Nc = 32 in FP64).  Launch shapes do not apply to it, and batches do
  * not accept it. */
 enum {

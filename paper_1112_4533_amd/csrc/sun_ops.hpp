@@ -107,7 +107,7 @@ const Ops* ops_wide(int f64);         // 4 <= Nc <= 32: one workgroup per link, 
 
 // Dynamic LDS of the wide phase kernel, and whether it fits a workgroup.
 constexpr size_t kWideLdsMax = 64 * 1024;
-inline size_t wide_update_lds(int nc, int f64) { return (size_t)4 * nc * nc * (f64 ? 16 : 8); }
+inline size_t wide_update_lds(int nc, int f64) { return (size_t)3 * nc * nc * (f64 ? 16 : 8); }
 
 void launch_finalize_max2(const double* partial, int nblk, double* out, hipStream_t s);
 void launch_finalize_sum2(const double* partial, int nblk, double* out, double scale, hipStream_t s);

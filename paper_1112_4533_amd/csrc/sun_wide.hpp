@@ -93,7 +93,11 @@ __device__ __forceinline__ void lds_load(T2<D>* dst, const T2<S>* src, int n, bo
     }
 }
 
-// C = A B, or C += A B (C distinct from A and B; n <= 32).  With g = 64 / n
+// C = A B, or C += A B (n <= 32; C distinct from B, and from A unless acc is
+// false: then C may be A itself, because a lane reads its block of rows
+// completely in the k loop before it stores any of it, the lanes of a row
+// group run that loop together in the one wavefront of the workgroup, and no
+// other lane touches those rows).  With g = 64 / n
 // row groups, lane l < g n owns column j = l mod n and rows i0, i0 + g, ...
 // (i0 = l / n), which it takes R at a time: each B_kj it reads serves R rows,
 // and the n lanes of a row group read the same A_ik (an LDS broadcast).  A
@@ -306,8 +310,9 @@ __device__ __forceinline__ void rows_left_mul_col(T2<T>* M, int n, int i, int j,
 
 // ---------------------------------------------------------------------------
 // One checkerboard phase: workgroup h updates U_mu(x), x = site h of parity
-// par.  LDS: A (staple), B0, B1 (neighbour links), Tm (product); after the
-// staple, B1 holds U and Tm holds W = U A.
+// par.  LDS: A (staple), B0, B1 (neighbour links); the first product of each
+// staple term overwrites its left factor (B0 <- B0 B1), and after the staple
+// B1 holds U and B0 holds W = U A.
 // ---------------------------------------------------------------------------
 template <typename T>
 __global__ __launch_bounds__(kLanes) void k_update(T2<T>* __restrict__ U, Geom g, int n, int mu, int par, int hb,
@@ -317,7 +322,6 @@ __global__ __launch_bounds__(kLanes) void k_update(T2<T>* __restrict__ U, Geom g
     T2<T>* A = reinterpret_cast<T2<T>*>(smem_update);
     T2<T>* B0 = A + n2;
     T2<T>* B1 = B0 + n2;
-    T2<T>* Tm = B1 + n2;
     const int h = blockIdx.x;
     const int Vh = g.Vh;
     const Site x = site_of(g, par, h);
@@ -332,27 +336,27 @@ __global__ __launch_bounds__(kLanes) void k_update(T2<T>* __restrict__ U, Geom g
         lds_load<T, T>(B0, link_at<T>(U, n2, nu, op, xp.s >> 1, Vh), n, false);
         lds_load<T, T>(B1, link_at<T>(U, n2, mu, op, xpn.s >> 1, Vh), n, true);
         __syncthreads();
-        lds_mm<T>(Tm, B0, B1, n, false);
+        lds_mm<T>(B0, B0, B1, n, false);
         __syncthreads();
-        lds_load<T, T>(B0, link_at<T>(U, n2, nu, par, h, Vh), n, true);
+        lds_load<T, T>(B1, link_at<T>(U, n2, nu, par, h, Vh), n, true);
         __syncthreads();
-        lds_mm<T>(A, Tm, B0, n, true);
+        lds_mm<T>(A, B0, B1, n, true);
         __syncthreads();
         // lower staple U_nu(x+mu-nu)^dag U_mu(x-nu)^dag U_nu(x-nu)
         lds_load<T, T>(B0, link_at<T>(U, n2, nu, par, xpmn.s >> 1, Vh), n, true);
         lds_load<T, T>(B1, link_at<T>(U, n2, mu, op, xmn.s >> 1, Vh), n, true);
         __syncthreads();
-        lds_mm<T>(Tm, B0, B1, n, false);
+        lds_mm<T>(B0, B0, B1, n, false);
         __syncthreads();
-        lds_load<T, T>(B0, link_at<T>(U, n2, nu, op, xmn.s >> 1, Vh), n, false);
+        lds_load<T, T>(B1, link_at<T>(U, n2, nu, op, xmn.s >> 1, Vh), n, false);
         __syncthreads();
-        lds_mm<T>(A, Tm, B0, n, true);
+        lds_mm<T>(A, B0, B1, n, true);
         __syncthreads();
     }
     T2<T>* Us = B1;
     lds_load<T, T>(Us, link_at<T>(U, n2, mu, par, h, Vh), n, false);
     __syncthreads();
-    T2<T>* W = Tm;  // W = U A
+    T2<T>* W = B0;  // W = U A
     lds_mm<T>(W, Us, A, n, false);
     __syncthreads();
 
