@@ -181,7 +181,11 @@ int sun_profile_read(sun_lattice_t h, int kernel, double *total_ms, int64_t *lau
 /* The SU(2) heatbath draw alone (paper Sec. 2, SU(2) heatbath), for tests:
  * for i < n draws x in SU(2) with density ~ exp(alpha[i] x0) dHaar using the
  * counter (i, step, mu_sg, ...), computing in the given dtype.  dev_x gets 4n
- * doubles, dev_attempts n ints (0 = attempt cap reached). */
+ * doubles, dev_attempts n ints (the accepted attempt's number, 0 = attempt
+ * cap reached).  With SUN_F32_WIDE / SUN_F64_WIDE the draw is the large-Nc
+ * path's, batched over eight subgroups: element i uses the counter of site
+ * i / 8 and subgroup mu_sg + (i mod 8), which is the sequential draw's
+ * result for that counter. */
 int sun_sample_su2(int dtype, const double *dev_alpha, int n, uint64_t seed, uint32_t step,
                    uint32_t mu_sg, double *dev_x, int *dev_attempts, sun_stream_t stream);
 

@@ -62,4 +62,13 @@ struct OpsWide {
 
 const Ops* ops_wide(int f64) { return f64 ? OpsWide<double>::table() : OpsWide<float>::table(); }
 
+void launch_sample_su2_batched(int f64, const double* alpha, int n, uint32_t k0, uint32_t k1, uint32_t step,
+                               uint32_t mu_sg, double* x, int* attempts, hipStream_t s) {
+    const int sites = (n + wide::kSgBatch - 1) / wide::kSgBatch;
+    if (f64)
+        wide::k_sample_su2_batched<double><<<sites, wide::kLanes, 0, s>>>(alpha, n, k0, k1, step, mu_sg, x, attempts);
+    else
+        wide::k_sample_su2_batched<float><<<sites, wide::kLanes, 0, s>>>(alpha, n, k0, k1, step, mu_sg, x, attempts);
+}
+
 }  // namespace sun

@@ -425,12 +425,17 @@ int sun_profile_read(sun_lattice_t h, int kernel, double* total_ms, int64_t* lau
 
 int sun_sample_su2(int dtype, const double* dev_alpha, int n, uint64_t seed, uint32_t step, uint32_t mu_sg,
                    double* dev_x, int* dev_attempts, sun_stream_t stream) {
-    if (dtype != SUN_F32 && dtype != SUN_F64) return fail(SUN_EINVAL, "dtype %d", dtype);
+    if (dtype != SUN_F32 && dtype != SUN_F64 && dtype != SUN_F32_WIDE && dtype != SUN_F64_WIDE)
+        return fail(SUN_EINVAL, "dtype %d", dtype);
     if (n < 0) return fail(SUN_EINVAL, "n = %d", n);
     if (n == 0) return SUN_OK;
     if (!dev_alpha || !dev_x || !dev_attempts) return fail(SUN_ESIZE, "null buffer");
-    sun::launch_sample_su2(dtype == SUN_F64, dev_alpha, n, (uint32_t)seed, (uint32_t)(seed >> 32), step, mu_sg,
-                           dev_x, dev_attempts, as_stream(stream));
+    if (dtype == SUN_F32_WIDE || dtype == SUN_F64_WIDE)
+        sun::launch_sample_su2_batched(is_f64(dtype), dev_alpha, n, (uint32_t)seed, (uint32_t)(seed >> 32), step,
+                                       mu_sg, dev_x, dev_attempts, as_stream(stream));
+    else
+        sun::launch_sample_su2(dtype == SUN_F64, dev_alpha, n, (uint32_t)seed, (uint32_t)(seed >> 32), step, mu_sg,
+                               dev_x, dev_attempts, as_stream(stream));
     return launch_check("sample_su2");
 }
 

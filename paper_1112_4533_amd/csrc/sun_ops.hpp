@@ -116,5 +116,8 @@ void launch_plaquette_final(const double* partial, int nblk, double* out, double
 void launch_advance_steps(ChainDesc* d, int n, int n_hb, hipStream_t s);
 void launch_sample_su2(int f64, const double* alpha, int n, uint32_t k0, uint32_t k1, uint32_t step,
                        uint32_t mu_sg, double* x, int* attempts, hipStream_t s);
+// the large-Nc path's batched draw (element i: subgroup mu_sg + i mod 8 of site i / 8)
+void launch_sample_su2_batched(int f64, const double* alpha, int n, uint32_t k0, uint32_t k1, uint32_t step,
+                               uint32_t mu_sg, double* x, int* attempts, hipStream_t s);
 
 }  // namespace sun

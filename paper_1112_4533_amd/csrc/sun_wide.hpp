@@ -267,23 +267,26 @@ __device__ __forceinline__ bool su2_attempt_batched(T alpha, T ia, bool creutz, 
     return false;
 }
 
-// The draw of subgroup mu_sg, slot s = mu_sg mod 8 of batch b.  Returns false
-// (skip the step) when all kMaxAttempts attempts are rejected.
+// The draw of subgroup mu_sg, slot s of batch b.  Returns the number of the
+// accepted attempt (1-based), or 0 (skip the step) when all kMaxAttempts
+// attempts are rejected.
 template <typename T>
-__device__ __forceinline__ bool sample_su2_lanes(T alpha, const DrawBatch<T>& b, int s, uint32_t k0, uint32_t k1,
-                                                 uint32_t site, uint32_t step, uint32_t mu_sg, Quat<T>& x) {
+__device__ __forceinline__ int sample_su2_lanes(T alpha, const DrawBatch<T>& b, int s, uint32_t k0, uint32_t k1,
+                                                uint32_t site, uint32_t step, uint32_t mu_sg, Quat<T>& x) {
     const bool creutz = alpha < Const<T>::switch_alpha;
     const T em = creutz ? d_expm1(T(-2) * alpha) : T(0);
     const T ia = alpha > T(0) ? T(1) / alpha : T(0);
     T x0 = T(1), rad = T(0);
     bool ok = su2_attempt_batched(alpha, ia, creutz, em, b, x0, rad);
     unsigned long long mask = __ballot(ok) & (0xFFull << (kFirstHits * s));
+    int hit0 = -kFirstHits * s;  // attempt number of lane 0, 0-based
     if (mask == 0ull) {
         const uint32_t hit = threadIdx.x + kFirstHits;
         const U4 r = philox(site, step, mu_sg, (RNG_ATTEMPT << 24) | hit, k0, k1);
         ok = hit < (uint32_t)kMaxAttempts && su2_attempt(alpha, ia, creutz, em, r, x0, rad);
         mask = __ballot(ok);
-        if (mask == 0ull) return false;
+        if (mask == 0ull) return 0;
+        hit0 = kFirstHits;
     }
     const int first = __ffsll(mask) - 1;  // the same on every lane
     x0 = lane_value(x0, first);
@@ -294,7 +297,7 @@ __device__ __forceinline__ bool sample_su2_lanes(T alpha, const DrawBatch<T>& b,
     x.q[1] = rad * sin_t * cos_p;
     x.q[2] = rad * sin_t * sin_p;
     x.q[3] = rad * cos_t;
-    return true;
+    return hit0 + first + 1;
 }
 
 // Rows i, j of M (LDS), column c, left-multiplied by the 2x2 form of a,
@@ -390,7 +393,7 @@ __global__ __launch_bounds__(kLanes) void k_update(T2<T>* __restrict__ U, Geom g
                 if (slot == 0) batch = draw_batch<T>(k0, k1, (uint32_t)x.s, step, mu_hi, sg);
                 const T alpha = cb * k;
                 Quat<T> xs;
-                apply = sample_su2_lanes<T>(alpha, batch, slot, k0, k1, (uint32_t)x.s, step, mu_hi | sg, xs);
+                apply = sample_su2_lanes<T>(alpha, batch, slot, k0, k1, (uint32_t)x.s, step, mu_hi | sg, xs) != 0;
                 if (apply) a = qmul(xs, qconj(v));
             } else {
                 const Quat<T> vc = qconj(v);
@@ -788,6 +791,31 @@ __global__ __launch_bounds__(256) void k_import(T2<T>* __restrict__ U, Geom g, i
     const double* p = in + (((size_t)mu * g.V + s) * n2 + e) * 2;
     T2<T>* dst = const_cast<T2<T>*>(link_at<T>(U, n2, mu, par, h, g.Vh));
     dst[e] = cpx<T>((T)p[0], (T)p[1]);
+}
+
+// ---------------------------------------------------------------------------
+// The batched SU(2) draw alone, for parity tests: element i is subgroup
+// mu_sg + (i mod 8) of site i / 8, drawn as the update draws it (one batch
+// per site, the slots in order).  dev_x gets 4n doubles, attempts n ints
+// (the accepted attempt's number, 0 when all were rejected).
+// ---------------------------------------------------------------------------
+template <typename T>
+__global__ __launch_bounds__(kLanes) void k_sample_su2_batched(const double* __restrict__ alpha, int n, uint32_t k0,
+                                                               uint32_t k1, uint32_t step, uint32_t mu_sg,
+                                                               double* __restrict__ x, int* __restrict__ attempts) {
+    const uint32_t site = blockIdx.x;
+    const DrawBatch<T> b = draw_batch<T>(k0, k1, site, step, 0u, mu_sg);
+    for (int s = 0; s < kSgBatch; ++s) {
+        const int i = (int)site * kSgBatch + s;
+        if (i >= n) break;
+        Quat<T> q{{T(1), T(0), T(0), T(0)}};
+        const int a = sample_su2_lanes<T>((T)alpha[i], b, s, k0, k1, site, step, mu_sg + (uint32_t)s, q);
+        if (threadIdx.x == 0) {
+#pragma unroll
+            for (int c = 0; c < 4; ++c) x[4 * (size_t)i + c] = q.q[c];
+            attempts[i] = a;
+        }
+    }
 }
 
 }  // namespace wide

@@ -15,8 +15,8 @@ import pytest
 import torch
 
 import oracle as O
-from gpu_common import (beta_for, compare_links, gpu_lattice, oracle_phase_diag, rounded, thermal_field, to_np,
-                        twin_spread)
+from gpu_common import (FLIP_MARGIN, TOL, beta_for, compare_links, gpu_lattice, oracle_phase_diag, rounded,
+                        thermal_field, to_np, twin_spread)
 
 pytestmark = pytest.mark.gpu
 
@@ -110,6 +110,32 @@ def test_wide_su32_8x4_phase_parity(gpu):
     m, k = oracle_phase_diag(base, nc, L, 0, 1, 0, beta, 1234, 0)
     flips = compare_links(got, base, "f32", m, k, "SU(32) 8^4 heatbath", spread=sp)
     print(f"flips: {flips}")
+
+
+@pytest.mark.parametrize("dtype", ["f64w", "f32w"])
+def test_wide_batched_sampler_parity(gpu, dtype):
+    """The large-Nc draw, batched over eight subgroups with the fall-back to
+    attempts 8..63, against the oracle's sequential sampler on the same
+    counters (element i: subgroup mu_sg + i mod 8 of site i / 8).  Near
+    alpha = 1.7, the hybrid's lowest acceptance, some draws need more than
+    eight attempts on either side of the switch and so take the fall-back."""
+    sun = gpu
+    alpha = np.concatenate([np.zeros(64), np.linspace(0.01, 60.0, 40000), np.full(160000, 1.7),
+                            np.full(160000, 1.69)])
+    mu_sg = (2 << 16) | 8
+    xg, ag = sun.sample_su2(torch.from_numpy(alpha).cuda(), seed=31, step=5, mu_sg=mu_sg, dtype=dtype)
+    xg, ag = to_np(xg), to_np(ag)
+    xo, ao, margin = np.zeros((alpha.size, 4)), np.zeros(alpha.size, dtype=np.int32), np.zeros(alpha.size)
+    for s in range(8):
+        xo[s::8], ao[s::8], margin[s::8] = O.sample_su2(alpha[s::8], seed=31, step=5, mu_sg=mu_sg + s)
+    assert (ao[alpha == 1.7] > 8).sum() > 0 and (ao[alpha == 1.69] > 8).sum() > 0
+    d = np.abs(xg - xo).max(axis=1)
+    bad = (d > TOL[dtype]) | (ag != ao)
+    if dtype == "f64w":
+        assert not bad.any(), (d.max(), int((ag != ao).sum()))
+    else:
+        assert np.all(margin[bad] < FLIP_MARGIN)
+        assert bad.sum() <= 10
 
 
 @pytest.mark.parametrize("nc", [4])
