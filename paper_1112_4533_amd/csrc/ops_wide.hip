@@ -12,8 +12,15 @@ struct OpsWide {
 
     static void update(const Ctx& c, int kind, int mu, int par, double beta, uint32_t k0, uint32_t k1, uint32_t step) {
         const size_t lds = wide_update_lds(c.nc, f64);
-        wide::k_update<T><<<c.g.Vh, wide::kLanes, lds, c.stream>>>((P*)c.links, c.g, c.nc, mu, par, kind == 0 ? 1 : 0,
-                                                                   (T)beta, k0, k1, step);
+        if constexpr (!f64) {
+            if (c.nc > wide::kMfmaMinN) {
+                wide::k_update<T, true><<<c.g.Vh, wide::kLanes, lds, c.stream>>>(
+                    (P*)c.links, c.g, c.nc, mu, par, kind == 0 ? 1 : 0, (T)beta, k0, k1, step);
+                return;
+            }
+        }
+        wide::k_update<T, false><<<c.g.Vh, wide::kLanes, lds, c.stream>>>((P*)c.links, c.g, c.nc, mu, par,
+                                                                          kind == 0 ? 1 : 0, (T)beta, k0, k1, step);
     }
     static void init(const Ctx& c, int hot, uint32_t k0, uint32_t k1) {
         wide::k_init<T><<<4 * c.g.V, wide::kLanes, wide::fp64_lds(c.nc, 2), c.stream>>>((P*)c.links, c.g, c.nc, hot, k0,

@@ -152,8 +152,62 @@ __device__ __forceinline__ void lds_mm_rows(T2<T>* C, const T2<T>* A, const T2<T
     }
 }
 
-template <typename T>
+// The same product on the matrix cores for FP32 and kMfmaMinN < n <= 32:
+// the complex product is four real 32 x 32 x 32 products (C_re += A_re B_re
+// - A_im B_im, C_im += A_re B_im + A_im B_re), each 16 v_mfma_f32_32x32x2f32
+// over k in pairs, with rows, columns and k beyond n read as zero.  Operand
+// layout: lane l gives A[l mod 32][k0 + l / 32] and B[k0 + l / 32][l mod 32];
+// result register r of lane l is entry (8 (r / 4) + 4 (l / 32) + r mod 4,
+// l mod 32).  Every lane takes part (the matrix instructions need the whole
+// wavefront), and all reads of A and B precede the stores, so C may be A
+// when acc is false.  Below kMfmaMinN the padded tile wastes more than the
+// VALU product costs.
+constexpr int kMfmaMinN = 20;
+typedef float f32x16 __attribute__((ext_vector_type(16)));
+
+__device__ __forceinline__ void lds_mm_mfma(T2<float>* C, const T2<float>* A, const T2<float>* B, int n, bool acc) {
+    const int l = threadIdx.x;
+    const int lo = l & 31, hi = l >> 5;
+    f32x16 cr, ci;
+#pragma unroll
+    for (int r = 0; r < 16; ++r) {
+        const int i = 8 * (r / 4) + 4 * hi + (r % 4);
+        T2<float> c = cpx<float>(0.f, 0.f);
+        if (acc && i < n && lo < n) c = C[i * n + lo];
+        cr[r] = c.x;
+        ci[r] = c.y;
+    }
+    // the real and imaginary accumulations alternate, so that consecutive
+    // matrix instructions do not wait on each other's result
+#pragma unroll 2
+    for (int k0 = 0; k0 < n; k0 += 2) {
+        const int k = k0 + hi;
+        T2<float> a = cpx<float>(0.f, 0.f), b = cpx<float>(0.f, 0.f);
+        if (k < n && lo < n) {
+            a = A[lo * n + k];
+            b = B[k * n + lo];
+        }
+        cr = __builtin_amdgcn_mfma_f32_32x32x2f32(a.x, b.x, cr, 0, 0, 0);
+        ci = __builtin_amdgcn_mfma_f32_32x32x2f32(a.x, b.y, ci, 0, 0, 0);
+        cr = __builtin_amdgcn_mfma_f32_32x32x2f32(-a.y, b.y, cr, 0, 0, 0);
+        ci = __builtin_amdgcn_mfma_f32_32x32x2f32(a.y, b.x, ci, 0, 0, 0);
+    }
+#pragma unroll
+    for (int r = 0; r < 16; ++r) {
+        const int i = 8 * (r / 4) + 4 * hi + (r % 4);
+        if (i < n && lo < n) C[i * n + lo] = cpx<float>(cr[r], ci[r]);
+    }
+}
+
+// MM: the matrix-core form (FP32, kMfmaMinN < n), compiled into its own
+// kernel variant so that the others keep their register budget.
+template <typename T, bool MM = false>
 __device__ __forceinline__ void lds_mm(T2<T>* C, const T2<T>* A, const T2<T>* B, int n, bool acc) {
+    if constexpr (MM) {
+        static_assert(sizeof(T) == 4, "the matrix-core product is FP32");
+        lds_mm_mfma(C, A, B, n, acc);
+        return;
+    }
     const int g = kLanes / n;
     const int lane = threadIdx.x;
     if (lane >= g * n) return;
@@ -317,7 +371,7 @@ __device__ __forceinline__ void rows_left_mul_col(T2<T>* M, int n, int i, int j,
 // staple term overwrites its left factor (B0 <- B0 B1), and after the staple
 // B1 holds U and B0 holds W = U A.
 // ---------------------------------------------------------------------------
-template <typename T>
+template <typename T, bool MM>
 __global__ __launch_bounds__(kLanes) void k_update(T2<T>* __restrict__ U, Geom g, int n, int mu, int par, int hb,
                                                    T beta, uint32_t k0, uint32_t k1, uint32_t step) {
     extern __shared__ double4 smem_update[];
@@ -339,28 +393,28 @@ __global__ __launch_bounds__(kLanes) void k_update(T2<T>* __restrict__ U, Geom g
         lds_load<T, T>(B0, link_at<T>(U, n2, nu, op, xp.s >> 1, Vh), n, false);
         lds_load<T, T>(B1, link_at<T>(U, n2, mu, op, xpn.s >> 1, Vh), n, true);
         __syncthreads();
-        lds_mm<T>(B0, B0, B1, n, false);
+        lds_mm<T, MM>(B0, B0, B1, n, false);
         __syncthreads();
         lds_load<T, T>(B1, link_at<T>(U, n2, nu, par, h, Vh), n, true);
         __syncthreads();
-        lds_mm<T>(A, B0, B1, n, true);
+        lds_mm<T, MM>(A, B0, B1, n, true);
         __syncthreads();
         // lower staple U_nu(x+mu-nu)^dag U_mu(x-nu)^dag U_nu(x-nu)
         lds_load<T, T>(B0, link_at<T>(U, n2, nu, par, xpmn.s >> 1, Vh), n, true);
         lds_load<T, T>(B1, link_at<T>(U, n2, mu, op, xmn.s >> 1, Vh), n, true);
         __syncthreads();
-        lds_mm<T>(B0, B0, B1, n, false);
+        lds_mm<T, MM>(B0, B0, B1, n, false);
         __syncthreads();
         lds_load<T, T>(B1, link_at<T>(U, n2, nu, op, xmn.s >> 1, Vh), n, false);
         __syncthreads();
-        lds_mm<T>(A, B0, B1, n, true);
+        lds_mm<T, MM>(A, B0, B1, n, true);
         __syncthreads();
     }
     T2<T>* Us = B1;
     lds_load<T, T>(Us, link_at<T>(U, n2, mu, par, h, Vh), n, false);
     __syncthreads();
     T2<T>* W = B0;  // W = U A
-    lds_mm<T>(W, Us, A, n, false);
+    lds_mm<T, MM>(W, Us, A, n, false);
     __syncthreads();
 
     const int lane = threadIdx.x;

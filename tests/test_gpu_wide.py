@@ -95,7 +95,9 @@ def test_wide_phase_parity(gpu, nc, dtype):
         sp = twin_spread(before, nc, SMALL, kind, mu, par, beta, 77, 3, rel=REL[dtype[:3]])
         want = before.copy()
         m, k = oracle_phase_diag(want, nc, SMALL, kind, mu, par, beta, 77, 3)
-        flips += compare_links(got, want, dtype, m, k, f"nc={nc} {dtype} kind={kind} mu={mu} p={par}", spread=sp)
+        dec = (np.prod(SMALL) // 2) * nc * (nc - 1) // 2 if kind == 0 else None
+        flips += compare_links(got, want, dtype, m, k, f"nc={nc} {dtype} kind={kind} mu={mu} p={par}", spread=sp,
+                               decisions=dec)
     print(f"flips: {flips}")
 
 
@@ -108,7 +110,8 @@ def test_wide_su32_8x4_phase_parity(gpu):
     got = to_np(lat.export())
     sp = twin_spread(base, nc, L, 0, 1, 0, beta, 1234, 0, rel=REL["f32"])
     m, k = oracle_phase_diag(base, nc, L, 0, 1, 0, beta, 1234, 0)
-    flips = compare_links(got, base, "f32", m, k, "SU(32) 8^4 heatbath", spread=sp)
+    flips = compare_links(got, base, "f32", m, k, "SU(32) 8^4 heatbath", spread=sp,
+                          decisions=(8 ** 4 // 2) * nc * (nc - 1) // 2)
     print(f"flips: {flips}")
 
 
