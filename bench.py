@@ -293,7 +293,7 @@ def wide_update_flops(nc):
     return 13 * 8 * nc ** 3 + (nc * (nc - 1) // 2) * 2 * 32 * nc
 
 
-def run_nc_scan(reps, warmup):
+def run_nc_scan(reps, warmup, only=None):
     """Time per iteration (1 heatbath + 1 overrelaxation step + re-unitarization,
     the paper's large-Nc protocol) on 8^4 at beta 6.2, hot start, for the
     register path (Nc <= 4) and the workgroup-per-link path (Nc >= 4), a
@@ -308,6 +308,8 @@ def run_nc_scan(reps, warmup):
     rows, fits = [], {}
     for prec, ncs in NC_SCAN.items():
         for nc in ncs:
+            if only and nc not in only:
+                continue
             paths = (["register"] if nc <= sun.NC_MAX_REGISTER else []) + ["wide"]
             for path in paths:
                 dtype = prec if path == "register" or nc > sun.NC_MAX_REGISTER else prec + "w"
@@ -339,6 +341,8 @@ def run_nc_scan(reps, warmup):
                 print(json.dumps(row), flush=True)
                 del lat
         w = [r for r in rows if r["precision"] == prec and r["path"] == "wide"]
+        if len(w) < 5 or w[-1]["nc"] <= 16:   # too few sizes for the fit
+            continue
         x = np.array([r["nc"] for r in w], dtype=float)
         y = np.array([r["ms_per_iteration"] for r in w])
         c = np.polyfit(x, y, 3, w=1.0 / y)          # least squares in relative error
@@ -375,9 +379,12 @@ def main():
                          "scaling HBM byte counters), then exit")
     ap.add_argument("--nc-scan", action="store_true",
                     help="only time one iteration against Nc (4..32) on 8^4 and fit a cubic, then exit")
+    ap.add_argument("--nc-list", type=int, nargs="+", default=None,
+                    help="with --nc-scan: only these Nc (no fit below five sizes)")
     args = ap.parse_args()
     if args.nc_scan:
-        print(json.dumps(run_nc_scan(max(1, args.steps // 10), max(1, args.warmup // 3))), flush=True)
+        print(json.dumps(run_nc_scan(max(1, args.steps // 10), max(1, args.warmup // 3), only=args.nc_list)),
+              flush=True)
         return
     if args.copy_calibration > 0:
         import torch
