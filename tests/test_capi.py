@@ -152,3 +152,18 @@ def test_batch_argument_checks(lib):
     lib.sun_lattice_destroy(h)
     assert lib.sun_batch_sweep(None, 1, 1, 1, None) == -1
     assert lib.sun_batch_replay(None, None) == -1
+
+
+def test_sampler_hook_argument_checks(lib):
+    """The SU(2) draw hook checks its arguments before any launch: the
+    register-path and wide storage codes are accepted (the wide ones select
+    the batched draw), the two-row codes are not; a negative count or a null
+    buffer is refused and an empty draw is a no-op."""
+    p = ctypes.c_void_p(0x10000)
+    for dtype in (2, 3, 6, -1):
+        assert lib.sun_sample_su2(dtype, p, 8, 1, 0, 0, p, p, None) == -1
+    for dtype in (0, 1, 4, 5):
+        assert lib.sun_sample_su2(dtype, p, -1, 1, 0, 0, p, p, None) == -1
+        assert lib.sun_sample_su2(dtype, None, 8, 1, 0, 0, p, p, None) == -2
+        assert lib.sun_sample_su2(dtype, p, 8, 1, 0, 0, p, None, None) == -2
+        assert lib.sun_sample_su2(dtype, p, 0, 1, 0, 0, p, p, None) == 0
