@@ -228,8 +228,8 @@ int sun_batch_capture(sun_batch_t b, int n_sweeps, int n_hb, int n_or, int reuni
 int sun_batch_replay(sun_batch_t b, sun_stream_t stream);
 
 /* Launch shape of the batch's phase kernels (as sun_set_launch, always with
- * the linear tile walk).  Waits for the device, rewrites the table, and drops
- * any captured graph. */
+ * the linear tile walk; default (256, 1, 0) for both kinds).  Waits for the
+ * device, rewrites the table, and drops any captured graph. */
 int sun_batch_set_launch(sun_batch_t b, int kind, int block, int xcd, int waves);
 
 /* Writes the chains' advanced RNG step counters back to their handles. */

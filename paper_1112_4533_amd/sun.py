@@ -291,7 +291,7 @@ class Batch:
         self.n = n
         self.betas = [float(x) for x in betas]
         self.seeds = [int(x) for x in seeds]
-        self.launch = [(256, 1, 0), (256, 1, 12)]   # heatbath, overrelaxation (block, xcd, waves)
+        self.launch = [(256, 1, 0), (256, 1, 0)]    # heatbath, overrelaxation (block, xcd, waves)
         self.stream = torch.cuda.Stream(device=dev)   # graphs need a non-null stream
 
     def __del__(self):
