@@ -148,7 +148,8 @@ def run_gpu(run, steps, warmup, tune=False):
         "unitarity_before_reunit": drift.cpu().tolist(),
         "step_counter": lat.step,
         "or_dS_over_S": or_ds,
-        "launch": {"heatbath": lat.get_launch(sun.HEATBATH), "overrelax": lat.get_launch(sun.OVERRELAX)},
+        "launch": {"heatbath": lat.get_launch(sun.HEATBATH), "overrelax": lat.get_launch(sun.OVERRELAX),
+                   "sites_per_item": [lat.get_sites_per_item(sun.HEATBATH), lat.get_sites_per_item(sun.OVERRELAX)]},
     }
 
 
@@ -249,7 +250,8 @@ def run_batch(steps, warmup, f64_sweeps, tune=False):
     return {
         "chains": len(spec), "sites": total_sites,
         "fp32_batched_graph": {"value": upd32, "unit": "link_updates/s", "ms_per_sweep": 1e3 * dt32 / steps,
-                               "sweeps": steps, "launch": {"heatbath": bt.launch[0], "overrelax": bt.launch[1]}},
+                               "sweeps": steps, "launch": {"heatbath": bt.launch[0], "overrelax": bt.launch[1],
+                                                           "sites_per_item": list(bt.sites_per_item)}},
         "fp64_per_chain_eager": {"value": upd64, "unit": "link_updates/s", "ms_per_sweep": 1e3 * dt64 / f64_sweeps,
                                  "sweeps": f64_sweeps},
         "speedup": upd32 / upd64,

@@ -165,6 +165,14 @@ int sun_set_step(sun_lattice_t h, uint64_t step);
 int sun_set_launch(sun_lattice_t h, int kind, int block, int xcd, int waves, int tblock);
 int sun_get_launch(sun_lattice_t h, int kind, int *block, int *xcd, int *waves, int *tblock);
 
+/* Sites per work-item of the phase kernels of one update kind (SUN_HEATBATH,
+ * SUN_OVERRELAX, or -1 for both): 1, 2 or 4 (default 1).  A workgroup then
+ * updates that many tiles of its walk in turn and the grid is that many
+ * times smaller.  Kept by sun_set_launch.  A tuning choice only: results are
+ * bitwise the same. */
+int sun_set_sites_per_item(sun_lattice_t h, int kind, int spt);
+int sun_get_sites_per_item(sun_lattice_t h, int kind, int *spt);
+
 /* Per-kernel timing with HIP events recorded around launches on the launch
  * stream.  kernel: 0 heatbath phase, 1 overrelaxation phase,
  * 2 re-unitarization, 3 plaquette, 4 Polyakov loop.  sun_profile(h, every)
@@ -231,6 +239,10 @@ int sun_batch_replay(sun_batch_t b, sun_stream_t stream);
  * the linear tile walk; default (256, 1, 0) for both kinds).  Waits for the
  * device, rewrites the table, and drops any captured graph. */
 int sun_batch_set_launch(sun_batch_t b, int kind, int block, int xcd, int waves);
+/* Sites per work-item of the batch's phase kernels (as
+ * sun_set_sites_per_item; same waiting, table rewrite and graph drop as
+ * sun_batch_set_launch). */
+int sun_batch_set_sites_per_item(sun_batch_t b, int kind, int spt);
 
 /* Writes the chains' advanced RNG step counters back to their handles. */
 int sun_batch_sync(sun_batch_t b);

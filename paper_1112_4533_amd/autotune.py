@@ -2,8 +2,9 @@
 
 The phase kernels come in workgroup sizes of 64, 128 and 256 work-items, with
 the XCD-aware or the plain workgroup order, with a cap of 8, 12, 16 or no
-limit on resident waves per CU, and (single lattices) with the linear or a
-t-blocked tile walk of 2, 4 or 8 time slices.  Every shape computes the same bits, so the
+limit on resident waves per CU, (single lattices) with the linear or a
+t-blocked tile walk of 2, 4 or 8 time slices, and with 1, 2 or 4 sites per
+work-item (searched after the rest, with the chosen shape in place).  Every shape computes the same bits, so the
 choice is a pure speed question, made separately for the heatbath and the
 overrelaxation kernels (the heatbath draws cost arithmetic, so it prefers
 more resident waves).  It depends on the lattice: a small lattice needs small
@@ -73,6 +74,21 @@ def _search(shapes, set_shape, step_hb, step_or, reps):
     return best, times
 
 
+def _search_spt(set_spt, step_hb, step_or, reps):
+    """With the chosen shapes in place, times 1, 2 and 4 sites per
+    work-item for each kind; returns ({kind: best}, timings)."""
+    best, times = {}, {}
+    for kind, step in ((sun.HEATBATH, step_hb), (sun.OVERRELAX, step_or)):
+        t = {}
+        for spt in sun.Lattice.SITES_PER_ITEM:
+            set_spt(spt, kind)
+            t[str(spt)] = _time(step, reps)
+        best[kind] = int(min(t, key=t.get))
+        set_spt(best[kind], kind)
+        times[("heatbath" if kind == sun.HEATBATH else "overrelax") + "_sites_per_item"] = t
+    return best, times
+
+
 def lattice_key(lat):
     return f"{_arch()}:su{lat.nc}:{'x'.join(map(str, lat.L))}:{sun.DTYPE_NAMES[lat.dtype]}"
 
@@ -87,6 +103,8 @@ def tune_lattice(lat, reps=5, use_cache=True):
         best = {int(k): tuple(v) for k, v in cache[key]["shape"].items()}
         for kind, shape in best.items():
             lat.set_launch(*shape, kind=kind)
+        for kind, spt in cache[key].get("sites_per_item", {}).items():
+            lat.set_sites_per_item(spt, kind=int(kind))
         return best, cache[key].get("ms", {})
     clone = sun.Lattice(lat.nc, lat.L, lat.dtype, device=lat.links.device)
     clone.links.copy_(lat.links)
@@ -99,8 +117,15 @@ def tune_lattice(lat, reps=5, use_cache=True):
     best, times = _search(shapes, lambda shape, kind: clone.set_launch(*shape, kind=kind),
                           lambda: clone.phase_step(sun.HEATBATH), lambda: clone.phase_step(sun.OVERRELAX), reps)
     for kind, shape in best.items():
+        clone.set_launch(*shape, kind=kind)
         lat.set_launch(*shape, kind=kind)
-    cache[key] = {"shape": {str(k): list(v) for k, v in best.items()}, "ms": times}
+    spt, t_spt = _search_spt(lambda v, kind: clone.set_sites_per_item(v, kind=kind),
+                             lambda: clone.phase_step(sun.HEATBATH), lambda: clone.phase_step(sun.OVERRELAX), reps)
+    times.update(t_spt)
+    for kind, v in spt.items():
+        lat.set_sites_per_item(v, kind=kind)
+    cache[key] = {"shape": {str(k): list(v) for k, v in best.items()},
+                  "sites_per_item": {str(k): v for k, v in spt.items()}, "ms": times}
     if use_cache:
         _save_cache(cache)
     return best, times
@@ -120,6 +145,8 @@ def tune_batch(batch, reps=3, use_cache=True):
         best = {int(k): tuple(v) for k, v in cache[key]["shape"].items()}
         for kind, shape in best.items():
             batch.set_launch(*shape, kind=kind)
+        for kind, spt in cache[key].get("sites_per_item", {}).items():
+            batch.set_sites_per_item(spt, kind=int(kind))
         return best, cache[key].get("ms", {})
     clones = []
     for l in batch.lattices:
@@ -130,8 +157,15 @@ def tune_batch(batch, reps=3, use_cache=True):
     best, times = _search(sun.Batch.LAUNCH_SHAPES, lambda shape, kind: cb.set_launch(*shape, kind=kind),
                           lambda: cb.sweep(1, 0, reunit=False), lambda: cb.sweep(0, 1, reunit=False), reps)
     for kind, shape in best.items():
+        cb.set_launch(*shape, kind=kind)
         batch.set_launch(*shape, kind=kind)
-    cache[key] = {"shape": {str(k): list(v) for k, v in best.items()}, "ms": times}
+    spt, t_spt = _search_spt(lambda v, kind: cb.set_sites_per_item(v, kind=kind),
+                             lambda: cb.sweep(1, 0, reunit=False), lambda: cb.sweep(0, 1, reunit=False), reps)
+    times.update(t_spt)
+    for kind, v in spt.items():
+        batch.set_sites_per_item(v, kind=kind)
+    cache[key] = {"shape": {str(k): list(v) for k, v in best.items()},
+                  "sites_per_item": {str(k): v for k, v in spt.items()}, "ms": times}
     if use_cache:
         _save_cache(cache)
     return best, times

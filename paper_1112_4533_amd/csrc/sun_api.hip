@@ -372,7 +372,24 @@ int sun_set_launch(sun_lattice_t h, int kind, int block, int xcd, int waves, int
     if (!h) return fail(SUN_EINVAL, "null handle");
     if (int rc = check_shape(kind, block, waves, tblock)) return rc;
     for (int k = 0; k < 2; ++k)
-        if (kind < 0 || kind == k) h->shape[k] = sun::Shape{block, xcd ? 1 : 0, waves, tblock > 1 ? tblock : 0};
+        if (kind < 0 || kind == k)
+            h->shape[k] = sun::Shape{block, xcd ? 1 : 0, waves, tblock > 1 ? tblock : 0, h->shape[k].spt};
+    return SUN_OK;
+}
+
+int sun_set_sites_per_item(sun_lattice_t h, int kind, int spt) {
+    if (!h) return fail(SUN_EINVAL, "null handle");
+    if (kind < -1 || kind > 1) return fail(SUN_EINVAL, "kind %d is not -1, SUN_HEATBATH or SUN_OVERRELAX", kind);
+    if (!sun::valid_spt(spt)) return fail(SUN_EINVAL, "sites per work-item %d is not 1, 2 or 4", spt);
+    for (int k = 0; k < 2; ++k)
+        if (kind < 0 || kind == k) h->shape[k].spt = spt;
+    return SUN_OK;
+}
+
+int sun_get_sites_per_item(sun_lattice_t h, int kind, int* spt) {
+    if (!h || !spt) return fail(SUN_EINVAL, "null argument");
+    if (kind != SUN_HEATBATH && kind != SUN_OVERRELAX) return fail(SUN_EINVAL, "kind %d", kind);
+    *spt = h->shape[kind].spt;
     return SUN_OK;
 }
 
@@ -515,6 +532,29 @@ int batch_plaquette_launches(sun_batch_t b, double* out, hipStream_t s) {
 
 }  // namespace
 
+// Rewrites a batch's launch shapes: waits for the device (the table holds
+// the device step counters, so the host copy is brought up to date first),
+// applies `apply` to the shape of each selected kind, drops any captured
+// graph and uploads the table again.
+template <typename F>
+int batch_reshape(sun_batch_t b, int kind, F apply) {
+    for (size_t i = 0; i < b->host.size(); ++i)
+        b->host[i].step = b->step0[b->host[i].out_index] + b->hb_steps_done;
+    if (int rc = hip_check(hipDeviceSynchronize(), "hipDeviceSynchronize")) return rc;
+    for (int k = 0; k < 2; ++k)
+        if (kind < 0 || kind == k) apply(b->shape[k]);
+    if (b->exec) {
+        (void)hipGraphExecDestroy(b->exec);
+        b->exec = nullptr;
+    }
+    if (b->graph) {
+        (void)hipGraphDestroy(b->graph);
+        b->graph = nullptr;
+    }
+    return upload_table(b);
+}
+
+
 extern "C" {
 
 int sun_batch_bytes(int n, size_t* table_bytes) {
@@ -633,21 +673,14 @@ int sun_batch_replay(sun_batch_t b, sun_stream_t stream) {
 int sun_batch_set_launch(sun_batch_t b, int kind, int block, int xcd, int waves) {
     if (!b) return fail(SUN_EINVAL, "null batch");
     if (int rc = check_shape(kind, block, waves)) return rc;
-    // the table holds the device step counters: bring the host copy up to date first
-    for (size_t i = 0; i < b->host.size(); ++i)
-        b->host[i].step = b->step0[b->host[i].out_index] + b->hb_steps_done;
-    if (int rc = hip_check(hipDeviceSynchronize(), "hipDeviceSynchronize")) return rc;
-    for (int k = 0; k < 2; ++k)
-        if (kind < 0 || kind == k) b->shape[k] = sun::Shape{block, xcd ? 1 : 0, waves};
-    if (b->exec) {
-        (void)hipGraphExecDestroy(b->exec);
-        b->exec = nullptr;
-    }
-    if (b->graph) {
-        (void)hipGraphDestroy(b->graph);
-        b->graph = nullptr;
-    }
-    return upload_table(b);
+    return batch_reshape(b, kind, [&](sun::Shape& sh) { sh = sun::Shape{block, xcd ? 1 : 0, waves, 0, sh.spt}; });
+}
+
+int sun_batch_set_sites_per_item(sun_batch_t b, int kind, int spt) {
+    if (!b) return fail(SUN_EINVAL, "null batch");
+    if (kind < -1 || kind > 1) return fail(SUN_EINVAL, "kind %d is not -1, SUN_HEATBATH or SUN_OVERRELAX", kind);
+    if (!sun::valid_spt(spt)) return fail(SUN_EINVAL, "sites per work-item %d is not 1, 2 or 4", spt);
+    return batch_reshape(b, kind, [&](sun::Shape& sh) { sh.spt = spt; });
 }
 
 int sun_batch_sync(sun_batch_t b) {

@@ -153,11 +153,12 @@ __device__ __forceinline__ int xcd_tile(int b, int nblk) {
 // sets tb > 1 only where a plane holds a whole number of tiles and tb
 // divides L_t, which makes the walk a permutation of the tiles.
 struct Walk {
-    int xcd;  // XCD-aware workgroup order
-    int tb;   // time slices per block of the walk (0 or 1: linear walk)
-    int tpp;  // tiles per (z, t) plane
-    int lz;   // L_z
-    int rev;  // walk the tiles in reverse order
+    int xcd;      // XCD-aware workgroup order
+    int tb;       // time slices per block of the walk (0 or 1: linear walk)
+    int tpp;      // tiles per (z, t) plane
+    int lz;       // L_z
+    int rev;      // walk the tiles in reverse order
+    int spt = 1;  // tiles per workgroup (sites per work-item), taken in turn
 };
 
 // Tiles of the plaquette grid (256-item workgroups): both parities of every

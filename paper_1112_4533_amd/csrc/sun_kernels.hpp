@@ -284,13 +284,18 @@ __device__ __forceinline__ void update_any(T2<T>* __restrict__ U, const Geom& g,
 // reserves per workgroup; the kernels never touch it (a reference to a
 // dynamic LDS array costs them a scratch spill).
 
+// Grid: ceil(nblk / walk.spt) workgroups over nblk tiles of BS sites; a
+// workgroup takes walk positions blockIdx.x + r gridDim.x, r < walk.spt, in
+// turn (r apart by a multiple of 8 when the grid is, so they stay on one XCD).
 template <int N, typename T, int R, bool HB, int MU, int BS, bool NT>
 __global__ __launch_bounds__(BS) void k_update(T2<T>* __restrict__ U, Geom g, int par, T beta, uint32_t k0,
-                                               uint32_t k1, uint32_t step, Walk walk) {
-    const int tile = walk_tile(blockIdx.x, gridDim.x, walk);
-    const int h = tile * BS + threadIdx.x;
-    if (h >= g.Vh) return;
-    update_any<N, T, R, HB, MU, NT>(U, g, par, h, beta, k0, k1, step);
+                                               uint32_t k1, uint32_t step, Walk walk, int nblk) {
+    for (int r = 0; r < walk.spt; ++r) {
+        const int b = (int)blockIdx.x + r * (int)gridDim.x;
+        if (b >= nblk) break;
+        const int h = walk_tile(b, nblk, walk) * BS + threadIdx.x;
+        if (h < g.Vh) update_any<N, T, R, HB, MU, NT>(U, g, par, h, beta, k0, k1, step);
+    }
 }
 
 // ---------------------------------------------------------------------------
@@ -317,17 +322,23 @@ __device__ __forceinline__ int find_chain(const ChainDesc* __restrict__ d, int n
 }
 
 // Batched phase: tile0[TILE_HALF_HB / _OR] counts tiles of BS work-items.
+// Grid: ceil(tiles / spt) workgroups; workgroup b takes tiles b + r gridDim.x,
+// r < spt, in turn.
 template <int N, typename T, int R, bool HB, int MU, int BS>
 __global__ __launch_bounds__(BS) void k_update_batch(const ChainDesc* __restrict__ d, int n, int par,
-                                                     uint32_t step_offset, int xcd) {
-    const int tile = xcd ? xcd_tile(blockIdx.x, gridDim.x) : (int)blockIdx.x;
+                                                     uint32_t step_offset, int xcd, int tiles, int spt) {
     constexpr int KIND = HB ? TILE_HALF_HB : TILE_HALF_OR;
-    const int c = find_chain<KIND>(d, n, tile);
-    const Geom g = d[c].g;
-    const int h = (tile - d[c].tile0[KIND]) * BS + threadIdx.x;
-    if (h >= g.Vh || !((g.present >> MU) & 1)) return;
-    update_any<N, T, R, HB, MU, false>((T2<T>*)d[c].links, g, par, h, (T)d[c].beta, d[c].k0, d[c].k1,
-                                    (uint32_t)(d[c].step + step_offset));
+    for (int r = 0; r < spt; ++r) {
+        const int b = (int)blockIdx.x + r * (int)gridDim.x;
+        if (b >= tiles) break;
+        const int tile = xcd ? xcd_tile(b, tiles) : b;
+        const int c = find_chain<KIND>(d, n, tile);
+        const Geom g = d[c].g;
+        const int h = (tile - d[c].tile0[KIND]) * BS + threadIdx.x;
+        if (h < g.Vh && ((g.present >> MU) & 1))
+            update_any<N, T, R, HB, MU, false>((T2<T>*)d[c].links, g, par, h, (T)d[c].beta, d[c].k0, d[c].k1,
+                                               (uint32_t)(d[c].step + step_offset));
+    }
 }
 
 // Advances every chain's RNG step counter after a sweep of n_hb heatbath steps.

@@ -15,12 +15,15 @@ struct Shape {
     int xcd = 1;      // XCD-aware workgroup order
     int waves = 0;    // resident waves per CU (0 = no cap)
     int tblock = 0;   // time slices per block of the tile walk (0: linear)
+    int spt = 1;      // sites per work-item (1, 2 or 4): tiles a workgroup takes in turn
 };
+inline bool valid_spt(int s) { return s == 1 || s == 2 || s == 4; }
+inline int grid_for(int nblk, int spt) { return (nblk + spt - 1) / spt; }
 
 // The walk of a single lattice's phase for a shape; falls back to the linear
 // walk where the t-blocked one is not a permutation of the tiles.
 inline Walk walk_for(const Geom& g, const Shape& sh) {
-    Walk w{sh.xcd, 0, 1, 1, 0};
+    Walk w{sh.xcd, 0, 1, 1, 0, sh.spt};
     const long long plane_h = (long long)g.L[0] * g.L[1] / 2;
     if (sh.tblock > 1 && plane_h % sh.block == 0 && g.L[3] % sh.tblock == 0) {
         w.tb = sh.tblock;

@@ -14,12 +14,11 @@ struct OpsImpl {
     static void update_bs(const Ctx& c, int par, T beta, uint32_t k0, uint32_t k1, uint32_t step, int lds,
                           const Walk& w) {
         P* u = (P*)c.links;
+        const int nblk = half_blocks(c.g, BS), grid = grid_for(nblk, w.spt);
         if (c.nt)
-            k_update<N, T, R, HB, MU, BS, true><<<half_blocks(c.g, BS), BS, lds, c.stream>>>(u, c.g, par, beta, k0, k1,
-                                                                                             step, w);
+            k_update<N, T, R, HB, MU, BS, true><<<grid, BS, lds, c.stream>>>(u, c.g, par, beta, k0, k1, step, w, nblk);
         else
-            k_update<N, T, R, HB, MU, BS, false><<<half_blocks(c.g, BS), BS, lds, c.stream>>>(u, c.g, par, beta, k0,
-                                                                                              k1, step, w);
+            k_update<N, T, R, HB, MU, BS, false><<<grid, BS, lds, c.stream>>>(u, c.g, par, beta, k0, k1, step, w, nblk);
     }
 
     template <bool HB, int MU>
@@ -37,22 +36,23 @@ struct OpsImpl {
 
     template <bool HB, int BS>
     static void update_batch_bs(const ChainDesc* d, int n, int tiles, int mu, int par, uint32_t off, int xcd,
-                                int lds, hipStream_t s) {
+                                int spt, int lds, hipStream_t s) {
+        const int grid = grid_for(tiles, spt);
         switch (mu) {
-            case 0: k_update_batch<N, T, R, HB, 0, BS><<<tiles, BS, lds, s>>>(d, n, par, off, xcd); break;
-            case 1: k_update_batch<N, T, R, HB, 1, BS><<<tiles, BS, lds, s>>>(d, n, par, off, xcd); break;
-            case 2: k_update_batch<N, T, R, HB, 2, BS><<<tiles, BS, lds, s>>>(d, n, par, off, xcd); break;
-            default: k_update_batch<N, T, R, HB, 3, BS><<<tiles, BS, lds, s>>>(d, n, par, off, xcd); break;
+            case 0: k_update_batch<N, T, R, HB, 0, BS><<<grid, BS, lds, s>>>(d, n, par, off, xcd, tiles, spt); break;
+            case 1: k_update_batch<N, T, R, HB, 1, BS><<<grid, BS, lds, s>>>(d, n, par, off, xcd, tiles, spt); break;
+            case 2: k_update_batch<N, T, R, HB, 2, BS><<<grid, BS, lds, s>>>(d, n, par, off, xcd, tiles, spt); break;
+            default: k_update_batch<N, T, R, HB, 3, BS><<<grid, BS, lds, s>>>(d, n, par, off, xcd, tiles, spt); break;
         }
     }
 
     template <bool HB>
-    static void update_batch_kind(const ChainDesc* d, int n, int tiles, int mu, int par, uint32_t off, int block,
-                                  int xcd, int lds, hipStream_t s) {
-        switch (block) {
-            case 64: update_batch_bs<HB, 64>(d, n, tiles, mu, par, off, xcd, lds, s); break;
-            case 128: update_batch_bs<HB, 128>(d, n, tiles, mu, par, off, xcd, lds, s); break;
-            default: update_batch_bs<HB, 256>(d, n, tiles, mu, par, off, xcd, lds, s); break;
+    static void update_batch_kind(const ChainDesc* d, int n, int tiles, int mu, int par, uint32_t off,
+                                  const Shape& sh, int lds, hipStream_t s) {
+        switch (sh.block) {
+            case 64: update_batch_bs<HB, 64>(d, n, tiles, mu, par, off, sh.xcd, sh.spt, lds, s); break;
+            case 128: update_batch_bs<HB, 128>(d, n, tiles, mu, par, off, sh.xcd, sh.spt, lds, s); break;
+            default: update_batch_bs<HB, 256>(d, n, tiles, mu, par, off, sh.xcd, sh.spt, lds, s); break;
         }
     }
 
@@ -60,9 +60,9 @@ struct OpsImpl {
                              const Shape& sh, hipStream_t s) {
         const int lds = lds_for_wave_cap(sh.waves, sh.block);
         if (kind == 0)
-            update_batch_kind<true>(d, n, tiles, mu, par, off, sh.block, sh.xcd, lds, s);
+            update_batch_kind<true>(d, n, tiles, mu, par, off, sh, lds, s);
         else
-            update_batch_kind<false>(d, n, tiles, mu, par, off, sh.block, sh.xcd, lds, s);
+            update_batch_kind<false>(d, n, tiles, mu, par, off, sh, lds, s);
     }
 
     static void reunit_batch(const ChainDesc* d, int n, int tiles, hipStream_t s) {

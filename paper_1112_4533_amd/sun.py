@@ -69,6 +69,9 @@ def load():
         "sun_get_launch": [vp, c_int, ctypes.POINTER(c_int), ctypes.POINTER(c_int), ctypes.POINTER(c_int),
                            ctypes.POINTER(c_int)],
         "sun_batch_set_launch": [vp, c_int, c_int, c_int, c_int],
+        "sun_set_sites_per_item": [vp, c_int, c_int],
+        "sun_get_sites_per_item": [vp, c_int, ctypes.POINTER(c_int)],
+        "sun_batch_set_sites_per_item": [vp, c_int, c_int],
     }
     for name, args in sigs.items():
         f = getattr(L, name)
@@ -93,7 +96,8 @@ def exported_symbols():
                         "sun_profile", "sun_profile_read", "sun_sample_su2", "sun_last_error",
                         "sun_batch_bytes", "sun_batch_create", "sun_batch_sweep", "sun_batch_plaquette",
                         "sun_batch_capture", "sun_batch_replay", "sun_batch_sync", "sun_batch_destroy",
-                        "sun_set_launch", "sun_get_launch", "sun_batch_set_launch")
+                        "sun_set_launch", "sun_get_launch", "sun_batch_set_launch", "sun_set_sites_per_item",
+                        "sun_get_sites_per_item", "sun_batch_set_sites_per_item")
             if hasattr(L, n)]
 
 
@@ -251,6 +255,18 @@ class Lattice:
         """(heatbath shape, overrelaxation shape)."""
         return self.get_launch(HEATBATH), self.get_launch(OVERRELAX)
 
+    SITES_PER_ITEM = (1, 2, 4)
+
+    def set_sites_per_item(self, spt, kind=-1):
+        """Sites each work-item of the phase kernels updates in turn (1, 2
+        or 4), for kind 0, 1 or both (-1)."""
+        _check(load().sun_set_sites_per_item(self._h, int(kind), int(spt)))
+
+    def get_sites_per_item(self, kind):
+        v = ctypes.c_int()
+        _check(load().sun_get_sites_per_item(self._h, int(kind), ctypes.byref(v)))
+        return v.value
+
     # -- event timing ----------------------------------------------------
     def profile(self, enable=True, every=1):
         """Starts (or with enable=False stops) event timing of one launch in
@@ -292,6 +308,7 @@ class Batch:
         self.betas = [float(x) for x in betas]
         self.seeds = [int(x) for x in seeds]
         self.launch = [(256, 1, 0), (256, 1, 0)]    # heatbath, overrelaxation (block, xcd, waves)
+        self.sites_per_item = [1, 1]
         self.stream = torch.cuda.Stream(device=dev)   # graphs need a non-null stream
 
     def __del__(self):
@@ -333,6 +350,13 @@ class Batch:
         _check(load().sun_batch_set_launch(self._h, int(kind), int(block), int(xcd), int(waves)))
         for k in ((HEATBATH, OVERRELAX) if kind < 0 else (kind,)):
             self.launch[k] = (int(block), int(xcd), int(waves))
+
+    def set_sites_per_item(self, spt, kind=-1):
+        """Sites per work-item of the phase kernels (as Lattice); drops a
+        captured graph."""
+        _check(load().sun_batch_set_sites_per_item(self._h, int(kind), int(spt)))
+        for k in ((HEATBATH, OVERRELAX) if kind < 0 else (kind,)):
+            self.sites_per_item[k] = int(spt)
 
 
 def sample_su2(alpha, seed, step=0, mu_sg=0, dtype="f64"):

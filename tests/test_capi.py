@@ -113,6 +113,19 @@ def test_create_validates_buffers_without_touching_them(lib):
     assert lib.sun_set_launch(h, -1, 128, 1, 8, 0) == 0
     assert get(0) == (0, 128, 1, 8, 0) and get(1) == (0, 128, 1, 8, 0)
     assert lib.sun_get_launch(h, 0, None, None, None, None) == -1
+    # sites per work-item: 1, 2 or 4 per kind, kept by sun_set_launch
+    s = ctypes.c_int()
+    assert lib.sun_get_sites_per_item(h, 0, ctypes.byref(s)) == 0 and s.value == 1
+    assert lib.sun_set_sites_per_item(h, -1, 3) == -1
+    assert lib.sun_set_sites_per_item(h, 2, 2) == -1
+    assert lib.sun_set_sites_per_item(None, -1, 2) == -1
+    assert lib.sun_set_sites_per_item(h, 1, 4) == 0
+    assert lib.sun_get_sites_per_item(h, 1, ctypes.byref(s)) == 0 and s.value == 4
+    assert lib.sun_get_sites_per_item(h, 0, ctypes.byref(s)) == 0 and s.value == 1
+    assert lib.sun_set_launch(h, -1, 128, 1, 8, 0) == 0
+    assert lib.sun_get_sites_per_item(h, 1, ctypes.byref(s)) == 0 and s.value == 4
+    assert lib.sun_get_sites_per_item(h, 1, None) == -1
+    assert lib.sun_set_sites_per_item(h, -1, 1) == 0
     # a 4^4 plane holds 8 checkerboard sites: no whole workgroup, linear walk
     assert lib.sun_set_launch(h, -1, 64, 1, 0, 4) == 0
     assert get(1) == (0, 64, 1, 0, 0)

@@ -489,6 +489,18 @@ def test_every_launch_shape_gives_the_same_bits(gpu, nc, dtype):
             ref = lat.links.clone()
         else:
             assert torch.equal(ref, lat.links), shape
+    # several sites per work-item: a workgroup takes 2 or 4 tiles of its walk
+    for shape in [(256, 1, 12, 4), (64, 0, 0, 4), (128, 1, 16, 0)]:
+        for spt in (2, 4):
+            lat = gpu_lattice(sun, nc, L, dtype, hot=True, seed=8)
+            lat.set_launch(*shape)
+            lat.set_sites_per_item(spt)
+            lat.set_launch(*shape)   # keeps the sites per work-item
+            assert lat.get_sites_per_item(0) == lat.get_sites_per_item(1) == spt
+            lat.sweep(BETA[nc], 1, 2, seed=8)
+            lat.sweep(BETA[nc], 1, 2, seed=8)
+            torch.cuda.synchronize()
+            assert torch.equal(ref, lat.links), (shape, spt)
 
 
 def test_batch_launch_shapes_and_tuner(gpu, tmp_path, monkeypatch):
@@ -500,12 +512,15 @@ def test_batch_launch_shapes_and_tuner(gpu, tmp_path, monkeypatch):
     rb = sun.Batch(ref, [c[3] for c in spec], [c[4] for c in spec])
     rb.sweep(1, 2)
     rb.sweep(1, 2)
-    for hb, orx in [((64, 0, 0), (128, 1, 12)), ((256, 1, 16), (64, 1, 8)), ((128, 0, 8), (256, 0, 0))]:
-        shape = (hb, orx)
+    for hb, orx, spt in [((64, 0, 0), (128, 1, 12), (1, 1)), ((256, 1, 16), (64, 1, 8), (2, 4)),
+                         ((128, 0, 8), (256, 0, 0), (4, 2))]:
+        shape = (hb, orx, spt)
         lats = [gpu_lattice(sun, nc, L, dt, hot=True, seed=sd) for nc, L, dt, b, sd in spec]
         bt = sun.Batch(lats, [c[3] for c in spec], [c[4] for c in spec])
         bt.set_launch(*hb, kind=0)
         bt.set_launch(*orx, kind=1)
+        bt.set_sites_per_item(spt[0], kind=0)
+        bt.set_sites_per_item(spt[1], kind=1)
         bt.sweep(1, 2)
         bt.capture(n_sweeps=1, n_hb=1, n_or=2)
         bt.replay()
@@ -523,6 +538,8 @@ def test_batch_launch_shapes_and_tuner(gpu, tmp_path, monkeypatch):
     before = lat.links.clone()
     best, times = autotune.tune_lattice(lat, reps=1)
     assert lat.launch == (best[0], best[1])
+    assert all(lat.get_sites_per_item(k) in sun.Lattice.SITES_PER_ITEM for k in (0, 1))
+    assert len(times["overrelax_sites_per_item"]) == len(sun.Lattice.SITES_PER_ITEM)
     assert all(tuple(map(int, k.split("/"))) in sun.Lattice.LAUNCH_SHAPES for k in times["overrelax"])
     assert torch.equal(before, lat.links)
     # a second call comes from the cache
