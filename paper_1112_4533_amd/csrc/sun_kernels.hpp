@@ -794,43 +794,54 @@ __global__ __launch_bounds__(kBlock) void k_polyakov(const T2<T>* __restrict__ U
     const bool live = xs < Vs;
     Mat<N, double> P;
     set_identity(P);
-    if (live) {
-        const int t0 = seg * g.L[3] / S, t1 = (seg + 1) * g.L[3] / S;
-        for (int t = t0; t < t1; ++t) {
-            const int s = xs + t * Vs;
-            Site st;
-            int r = s;
+    const int t0 = seg * g.L[3] / S, t1 = (seg + 1) * g.L[3] / S;
+    // link U_3 at time t of this spatial site
+    auto time_link = [&](int t) {
+        const int s = xs + t * Vs;
+        Site st;
+        int r = s;
 #pragma unroll
-            for (int m = 0; m < 4; ++m) {
-                const int q = r / g.L[m];
-                st.x[m] = r - q * g.L[m];
-                r = q;
-            }
-            st.s = s;
-            P = mul_nn(P, load_link_f64<N, T, R>(U, 3, parity_of(st), s >> 1, g.Vh));
+        for (int m = 0; m < 4; ++m) {
+            const int q = r / g.L[m];
+            st.x[m] = r - q * g.L[m];
+            r = q;
         }
+        st.s = s;
+        return load_link_f64<N, T, R>(U, 3, parity_of(st), s >> 1, g.Vh);
+    };
+    if (live && t1 > t0) {
+        // the stretch's product, starting from its first link
+        P = time_link(t0);
+        for (int t = t0 + 1; t < t1; ++t) P = mul_nn(P, time_link(t));
     }
     double tr[2] = {0.0, 0.0};
     if constexpr (S > 1) {
+        // ordered product of the S stretches as a tree: at level w, stretch
+        // seg (a multiple of 2w) takes the product of seg + w on its right
         __shared__ double part[S][2 * N * N][SITES];
-        if (seg > 0) {
 SUN_MAT_UNROLL
-            for (int e = 0; e < N * N; ++e) {
-                part[seg][2 * e][j] = P.re[e / N][e % N];
-                part[seg][2 * e + 1][j] = P.im[e / N][e % N];
-            }
+        for (int e = 0; e < N * N; ++e) {
+            part[seg][2 * e][j] = P.re[e / N][e % N];
+            part[seg][2 * e + 1][j] = P.im[e / N][e % N];
         }
         __syncthreads();
-        if (seg == 0 && live) {
-            for (int k = 1; k < S; ++k) {
+#pragma unroll
+        for (int w = 1; w < S; w *= 2) {
+            if (seg % (2 * w) == 0 && live) {
                 Mat<N, double> Q;
 SUN_MAT_UNROLL
                 for (int e = 0; e < N * N; ++e) {
-                    Q.re[e / N][e % N] = part[k][2 * e][j];
-                    Q.im[e / N][e % N] = part[k][2 * e + 1][j];
+                    Q.re[e / N][e % N] = part[seg + w][2 * e][j];
+                    Q.im[e / N][e % N] = part[seg + w][2 * e + 1][j];
                 }
                 P = mul_nn(P, Q);
+SUN_MAT_UNROLL
+                for (int e = 0; e < N * N; ++e) {
+                    part[seg][2 * e][j] = P.re[e / N][e % N];
+                    part[seg][2 * e + 1][j] = P.im[e / N][e % N];
+                }
             }
+            __syncthreads();
         }
     }
     if (seg == 0 && live) {
