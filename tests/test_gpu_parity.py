@@ -333,9 +333,10 @@ def test_2d_su2_exact_plaquette_on_gpu(gpu):
 
 
 # ---------------------------------------------------------------------------
-# Full size, launch configuration of the benchmark (SU(3) 32^4 FP32)
+# Full size, launch configuration of the benchmark (SU(3) 32^4; FP32 two-row
+# is the headline, FP32 18-real and FP64 the precision comparison)
 # ---------------------------------------------------------------------------
-@pytest.mark.parametrize("dtype", ["f32", "f32r12"])
+@pytest.mark.parametrize("dtype", ["f32", "f32r12", "f64"])
 def test_full_size_su3_32_phase_parity(gpu, dtype):
     nc, L, beta = 3, (32, 32, 32, 32), 6.2
     lat = gpu_lattice(gpu, nc, L, dtype, hot=True, seed=1234)
