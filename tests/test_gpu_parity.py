@@ -107,6 +107,27 @@ def test_observables_parity(gpu, nc, dtype):
     np.testing.assert_allclose(ug, uo, rtol=1e-6, atol=1e-15)
 
 
+@pytest.mark.parametrize("nc,dtype,L", [
+    (3, "f32r12", (4, 4, 4, 2)),    # fewer time slices than stretches: most stretches empty
+    (3, "f64", (4, 4, 2, 12)),      # stretches of one and two links
+    (2, "f32", (2, 2, 4, 10)),
+    (4, "f64", (2, 4, 2, 18)),      # four stretches for SU(4), lengths 4 and 5
+    (3, "f32", (4, 4, 4, 1)),       # no time direction: the loop is the identity
+    (6, "f32", (2, 2, 2, 6)),       # one work-item per site (large Nc)
+])
+def test_polyakov_every_time_extent(gpu, nc, dtype, L):
+    """The product along t is split into stretches combined as an ordered
+    tree; every extent, including ones shorter than the stretch count, must
+    give the ordered product of the oracle."""
+    lat = gpu_lattice(gpu, nc, L, dtype, hot=True, seed=99)
+    U = to_np(lat.export())
+    pg = to_np(lat.polyakov())
+    po = O.polyakov(U, nc, L)
+    assert abs(complex(pg[0], pg[1]) - po) < 1e-12, (complex(pg[0], pg[1]), po)
+    if L[3] == 1:
+        assert abs(po - 1.0) < 1e-12
+
+
 @pytest.mark.parametrize("nc", [2, 3, 4, 6, 8])
 def test_reunitarize_parity(gpu, nc):
     L = (4, 4, 4, 4)
