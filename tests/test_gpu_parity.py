@@ -51,6 +51,25 @@ def test_sampler_parity(gpu, dtype):
         assert bad.sum() <= 5
 
 
+@pytest.mark.parametrize("dtype", ["f64", "f32"])
+def test_sampler_parity_large_alpha(gpu, dtype):
+    # the couplings of the large-Nc runs (beta ~ Nc^2) reach the hundreds
+    sun = gpu
+    alpha = np.geomspace(60.0, 5000.0, 8192)
+    xg, ag = sun.sample_su2(torch.from_numpy(alpha).cuda(), seed=77, step=3, mu_sg=(1 << 16) | 5, dtype=dtype)
+    xg, ag = to_np(xg), to_np(ag)
+    xo, ao, margin = O.sample_su2(alpha, seed=77, step=3, mu_sg=(1 << 16) | 5)
+    d = np.abs(xg - xo).max(axis=1)
+    bad = (d > TOL[dtype]) | (ag != ao)
+    if dtype == "f64":
+        assert not bad.any(), d.max()
+    else:
+        assert np.all(margin[bad] < FLIP_MARGIN)
+        assert bad.sum() <= 5
+    assert np.all(ag > 0)                        # no draw runs out of attempts
+    assert np.all(np.abs(np.linalg.norm(xg, axis=1) - 1) < 1e-5)
+
+
 def test_sampler_empty_input(gpu):
     x, a = gpu.sample_su2(torch.zeros(0, dtype=torch.float64, device="cuda"), seed=1)
     assert x.shape == (0, 4) and a.shape == (0,)
@@ -468,6 +487,25 @@ def test_batch_is_bitwise_the_chains_alone(gpu):
         assert torch.equal(a.links, b.links), f"chain {i} differs"
         assert a.step == b.step == 5
         assert torch.equal(a.plaquette(), plaq[i]), f"plaquette of chain {i}"
+
+
+@pytest.mark.parametrize("nc,L,dt", [(3, (6, 4, 2, 4), "f32r12"), (2, (4, 2, 2, 6), "f64")])
+def test_one_chain_batch_is_the_chain_alone(gpu, nc, L, dt):
+    """The degenerate batch: one chain, ragged extents (V/2 not a multiple
+    of the workgroup size)."""
+    sun = gpu
+    beta, sd = BETA[nc], 4321
+    alone = gpu_lattice(sun, nc, L, dt, hot=True, seed=sd)
+    batched = gpu_lattice(sun, nc, L, dt, hot=True, seed=sd)
+    for _ in range(3):
+        alone.sweep(beta, 1, 3, seed=sd)
+    bt = sun.Batch([batched], [beta], [sd])
+    for _ in range(3):
+        bt.sweep(1, 3)
+    bt.sync()
+    assert torch.equal(alone.links, batched.links)
+    assert alone.step == batched.step == 3
+    assert torch.equal(alone.plaquette(), bt.plaquette()[0])
 
 
 def test_batch_eager_and_graph_agree_over_many_replays(gpu):
