@@ -52,7 +52,7 @@ def test_wide_roundtrip(gpu, nc, dtype):
     assert np.array_equal(to_np(lat.export()), rounded(U, dtype))
 
 
-@pytest.mark.parametrize("nc,dtype", [(4, "f64w"), (9, "f64"), (9, "f32"), (16, "f64")])
+@pytest.mark.parametrize("nc,dtype", [(4, "f64w"), (9, "f64"), (9, "f32"), (13, "f64"), (16, "f64"), (32, "f32")])
 def test_wide_observables_parity(gpu, nc, dtype):
     L = (4, 2, 2, 4)
     lat = gpu_lattice(gpu, nc, L, dtype, field=thermal_field(nc, L, beta_for(nc), sweeps=1))
@@ -63,7 +63,7 @@ def test_wide_observables_parity(gpu, nc, dtype):
     np.testing.assert_allclose(to_np(lat.unitarity()), O.unitarity(U, nc, L), rtol=1e-6, atol=1e-14)
 
 
-@pytest.mark.parametrize("nc", [4, 9, 16])
+@pytest.mark.parametrize("nc", [4, 9, 16, 32])
 def test_wide_reunitarize_parity(gpu, nc):
     L = (4, 2, 2, 2)
     rng = np.random.default_rng(nc)
