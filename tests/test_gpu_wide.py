@@ -180,11 +180,11 @@ def test_wide_rejected_by_batches(gpu):
         sun.Batch([lat], [6.0], [1])
 
 
-@pytest.mark.parametrize("nc,dtype,L", [(5, "f64", (4, 4, 1, 4)), (9, "f32", (4, 2, 4, 1))])
+@pytest.mark.parametrize("nc,dtype,L", [(5, "f64", (4, 4, 1, 4)), (9, "f32", (4, 2, 4, 1)), (6, "f64", (4, 1, 4, 1))])
 def test_wide_absent_direction(gpu, nc, dtype, L):
-    """3D lattices: links of the absent direction stay the identity, the
-    staple has four terms, and the observables normalise over the planes
-    that exist."""
+    """3D and 2D lattices: links of an absent direction stay the identity,
+    the staple has 2(d-1) terms, and the observables normalise over the
+    planes that exist."""
     beta = beta_for(nc)
     base = O.new_field(nc, L, hot=True, seed=31)
     lat = gpu_lattice(gpu, nc, L, dtype, field=base)
