@@ -76,3 +76,14 @@ def test_stored_traffic_follows_the_kernel_sources(bench, tmp_path, monkeypatch)
     assert bench.stored_traffic("other") is None
     monkeypatch.setattr(bench, "kernel_source_hash", lambda: "0" * 16)   # the kernels changed
     assert bench.stored_traffic("w") is None
+
+
+def test_cpu_baseline_fields(bench):
+    # the oracle leg on a tiny lattice: the same fields as the 32^4 sample
+    from paper_1112_4533_amd.workloads import Run
+    run = Run("su3_4^4_hot_f32", 3, (4, 4, 4, 4), 6.2, True, "f32", 1, 4, 1)
+    cb = bench.run_cpu_baseline(run, 1)
+    assert cb["kind"] == "oracle" and cb["unit"] == "link_updates/s"
+    assert cb["value"] > 0 and cb["cores"] >= 1
+    assert "1 sweeps" in cb["sample"] and f"{5 * 4 * 4 ** 4} link updates" in cb["sample"]
+    json.dumps(cb)
