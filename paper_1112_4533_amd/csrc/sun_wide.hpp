@@ -566,29 +566,53 @@ __device__ __forceinline__ void lds_unitarity(const double2* M, double2* D, int 
 __device__ __forceinline__ void lds_reunit(double2* M, double2* D, int n) {
     const int lane = threadIdx.x;
     const bool own = lane < n;
+    // n <= 32.  Above n = 8 the two halves of the wavefront share each sum,
+    // lane q and lane q + 32 taking half of its terms each (below, the
+    // exchange costs more than it saves and the lower half does it all).
+    const bool split = n > 8;
+    const int q = lane & 31, half = lane >> 5;
+    const int m0 = split ? n / 2 : n;                    // columns of the lower half
+    const int cbeg = half ? m0 : 0, clen = half ? n - m0 : m0;
     double2* P = D;
     for (int i = 0; i < n; ++i) {
         for (int pass = 0; pass < 2 && i > 0; ++pass) {
-            if (lane < i) {
-                double pr = 0.0, pi = 0.0;  // <r_lane, r_i>, columns taken from a
-                int c = lane % n;            // lane-dependent start: no bank conflicts
+            // p_q = <r_q, r_i> for q < i; columns taken from a lane-dependent
+            // start within the half's range, so lanes hit different banks
+            double pr = 0.0, pi = 0.0;
+            if (q < i && clen > 0) {
+                int t = q % clen;
 #pragma unroll 4
-                for (int t = 0; t < n; ++t) {
-                    const double2 a = M[lane * n + c], b = M[i * n + c];
+                for (int u = 0; u < clen; ++u) {
+                    const int c = cbeg + t;
+                    const double2 a = M[q * n + c], b = M[i * n + c];
                     cmac(pr, pi, a.x, -a.y, b.x, b.y);
-                    c = (c + 1 == n) ? 0 : c + 1;
+                    t = (t + 1 == clen) ? 0 : t + 1;
                 }
-                P[lane] = make_double2(pr, pi);
             }
+            if (split) {
+                pr += __shfl_xor(pr, 32, kLanes);
+                pi += __shfl_xor(pi, 32, kLanes);
+            }
+            if (q < i && half == 0) P[q] = make_double2(pr, pi);
             wave_lds_order();
-            if (own) {
-                double2 b = M[i * n + lane];
+            // r_i -= sum_{k < i} p_k r_k, the k range split between the halves
+            double sr = 0.0, si = 0.0;
+            if (q < n) {
+                const int kmid = split ? i / 2 : i;
+                const int kb = half ? kmid : 0, ke = half ? i : kmid;
 #pragma unroll 4
-                for (int k = 0; k < i; ++k) {
-                    const double2 p = P[k], a = M[k * n + lane];
-                    cmac(b.x, b.y, -p.x, -p.y, a.x, a.y);
+                for (int k = kb; k < ke; ++k) {
+                    const double2 p = P[k], a = M[k * n + q];
+                    cmac(sr, si, p.x, p.y, a.x, a.y);
                 }
-                M[i * n + lane] = b;
+            }
+            if (split) {
+                sr += __shfl_xor(sr, 32, kLanes);
+                si += __shfl_xor(si, 32, kLanes);
+            }
+            if (own) {
+                const double2 b = M[i * n + lane];
+                M[i * n + lane] = make_double2(b.x - sr, b.y - si);
             }
             wave_lds_order();
         }
