@@ -520,16 +520,23 @@ __device__ __forceinline__ void lds_det(double2* D, int n, double& dr, double& d
         dr = nr;
         di = ni;
         const double inv = 1.0 / (pr * pr + pi * pi);
-        for (int r = col + 1; r < n; ++r) {
+        // rows below the pivot are independent: above n = 8 the lower half
+        // of the wavefront eliminates rows col + 1, col + 3, ... and the upper
+        // half rows col + 2, col + 4, ..., lane q taking column q (n <= 32);
+        // every entry sees the same operations in the same order either way
+        const bool split = n > 8;
+        const int q = c & 31, half = c >> 5;
+        const bool works = (split || half == 0) && q >= col && q < n;
+        for (int r = col + 1 + (split ? half : 0); r < n; r += split ? 2 : 1) {
             const double2 m = D[r * n + col];
             const double fr = (m.x * pr + m.y * pi) * inv;
             const double fi = (m.y * pr - m.x * pi) * inv;
-            if (c >= col && c < n) {
-                const double2 u = D[col * n + c];
-                double2 w = D[r * n + c];
+            if (works) {
+                const double2 u = D[col * n + q];
+                double2 w = D[r * n + q];
                 w.x -= fr * u.x - fi * u.y;
                 w.y -= fr * u.y + fi * u.x;
-                D[r * n + c] = w;
+                D[r * n + q] = w;
             }
         }
     }
