@@ -202,3 +202,26 @@ def test_wide_absent_direction(gpu, nc, dtype, L):
     np.testing.assert_allclose(to_np(lat.plaquette()), O.plaquette(U, nc, L), rtol=1e-13, atol=1e-15)
     pg = to_np(lat.polyakov())
     assert abs(complex(pg[0], pg[1]) - O.polyakov(U, nc, L)) < 1e-13
+
+
+@pytest.mark.parametrize("nc", [6, 12, 32])
+def test_wide_permutation_links_need_pivoting(gpu, nc):
+    """Links that are permutation matrices times phases: every column of the
+    LU elimination has a single nonzero below the pivot row, so the
+    determinant depends on the row exchanges (and on the first largest pivot
+    among zeros).  Re-unitarization and the unitarity report must match the
+    oracle."""
+    L = (4, 2, 2, 2)
+    rng = np.random.default_rng(nc)
+    V = int(np.prod(L))
+    U = np.zeros((4, V, nc, nc), dtype=np.complex128)
+    for mu in range(4):
+        for s in range(V):
+            perm = rng.permutation(nc)
+            U[mu, s, np.arange(nc), perm] = np.exp(1j * rng.uniform(-np.pi, np.pi, nc))
+    lat = gpu_lattice(gpu, nc, L, "f64", field=U)
+    np.testing.assert_allclose(to_np(lat.unitarity()), O.unitarity(U, nc, L), rtol=1e-10, atol=1e-14)
+    lat.reunitarize()
+    O.reunitarize(U, nc, L)
+    assert np.abs(to_np(lat.export()) - U).max() < 1e-13
+    assert to_np(lat.unitarity()).max() < 1e-13
