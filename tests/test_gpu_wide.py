@@ -204,13 +204,14 @@ def test_wide_absent_direction(gpu, nc, dtype, L):
     assert abs(complex(pg[0], pg[1]) - O.polyakov(U, nc, L)) < 1e-13
 
 
-@pytest.mark.parametrize("nc", [6, 12, 32])
-def test_wide_permutation_links_need_pivoting(gpu, nc):
+@pytest.mark.parametrize("nc,dtype", [(4, "f64"), (4, "f64w"), (6, "f64"), (12, "f64"), (32, "f64")])
+def test_wide_permutation_links_need_pivoting(gpu, nc, dtype):
     """Links that are permutation matrices times phases: every column of the
     LU elimination has a single nonzero below the pivot row, so the
     determinant depends on the row exchanges (and on the first largest pivot
     among zeros).  Re-unitarization and the unitarity report must match the
-    oracle."""
+    oracle (SU(4) also on the register path, whose determinant pivots the
+    same way)."""
     L = (4, 2, 2, 2)
     rng = np.random.default_rng(nc)
     V = int(np.prod(L))
@@ -219,7 +220,7 @@ def test_wide_permutation_links_need_pivoting(gpu, nc):
         for s in range(V):
             perm = rng.permutation(nc)
             U[mu, s, np.arange(nc), perm] = np.exp(1j * rng.uniform(-np.pi, np.pi, nc))
-    lat = gpu_lattice(gpu, nc, L, "f64", field=U)
+    lat = gpu_lattice(gpu, nc, L, dtype, field=U)
     np.testing.assert_allclose(to_np(lat.unitarity()), O.unitarity(U, nc, L), rtol=1e-10, atol=1e-14)
     lat.reunitarize()
     O.reunitarize(U, nc, L)
