@@ -113,3 +113,43 @@ def test_2d_su8_one_link_plaquette():
     exact = one_link_plaquette(nc, beta)
     assert abs(m - exact) < 4 * e, (m, e, exact)
     assert e < 0.004
+
+
+def _perm_sign(perm):
+    """Sign of a permutation from its cycle decomposition."""
+    seen, sign = np.zeros(len(perm), dtype=bool), 1
+    for i in range(len(perm)):
+        if not seen[i]:
+            j, length = i, 0
+            while not seen[j]:
+                seen[j] = True
+                j = perm[j]
+                length += 1
+            sign *= -1 if length % 2 == 0 else 1
+    return sign
+
+
+@pytest.mark.parametrize("nc", [4, 7, 12])
+def test_determinant_of_phased_permutations(nc):
+    """Links P D (a permutation matrix times unit phases) have the closed-form
+    determinant sign(P) prod(phases), reached by the LU elimination only
+    through its row exchanges; re-unitarization keeps the rows and multiplies
+    the last one by the conjugate of that determinant."""
+    L = (2, 2, 2, 2)
+    rng = np.random.default_rng(5 + nc)
+    V = int(np.prod(L))
+    U = np.zeros((4, V, nc, nc), dtype=np.complex128)
+    dets = np.zeros((4, V), dtype=np.complex128)
+    for mu in range(4):
+        for s in range(V):
+            perm = rng.permutation(nc)
+            ph = np.exp(1j * rng.uniform(-np.pi, np.pi, nc))
+            U[mu, s, np.arange(nc), perm] = ph
+            dets[mu, s] = _perm_sign(perm) * np.prod(ph)
+    dev = O.unitarity(U, nc, L)
+    assert dev[0] < 1e-15
+    assert abs(dev[1] - np.abs(dets - 1).max()) < 1e-13
+    want = U.copy()
+    want[:, :, nc - 1, :] *= np.conj(dets)[:, :, None]
+    O.reunitarize(U, nc, L)
+    assert np.abs(U - want).max() < 1e-14
