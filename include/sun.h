@@ -46,7 +46,8 @@ enum {
     SUN_EINVAL = -1, /* bad Nc, extent, dtype, direction, parity or count */
     SUN_ESIZE = -2,  /* null or undersized buffer */
     SUN_EHIP = -3,   /* a HIP runtime error (text in sun_last_error) */
-    SUN_EUNSUP = -4  /* valid request this build does not implement */
+    SUN_EUNSUP = -4, /* valid request this build does not implement */
+    SUN_ENUMERIC = -5 /* the watchdog found a non-finite or non-unitary field */
 };
 
 /* Link storage.  Reductions, re-unitarization and the start configuration
@@ -137,6 +138,30 @@ int sun_polyakov(sun_lattice_t h, double *dev_out2, sun_stream_t stream);
  * max |det U - 1|} over present links. */
 int sun_unitarity(sun_lattice_t h, double *dev_out2, sun_stream_t stream);
 
+/* Watchdog (failure detection; not in the paper, whose runs assume a healthy
+ * field).  threshold > 0 arms a check in every later re-unitarization on this
+ * handle (sun_reunitarize, and sun_sweep with reunit != 0): from the field
+ * before the projection it takes max_ij |(U^dag U - 1)_ij| and
+ * max |det U - 1| over the present links in FP64 -- the numbers the
+ * re-unitarization's drift report gives -- and counts the check as tripped
+ * when either exceeds threshold; a NaN or infinite entry counts as an
+ * infinite deviation.  No extra pass over the field is made.  The state lives
+ * in the scratch buffer, on the device, and nothing synchronizes until
+ * sun_check.  threshold = 0 disarms the check.  Every call clears the state
+ * (a kernel on stream).  SUN_EINVAL for a negative, infinite or NaN
+ * threshold.  Typical thresholds: ~1e-4 for FP32 storage, whose drift between
+ * re-unitarizations is ~1e-6..1e-5; ~1e-10 for FP64.  Batch sweeps do not run
+ * the check. */
+int sun_watchdog(sun_lattice_t h, double threshold, sun_stream_t stream);
+
+/* Waits for the work queued on stream and reads the watchdog state:
+ * SUN_ENUMERIC if any check since sun_watchdog tripped (the message gives
+ * the number of tripped checks and the largest deviation), SUN_OK otherwise;
+ * *deviation (if not NULL) receives the largest deviation a tripped check saw
+ * (0 if none).  SUN_EINVAL if sun_watchdog was never called on the handle.
+ * Synchronous. */
+int sun_check(sun_lattice_t h, double *deviation, sun_stream_t stream);
+
 /* Field in the canonical layout: 4*V*Nc*Nc complex FP64 values, indexed
  * [mu][s][i][j], (re, im) interleaved, on the device.  Import of Nc = 2 reads
  * row 0 of each matrix (an SU(2) matrix is fixed by it). */
@@ -181,6 +206,10 @@ int sun_get_sites_per_item(sun_lattice_t h, int kind, int *spt);
  * the 8 phases of an update step samples all directions and parities);
  * every = 0 stops recording.  An event pair costs a few microseconds of
  * stream time, so sampling keeps timed runs close to unprofiled ones.
+ * every = -1 brackets runs instead: the heatbath phases of a sun_sweep, and
+ * its overrelaxation phases, are each one run of back-to-back launches timed
+ * by one event pair (the time includes the gaps between those launches, and
+ * no bracket slows a launch); every other call is a run of one launch.
  * sun_profile_read synchronizes the recorded events and returns the summed
  * milliseconds and the number of launches recorded. */
 int sun_profile(sun_lattice_t h, int every);

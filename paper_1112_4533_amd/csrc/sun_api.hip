@@ -13,31 +13,13 @@
 #include <vector>
 
 #include "sun.h"
+#include "sun_host.hpp"
 #include "sun_kernels.hpp"
 #include "sun_ops.hpp"
 
+using namespace sun_host;
+
 namespace {
-
-thread_local std::string g_last_error;
-
-int fail(int code, const char* fmt, ...) __attribute__((format(printf, 2, 3)));
-int fail(int code, const char* fmt, ...) {
-    char buf[512];
-    va_list ap;
-    va_start(ap, fmt);
-    vsnprintf(buf, sizeof buf, fmt, ap);
-    va_end(ap);
-    g_last_error = buf;
-    return code;
-}
-
-int hip_check(hipError_t e, const char* what) {
-    if (e == hipSuccess) return SUN_OK;
-    return fail(SUN_EHIP, "%s: %s", what, hipGetErrorString(e));
-}
-
-// Any launch error of the kernels just queued.
-int launch_check(const char* what) { return hip_check(hipGetLastError(), what); }
 
 constexpr int kKernels = 5;  // heatbath, overrelaxation, reunit, plaquette, polyakov
 
@@ -54,10 +36,13 @@ struct sun_lattice_s {
     // event timing
     bool profiling = false;
     int profile_every = 1;           // record one launch in this many per kernel kind
+    bool profile_runs = false;       // bracket runs of consecutive launches of one kind instead
+    bool in_run = false;             // a run bracket is open: launches are not bracketed singly
     int64_t seen[kKernels] = {};     // launches issued since profiling started
     struct Pending {
         int kernel;
         hipEvent_t a, b;
+        int count;                   // launches between the two events
     };
     std::vector<Pending> pending;
     std::vector<hipEvent_t> pool;
@@ -69,6 +54,12 @@ struct sun_lattice_s {
 
     size_t link_bytes = 0;
     uint64_t phases_run = 0;  // alternates the walk direction of successive phases
+    // watchdog (sun_watchdog): threshold > 0 arms a check in every
+    // re-unitarization; its state (3 doubles) sits in the last 256 bytes of
+    // the scratch buffer
+    double watch_threshold = 0.0;
+    double* watch_state = nullptr;
+    bool watch_reset = false;  // the state has been cleared by sun_watchdog
     sun::Ctx ctx(hipStream_t s) const {
         return sun::Ctx{links, g, s, {shape[0], shape[1]}, nc, link_bytes > sun::kPlainAccessMaxBytes ? 1 : 0, 0};
     }
@@ -76,78 +67,25 @@ struct sun_lattice_s {
 
 namespace {
 
-// dtype bit 0: FP64 storage; bit 1: SU(3) two-row storage; bit 2: the
-// workgroup-per-link path (also taken by every Nc above the register path's).
-inline int is_f64(int dtype) { return dtype & 1; }
-inline int is_two_row(int dtype) { return (dtype >> 1) & 1; }
-inline bool is_wide(int nc, int dtype) { return ((dtype >> 2) & 1) || nc > SUN_NC_MAX_REGISTER; }
-
-const sun::Ops* ops_for(int nc, int dtype) {
-    const int f64 = is_f64(dtype);
-    if (is_wide(nc, dtype)) return sun::ops_wide(f64);
-    if (is_two_row(dtype)) return nc == 3 ? sun::ops_nc3_two_row(f64) : nullptr;
-    switch (nc) {
-        case 2: return sun::ops_nc2(f64);
-        case 3: return sun::ops_nc3(f64);
-        case 4: return sun::ops_nc4(f64);
-        default: return nullptr;
-    }
-}
-
-int check_lattice(int nc, const int L[4], int dtype) {
-    if (!L) return fail(SUN_EINVAL, "L is null");
-    if (nc < 2 || nc > SUN_NC_MAX) return fail(SUN_EINVAL, "Nc = %d outside 2..%d", nc, SUN_NC_MAX);
-    if (dtype < SUN_F32 || dtype > SUN_F64_WIDE) return fail(SUN_EINVAL, "dtype %d is not a SUN_F* code", dtype);
-    if (is_two_row(dtype) && nc != 3) return fail(SUN_EUNSUP, "two-row storage exists for SU(3) only (Nc = %d)", nc);
-    if (is_wide(nc, dtype)) {
-        if (nc < 4) return fail(SUN_EUNSUP, "the workgroup-per-link path starts at Nc = 4 (Nc = %d)", nc);
-        if (sun::wide_update_lds(nc, is_f64(dtype)) > sun::kWideLdsMax)
-            return fail(SUN_EUNSUP, "Nc = %d in FP64 needs %zu bytes of LDS per workgroup (limit %zu)", nc,
-                        sun::wide_update_lds(nc, 1), sun::kWideLdsMax);
-    }
-    if (L[0] < 2 || (L[0] & 1)) return fail(SUN_EINVAL, "L[0] = %d must be even and >= 2", L[0]);
-    long long V = 1;
-    for (int mu = 0; mu < 4; ++mu) {
-        if (!(L[mu] == 1 || (L[mu] >= 2 && !(L[mu] & 1))))
-            return fail(SUN_EINVAL, "L[%d] = %d must be 1 or even >= 2 (checkerboard)", mu, L[mu]);
-        V *= L[mu];
-    }
-    if (4 * V >= (1LL << 31)) return fail(SUN_EINVAL, "volume %lld too large (4V must fit in int32)", V);
-    return SUN_OK;
-}
-
-sun::Geom make_geom(const int L[4]) {
-    sun::Geom g{};
-    int V = 1;
-    g.present = 0;
-    for (int mu = 0; mu < 4; ++mu) {
-        g.L[mu] = L[mu];
-        g.stride[mu] = V;
-        V *= L[mu];
-        if (L[mu] > 1) g.present |= 1 << mu;
-    }
-    g.V = V;
-    g.Vh = V / 2;
-    return g;
-}
-
 size_t link_bytes_of(int nc, const sun::Geom& g, int dtype) {
     const size_t rows = is_two_row(dtype) ? 2 : (size_t)nc;
     const size_t reals = (nc == 2) ? 4 : 2 * rows * nc;
     return reals * 4 * (size_t)g.V * (is_f64(dtype) ? 8 : 4);
 }
 
-size_t scratch_bytes_of(const sun::Geom& g, bool wide) {
-    // the largest partial array: per link block, per plaquette tile, or per
-    // Polyakov workgroup (at least 32 spatial sites each); the wide path
-    // reduces per link
+// Bytes of the reduction partials: the largest partial array, per link
+// block, per plaquette tile, or per Polyakov workgroup (at least 32 spatial
+// sites each); the wide path reduces per link.
+size_t partial_bytes_of(const sun::Geom& g, bool wide) {
     const int nblk = wide ? 4 * g.V
                           : std::max({sun::link_blocks(g), sun::plaquette_tiles(g), (g.V / g.L[3] + 31) / 32});
     const size_t b = 2 * sizeof(double) * (size_t)nblk;
     return (b + 255) & ~(size_t)255;
 }
 
-inline hipStream_t as_stream(sun_stream_t s) { return reinterpret_cast<hipStream_t>(s); }
+// The partials, then 256 bytes of watchdog state.
+constexpr size_t kWatchBytes = 256;
+size_t scratch_bytes_of(const sun::Geom& g, bool wide) { return partial_bytes_of(g, wide) + kWatchBytes; }
 
 // kind: SUN_HEATBATH, SUN_OVERRELAX, or -1 for both.
 int check_shape(int kind, int block, int waves, int tblock = 0) {
@@ -158,7 +96,9 @@ int check_shape(int kind, int block, int waves, int tblock = 0) {
     return SUN_OK;
 }
 
-// Records an event pair around one launch when profiling is on.
+// Records an event pair around one launch when profiling is on, or, with
+// run_launches > 0, around a run of that many launches of kernel kind k (only
+// in the run-timing mode; launches inside an open run are not bracketed).
 struct Timed {
     sun_lattice_s* h;
     int kernel;
@@ -166,9 +106,16 @@ struct Timed {
     hipEvent_t a = nullptr, b = nullptr;
     int rc = SUN_OK;
     bool on = false;
-    Timed(sun_lattice_s* h_, int k, hipStream_t s_) : h(h_), kernel(k), s(s_) {
+    int count = 1;
+    Timed(sun_lattice_s* h_, int k, hipStream_t s_, int run_launches = 0)
+        : h(h_), kernel(k), s(s_), count(run_launches > 0 ? run_launches : 1) {
         if (!h->profiling) return;
-        if (h->seen[k]++ % h->profile_every != 0) return;
+        if (run_launches > 0) {
+            if (!h->profile_runs) return;
+        } else {
+            if (h->in_run) return;
+            if (!h->profile_runs && h->seen[k]++ % h->profile_every != 0) return;
+        }
         on = true;
         for (hipEvent_t* e : {&a, &b}) {
             if (!h->pool.empty()) {
@@ -183,7 +130,7 @@ struct Timed {
     int done() {
         if (!on || rc != SUN_OK) return rc;
         rc = hip_check(hipEventRecord(b, s), "hipEventRecord");
-        if (rc == SUN_OK) h->pending.push_back({kernel, a, b});
+        if (rc == SUN_OK) h->pending.push_back({kernel, a, b, count});
         return rc;
     }
 };
@@ -192,7 +139,7 @@ struct Timed {
 
 extern "C" {
 
-const char* sun_last_error(void) { return g_last_error.c_str(); }
+const char* sun_last_error(void) { return last_error.c_str(); }
 
 int sun_lattice_bytes(int nc, const int L[4], int dtype, size_t* link_bytes, size_t* scratch_bytes) {
     if (int rc = check_lattice(nc, L, dtype)) return rc;
@@ -227,6 +174,7 @@ int sun_lattice_create(int nc, const int L[4], int dtype, void* links, size_t li
     // for larger ones (18-real FP32: 70.0 -> 67.3 us, FP64: 161 -> 152 us).
     h->shape[SUN_OVERRELAX].waves = h->link_bytes / (4 * (size_t)g.V) > 48 ? 8 : 12;
     h->scratch = static_cast<double*>(scratch);
+    h->watch_state = reinterpret_cast<double*>(static_cast<char*>(scratch) + partial_bytes_of(g, is_wide(nc, dtype)));
     h->ops = ops_for(nc, dtype);
     *out = h;
     return SUN_OK;
@@ -271,11 +219,18 @@ int sun_phase(sun_lattice_t h, int kind, int mu, int parity, double beta, uint64
     return run_phase(h, kind, mu, parity, beta, seed, step, as_stream(stream));
 }
 
+// Watchdog pass over the unitarity partials of h's scratch, if armed.
+static void watch_partials(sun_lattice_t h, int nblk, hipStream_t s) {
+    sun::k_watchdog<><<<1, sun::kBlock, 0, s>>>(h->scratch, nblk, h->watch_threshold, h->watch_state);
+}
+
 static int run_reunit(sun_lattice_t h, double* dev_out2, hipStream_t s) {
     Timed t(h, 2, s);
     if (t.rc) return t.rc;
-    const int nblk = h->ops->reunit(h->ctx(s), dev_out2 ? h->scratch : nullptr);
+    const bool watch = h->watch_threshold > 0.0;
+    const int nblk = h->ops->reunit(h->ctx(s), (dev_out2 || watch) ? h->scratch : nullptr);
     if (dev_out2) sun::launch_finalize_max2(h->scratch, nblk, dev_out2, s);
+    if (watch) watch_partials(h, nblk, s);
     if (int rc = launch_check("reunitarize")) return rc;
     return t.done();
 }
@@ -284,14 +239,28 @@ int sun_sweep(sun_lattice_t h, double beta, int n_hb, int n_or, uint64_t seed, i
     if (!h) return fail(SUN_EINVAL, "null handle");
     if (n_hb < 0 || n_or < 0) return fail(SUN_EINVAL, "negative step count (n_hb %d, n_or %d)", n_hb, n_or);
     const hipStream_t s = as_stream(stream);
-    for (int k = 0; k < n_hb; ++k)
-        for (int mu = 0; mu < 4; ++mu)
-            for (int p = 0; p < 2; ++p)
-                if (int rc = run_phase(h, SUN_HEATBATH, mu, p, beta, seed, h->step + (uint64_t)k, s)) return rc;
-    for (int k = 0; k < n_or; ++k)
-        for (int mu = 0; mu < 4; ++mu)
-            for (int p = 0; p < 2; ++p)
-                if (int rc = run_phase(h, SUN_OVERRELAX, mu, p, beta, seed, 0, s)) return rc;
+    int present = 0;
+    for (int mu = 0; mu < 4; ++mu) present += (h->g.present >> mu) & 1;
+    // the heatbath phases, then the overrelaxation phases, each a run of
+    // consecutive launches of one kernel kind (bracketed as a whole in the
+    // run-timing mode of sun_profile)
+    for (int kind : {SUN_HEATBATH, SUN_OVERRELAX}) {
+        const int steps = kind == SUN_HEATBATH ? n_hb : n_or;
+        if (steps == 0) continue;
+        Timed run(h, kind == SUN_HEATBATH ? 0 : 1, s, steps * 2 * present);
+        if (run.rc) return run.rc;
+        h->in_run = run.on;
+        for (int k = 0; k < steps; ++k)
+            for (int mu = 0; mu < 4; ++mu)
+                for (int p = 0; p < 2; ++p)
+                    if (int rc = run_phase(h, kind, mu, p, beta, seed,
+                                           kind == SUN_HEATBATH ? h->step + (uint64_t)k : 0, s)) {
+                        h->in_run = false;
+                        return rc;
+                    }
+        h->in_run = false;
+        if (int rc = run.done()) return rc;
+    }
     if (reunit)
         if (int rc = run_reunit(h, nullptr, s)) return rc;
     h->step += (uint64_t)n_hb;
@@ -309,13 +278,7 @@ int sun_plaquette(sun_lattice_t h, double* dev_out3, sun_stream_t stream) {
     const hipStream_t s = as_stream(stream);
     Timed t(h, 3, s);
     if (t.rc) return t.rc;
-    int n_sp = 0, n_tm = 0;
-    for (int mu = 0; mu < 4; ++mu)
-        for (int nu = mu + 1; nu < 4; ++nu)
-            if (((h->g.present >> mu) & 1) && ((h->g.present >> nu) & 1)) (nu == 3 ? n_tm : n_sp)++;
-    const double norm = (double)h->nc * (double)h->g.V;
-    const int nblk = h->ops->plaquette(h->ctx(s), h->scratch);
-    sun::launch_plaquette_final(h->scratch, nblk, dev_out3, norm * n_sp, norm * n_tm, norm * (n_sp + n_tm), s);
+    launch_plaquette(h->ops, h->ctx(s), h->scratch, dev_out3);
     if (int rc = launch_check("plaquette")) return rc;
     return t.done();
 }
@@ -340,6 +303,34 @@ int sun_unitarity(sun_lattice_t h, double* dev_out2, sun_stream_t stream) {
     const int nblk = h->ops->unitarity(h->ctx(s), h->scratch);
     sun::launch_finalize_max2(h->scratch, nblk, dev_out2, s);
     return launch_check("unitarity");
+}
+
+int sun_watchdog(sun_lattice_t h, double threshold, sun_stream_t stream) {
+    if (!h) return fail(SUN_EINVAL, "null handle");
+    if (!(threshold >= 0.0) || threshold == __builtin_inf())
+        return fail(SUN_EINVAL, "watchdog threshold %g is not finite and >= 0", threshold);
+    h->watch_threshold = threshold;
+    sun::k_fill<><<<1, 64, 0, as_stream(stream)>>>(h->watch_state, 3, 0.0);
+    if (int rc = launch_check("watchdog reset")) return rc;
+    h->watch_reset = true;
+    return SUN_OK;
+}
+
+int sun_check(sun_lattice_t h, double* deviation, sun_stream_t stream) {
+    if (!h) return fail(SUN_EINVAL, "null handle");
+    if (!h->watch_reset) return fail(SUN_EINVAL, "the watchdog was never set (call sun_watchdog first)");
+    const hipStream_t s = as_stream(stream);
+    double st[3] = {0.0, 0.0, 0.0};
+    if (int rc = hip_check(hipMemcpyAsync(st, h->watch_state, sizeof st, hipMemcpyDeviceToHost, s), "watchdog read"))
+        return rc;
+    if (int rc = hip_check(hipStreamSynchronize(s), "hipStreamSynchronize")) return rc;
+    if (deviation) *deviation = st[1];
+    if (st[0] > 0.0)
+        return fail(SUN_ENUMERIC,
+                    "watchdog: %.0f check(s) found a unitarity or determinant deviation above %g (largest %g; "
+                    "a NaN or infinite entry counts as infinite)",
+                    st[0], h->watch_threshold, st[1]);
+    return SUN_OK;
 }
 
 int sun_export(sun_lattice_t h, double* dev_canonical, sun_stream_t stream) {
@@ -405,7 +396,7 @@ int sun_get_launch(sun_lattice_t h, int kind, int* block, int* xcd, int* waves, 
 
 int sun_profile(sun_lattice_t h, int every) {
     if (!h) return fail(SUN_EINVAL, "null handle");
-    if (every < 0) return fail(SUN_EINVAL, "profile sampling period %d", every);
+    if (every < -1) return fail(SUN_EINVAL, "profile sampling period %d", every);
     for (auto& p : h->pending) {
         if (int rc = hip_check(hipEventSynchronize(p.b), "hipEventSynchronize")) return rc;
         h->pool.push_back(p.a);
@@ -418,6 +409,7 @@ int sun_profile(sun_lattice_t h, int every) {
         h->seen[k] = 0;
     }
     h->profiling = every != 0;
+    h->profile_runs = every == -1;
     h->profile_every = every > 0 ? every : 1;
     return SUN_OK;
 }
@@ -430,7 +422,7 @@ int sun_profile_read(sun_lattice_t h, int kernel, double* total_ms, int64_t* lau
         float ms = 0.0f;
         if (int rc = hip_check(hipEventElapsedTime(&ms, p.a, p.b), "hipEventElapsedTime")) return rc;
         h->total_ms[p.kernel] += ms;
-        h->launches[p.kernel] += 1;
+        h->launches[p.kernel] += p.count;
         h->pool.push_back(p.a);
         h->pool.push_back(p.b);
     }
@@ -577,6 +569,30 @@ int sun_batch_create(int n, const sun_lattice_t* chains, const double* betas, co
         if (is_wide(chains[i]->nc, chains[i]->dtype))
             return fail(SUN_EUNSUP, "chain %d uses the workgroup-per-link path (Nc = %d), which batches do not run", i,
                         chains[i]->nc);
+    }
+    // Two descriptors over the same memory would update the same links (or
+    // write the same partials) in one launch: refuse a lattice listed twice
+    // and lattices whose link or scratch buffers overlap.
+    {
+        struct Range {
+            uintptr_t lo, hi;
+            int chain;
+        };
+        std::vector<Range> r;
+        for (int i = 0; i < n; ++i) {
+            const sun_lattice_t h = chains[i];
+            const uintptr_t l = (uintptr_t)h->links, sc = (uintptr_t)h->scratch;
+            r.push_back({l, l + h->link_bytes, i});
+            r.push_back({sc, sc + scratch_bytes_of(h->g, is_wide(h->nc, h->dtype)), i});
+        }
+        std::sort(r.begin(), r.end(), [](const Range& a, const Range& b) { return a.lo < b.lo; });
+        for (size_t k = 1; k < r.size(); ++k)
+            if (r[k].lo < r[k - 1].hi) {
+                const int a = std::min(r[k].chain, r[k - 1].chain), b = std::max(r[k].chain, r[k - 1].chain);
+                if (a == b) return fail(SUN_EINVAL, "chain %d: its link and scratch buffers overlap", a);
+                return fail(SUN_EINVAL, "chains %d and %d share device memory (the same lattice listed twice, or "
+                                        "overlapping buffers)", a, b);
+            }
     }
     auto* b = new sun_batch_s;
     b->chains.assign(chains, chains + n);

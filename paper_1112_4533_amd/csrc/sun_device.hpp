@@ -214,6 +214,10 @@ SUN_MAT_UNROLL
 __device__ __forceinline__ float fmadd(float a, float b, float c) { return __builtin_fmaf(a, b, c); }
 __device__ __forceinline__ double fmadd(double a, double b, double c) { return __builtin_fma(a, b, c); }
 
+// NaN -> +infinity, for maxima that must not lose a NaN (fmax returns the
+// other operand).
+__device__ __forceinline__ double nan_to_inf(double x) { return x == x ? x : __builtin_inf(); }
+
 // (r, m) += (ar + i ai)(br + i bi)
 template <typename T>
 __device__ __forceinline__ void cmac(T& r, T& m, T ar, T ai, T br, T bi) {

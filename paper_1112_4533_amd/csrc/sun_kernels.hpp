@@ -89,6 +89,36 @@ __global__ __launch_bounds__(kBlock) void k_finalize(const double* __restrict__ 
     }
 }
 
+// Watchdog pass over nblk partial records {max |U^dag U - 1|, max |det U - 1|}
+// (NaN entries already turned into infinities): when either maximum exceeds
+// threshold the check counts as tripped, state[0] += 1 and state[1] keeps the
+// largest deviation a tripped check saw; state[2] is this check's deviation.
+template <int Dummy = 0>
+__global__ __launch_bounds__(kBlock) void k_watchdog(const double* __restrict__ partial, int nblk, double threshold,
+                                                     double* __restrict__ state) {
+    double v[1] = {0.0};
+    for (int b = threadIdx.x; b < nblk; b += kBlock)
+        v[0] = fmax(v[0], fmax(partial[2 * (size_t)b], partial[2 * (size_t)b + 1]));
+    __shared__ double res[1];
+    block_max<1>(v, res);
+    if (threadIdx.x == 0) {
+        const double d = res[0];
+        state[2] = d;
+        if (d > threshold) {
+            state[0] += 1.0;
+            state[1] = fmax(state[1], d);
+        }
+    }
+}
+
+// p[0 .. n) = v (a kernel rather than a memset, so that captured graphs hold
+// no memset nodes).
+template <int Dummy = 0>
+__global__ void k_fill(double* __restrict__ p, int n, double v) {
+    const int i = blockIdx.x * blockDim.x + threadIdx.x;
+    if (i < n) p[i] = v;
+}
+
 // ---------------------------------------------------------------------------
 // Staple (paper Sec. 2), closing orientation: for nu != mu
 //   U_nu(x+mu) U_mu(x+nu)^dag U_nu(x)^dag + U_nu(x+mu-nu)^dag U_mu(x-nu)^dag U_nu(x-nu)
@@ -528,7 +558,8 @@ __device__ __forceinline__ void det3(const Mat<3, double>& m, double& dr, double
 
 // {max_ij |(U^dag U - 1)_ij|, |det U - 1|}.  U^dag U - 1 is Hermitian, so
 // its upper triangle holds every modulus; the maximum is taken over squared
-// moduli and rooted once.
+// moduli and rooted once.  A NaN entry makes both deviations infinite (fmax
+// alone would drop it), so that every maximum over links reports it.
 template <int N>
 __device__ __forceinline__ void unitarity_dev(const Mat<N, double>& M, double& du, double& dd) {
     double du2 = 0.0;
@@ -539,7 +570,7 @@ SUN_MAT_UNROLL
             double r = (i == j) ? -1.0 : 0.0, m = 0.0;
 SUN_MAT_UNROLL
             for (int k = 0; k < N; ++k) cmac(r, m, M.re[k][i], -M.im[k][i], M.re[k][j], M.im[k][j]);
-            du2 = fmax(du2, fmadd(m, m, r * r));
+            du2 = fmax(du2, nan_to_inf(fmadd(m, m, r * r)));
         }
     du = sqrt(du2);
     double dr, di;
@@ -547,7 +578,7 @@ SUN_MAT_UNROLL
         det3(M, dr, di);
     else
         det_lu<N>(M, dr, di);
-    dd = sqrt(fmadd(di, di, (dr - 1.0) * (dr - 1.0)));
+    dd = nan_to_inf(sqrt(fmadd(di, di, (dr - 1.0) * (dr - 1.0))));
 }
 
 // Link id in [0, 4V): mu-major, then parity, then checkerboard index.

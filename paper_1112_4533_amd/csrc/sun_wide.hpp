@@ -554,13 +554,13 @@ __device__ __forceinline__ void lds_unitarity(const double2* M, double2* D, int 
             const double2 a = M[k * n + i], b = M[k * n + j];
             cmac(r, m, a.x, -a.y, b.x, b.y);
         }
-        du2 = fmax(du2, fmadd(m, m, r * r));
+        du2 = fmax(du2, nan_to_inf(fmadd(m, m, r * r)));  // a NaN entry counts as infinite
     }
     du = sqrt(wave_max(du2));
     for (int e = threadIdx.x; e < n2; e += kLanes) D[e] = M[e];
     double dr, di;
     lds_det(D, n, dr, di);
-    dd = sqrt(fmadd(di, di, (dr - 1.0) * (dr - 1.0)));
+    dd = nan_to_inf(sqrt(fmadd(di, di, (dr - 1.0) * (dr - 1.0))));
 }
 
 // Gram-Schmidt on all rows, then the last row times conj(det)/|det| (paper

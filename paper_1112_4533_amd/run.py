@@ -17,6 +17,12 @@ Writes into --out:
 the RNG step counter and the sweep count), after checking that it belongs to
 the same run; the continued chain is bitwise the chain that was never
 interrupted.
+
+The library's watchdog checks the field in every re-unitarization (a NaN or
+infinite entry, or a unitarity or determinant deviation above --watchdog
+before the projection).  When it trips the run stops without writing that
+sweep, records the failure in summary.json and exits with an error; the
+newest configuration file is then the last good state to --resume from.
 """
 import argparse
 import glob
@@ -71,6 +77,8 @@ def run(args):
         for r in history:
             f.write(json.dumps(r) + "\n")
 
+    watch = args.watchdog if args.watchdog is not None else (1e-4 if args.dtype.startswith("f32") else 1e-10)
+    lat.watchdog(watch)
     dev = lat.links.device
     plaq = torch.zeros(3, dtype=torch.float64, device=dev)
     poly = torch.zeros(2, dtype=torch.float64, device=dev)
@@ -85,6 +93,16 @@ def run(args):
             sun._check(lib.sun_reunitarize(lat._h, sun._ptr(drift), stream))
             lat.plaquette(plaq)
             lat.polyakov(poly)
+            if watch > 0:
+                try:
+                    lat.check()
+                except sun.SunNumericError as e:
+                    last = _latest_config(args.out)
+                    fail = {"params": params, "failed_at_sweep": sweep, "error": str(e),
+                            "resume_from": os.path.basename(last) if last else None}
+                    with open(os.path.join(args.out, "summary.json"), "w") as f:
+                        json.dump(fail, f, indent=1)
+                    raise SystemExit(f"sweep {sweep}: {e}; last good configuration: {fail['resume_from']}")
             row = {"sweep": sweep, "plaquette": plaq.cpu().tolist(), "polyakov": poly.cpu().tolist(),
                    "drift": drift.cpu().tolist(), "seconds": time.perf_counter() - t0}
             hf.write(json.dumps(row) + "\n")
@@ -131,6 +149,9 @@ def main(argv=None):
     ap.add_argument("--out", required=True)
     ap.add_argument("--resume", action="store_true")
     ap.add_argument("--progress", type=int, default=0, help="print the plaquette every this many sweeps")
+    ap.add_argument("--watchdog", type=float, default=None,
+                    help="largest unitarity or determinant deviation a re-unitarization may find (default 1e-4 "
+                         "for FP32 storage, 1e-10 for FP64; 0 turns the check off)")
     args = ap.parse_args(argv)
     run(args)
     return 0

@@ -19,14 +19,21 @@ DTYPE_NAMES = {F32: "f32", F64: "f64", F32_TWO_ROW: "f32r12", F64_TWO_ROW: "f64r
 NC_MAX_REGISTER, NC_MAX = 4, 32
 HEATBATH, OVERRELAX = 0, 1
 KERNEL_IDS = {"heatbath": 0, "overrelax": 1, "reunit": 2, "plaquette": 3, "polyakov": 4}
-SUN_OK = 0
-NC_MAX = 8
+SUN_OK, SUN_EINVAL, SUN_ESIZE, SUN_EHIP, SUN_EUNSUP, SUN_ENUMERIC = 0, -1, -2, -3, -4, -5
 
 _lib = None
 
 
 class SunError(RuntimeError):
-    pass
+    """A libsun call failed; `code` is its SUN_E* status."""
+
+    def __init__(self, msg, code=None):
+        super().__init__(msg)
+        self.code = code
+
+
+class SunNumericError(SunError):
+    """The watchdog found a non-finite or non-unitary field (SUN_ENUMERIC)."""
 
 
 def load():
@@ -50,6 +57,8 @@ def load():
         "sun_plaquette": [vp, vp, vp],
         "sun_polyakov": [vp, vp, vp],
         "sun_unitarity": [vp, vp, vp],
+        "sun_watchdog": [vp, c_dbl, vp],
+        "sun_check": [vp, ctypes.POINTER(c_dbl), vp],
         "sun_export": [vp, vp, vp],
         "sun_import": [vp, vp, vp],
         "sun_get_step": [vp, ctypes.POINTER(c_u64)],
@@ -92,7 +101,7 @@ def exported_symbols():
     L = load()
     return [n for n in ("sun_lattice_bytes", "sun_lattice_create", "sun_lattice_destroy", "sun_init",
                         "sun_phase", "sun_sweep", "sun_reunitarize", "sun_plaquette", "sun_polyakov",
-                        "sun_unitarity", "sun_export", "sun_import", "sun_get_step", "sun_set_step",
+                        "sun_unitarity", "sun_watchdog", "sun_check", "sun_export", "sun_import", "sun_get_step", "sun_set_step",
                         "sun_profile", "sun_profile_read", "sun_sample_su2", "sun_last_error",
                         "sun_batch_bytes", "sun_batch_create", "sun_batch_sweep", "sun_batch_plaquette",
                         "sun_batch_capture", "sun_batch_replay", "sun_batch_sync", "sun_batch_destroy",
@@ -103,7 +112,8 @@ def exported_symbols():
 
 def _check(rc):
     if rc != SUN_OK:
-        raise SunError(f"libsun error {rc}: {load().sun_last_error().decode()}")
+        cls = SunNumericError if rc == SUN_ENUMERIC else SunError
+        raise cls(f"libsun error {rc}: {load().sun_last_error().decode()}", rc)
 
 
 def _stream():
@@ -206,6 +216,20 @@ class Lattice:
         out = out if out is not None else torch.empty(2, dtype=torch.float64, device=self.links.device)
         _check(load().sun_unitarity(self._h, _ptr(out), _stream()))
         return out
+
+    # -- watchdog ---------------------------------------------------------
+    def watchdog(self, threshold):
+        """Arms (threshold > 0) or disarms (0) the check made by every later
+        re-unitarization (reunitarize(), and sweep() with reunit), and clears
+        its state."""
+        _check(load().sun_watchdog(self._h, float(threshold), _stream()))
+
+    def check(self):
+        """Waits for the queued work; raises SunNumericError if a check since
+        watchdog() tripped, else returns 0.0."""
+        d = ctypes.c_double()
+        _check(load().sun_check(self._h, ctypes.byref(d), _stream()))
+        return d.value
 
     # -- field transfer --------------------------------------------------
     def export(self):

@@ -95,7 +95,9 @@ def test_create_validates_buffers_without_touching_them(lib):
     assert lib.sun_sweep(h, 6.0, -1, 0, 1, 1, None) == -1
     assert lib.sun_plaquette(h, None, None) == -2
     assert lib.sun_profile_read(h, 9, None, None) == -1
-    assert lib.sun_profile(h, -1) == -1
+    assert lib.sun_profile(h, -2) == -1
+    assert lib.sun_profile(h, -1) == 0          # run-timing mode
+    assert lib.sun_profile(h, 0) == 0
     # launch shapes: only the instantiated workgroup sizes, wave caps and walks
     b, x, w, t = ctypes.c_int(), ctypes.c_int(), ctypes.c_int(), ctypes.c_int()
     get = lambda k: (lib.sun_get_launch(h, k, ctypes.byref(b), ctypes.byref(x), ctypes.byref(w), ctypes.byref(t)),
@@ -163,8 +165,49 @@ def test_batch_argument_checks(lib):
     wide = (ctypes.c_void_p * 1)(h.value)
     assert lib.sun_batch_create(1, wide, d, s, ctypes.c_void_p(0x10000), tb.value, ctypes.byref(out)) == -4
     lib.sun_lattice_destroy(h)
+    # a lattice listed twice, or two lattices over overlapping buffers, would
+    # update the same links in one launch: refused before the table is written
+    assert lib.sun_lattice_bytes(3, L, 0, ctypes.byref(lb), ctypes.byref(sb)) == 0
+    hs = []
+    for links, scr in [(0x1000000, 0x2000000), (0x3000000, 0x4000000), (0x1000000 + 256, 0x5000000),
+                       (0x6000000, 0x4000000 + sb.value - 256)]:
+        h = ctypes.c_void_p()
+        assert lib.sun_lattice_create(3, L, 0, ctypes.c_void_p(links), lb.value, ctypes.c_void_p(scr), sb.value,
+                                      ctypes.byref(h)) == 0
+        hs.append(h.value)
+    two = (ctypes.c_double * 2)(6.0, 6.0)
+    s2 = (ctypes.c_uint64 * 2)(1, 2)
+    for pair in [(0, 0), (0, 2), (1, 3)]:
+        arr = (ctypes.c_void_p * 2)(hs[pair[0]], hs[pair[1]])
+        assert lib.sun_batch_create(2, arr, two, s2, ctypes.c_void_p(0x10000), tb.value, ctypes.byref(out)) == -1, pair
+        assert b"share device memory" in lib.sun_last_error(), pair
+    for hv in hs:
+        lib.sun_lattice_destroy(ctypes.c_void_p(hv))
     assert lib.sun_batch_sweep(None, 1, 1, 1, None) == -1
     assert lib.sun_batch_replay(None, None) == -1
+
+
+def test_watchdog_argument_checks(lib):
+    """The watchdog's threshold must be finite and >= 0, and sun_check needs
+    a preceding sun_watchdog; both refusals come before any launch."""
+    L = (4, 4, 4, 4)
+    rc, lb, sb = _bytes(lib, 3, L, 0)
+    h = ctypes.c_void_p()
+    assert lib.sun_lattice_create(3, (ctypes.c_int * 4)(*L), 0, ctypes.c_void_p(0x10000), lb, ctypes.c_void_p(0x200000),
+                                  sb, ctypes.byref(h)) == 0
+    for bad in (-1e-3, float("nan"), float("inf")):
+        assert lib.sun_watchdog(h, bad, None) == -1
+        assert b"threshold" in lib.sun_last_error()
+    assert lib.sun_watchdog(None, 1e-4, None) == -1
+    d = ctypes.c_double()
+    assert lib.sun_check(h, ctypes.byref(d), None) == -1
+    assert b"never set" in lib.sun_last_error()
+    assert lib.sun_check(None, ctypes.byref(d), None) == -1
+    lib.sun_lattice_destroy(h)
+    # the watchdog state adds 256 bytes to the scratch buffer
+    from paper_1112_4533_amd import sun
+    assert sun.SUN_ENUMERIC == -5
+    assert issubclass(sun.SunNumericError, sun.SunError)
 
 
 def test_sampler_hook_argument_checks(lib):
