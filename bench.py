@@ -7,10 +7,15 @@ FP64 reductions and FP64 re-unitarization.  One step is one pass
 of the whole hot path over the lattice: 1 heatbath step + 4 overrelaxation
 steps (each 4 directions x {even, odd} phases), re-unitarization (reporting
 the unitarity drift it removed), the plaquette (FP64) and the Polyakov loop.
-The same workload with 18-real FP32 links, with FP64 links, and a batch of
-64 small independent chains replayed from a HIP graph are timed beside it,
-and (untimed) the FP32-storage chain is compared with the FP64 chain of the
-same seed, sweep by sweep.
+The same workload with 18-real FP32 links and with FP64 links is timed beside
+it.  `configs` then runs every workload of the table (SU(2) 8^4 cold FP64,
+SU(3) 16^4 and 32^4 hot, SU(4/6/8) 12^4, a batch of 64 small independent
+chains replayed from a HIP graph) in its stated storage and in the other
+precision, with throughput and the thermalized plaquette (and Polyakov loop)
+means with errors from the integrated autocorrelation time, their
+FP32-vs-FP64 difference in units of its error, the unitarity drift before
+each re-unitarization and the relative action change of an overrelaxation
+step.
 
 Prints one JSON line.  `value` is link updates per second (one update = one
 heatbath or overrelaxation visit of one link) with the field resident in HBM.
@@ -50,6 +55,7 @@ def step_bytes(nc, V, dtype, n_hb, n_or):
 
 KERNEL_SOURCES = ["sun_device.hpp", "sun_kernels.hpp"]
 TRAFFIC_FILE = os.path.join(ROOT, "profiles", "traffic.json")
+MALL_BYTES = 256 * 2 ** 20       # MI355X Infinity Cache (last level, in front of HBM)
 
 
 def kernel_source_hash():
@@ -64,9 +70,10 @@ def kernel_source_hash():
 
 
 def stored_traffic(workload):
-    """HBM-side bytes per launch of the overrelaxation phase kernel from the
-    committed rocprofv3 FETCH_SIZE / WRITE_SIZE summary, or None when the
-    kernels changed after those counters were taken."""
+    """Bytes per launch of the overrelaxation phase kernel that miss the L2
+    (served by the Infinity Cache or HBM), from the committed rocprofv3
+    FETCH_SIZE / WRITE_SIZE summary, or None when the kernels changed after
+    those counters were taken."""
     try:
         with open(TRAFFIC_FILE) as f:
             t = json.load(f)
@@ -78,16 +85,55 @@ def stored_traffic(workload):
     return e["read_bytes"] + e["write_bytes"]
 
 
-def roofline(run, r):
+def field_bytes(run):
+    return 4 * run.volume * link_bytes(run.nc, run.dtype)
+
+
+def roofline(run, r, copy_gbps=None):
+    """The overrelaxation phase kernel (32 of the 40 phases of a step):
+    algorithmic bytes per launch over its mean launch time, against the HBM
+    peak; plus the measured device-copy ceiling of the same run."""
     k = r["kernels"]["overrelax"]
     per_launch = phase_bytes(run.nc, run.volume, run.dtype)
     achieved = per_launch / (k["avg_ms"] * 1e-3) / 1e9
-    return {"bound": "hbm", "kernel": f"overrelaxation phase ({run.dtype} storage)", "achieved": achieved,
-            "peak": PEAK_HBM_GBS, "unit": "GB/s", "frac": achieved / PEAK_HBM_GBS,
-            "traffic": stored_traffic(run.name), "bytes_per_launch": per_launch, "avg_launch_ms": k["avg_ms"]}
+    fb = field_bytes(run)
+    resident = fb <= MALL_BYTES
+    out = {"bound": "hbm", "kernel": f"overrelaxation phase ({run.dtype} storage)", "achieved": achieved,
+           "peak": PEAK_HBM_GBS, "unit": "GB/s", "frac": achieved / PEAK_HBM_GBS,
+           "traffic": stored_traffic(run.name),
+           "traffic_kind": "bytes per launch beyond L2 (Infinity Cache hits + HBM), rocprofv3 FETCH_SIZE + "
+                           "WRITE_SIZE scaled by a device copy",
+           "bytes_per_launch": per_launch, "avg_launch_ms": k["avg_ms"],
+           "timing": r.get("timing"),
+           "field_bytes": fb, "cache_resident": resident,
+           "bound_note": (f"the {fb / 1e6:.0f} MB field fits the 256 MiB Infinity Cache, so part of the "
+                          "re-read neighbour traffic is served there rather than by HBM" if resident else
+                          f"the {fb / 1e6:.0f} MB field exceeds the 256 MiB Infinity Cache: an HBM measurement")}
+    if copy_gbps:
+        out["copy_ceiling_GBps"] = copy_gbps
+        out["frac_of_copy_ceiling"] = achieved / copy_gbps
+    return out
 
 
-PROFILE_EVERY = 9
+def copy_ceiling(nbytes=2 ** 30, reps=10):
+    """Device-to-device copy rate (bytes read + written per second, GB/s) of
+    an nbytes buffer, timed with events around reps copies on torch's stream:
+    the practical HBM ceiling of this GPU in this run."""
+    import torch
+    a = torch.ones(nbytes // 4, dtype=torch.float32, device="cuda")
+    b = torch.empty_like(a)
+    for _ in range(2):
+        b.copy_(a)
+    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    e0.record()
+    for _ in range(reps):
+        b.copy_(a)
+    e1.record()
+    e1.synchronize()
+    gbps = 2 * nbytes * reps / (e0.elapsed_time(e1) * 1e-3) / 1e9
+    del a, b
+    torch.cuda.empty_cache()
+    return gbps
 
 
 def run_gpu(run, steps, warmup, tune=False):
@@ -113,12 +159,11 @@ def run_gpu(run, steps, warmup, tune=False):
     for _ in range(warmup):
         step()
     torch.cuda.synchronize()
-    # HIP events bracket one launch in PROFILE_EVERY of each kernel kind in
-    # the timed region (a period coprime to the 8 phases of an update step,
-    # so every direction and parity is sampled); an event pair costs a few
-    # microseconds of stream time, and timing every launch would slow the
-    # step by about a tenth
-    lat.profile(True, every=PROFILE_EVERY)
+    # HIP events on the launch stream bracket each run of back-to-back
+    # launches of one kernel kind (the 8 heatbath and the 32 overrelaxation
+    # phases of a step, each as one run; the other kernels singly), so no
+    # launch is slowed by a bracket of its own
+    lat.profile(True, every=-1)
     torch.cuda.synchronize()
     t0 = time.perf_counter()
     for _ in range(steps):
@@ -143,6 +188,8 @@ def run_gpu(run, steps, warmup, tune=False):
         "ms_per_step": 1e3 * elapsed / steps,
         "updates_per_s": updates / elapsed,
         "kernels": kernels,
+        "timing": "one event pair per run of back-to-back launches of a kernel (per step: 8 heatbath, "
+                  "32 overrelaxation phases), average = run time / launches, gaps between launches included",
         "plaquette": plaq.cpu().tolist(),
         "polyakov": poly.cpu().tolist(),
         "unitarity_before_reunit": drift.cpu().tolist(),
@@ -153,66 +200,171 @@ def run_gpu(run, steps, warmup, tune=False):
     }
 
 
-def run_precision(run, sweeps):
-    """Precision pattern: the same chain (seed, hot start, beta, schedule)
-    with `run`'s FP32 storage and with FP64 links, untimed.  Reports both
-    plaquettes after each sweep and their difference: the drift that FP32
-    storage introduces (the two chains start from the same FP64 Haar field,
-    one rounded to FP32, and part once a heatbath acceptance test falls on
-    the other side of its threshold)."""
+# ---------------------------------------------------------------------------
+# Every configuration of the workload table, with its precision statement
+# ---------------------------------------------------------------------------
+def stat_summary(series, cut):
+    """Mean and error (integrated autocorrelation time) after the cut."""
+    from paper_1112_4533_amd import analysis
+    m, e, tau = analysis.mean_error(series[cut:])
+    return {"mean": m, "err": e, "tau_int": tau}
+
+
+def chain_run(run, dtype, sweeps, cut):
+    """One chain of `run` with link storage `dtype`: per sweep the sweep,
+    re-unitarization reporting the drift it removed, plaquette and Polyakov
+    loop, all queued on the device (no host round trip inside the loop).
+    Returns throughput, the thermalized plaquette and Polyakov means with
+    their errors, the largest drift, and the relative action change of one
+    further overrelaxation step."""
+    import numpy as np
     import torch
     from paper_1112_4533_amd import sun
 
-    out = {"sweeps": sweeps, "storage": [run.dtype, "f64"]}
-    plaqs, devs = [], []
-    for dtype in (run.dtype, "f64"):
-        lat = sun.Lattice(run.nc, run.L, dtype)
-        lat.init(hot=run.hot, seed=run.seed)
-        dev = lat.links.device
-        drift = torch.zeros(2, dtype=torch.float64, device=dev)
-        lib, stream = sun.load(), sun._stream()
-        p, d = [], []
-        for _ in range(sweeps):
-            lat.sweep(run.beta, run.n_hb, run.n_or, seed=run.seed, reunit=False)
-            sun._check(lib.sun_reunitarize(lat._h, sun._ptr(drift), stream))
-            p.append(float(lat.plaquette().cpu()[0]))
-            d.append(float(drift.cpu()[0]))
-        plaqs.append(p)
-        devs.append(max(d))
-        del lat
-        torch.cuda.empty_cache()
-    out["plaquette_fp32_storage"], out["plaquette_fp64"] = plaqs
-    out["plaquette_diff"] = [a - b for a, b in zip(*plaqs)]
-    out["max_unitarity_dev_before_reunit"] = {run.dtype: devs[0], "f64": devs[1]}
+    lat = sun.Lattice(run.nc, run.L, dtype)
+    lat.init(hot=run.hot, seed=run.seed)
+    dev = lat.links.device
+    plaq = torch.zeros((sweeps, 3), dtype=torch.float64, device=dev)
+    poly = torch.zeros((sweeps, 2), dtype=torch.float64, device=dev)
+    drift = torch.zeros((sweeps, 2), dtype=torch.float64, device=dev)
+    lib, stream = sun.load(), sun._stream()
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for k in range(sweeps):
+        lat.sweep(run.beta, run.n_hb, run.n_or, seed=run.seed, reunit=False)
+        sun._check(lib.sun_reunitarize(lat._h, sun._ptr(drift[k]), stream))
+        lat.plaquette(plaq[k])
+        lat.polyakov(poly[k])
+    torch.cuda.synchronize()
+    dt = time.perf_counter() - t0
+    p0 = lat.plaquette().cpu()
+    lat.sweep(run.beta, 0, 1, seed=run.seed, reunit=False)
+    p1 = lat.plaquette().cpu()
+    P, Pl, D = plaq.cpu().numpy(), poly.cpu().numpy(), drift.cpu().numpy()
+    del lat
+    torch.cuda.empty_cache()
+    absL = np.hypot(Pl[:, 0], Pl[:, 1])
+    return {
+        "link_updates_per_s": sweeps * (run.n_hb + run.n_or) * 4 * run.volume / dt,
+        "ms_per_sweep": 1e3 * dt / sweeps,
+        "plaquette": stat_summary(P[:, 0], cut),
+        "plaquette_spatial": stat_summary(P[:, 1], cut)["mean"],
+        "plaquette_temporal": stat_summary(P[:, 2], cut)["mean"],
+        "polyakov_re": stat_summary(Pl[:, 0], cut),
+        "polyakov_abs": stat_summary(absL, cut),
+        "max_unitarity_dev_before_reunit": float(D[:, 0].max()),
+        "max_det_dev_before_reunit": float(D[:, 1].max()),
+        "or_rel_action_change": float((p0[0] - p1[0]) / (1.0 - p0[0])),
+        "series_first_last": [float(P[0, 0]), float(P[-1, 0])],
+    }
+
+
+def difference(a, b):
+    """a - b of two thermalized means, its combined error and the ratio."""
+    d = a["mean"] - b["mean"]
+    s = (a["err"] ** 2 + b["err"] ** 2) ** 0.5
+    return {"diff": d, "sigma": s, "z": d / s if s > 0 else None}
+
+
+def config_entry(run, storages, sweeps, cut, reference="f64", label=None):
+    out = {"workload": label or run.name, "nc": run.nc, "L": list(run.L), "beta": run.beta,
+           "start": "hot" if run.hot else "cold", "n_hb": run.n_hb, "n_or": run.n_or,
+           "reunit": "every sweep", "sweeps_in_config": run.sweeps, "sweeps_run": sweeps,
+           "thermalization_cut": cut, "storage": {}}
+    for dt in storages:
+        out["storage"][dt] = chain_run(run, dt, sweeps, cut)
+        print(f"config {out['workload']} {dt}: {out['storage'][dt]['ms_per_sweep']:.3f} ms/sweep, plaquette "
+              f"{out['storage'][dt]['plaquette']['mean']:.6f} +- {out['storage'][dt]['plaquette']['err']:.6f}",
+              file=sys.stderr, flush=True)
+    ref = out["storage"][reference]["plaquette"]
+    out["minus_" + reference] = {dt: difference(out["storage"][dt]["plaquette"], ref)
+                                 for dt in storages if dt != reference}
     return out
 
 
-def run_batch(steps, warmup, f64_sweeps, tune=False):
+def run_configs(batch_steps):
+    """The five workloads: SU(2) 8^4 cold FP64, SU(3) 16^4 hot FP32, SU(3)
+    32^4 hot FP32 (two-row and 18 reals) against FP64, SU(4/6/8) 12^4 FP32 and
+    FP64, and the 64-chain batch.  Each runs in its stated storage and in the
+    other precision from the same seed and start; chains that share seed and
+    start part after a few sweeps (a heatbath decision near its threshold
+    takes the other branch), after which the two are independent samples of
+    the same distribution: FP32 storage is unbiased when the thermalized means
+    agree within their errors (z = difference / combined error)."""
+    from paper_1112_4533_amd.workloads import (SU2_8_COLD, SU3_16_HOT, SU3_32_F32_TWO_ROW, large_nc_runs)
+    out = {}
+    # SU(2) 8^4: the stated 20 sweeps are far too few for a mean with an
+    # error, so the chains run 2000 sweeps (0.2 ms each)
+    out["c1"] = config_entry(SU2_8_COLD, ["f64", "f32"], 2000, 100)
+    out["c2"] = config_entry(SU3_16_HOT, ["f32", "f64"], 400, 100)
+    out["c3"] = config_entry(SU3_32_F32_TWO_ROW, ["f32r12", "f32", "f64"], 200, 100,
+                             label="su3_32^4_hot (two-row FP32, 18-real FP32, FP64)")
+    for r32, r64 in zip(large_nc_runs("f32"), large_nc_runs("f64")):
+        out[f"c4_su{r32.nc}"] = config_entry(r32, ["f32", "f64"], 200, 100, label=f"su{r32.nc}_12^4_hot")
+    out["c5"] = run_batch(batch_steps, sweeps=200, cut=100)
+    # the z of every FP32-vs-FP64 comparison above, as one chi-square
+    import numpy as np
+    from scipy.stats import chi2
+    zs = []
+    for k, v in out.items():
+        if k == "c5":
+            zs += v["per_chain_z"]
+        else:
+            zs += [d["z"] for d in v["minus_f64"].values()]
+    zs = np.array([z for z in zs if z is not None])
+    out["all_fp32_vs_fp64"] = {"comparisons": int(zs.size), "chi2": float((zs ** 2).sum()),
+                               "p_value": float(chi2.sf((zs ** 2).sum(), zs.size)),
+                               "max_abs_z": float(np.abs(zs).max())}
+    return out
+
+
+def run_batch(steps, sweeps=200, cut=100, tune=True):
     """The 64-chain batch (mixed SU(2)/SU(3), extents 8..20, per-chain beta
-    and seed): FP32 links swept together from a captured graph (each replay
-    is one sweep of every chain: 1 HB + 4 OR, re-unitarization, plaquettes),
-    against the same chains in FP64 swept one chain at a time with eager
-    launches."""
+    and seed), hot start.  FP32 links swept together from a captured graph
+    (each replay one sweep of every chain: 1 HB + 4 OR, re-unitarization,
+    plaquettes), with the launch shapes and the SU(3) link layout chosen by
+    the autotuner; against the same chains in FP64 swept one chain at a time
+    with eager launches.  Both sets run `sweeps` sweeps with the plaquettes
+    of every sweep kept; then `steps` more graph replays are timed alone."""
+    import numpy as np
     import torch
-    from paper_1112_4533_amd import sun
+    from paper_1112_4533_amd import autotune, sun
     from paper_1112_4533_amd.workloads import batch_spec
 
     spec = batch_spec()
     total_sites = sum(r.volume for r in spec)
     n_hb, n_or = spec[0].n_hb, spec[0].n_or
+    betas, seeds = [r.beta for r in spec], [r.seed for r in spec]
     lats = []
     for r in spec:
         lat = sun.Lattice(r.nc, r.L, "f32")
         lat.init(hot=True, seed=r.seed)
         lats.append(lat)
-    bt = sun.Batch(lats, [r.beta for r in spec], [r.seed for r in spec])
+    tuned = {}
     if tune:
-        from paper_1112_4533_amd import autotune
-        autotune.tune_batch(bt, reps=2, use_cache=False)
+        layout, t_layout = autotune.tune_batch_layout(lats, betas, seeds, reps=3, use_cache=False)
+        if layout != "f32":
+            lats = autotune.relayout(lats, layout)
+        tuned["su3_layout"] = layout
+        tuned["layout_ms_per_hb_or_step"] = t_layout
+    bt = sun.Batch(lats, betas, seeds)
+    if tune:
+        best, _ = autotune.tune_batch(bt, reps=2, use_cache=False)
+        tuned["shapes"] = {"heatbath": list(best[0]), "overrelax": list(best[1])}
     plaq32 = torch.zeros((len(spec), 3), dtype=torch.float64, device="cuda")
+    series32 = torch.zeros((sweeps, len(spec)), dtype=torch.float64, device="cuda")
     bt.capture(n_sweeps=1, n_hb=n_hb, n_or=n_or, reunit=True, plaq_out=plaq32)
-    for _ in range(warmup):
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for k in range(sweeps):
         bt.replay()
+        series32[k].copy_(plaq32[:, 0])
+    torch.cuda.synchronize()
+    dt_stats32 = time.perf_counter() - t0
+    # the drift one sweep leaves before re-unitarization
+    bt.sweep(n_hb, n_or, reunit=False)
+    drift32 = max(float(l.unitarity().cpu()[0]) for l in lats)
+    bt.sweep(0, 0, reunit=True)
     torch.cuda.synchronize()
     t0 = time.perf_counter()
     for _ in range(steps):
@@ -226,61 +378,105 @@ def run_batch(steps, warmup, f64_sweeps, tune=False):
         lat = sun.Lattice(r.nc, r.L, "f64")
         lat.init(hot=True, seed=r.seed)
         l64.append(lat)
+    series64 = torch.zeros((sweeps, len(spec)), dtype=torch.float64, device="cuda")
     plaq64 = torch.zeros((len(spec), 3), dtype=torch.float64, device="cuda")
-
-    def sweep64():
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for k in range(sweeps):
         for i, (r, lat) in enumerate(zip(spec, l64)):
             lat.sweep(r.beta, n_hb, n_or, seed=r.seed)
             lat.plaquette(plaq64[i])
-
-    for _ in range(warmup):
-        sweep64()
-    torch.cuda.synchronize()
-    t0 = time.perf_counter()
-    for _ in range(f64_sweeps):
-        sweep64()
+        series64[k].copy_(plaq64[:, 0])
     torch.cuda.synchronize()
     dt64 = time.perf_counter() - t0
-    upd64 = f64_sweeps * (n_hb + n_or) * 4 * total_sites / dt64
-    # both chains sets have now run warmup + timed sweeps; compare their plaquettes
-    # after catching the FP64 set up to the same sweep count
-    for _ in range(steps - f64_sweeps):
-        sweep64()
-    d = (plaq32[:, 0] - plaq64[:, 0]).cpu()
+    upd64 = sweeps * (n_hb + n_or) * 4 * total_sites / dt64
+    for lat, r in zip(l64, spec):
+        lat.sweep(r.beta, n_hb, n_or, seed=r.seed, reunit=False)
+    drift64 = max(float(l.unitarity().cpu()[0]) for l in l64)
+
+    s32, s64 = series32.cpu().numpy(), series64.cpu().numpy()
+    z = []
+    for i in range(len(spec)):
+        z.append(difference(stat_summary(s32[:, i], cut), stat_summary(s64[:, i], cut))["z"])
+    from scipy.stats import chi2
+    zz = np.array(z)
     return {
-        "chains": len(spec), "sites": total_sites,
+        "workload": "64 chains, SU(2) x 32 + SU(3) x 32, extents {8,12,16,20}^4, hot start, 1 HB + 4 OR, "
+                    "re-unitarization every sweep",
+        "chains": len(spec), "sites": total_sites, "sweeps_run": sweeps, "thermalization_cut": cut,
+        "autotuned": tuned,
         "fp32_batched_graph": {"value": upd32, "unit": "link_updates/s", "ms_per_sweep": 1e3 * dt32 / steps,
-                               "sweeps": steps, "launch": {"heatbath": bt.launch[0], "overrelax": bt.launch[1],
-                                                           "sites_per_item": list(bt.sites_per_item)}},
-        "fp64_per_chain_eager": {"value": upd64, "unit": "link_updates/s", "ms_per_sweep": 1e3 * dt64 / f64_sweeps,
-                                 "sweeps": f64_sweeps},
+                               "sweeps_timed": steps,
+                               "ms_per_sweep_with_plaquette_copy": 1e3 * dt_stats32 / sweeps,
+                               "max_unitarity_dev_before_reunit": drift32},
+        "fp64_per_chain_eager": {"value": upd64, "unit": "link_updates/s", "ms_per_sweep": 1e3 * dt64 / sweeps,
+                                 "sweeps_timed": sweeps, "max_unitarity_dev_before_reunit": drift64},
         "speedup": upd32 / upd64,
-        "plaquette_f32_minus_f64": {"mean": float(d.mean()), "std": float(d.std()),
-                                    "after_sweeps": warmup + steps},
+        "per_chain_z": [float(v) for v in z],
+        "fp32_vs_fp64": {"chi2": float((zz ** 2).sum()), "dof": len(z), "p_value": float(chi2.sf((zz ** 2).sum(),
+                                                                                                  len(z))),
+                         "max_abs_z": float(np.abs(zz).max()), "mean_z": float(zz.mean())},
     }
 
 
-def run_cpu_baseline(run, sweeps):
+def cpu_model():
+    try:
+        with open("/proc/cpuinfo") as f:
+            for line in f:
+                if line.startswith("model name"):
+                    return line.split(":", 1)[1].strip()
+    except OSError:
+        pass
+    import platform
+    return platform.processor() or "unknown"
+
+
+def run_cpu_baseline(run, sweeps, single_thread=True):
     """The FP64 CPU oracle on a bounded sample of the same workload: a few
-    full sweeps (1 HB + 4 OR, re-unitarization, plaquette) of the 32^4 lattice
-    from the same hot start."""
+    full sweeps (1 HB + 4 OR, re-unitarization, plaquette) of the lattice
+    from the same hot start on all the threads OpenMP gives it, and on one
+    thread one heatbath phase and two overrelaxation phases, weighted as the
+    1 : 4 mix of a sweep."""
     import oracle as O
 
     U = O.new_field(run.nc, run.L, hot=run.hot, seed=run.seed)
+    threads = O.num_threads()
     t0 = time.perf_counter()
     for k in range(sweeps):
         O.sweep(U, run.nc, run.L, run.beta, run.n_hb, run.n_or, run.seed, k * run.n_hb, reunit=True)
         O.plaquette(U, run.nc, run.L)
     dt = time.perf_counter() - t0
     updates = sweeps * (run.n_hb + run.n_or) * 4 * run.volume
-    return {
+    out = {
         "value": updates / dt,
         "unit": "link_updates/s",
-        "cores": O.num_threads(),
+        "cores": threads,
         "kind": "oracle",
         "sample": (f"{sweeps} sweeps (1 HB + 4 OR + re-unitarization + plaquette) of SU(3) {run.L[0]}^4 "
-                   f"from the hot start, FP64: {updates} link updates in {dt:.2f} s"),
+                   f"from the hot start, FP64: {updates} link updates in {dt:.2f} s on {threads} threads"),
+        "cpu_model": cpu_model(),
+        "host_cpus": os.cpu_count(),
     }
+    if single_thread:
+        O.set_num_threads(1)
+        try:
+            t0 = time.perf_counter()
+            O.phase(U, run.nc, run.L, 0, 0, 0, run.beta, run.seed, sweeps)
+            t_hb = time.perf_counter() - t0
+            t0 = time.perf_counter()
+            O.phase(U, run.nc, run.L, 1, 0, 0, run.beta, run.seed, 0)
+            O.phase(U, run.nc, run.L, 1, 0, 1, run.beta, run.seed, 0)
+            t_or = (time.perf_counter() - t0) / 2
+        finally:
+            O.set_num_threads(threads)
+        half = run.volume // 2
+        out["single_thread"] = {
+            "value": (run.n_hb + run.n_or) * half / (run.n_hb * t_hb + run.n_or * t_or),
+            "unit": "link_updates/s",
+            "sample": f"one heatbath phase ({t_hb:.2f} s) and two overrelaxation phases ({t_or:.2f} s each) of "
+                      f"{half} links on one thread, weighted {run.n_hb} : {run.n_or}",
+        }
+    return out
 
 
 PEAK_FP32_TFLOPS = 78.6          # MI355X vector FP32 without packed instructions (= the FP64 rate)
@@ -370,8 +566,8 @@ def main():
     ap.add_argument("--cpu-sweeps", type=int, default=8, help="oracle sweeps in the CPU-baseline sample")
     ap.add_argument("--no-f64", action="store_true")
     ap.add_argument("--no-batch", action="store_true")
-    ap.add_argument("--precision-sweeps", type=int, default=6,
-                    help="sweeps of the untimed FP32-storage vs FP64 chain comparison")
+    ap.add_argument("--no-configs", action="store_true",
+                    help="skip the run of every workload with its FP32-vs-FP64 statement")
     ap.add_argument("--head", choices=["two_row", "eighteen"], default="two_row",
                     help="SU(3) storage of the headline line (the other is reported beside it)")
     ap.add_argument("--no-second", action="store_true", help="skip the other storage's leg")
@@ -409,6 +605,7 @@ def main():
     # the headline is the faster FP32 storage of the same workload (two-row);
     # --head eighteen makes the 18-real form the headline
     head, other = ((SU3_32_F32_TWO_ROW, SU3_32_F32) if args.head == "two_row" else (SU3_32_F32, SU3_32_F32_TWO_ROW))
+    copy_gbps = copy_ceiling()
     r_head = run_gpu(head, args.steps, args.warmup, tune=args.tune)
     r18 = None if args.no_second else run_gpu(other, args.steps, args.warmup, tune=args.tune)
     r64 = None if args.no_f64 else run_gpu(SU3_32_F64, max(2, args.steps // 2), max(1, args.warmup // 2))
@@ -434,7 +631,7 @@ def main():
                         if head.dtype.endswith("r12") else "FP32, full 3x3 (18 reals per link)"),
             "step": "sweep + reunitarize(drift) + plaquette + polyakov",
         },
-        "roofline": roofline(head, r_head),
+        "roofline": roofline(head, r_head, copy_gbps),
         "effective_GBps_whole_step": step_bytes(head.nc, V, head.dtype, head.n_hb, head.n_or)
         / (r_head["ms_per_step"] * 1e-3) / 1e9,
         "kernels": r_head["kernels"],
@@ -449,7 +646,7 @@ def main():
     if r18:
         line["eighteen_real" if args.head == "two_row" else "two_row"] = {
             "workload": other.name, "value": r18["updates_per_s"], "unit": "link_updates/s",
-            "ms_per_step": r18["ms_per_step"], "roofline": roofline(other, r18), "kernels": r18["kernels"],
+            "ms_per_step": r18["ms_per_step"], "roofline": roofline(other, r18, copy_gbps), "kernels": r18["kernels"],
             "launch": r18["launch"], "plaquette": r18["plaquette"],
             "max_unitarity_dev_before_reunit": r18["unitarity_before_reunit"],
             "overrelaxation_rel_action_change": r18["or_dS_over_S"],
@@ -463,10 +660,16 @@ def main():
             "overrelaxation_rel_action_change": r64["or_dS_over_S"],
             "fp32_over_fp64": r_head["updates_per_s"] / r64["updates_per_s"],
         }
-    if not args.no_f64:
-        line["precision"] = run_precision(head, args.precision_sweeps)
-    if not args.no_batch:
-        line["batch"] = run_batch(max(4, args.steps), args.warmup, max(2, args.steps // 4), tune=args.tune)
+    if not args.no_configs:
+        line["configs"] = run_configs(max(4, args.steps))
+        if not args.no_batch:
+            c5 = line["configs"]["c5"]
+            line["batch"] = {k: c5[k] for k in ("chains", "sites", "autotuned", "fp32_batched_graph",
+                                                "fp64_per_chain_eager", "speedup")}
+    elif not args.no_batch:
+        b = run_batch(max(4, args.steps), sweeps=max(8, args.steps), cut=max(8, args.steps) // 2)
+        line["batch"] = {k: b[k] for k in ("chains", "sites", "autotuned", "fp32_batched_graph",
+                                           "fp64_per_chain_eager", "speedup")}
     if not args.no_cpu_baseline:
         line["cpu_baseline"] = run_cpu_baseline(SU3_32_F32, args.cpu_sweeps)
     print(json.dumps(line), flush=True)

@@ -31,6 +31,8 @@ def lib():
         L4 = ctypes.c_int * 4
         L.orc_num_threads.argtypes = []
         L.orc_num_threads.restype = ctypes.c_int
+        L.orc_set_num_threads.argtypes = [ctypes.c_int]
+        L.orc_set_num_threads.restype = ctypes.c_int
         L.orc_philox4x32_10.argtypes = [u32p, u32p, u32p]
         L.orc_uniform.argtypes = [ctypes.c_uint32]
         L.orc_uniform.restype = ctypes.c_double
@@ -88,6 +90,11 @@ def valid(nc, L):
 
 def num_threads():
     return int(lib().orc_num_threads())
+
+
+def set_num_threads(n):
+    """Threads of later lattice-wide calls (results do not depend on it)."""
+    _check(lib().orc_set_num_threads(int(n)), "set_num_threads")
 
 
 def philox(ctr, key):

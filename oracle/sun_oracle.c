@@ -80,6 +80,14 @@ int orc_num_threads(void)
     return omp_get_max_threads();
 }
 
+/* Threads of later lattice-wide calls (n >= 1); results do not depend on it. */
+int orc_set_num_threads(int n)
+{
+    if (n < 1) return -1;
+    omp_set_num_threads(n);
+    return 0;
+}
+
 /* 24-bit uniform in (0, 1]; exactly representable in float and double. */
 double orc_uniform(uint32_t w)
 {

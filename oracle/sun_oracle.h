@@ -31,8 +31,10 @@
 extern "C" {
 #endif
 
-/* OpenMP threads the lattice-wide calls use. */
+/* OpenMP threads the lattice-wide calls use, and a setter for them (n >= 1;
+ * results do not depend on the thread count). */
 int orc_num_threads(void);
+int orc_set_num_threads(int n);
 
 /* Raw generator, for known-answer tests. */
 void orc_philox4x32_10(const uint32_t ctr[4], const uint32_t key[2], uint32_t out[4]);

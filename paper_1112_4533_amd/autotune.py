@@ -1,4 +1,4 @@
-"""Launch-shape autotuner for the phase kernels.
+"""Launch-shape and layout autotuner for the phase kernels.
 
 The phase kernels come in workgroup sizes of 64, 128 and 256 work-items, with
 the XCD-aware or the plain workgroup order, with a cap of 8, 12, 16 or no
@@ -13,6 +13,13 @@ for L2 reuse.  The tuner times heatbath-only and overrelaxation-only steps on
 a clone of the field (the chain itself is never touched), applies the
 fastest shape of each kind, and remembers the choice in a JSON cache keyed
 by GPU architecture, Nc, extents and storage (or by the chain list of a batch).
+
+For batches the link layout is a dimension too: the FP32 SU(3) chains can be
+stored with all 18 reals or as two rows (12 reals, row 2 rebuilt on load;
+paper Sec. 3).  tune_batch_layout times a heatbath and an overrelaxation
+step of the whole batch in each layout (on clones) and relayout() moves the
+chains into the chosen one.  Unlike the launch shape, the layout changes the
+rounding of the links, so a chain keeps its layout for its whole run.
 """
 import json
 import os
@@ -166,6 +173,47 @@ def tune_batch(batch, reps=3, use_cache=True):
         batch.set_sites_per_item(v, kind=kind)
     cache[key] = {"shape": {str(k): list(v) for k, v in best.items()},
                   "sites_per_item": {str(k): v for k, v in spt.items()}, "ms": times}
+    if use_cache:
+        _save_cache(cache)
+    return best, times
+
+
+def relayout(lattices, su3_f32_dtype):
+    """New lattices holding the same fields, with every FP32 SU(3) chain
+    stored as su3_f32_dtype ("f32" or "f32r12") and the others unchanged;
+    step counters are carried over."""
+    out = []
+    for l in lattices:
+        dt = sun.DTYPE_NAMES[l.dtype]
+        if l.nc == 3 and dt in ("f32", "f32r12"):
+            dt = su3_f32_dtype
+        n = sun.Lattice(l.nc, l.L, dt, device=l.links.device)
+        n.import_(l.export())
+        n.step = l.step
+        out.append(n)
+    return out
+
+
+LAYOUTS = ("f32", "f32r12")
+
+
+def tune_batch_layout(lattices, betas, seeds, reps=3, use_cache=True):
+    """Times one heatbath and one overrelaxation step of the batch with its
+    FP32 SU(3) chains in each layout of LAYOUTS (on clones, default launch
+    shapes); returns (fastest layout, {layout: ms per HB + OR step})."""
+    key = f"{_arch()}:layout:" + ",".join(
+        f"su{l.nc}:{'x'.join(map(str, l.L))}:{sun.DTYPE_NAMES[l.dtype]}" for l in lattices)
+    cache = _load_cache() if use_cache else {}
+    if key in cache:
+        return cache[key]["layout"], cache[key]["ms"]
+    times = {}
+    for lay in LAYOUTS:
+        clones = relayout(lattices, lay)
+        cb = sun.Batch(clones, betas, seeds)
+        times[lay] = _time(lambda: (cb.sweep(1, 0, reunit=False), cb.sweep(0, 1, reunit=False)), reps)
+        del cb, clones
+    best = min(times, key=times.get)
+    cache[key] = {"layout": best, "ms": times}
     if use_cache:
         _save_cache(cache)
     return best, times
