@@ -33,6 +33,18 @@ def rounded(field, dtype):
     return r + 1j * i
 
 
+EPS = {"f32": 2.0 ** -24, "f64": 2.0 ** -53}   # unit roundoff of the storage precision
+EVIDENCE = []            # one record per comparison (written out by conftest)
+
+
+def record(**kw):
+    """Keeps a parity measurement; conftest prints them all at the end of
+    the session and writes them to $SUN_PARITY_EVIDENCE if set."""
+    import os
+    kw.setdefault("test", os.environ.get("PYTEST_CURRENT_TEST", "").split(" ")[0])
+    EVIDENCE.append(kw)
+
+
 def compare_links(gpu_field, orc_field, dtype, margin=None, cond=None, what="", spread=None, spread_factor=100.0,
                   decisions=None):
     """Link-by-link comparison; margin and cond are (4, V) arrays from the
@@ -42,24 +54,56 @@ def compare_links(gpu_field, orc_field, dtype, margin=None, cond=None, what="", 
     given, is the oracle's own per-link sensitivity (twin_spread); a link
     may then also differ by up to spread_factor times it."""
     d = np.abs(gpu_field - orc_field).reshape(4, gpu_field.shape[1], -1).max(axis=2)
-    scale = np.ones_like(d)
+    base = np.ones_like(d)
+    c = None
     if cond is not None:
         c = np.asarray(cond, dtype=np.float64)
-        scale = np.maximum(1.0, np.where(c > 0, c, 0.0) / (2.0 if dtype.startswith("f32") else 4.0))
-    tol = TOL[dtype] * scale
+        base = np.maximum(1.0, np.where(c > 0, c, 0.0) / (2.0 if dtype.startswith("f32") else 4.0))
+    tol = TOL[dtype] * base
     if spread is not None:
         tol = np.maximum(tol, spread_factor * spread)
+    bad = d > tol
+    ok = ~bad
+    rec = {"what": what, "dtype": dtype, "links": int(d.size), "max_dU": float(d.max()),
+           "max_dU_over_tol": float((d / tol)[ok].max()) if ok.any() else None,
+           "max_dU_over_ctol": float((d / (TOL[dtype] * base))[ok].max()) if ok.any() else None}
+    if c is not None:
+        upd = (c > 0) & ok
+        if upd.any():
+            eps = EPS[dtype[:3]]
+            # the rounding model: |dU| ~ K eps (1 + c); K measured here
+            rec["max_K"] = float((d[upd] / (eps * (1.0 + c[upd]))).max())
+            rec["max_cond"] = float(c[upd].max())
+    if spread is not None:
+        sp = np.asarray(spread)
+        m = (sp > 0) & ok
+        if m.any():
+            rec["max_dU_over_spread"] = float((d[m] / sp[m]).max())
+        # links that only the spread term admits
+        only = m & (d > TOL[dtype] * base)
+        rec["spread_admitted"] = int(only.sum())
+        if only.any():
+            rec["max_dU_over_spread_admitted"] = float((d[only] / sp[only]).max())
+    if decisions is not None:
+        rec["decisions"] = int(decisions)
     if cond is not None or spread is not None:
-        print(f"{what}: max |dU| {d.max():.2e}, max |dU| / tol {(d / tol).max():.3f}")
-    scale = tol / TOL[dtype]
-    bad = d > TOL[dtype] * scale
+        print(f"{what}: max |dU| {d.max():.2e}, max |dU| / tol {rec['max_dU_over_tol']}")
     if not bad.any():
+        rec["flips"] = 0
+        record(**rec)
         return 0
     idx = np.argwhere(bad)
+    rec["flips"] = int(len(idx))
+    if margin is not None:
+        mm = np.asarray(margin)
+        rec["flip_margins"] = [float(mm[a][b]) for a, b in idx[:50]]
+        if c is not None:
+            rec["flip_conds"] = [float(c[a][b]) for a, b in idx[:50]]
+    record(**rec)
     if dtype.startswith("f64") or margin is None:
         mu, s = idx[0]
         raise AssertionError(f"{what}: {len(idx)} links out of tolerance, e.g. (mu={mu}, s={s}) "
-                             f"|dU| = {d[mu, s]:.3e}, tol {TOL[dtype] * scale[mu, s]:.2e}")
+                             f"|dU| = {d[mu, s]:.3e}, tol {tol[mu, s]:.2e}")
     m = np.where(np.asarray(margin) < 0, np.inf, margin)
     # the window of flippable decisions widens by the measured amplification
     window = FLIP_MARGIN * (np.maximum(1.0, spread_factor * spread / TOL[dtype]) if spread is not None

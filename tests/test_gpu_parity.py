@@ -28,8 +28,21 @@ from stats import binned_mean_err
 
 pytestmark = pytest.mark.gpu
 
-from gpu_common import (BETA, FLIP_MARGIN, TOL, compare_links, gpu_lattice, oracle_phase_diag, rounded,
-                        thermal_field, to_np)
+from gpu_common import (BETA, EPS, FLIP_MARGIN, TOL, compare_links, gpu_lattice, oracle_phase_diag, record,
+                        rounded, thermal_field, to_np)
+
+
+def record_draws(what, dtype, alpha, d, bad, margin):
+    """Evidence of a sampler comparison: the largest deviation of the draws
+    that agree, in units of the tolerance and of eps (1 + alpha) (alpha
+    enters through the logarithms and the division by alpha), and the
+    margins of the draws whose decision flipped."""
+    ok = ~bad
+    record(what=what, dtype=dtype, links=int(d.size), max_dU=float(d[ok].max()),
+           max_dU_over_tol=float(d[ok].max() / TOL[dtype]),
+           max_K_alpha=float((d[ok] / (EPS[dtype[:3]] * (1.0 + alpha[ok]))).max()),
+           flips=int(bad.sum()), flip_margins=[float(m) for m in margin[bad][:50]],
+           flip_alphas=[float(a) for a in alpha[bad][:50]])
 
 
 # ---------------------------------------------------------------------------
@@ -44,6 +57,7 @@ def test_sampler_parity(gpu, dtype):
     xo, ao, margin = O.sample_su2(alpha, seed=31, step=5, mu_sg=(2 << 16) | 1)
     d = np.abs(xg - xo).max(axis=1)
     bad = (d > TOL[dtype]) | (ag != ao)
+    record_draws("sampler alpha 0..60", dtype, alpha, d, bad, margin)
     if dtype == "f64":
         assert not bad.any(), d.max()
     else:
@@ -61,6 +75,7 @@ def test_sampler_parity_large_alpha(gpu, dtype):
     xo, ao, margin = O.sample_su2(alpha, seed=77, step=3, mu_sg=(1 << 16) | 5)
     d = np.abs(xg - xo).max(axis=1)
     bad = (d > TOL[dtype]) | (ag != ao)
+    record_draws("sampler alpha 60..5000", dtype, alpha, d, bad, margin)
     if dtype == "f64":
         assert not bad.any(), d.max()
     else:
@@ -283,6 +298,32 @@ def test_sweep_trajectory_parity_phase_by_phase(gpu, nc, dtype, hot):
     print(f"FP32 decision flips along the trajectory: {flips}")
 
 
+@pytest.mark.parametrize("dtype", ["f32", "f32r12"])
+def test_bench_schedule_trajectory_phase_by_phase(gpu, dtype):
+    """The benchmark's schedule on 8^4 from a hot start: 1 HB + 4 OR with no
+    re-unitarization until the end of the sweep, so the FP32 links drift
+    away from unitarity (~1e-6) across the 40 phases while the SU(3) staple
+    terms are built with row 2 = conj(row0 x row1), which is exact only for
+    unitary links.  Every phase is compared with the oracle (full 3 x 3
+    products) applied to the GPU's own state before it."""
+    nc, L, beta, seed = 3, (8, 8, 8, 8), 6.2, 1234
+    lat = gpu_lattice(gpu, nc, L, dtype, hot=True, seed=seed)
+    flips = 0
+    for sweep in range(2):
+        for kind, step in [(0, sweep)] + [(1, 0)] * 4:
+            for mu in range(4):
+                for p in range(2):
+                    before = to_np(lat.export())
+                    lat.phase(kind, mu, p, beta, seed, step)
+                    m, k = oracle_phase_diag(before, nc, L, kind, mu, p, beta, seed, step)
+                    flips += compare_links(to_np(lat.export()), before, dtype, m, k,
+                                           f"bench schedule sweep {sweep} kind {kind} mu {mu} p {p}")
+        drift = to_np(lat.reunitarize(report=True))
+        record(what=f"drift before reunit, sweep {sweep}", dtype=dtype, drift=float(drift[0]))
+        assert 1e-8 < drift[0] < 1e-4
+    print(f"FP32 decision flips along the bench schedule: {flips}")
+
+
 def sensitivity(U0, nc, L, beta, n_hb, n_or, seed, nsweeps, eps):
     """Max |U - U'| per sweep between two oracle chains whose start differs
     by eps-sized noise: how far rounding alone can move this trajectory."""
@@ -437,6 +478,16 @@ def test_profile_counts_launches(gpu):
     lat.profile(False)
     lat.sweep(6.0, 1, 4, seed=1)
     assert lat.profile_read("overrelax")[1] == 0
+    # run mode: one event pair per run of back-to-back launches of a kind,
+    # counted as that many launches; single phases are runs of one
+    lat.profile(True, every=-1)
+    lat.sweep(6.0, 1, 4, seed=1)
+    lat.sweep(6.0, 2, 1, seed=1)
+    lat.phase(1, 0, 0, 6.0, 1, 0)
+    ms_or, n_or = lat.profile_read("overrelax")
+    assert lat.profile_read("heatbath")[1] == 24 and n_or == 41 and ms_or > 0
+    assert lat.profile_read("reunit")[1] == 2
+    lat.profile(False)
 
 
 def test_rejects_bad_arguments(gpu):
