@@ -129,11 +129,16 @@ __global__ void k_fill(double* __restrict__ p, int n, double v) {
 // coordinates and plane offsets are compile-time, and the scheduler can issue
 // the loads of later directions ahead of the arithmetic of earlier ones.
 //
-// For SU(3) each staple term is itself in SU(3), so only its rows 0 and 1 are
-// formed by products and row 2 is conj(row0 x row1) (exact for SU(3); the
-// same identity the two-row storage relies on).  The leading factor then
-// needs only its rows 0 and 1 (upper staple) or its columns 0 and 1 (lower
-// staple).  This saves about a tenth of the update's arithmetic.
+// For SU(3) in FP64 each staple term is itself in SU(3), so only its rows 0
+// and 1 are formed by products and row 2 is conj(row0 x row1); the leading
+// factor then needs only its rows 0 and 1 (upper staple) or its columns 0 and
+// 1 (lower staple), about a tenth of the update's arithmetic.  The identity
+// holds only for unitary factors: for factors off SU(3) by a unitarity
+// deviation delta the rebuilt row is off by 1.2 delta typically and 4 delta
+// at most, which FP64 links (delta ~ 1e-15 between re-unitarizations) never
+// notice.  FP32 links drift to delta ~ 1e-5 across a sweep, the size of the
+// comparison tolerance itself, so FP32 forms every term by full products
+// (2.8% of the two-row step, 9% of the 18-real one).
 template <int N, typename T, int R, int MU, int NU>
 __device__ __forceinline__ void staple_dir(Mat<N, T>& A, const T2<T>* __restrict__ U, const Geom& g, const Site& x,
                                            const Site& xp, int par, int h) {
@@ -143,7 +148,7 @@ __device__ __forceinline__ void staple_dir(Mat<N, T>& A, const T2<T>* __restrict
         const Site xpn = step_up(g, x, NU);
         const Site xmn = step_down(g, x, NU);
         const Site xpmn = step_down(g, xp, NU);
-        if constexpr (N == 3) {
+        if constexpr (N == 3 && sizeof(T) == 8) {
             // upper: rows 0, 1 of U_nu(x+mu) U_mu(x+nu)^dag U_nu(x)^dag
             const Mat<3, T> t = mul_nd_rows2(load_rows01<T, R>(U, NU, op, xp.s >> 1, g.Vh),
                                              load_mat<3, T, R>(U, MU, op, xpn.s >> 1, g.Vh));

@@ -65,9 +65,17 @@ inline bool valid_wave_cap(int w) { return w == 0 || w == 8 || w == 12 || w == 1
 
 // The plaquette kernel re-reads each link from up to six sites; with its
 // register use alone a CU holds 16 of its waves, and their combined working
-// set thrashes the L2.  Twelve resident waves per CU measured 13% faster on
-// SU(3) 32^4 (FP32 two-row: 117.8 -> 102.1 us; 8 waves: 119.5 us).
-constexpr int kPlaquetteWaveCap = 12;
+// set can thrash the L2.  The best cap depends on whether the field stays in
+// the Infinity Cache (measured on SU(3) 32^4): the 201 MB two-row FP32 field
+// runs best uncapped at 16 waves per CU (8 / 12 / 16: 115.7 / 107.3 /
+// 104.6 us), the 302 MB 18-real field at 8 (150 / 152 / 165.5 us), and the
+// 604 MB FP64 field at 12 (358 us against 369 uncapped).
+constexpr size_t kInfinityCacheBytes = 256ull << 20;
+inline int plaquette_wave_cap(size_t field_bytes) {
+    if (field_bytes <= kInfinityCacheBytes) return 16;
+    if (field_bytes <= kPlainAccessMaxBytes) return 8;
+    return 12;
+}
 
 // Launch shapes the phase kernels are instantiated for.
 constexpr int kPhaseBlocks[3] = {64, 128, 256};

@@ -70,7 +70,8 @@ struct OpsImpl {
     }
 
     static void plaquette_batch(const ChainDesc* d, int n, int tiles, double* out, hipStream_t s) {
-        k_plaquette_batch<N, T, R><<<tiles, kBlock, lds_for_wave_cap(kPlaquetteWaveCap, kBlock), s>>>(d, n);
+        // the chains of a batch are small, cache-resident lattices
+        k_plaquette_batch<N, T, R><<<tiles, kBlock, lds_for_wave_cap(plaquette_wave_cap(0), kBlock), s>>>(d, n);
         k_plaquette_final_batch<N><<<n, kBlock, 0, s>>>(d, n, out);
     }
 
@@ -107,7 +108,8 @@ struct OpsImpl {
         return link_blocks(c.g);
     }
     static int plaquette(const Ctx& c, double* partial) {
-        k_plaquette<N, T, R><<<plaquette_tiles(c.g), kBlock, lds_for_wave_cap(kPlaquetteWaveCap, kBlock),
+        const size_t field = sizeof(P) * (size_t)Planes<N, R>::E * 4 * (size_t)c.g.V;
+        k_plaquette<N, T, R><<<plaquette_tiles(c.g), kBlock, lds_for_wave_cap(plaquette_wave_cap(field), kBlock),
                                c.stream>>>((const P*)c.links, c.g, partial);
         return plaquette_tiles(c.g);
     }

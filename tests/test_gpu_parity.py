@@ -2,22 +2,29 @@
 
 Both sides draw the same Philox words, so one chain is one sample path.
 
-Tolerances.  Within one checkerboard phase every updated link depends only on
-links the phase does not touch, so a phase is compared link by link without
-cascades: FP64 to 1e-12 x max(1, c / 4) and FP32 to 1e-5 x max(1, c / 2),
-where c = |A|_F / k_min is the conditioning of that link's update (the
-rounding of W = U A is of order eps |A|, and the subgroup direction V = P / k
-divides it by k; c is about 4 for a typical link of a hot start).  The FP32
-constant 2 leaves room for the tail over the 2.1M links of the 32^4 case,
-where 1e-5 x c / 4 was exceeded by 28% at one link.  For
-FP32, a link may also differ by O(1) when one of its floating-point decisions
-(Creutz/KP switch, accept test) sits within 1e-4 of its threshold in the
-oracle; such links are counted and bounded.  Over several sweeps the chain is
-chaotic (the oracle itself, perturbed at 1e-16, drifts by orders of magnitude
-per sweep), so free-running sweeps are compared against that measured
-sensitivity, and whole-sweep parity is instead checked phase by phase along
-the trajectory, plus bitwise equality of a sweep with its documented sequence
-of phases.
+Tolerances (an error model, not fitted constants).  Within one checkerboard
+phase every updated link depends only on links the phase does not touch, so a
+phase is compared link by link without cascades.  The rounding of W = U A is
+of order eps |A| (eps the storage precision's unit roundoff), and the
+subgroup direction V = P / k divides it by k, so a link whose update has
+conditioning c = |A|_F / k_min (reported by the oracle) lands within
+K eps (1 + c) of the oracle.  Counting the operations gives a worst case of a
+few hundred for K (staple: six triple products of 3 x 3 matrices summed;
+W = U A; three subgroup steps, each dividing by its k); the test uses
+K = 64 (gpu_common.K_LINK), above the largest K measured over every
+comparison (19 in FP64, 14 in FP32 on fresh fields, 34 in FP32 on fields
+drifted by 6e-6 across a sweep without re-unitarization, where the staple's
+SU(3) row-2 shortcut adds an error of order the drift).  FP32 decisions
+(Creutz/KP switch, accept test) depend on alpha = 2 beta k / Nc and so move
+by about the same relative amount; a link may differ by O(1) only where the
+oracle's margin of one of its decisions lies within K_FLIP eps (1 + c),
+K_FLIP = 2 K_LINK, and no more links may do so than three times the
+expected number (or 3).  Over several sweeps the chain is chaotic (the
+oracle itself, perturbed at 1e-16, drifts by orders of magnitude per sweep),
+so free-running sweeps are compared against that measured sensitivity, and
+whole-sweep parity is instead checked phase by phase along the trajectory,
+plus bitwise equality of a sweep with its documented sequence of phases.
+Every comparison records how close it ran to its bound (gpu_common.record).
 """
 import numpy as np
 import pytest
@@ -28,8 +35,8 @@ from stats import binned_mean_err
 
 pytestmark = pytest.mark.gpu
 
-from gpu_common import (BETA, EPS, FLIP_MARGIN, TOL, compare_links, gpu_lattice, oracle_phase_diag, record,
-                        rounded, thermal_field, to_np)
+from gpu_common import (BETA, EPS, K_FLIP, K_TYP, SPREAD_FACTOR, TOL, compare_links, gpu_lattice,
+                        oracle_phase_diag, record, rounded, thermal_field, to_np)
 
 
 def record_draws(what, dtype, alpha, d, bad, margin):
@@ -45,6 +52,22 @@ def record_draws(what, dtype, alpha, d, bad, margin):
            flip_alphas=[float(a) for a in alpha[bad][:50]])
 
 
+def check_draw_flips(dtype, alpha, bad, margin):
+    """FP64 draws agree everywhere.  An FP32 draw may take the other branch
+    of a decision only where the oracle's margin lies within the decision
+    window K_FLIP eps (1 + alpha) (alpha rounded to FP32 moves every
+    decision input by about eps alpha), and no more draws may do so than
+    three times the expected count (two decisions per draw, each flipping
+    with probability at most 2 K_TYP eps (1 + alpha)), or 3."""
+    if dtype.startswith("f64"):
+        assert not bad.any(), int(bad.sum())
+        return
+    eps = EPS["f32"]
+    assert np.all(margin[bad] < K_FLIP * eps * (1.0 + alpha[bad])), margin[bad]
+    expected = float((2 * 2 * K_TYP * eps * (1.0 + alpha)).sum())
+    assert bad.sum() <= max(3.0, 3.0 * expected), (int(bad.sum()), expected)
+
+
 # ---------------------------------------------------------------------------
 # The SU(2) draw
 # ---------------------------------------------------------------------------
@@ -58,11 +81,7 @@ def test_sampler_parity(gpu, dtype):
     d = np.abs(xg - xo).max(axis=1)
     bad = (d > TOL[dtype]) | (ag != ao)
     record_draws("sampler alpha 0..60", dtype, alpha, d, bad, margin)
-    if dtype == "f64":
-        assert not bad.any(), d.max()
-    else:
-        assert np.all(margin[bad] < FLIP_MARGIN)
-        assert bad.sum() <= 5
+    check_draw_flips(dtype, alpha, bad, margin)
 
 
 @pytest.mark.parametrize("dtype", ["f64", "f32"])
@@ -76,11 +95,7 @@ def test_sampler_parity_large_alpha(gpu, dtype):
     d = np.abs(xg - xo).max(axis=1)
     bad = (d > TOL[dtype]) | (ag != ao)
     record_draws("sampler alpha 60..5000", dtype, alpha, d, bad, margin)
-    if dtype == "f64":
-        assert not bad.any(), d.max()
-    else:
-        assert np.all(margin[bad] < FLIP_MARGIN)
-        assert bad.sum() <= 5
+    check_draw_flips(dtype, alpha, bad, margin)
     assert np.all(ag > 0)                        # no draw runs out of attempts
     assert np.all(np.abs(np.linalg.norm(xg, axis=1) - 1) < 1e-5)
 
@@ -298,18 +313,19 @@ def test_sweep_trajectory_parity_phase_by_phase(gpu, nc, dtype, hot):
     print(f"FP32 decision flips along the trajectory: {flips}")
 
 
-@pytest.mark.parametrize("dtype", ["f32", "f32r12"])
-def test_bench_schedule_trajectory_phase_by_phase(gpu, dtype):
-    """The benchmark's schedule on 8^4 from a hot start: 1 HB + 4 OR with no
+@pytest.mark.parametrize("dtype,L,sweeps", [("f32", (8, 8, 8, 8), 2), ("f32r12", (8, 8, 8, 8), 2),
+                                            ("f32", (16, 16, 16, 16), 1), ("f32r12", (16, 16, 16, 16), 1)])
+def test_bench_schedule_trajectory_phase_by_phase(gpu, dtype, L, sweeps):
+    """The benchmark's schedule on 8^4 and 16^4 from a hot start: 1 HB + 4 OR with no
     re-unitarization until the end of the sweep, so the FP32 links drift
     away from unitarity (~1e-6) across the 40 phases while the SU(3) staple
     terms are built with row 2 = conj(row0 x row1), which is exact only for
     unitary links.  Every phase is compared with the oracle (full 3 x 3
     products) applied to the GPU's own state before it."""
-    nc, L, beta, seed = 3, (8, 8, 8, 8), 6.2, 1234
+    nc, beta, seed = 3, 6.2, 1234
     lat = gpu_lattice(gpu, nc, L, dtype, hot=True, seed=seed)
     flips = 0
-    for sweep in range(2):
+    for sweep in range(sweeps):
         for kind, step in [(0, sweep)] + [(1, 0)] * 4:
             for mu in range(4):
                 for p in range(2):
@@ -324,17 +340,19 @@ def test_bench_schedule_trajectory_phase_by_phase(gpu, dtype):
     print(f"FP32 decision flips along the bench schedule: {flips}")
 
 
-def sensitivity(U0, nc, L, beta, n_hb, n_or, seed, nsweeps, eps):
-    """Max |U - U'| per sweep between two oracle chains whose start differs
-    by eps-sized noise: how far rounding alone can move this trajectory."""
+def sensitivity(U0, nc, L, beta, n_hb, n_or, seed, nsweeps, eps, twins=3):
+    """Max |U - U'| per sweep between an oracle chain and twins whose start
+    differs by eps-sized noise (the largest over `twins` twins): how far
+    rounding alone can move this trajectory."""
     rng = np.random.default_rng(0)
     a = U0.copy()
-    b = U0 + eps * (rng.standard_normal(U0.shape) + 1j * rng.standard_normal(U0.shape))
+    bs = [U0 + eps * (rng.standard_normal(U0.shape) + 1j * rng.standard_normal(U0.shape)) for _ in range(twins)]
     out = []
     for k in range(nsweeps):
         O.sweep(a, nc, L, beta, n_hb, n_or, seed, k * n_hb)
-        O.sweep(b, nc, L, beta, n_hb, n_or, seed, k * n_hb)
-        out.append(np.abs(a - b).max())
+        for b in bs:
+            O.sweep(b, nc, L, beta, n_hb, n_or, seed, k * n_hb)
+        out.append(max(np.abs(a - b).max() for b in bs))
     return out
 
 
@@ -348,8 +366,12 @@ def sensitivity(U0, nc, L, beta, n_hb, n_or, seed, nsweeps, eps):
 ])
 def test_free_running_sweeps_f64(gpu, nc, L, beta, start, n_hb, n_or):
     """Three free-running FP64 sweeps: the GPU chain stays within the
-    rounding sensitivity of the oracle chain (1e-12 + 100 x the spread of a
-    1e-15-perturbed oracle twin), and the plaquettes agree to the same bound."""
+    rounding sensitivity of the oracle chain (1e-12 + SPREAD_FACTOR x the
+    largest spread of three 1e-15-perturbed oracle twins), and the
+    plaquettes agree to the same bound.  The chain is chaotic, so the bound
+    grows about a hundredfold per sweep from a hot start and this test
+    checks little after the first sweep; the phase-by-phase trajectory
+    tests carry the weight there."""
     seed = 1234
     if start == "thermal":
         U = O.new_field(nc, L, hot=False, seed=seed)
@@ -357,7 +379,8 @@ def test_free_running_sweeps_f64(gpu, nc, L, beta, start, n_hb, n_or):
             O.sweep(U, nc, L, beta, 1, 2, 99, k)
     else:
         U = O.new_field(nc, L, hot=(start == "hot"), seed=seed)
-    bound = [1e-12 + 100 * s for s in sensitivity(U, nc, L, beta, n_hb, n_or, seed, 3, 1e-15)]
+    sens = sensitivity(U, nc, L, beta, n_hb, n_or, seed, 3, 1e-15)
+    bound = [1e-12 + SPREAD_FACTOR["f64"] * s for s in sens]
     lat = gpu_lattice(gpu, nc, L, "f64", field=U)
     lat.step = 0
     for k in range(3):
@@ -366,6 +389,8 @@ def test_free_running_sweeps_f64(gpu, nc, L, beta, start, n_hb, n_or):
         assert lat.step == (k + 1) * n_hb
         dev = np.abs(to_np(lat.export()) - U).max()
         print(f"sweep {k}: max |dU| = {dev:.2e}, bound {bound[k]:.2e}")
+        record(what=f"free-running sweep {k}", dtype="f64", max_dU=float(dev), max_dU_over_tol=float(dev / bound[k]),
+               max_dU_over_spread=float(dev / sens[k]) if sens[k] > 0 else None)
         assert dev <= bound[k], (k, dev, bound[k])
         if bound[k] < 1e-6:
             assert np.abs(to_np(lat.plaquette()) - O.plaquette(U, nc, L)).max() <= bound[k]
@@ -419,25 +444,28 @@ def test_2d_su2_exact_plaquette_on_gpu(gpu):
 # ---------------------------------------------------------------------------
 @pytest.mark.parametrize("dtype", ["f32", "f32r12", "f64"])
 def test_full_size_su3_32_phase_parity(gpu, dtype):
+    """Every direction at the benchmark's shape and launch configuration: a
+    heatbath phase and an overrelaxation phase for each mu (the heatbath on
+    one parity, the overrelaxation on the other), each checked link by link
+    from the GPU's own input field (a phase's staples contain links the
+    previous phases updated, so an allowed FP32 decision flip would
+    otherwise cascade), then the plaquette of the final field."""
     nc, L, beta = 3, (32, 32, 32, 32), 6.2
     lat = gpu_lattice(gpu, nc, L, dtype, hot=True, seed=1234)
-    base = to_np(lat.export())
+    before = to_np(lat.export())
     want = O.new_field(nc, L, hot=True, seed=1234)
-    assert np.abs(base - want).max() < 1e-6
-    # Each phase is checked from the GPU's own input field: the second phase's
-    # staples contain links the first one updated, so an FP32 decision flip
-    # there (allowed, near its threshold) would otherwise cascade.
-    lat.phase(0, 2, 0, beta, seed=1234, step=0)
-    mid = to_np(lat.export())
-    m2, k2 = oracle_phase_diag(base, nc, L, 0, 2, 0, beta, 1234, 0)
-    flips = compare_links(mid, base, dtype, m2, k2, "32^4 heatbath")
-    del base
-    lat.phase(1, 3, 1, beta, seed=1234, step=0)
-    got = to_np(lat.export())
-    m3, k3 = oracle_phase_diag(mid, nc, L, 1, 3, 1, beta, 1234, 0)
-    compare_links(got, mid, dtype, m3, k3, "32^4 overrelaxation")
-    print(f"32^4 heatbath flips: {flips}")
-    np.testing.assert_allclose(to_np(lat.plaquette()), O.plaquette(got, nc, L), rtol=0, atol=1e-12)
+    assert np.abs(before - want).max() < 1e-6
+    del want
+    flips = 0
+    for mu in range(4):
+        for kind, par in ((0, mu & 1), (1, (mu & 1) ^ 1)):
+            lat.phase(kind, mu, par, beta, seed=1234, step=0)
+            got = to_np(lat.export())
+            m, k = oracle_phase_diag(before, nc, L, kind, mu, par, beta, 1234, 0)
+            flips += compare_links(got, before, dtype, m, k, f"32^4 kind {kind} mu {mu} p {par}")
+            before = got
+    print(f"32^4 flips: {flips}")
+    np.testing.assert_allclose(to_np(lat.plaquette()), O.plaquette(before, nc, L), rtol=0, atol=1e-12)
 
 
 # ---------------------------------------------------------------------------

@@ -1,22 +1,23 @@
 """GPU parity of the large-Nc path (one workgroup per link, link-major
 storage) against the FP64 oracle, for 4 <= Nc <= 32.
 
-The tolerances are those of test_gpu_parity (FP64 1e-12, FP32 1e-5, scaled
-by the update's conditioning, FP32 decision flips near their threshold
-counted), widened where the oracle itself is sensitive: one link update is a
-chain of Nc (Nc - 1) / 2 subgroup steps (496 at Nc = 32), each dividing by
-its own k, so rounding compounds along the chain.  The oracle's phase is run
-a second time with its input perturbed at the storage precision's rounding
-level (1e-7 FP32, 1e-15 FP64), and a link may differ by up to 100 times the
-change that perturbation makes to it.  A decision that the perturbation
-flips counts as sensitive in the same way."""
+The tolerances are those of test_gpu_parity (K_LINK eps (1 + c) per link,
+FP32 decision flips inside K_FLIP eps (1 + c) counted), widened where the
+oracle itself is sensitive: one link update is a chain of Nc (Nc - 1) / 2
+subgroup steps (496 at Nc = 32), each dividing by its own k, so rounding
+compounds along the chain.  The oracle's phase is run three more times with
+its input perturbed at the storage precision's rounding level (1e-7 FP32,
+1e-15 FP64), and a link may differ by up to SPREAD_FACTOR times the largest
+change those perturbations make to it (10 in FP64, 100 in FP32: the FP32
+arithmetic along the chain adds rounding at every step, which an input
+perturbation does not model)."""
 import numpy as np
 import pytest
 import torch
 
 import oracle as O
-from gpu_common import (FLIP_MARGIN, TOL, beta_for, compare_links, gpu_lattice, oracle_phase_diag, rounded,
-                        thermal_field, to_np, twin_spread)
+from gpu_common import (EPS, K_FLIP, K_TYP, TOL, beta_for, compare_links, gpu_lattice, oracle_phase_diag,
+                        record, rounded, thermal_field, to_np, twin_spread)
 
 pytestmark = pytest.mark.gpu
 
@@ -135,11 +136,18 @@ def test_wide_batched_sampler_parity(gpu, dtype):
     assert (ao[alpha == 1.7] > 8).sum() > 0 and (ao[alpha == 1.69] > 8).sum() > 0
     d = np.abs(xg - xo).max(axis=1)
     bad = (d > TOL[dtype]) | (ag != ao)
+    ok = ~bad
+    record(what="batched sampler", dtype=dtype, links=int(d.size), max_dU=float(d[ok].max()),
+           max_dU_over_tol=float(d[ok].max() / TOL[dtype]), flips=int(bad.sum()),
+           flip_margins=[float(m) for m in margin[bad][:50]])
     if dtype == "f64w":
         assert not bad.any(), (d.max(), int((ag != ao).sum()))
     else:
-        assert np.all(margin[bad] < FLIP_MARGIN)
-        assert bad.sum() <= 10
+        # as check_draw_flips of the register-path sampler test
+        eps = EPS["f32"]
+        assert np.all(margin[bad] < K_FLIP * eps * (1.0 + alpha[bad]))
+        expected = float((2 * 2 * K_TYP * eps * (1.0 + alpha)).sum())
+        assert bad.sum() <= max(3.0, 3.0 * expected), (int(bad.sum()), expected)
 
 
 @pytest.mark.parametrize("nc", [4])
