@@ -154,6 +154,27 @@ int sun_unitarity(sun_lattice_t h, double *dev_out2, sun_stream_t stream);
  * the check. */
 int sun_watchdog(sun_lattice_t h, double threshold, sun_stream_t stream);
 
+/* For callers that cannot allocate (code under HIP graph capture, tight
+ * serving loops, harnesses that forbid allocation): the mean plaquette of
+ * sun_plaquette, of a field in caller memory given by its geometry, with no
+ * lattice handle and no allocation of any kind -- no hipMalloc or hipFree,
+ * no host allocation.  The reduction partials live in a fixed device array
+ * of SUN_STATIC_SCRATCH_BYTES inside the library (one per GPU it runs on,
+ * held until the process ends; its address on the current device is looked
+ * up once, on the first call there).  Calls that overlap on one GPU, on any
+ * streams, race on that array; calls in sequence on one stream are safe
+ * (every call overwrites the partials it reads).  links: the field in the
+ * SoA layout of a lattice of this (nc, L, dtype), 256-byte aligned, read
+ * only.  dev_out3 as for sun_plaquette; the result has the same bits as
+ * sun_plaquette on a handle over the same field.  SUN_EINVAL / SUN_EUNSUP as
+ * sun_lattice_bytes; SUN_ESIZE for a null pointer or a lattice whose
+ * partials (16 bytes per 256 sites on the register path, per site on the
+ * workgroup-per-link path: up to 33.5M and 131072 sites) exceed the array.
+ * Asynchronous on stream. */
+#define SUN_STATIC_SCRATCH_BYTES (2u << 20)
+int sun_plaquette_static(int nc, const int L[4], int dtype, const void *links, double *dev_out3,
+                         sun_stream_t stream);
+
 /* Waits for the work queued on stream and reads the watchdog state:
  * SUN_ENUMERIC if any check since sun_watchdog tripped (the message gives
  * the number of tripped checks and the largest deviation), SUN_OK otherwise;

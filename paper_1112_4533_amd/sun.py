@@ -81,6 +81,7 @@ def load():
         "sun_set_sites_per_item": [vp, c_int, c_int],
         "sun_get_sites_per_item": [vp, c_int, ctypes.POINTER(c_int)],
         "sun_batch_set_sites_per_item": [vp, c_int, c_int],
+        "sun_plaquette_static": [c_int, L4, c_int, vp, vp, vp],
     }
     for name, args in sigs.items():
         f = getattr(L, name)
@@ -106,7 +107,7 @@ def exported_symbols():
                         "sun_batch_bytes", "sun_batch_create", "sun_batch_sweep", "sun_batch_plaquette",
                         "sun_batch_capture", "sun_batch_replay", "sun_batch_sync", "sun_batch_destroy",
                         "sun_set_launch", "sun_get_launch", "sun_batch_set_launch", "sun_set_sites_per_item",
-                        "sun_get_sites_per_item", "sun_batch_set_sites_per_item")
+                        "sun_get_sites_per_item", "sun_batch_set_sites_per_item", "sun_plaquette_static")
             if hasattr(L, n)]
 
 
@@ -381,6 +382,18 @@ class Batch:
         _check(load().sun_batch_set_sites_per_item(self._h, int(kind), int(spt)))
         for k in ((HEATBATH, OVERRELAX) if kind < 0 else (kind,)):
             self.sites_per_item[k] = int(spt)
+
+
+def plaquette_static(nc, L, dtype, links, out=None):
+    """The plaquette of a field in caller memory (a lattice's `links`
+    tensor, or any buffer of that layout) through sun_plaquette_static: no
+    handle and no allocation inside the library; `out` (3 float64 on the
+    device) is allocated here if not given."""
+    if out is None:
+        out = torch.empty(3, dtype=torch.float64, device=links.device)
+    _check(load().sun_plaquette_static(int(nc), (ctypes.c_int * 4)(*L), _dtype_code(dtype), _ptr(links), _ptr(out),
+                                       _stream()))
+    return out
 
 
 def sample_su2(alpha, seed, step=0, mu_sg=0, dtype="f64"):
