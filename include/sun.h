@@ -219,6 +219,18 @@ int sun_get_launch(sun_lattice_t h, int kind, int *block, int *xcd, int *waves, 
 int sun_set_sites_per_item(sun_lattice_t h, int kind, int spt);
 int sun_get_sites_per_item(sun_lattice_t h, int kind, int *spt);
 
+/* Race check, not a tuning choice: seed != 0 makes every later phase of this
+ * handle (register path, Nc <= SUN_NC_MAX_REGISTER) take the tiles of its
+ * walk in a random order of its own -- a random affine permutation of the
+ * walk positions, drawn from seed and the handle's phase count -- so that
+ * which workgroup updates which sites, and in what order the workgroups run,
+ * changes from phase to phase.  A phase's updates are independent of one
+ * another (the chessboard, paper Sec. 3), so results are bitwise those of
+ * the default order; a dependence between workgroups would show as a
+ * difference.  seed = 0 restores the default order.  Slower (the walk no
+ * longer keeps neighbour planes in L2). */
+int sun_set_tile_order(sun_lattice_t h, uint64_t seed);
+
 /* Per-kernel timing with HIP events recorded around launches on the launch
  * stream.  kernel: 0 heatbath phase, 1 overrelaxation phase,
  * 2 re-unitarization, 3 plaquette, 4 Polyakov loop.  sun_profile(h, every)

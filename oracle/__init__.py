@@ -53,6 +53,9 @@ def lib():
         L.orc_overrelax_link.argtypes = [ctypes.c_int, L4, dp, ctypes.c_int64, ctypes.c_int,
                                          ctypes.c_int]
         L.orc_reunit_matrix.argtypes = [ctypes.c_int, dp]
+        L.orc_phase_access_check.argtypes = [ctypes.c_int, L4, dp, ctypes.c_int, ctypes.c_int, ctypes.c_int,
+                                             ctypes.c_double, ctypes.c_uint64, ctypes.c_uint64,
+                                             ctypes.POINTER(ctypes.c_int64)]
         L.orc_sample_su2.argtypes = [dp, ctypes.c_int, ctypes.c_uint64, ctypes.c_uint32,
                                      ctypes.c_uint32, dp, ip, dp]
         _lib = L
@@ -132,6 +135,19 @@ def phase(U, nc, L, kind, mu, parity, beta, seed, step, want_margin=False):
                          _dp(cond) if cond is not None else None)
     _check(rc, "phase")
     return (margin, attempts, cond) if want_margin else None
+
+
+def phase_access_check(U, nc, L, kind, mu, parity, beta=1.0, seed=0, step=0):
+    """Runs one phase serially with the oracle's access log (race check of
+    the chessboard, Sec. 3): returns (links written by more than one update,
+    links written by one update and read by another, links written).
+    parity 2 updates both parities in one pass, a deliberately broken
+    schedule."""
+    _field(U, nc, L)
+    out = (ctypes.c_int64 * 3)()
+    _check(lib().orc_phase_access_check(nc, _L4(L), _dp(U), int(kind), int(mu), int(parity), float(beta),
+                                        int(seed), int(step), out), "phase_access_check")
+    return int(out[0]), int(out[1]), int(out[2])
 
 
 def sweep(U, nc, L, beta, n_hb, n_or, seed, step0, reunit=True):

@@ -171,13 +171,37 @@ static int64_t shift(const geom *g, int64_t s, int mu, int dir)
     return index_of(g, x);
 }
 
+/* ------------------------------------------------------------------------ */
+/* Access log (race check; test infrastructure of its own): while a phase   */
+/* runs serially under orc_phase_access_check, every link an update reads   */
+/* (clink) or takes for writing (link) is noted with the site of the update */
+/* that touched it.  Per link: -1 untouched, the site of its only toucher,  */
+/* or -2 when several updates touched it.                                   */
+/* ------------------------------------------------------------------------ */
+typedef struct {
+    int64_t owner;
+    int64_t *reader;
+    int64_t *writer;
+} access_log;
+static access_log *alog = NULL;
+
+static void note_access(int64_t *tab, int64_t l, int64_t owner)
+{
+    if (tab[l] == -1)
+        tab[l] = owner;
+    else if (tab[l] != owner)
+        tab[l] = -2;
+}
+
 static cplx *link(const geom *g, cplx *U, int mu, int64_t s)
 {
+    if (alog) note_access(alog->writer, (int64_t)mu * g->V + s, alog->owner);
     return U + ((int64_t)mu * g->V + s) * g->nc * g->nc;
 }
 
 static const cplx *clink(const geom *g, const cplx *U, int mu, int64_t s)
 {
+    if (alog) note_access(alog->reader, (int64_t)mu * g->V + s, alog->owner);
     return U + ((int64_t)mu * g->V + s) * g->nc * g->nc;
 }
 
@@ -619,6 +643,55 @@ int orc_phase(int nc, const int L[4], double *Ud, int kind, int mu, int parity,
             if (cond) cond[s] = c;
         }
     }
+    return 0;
+}
+
+/* The chessboard's promise (Sec. 3: the update kernels run on the even and
+ * then the odd sites of one direction so that the updates of one call are
+ * independent): no link a phase writes is read by any update of that phase
+ * other than its own, and no link is written twice.  Runs the phase serially
+ * with the access log on and counts out[0] links written by more than one
+ * update, out[1] links written by one update and read by another, out[2]
+ * links written.  parity 2 updates both parities in one pass (a broken
+ * schedule, for testing this check). */
+int orc_phase_access_check(int nc, const int L[4], double *Ud, int kind, int mu, int parity,
+                           double beta, uint64_t seed, uint64_t step, int64_t out[3])
+{
+    if (orc_check(nc, L) || mu < 0 || mu > 3 || (kind != 0 && kind != 1) || parity < 0 || parity > 2)
+        return -1;
+    geom g;
+    make_geom(nc, L, &g);
+    cplx *U = (cplx *)Ud;
+    const int64_t nl = 4 * g.V;
+    access_log log;
+    log.reader = (int64_t *)malloc(sizeof(int64_t) * nl);
+    log.writer = (int64_t *)malloc(sizeof(int64_t) * nl);
+    if (!log.reader || !log.writer) {
+        free(log.reader);
+        free(log.writer);
+        return -2;
+    }
+    for (int64_t l = 0; l < nl; ++l) log.reader[l] = log.writer[l] = -1;
+    alog = &log;
+    if (g.present[mu])
+        for (int64_t s = 0; s < g.V; ++s) {
+            if (parity != 2 && parity_of(&g, s) != parity) continue;
+            log.owner = s;
+            if (kind == 0)
+                heatbath_link(&g, U, s, mu, beta, seed, step, NULL, NULL);
+            else
+                overrelax_link(&g, U, s, mu, 0);
+        }
+    alog = NULL;
+    out[0] = out[1] = out[2] = 0;
+    for (int64_t l = 0; l < nl; ++l) {
+        if (log.writer[l] == -1) continue;
+        out[2] += 1;
+        if (log.writer[l] == -2) out[0] += 1;
+        else if (log.reader[l] != -1 && log.reader[l] != log.writer[l]) out[1] += 1;
+    }
+    free(log.reader);
+    free(log.writer);
     return 0;
 }
 

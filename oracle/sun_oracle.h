@@ -62,6 +62,9 @@ int orc_phase(int nc, const int L[4], double *U, int kind, int mu, int parity,
 int orc_sweep(int nc, const int L[4], double *U, double beta, int n_hb, int n_or,
               uint64_t seed, uint64_t step0, int reunit);
 int orc_reunitarize(int nc, const int L[4], double *U);
+/* Race check of one phase (chessboard independence); see the source. */
+int orc_phase_access_check(int nc, const int L[4], double *U, int kind, int mu, int parity,
+                           double beta, uint64_t seed, uint64_t step, int64_t out[3]);
 /* out = {mean plaquette, spatial-plane mean, planes-with-direction-3 mean} */
 int orc_plaquette(int nc, const int L[4], const double *U, double out[3]);
 /* out = {Re, Im} of the Polyakov loop along direction 3 */

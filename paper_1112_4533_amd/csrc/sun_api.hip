@@ -54,6 +54,7 @@ struct sun_lattice_s {
 
     size_t link_bytes = 0;
     uint64_t phases_run = 0;  // alternates the walk direction of successive phases
+    uint64_t tile_order = 0;  // sun_set_tile_order: random tile orders (race check), 0 = off
     // watchdog (sun_watchdog): threshold > 0 arms a check in every
     // re-unitarization; its state (3 doubles) sits in the last 256 bytes of
     // the scratch buffer
@@ -204,6 +205,8 @@ static int run_phase(sun_lattice_t h, int kind, int mu, int parity, double beta,
     Timed t(h, kind == SUN_HEATBATH ? 0 : 1, s);
     if (t.rc) return t.rc;
     sun::Ctx c = h->ctx(s);
+    // a fresh random order per phase, from the handle's seed and the phase count
+    if (h->tile_order) c.order = h->tile_order ^ (0xD1B54A32D192ED03ull * (h->phases_run + 1));
     c.rev = (int)(h->phases_run++ & 1);
     h->ops->update(c, kind, mu, parity, beta, (uint32_t)seed, (uint32_t)(seed >> 32), (uint32_t)step);
     if (int rc = launch_check(kind == SUN_HEATBATH ? "heatbath phase" : "overrelaxation phase")) return rc;
@@ -365,6 +368,12 @@ int sun_set_launch(sun_lattice_t h, int kind, int block, int xcd, int waves, int
     for (int k = 0; k < 2; ++k)
         if (kind < 0 || kind == k)
             h->shape[k] = sun::Shape{block, xcd ? 1 : 0, waves, tblock > 1 ? tblock : 0, h->shape[k].spt};
+    return SUN_OK;
+}
+
+int sun_set_tile_order(sun_lattice_t h, uint64_t seed) {
+    if (!h) return fail(SUN_EINVAL, "null handle");
+    h->tile_order = seed;
     return SUN_OK;
 }
 

@@ -159,6 +159,10 @@ struct Walk {
     int lz;       // L_z
     int rev;      // walk the tiles in reverse order
     int spt = 1;  // tiles per workgroup (sites per work-item), taken in turn
+    // Race check only: walk position q -> (pa q + pc) mod nblk, a random
+    // permutation of the positions (pa coprime to nblk; 0: off).  Results
+    // must not depend on which workgroup takes which tile, or when.
+    uint32_t pa = 0, pc = 0;
 };
 
 // Tiles of the plaquette grid (256-item workgroups): both parities of every
@@ -170,7 +174,8 @@ __host__ __device__ __forceinline__ int plaquette_tiles(const Geom& g) { return 
 // Infinity Cache, which matters once the field is larger than that cache.
 __device__ __forceinline__ int walk_tile(int b, int nblk, const Walk& w) {
     const int q0 = w.xcd ? xcd_tile(b, nblk) : b;
-    const int q = w.rev ? nblk - 1 - q0 : q0;
+    int q = w.rev ? nblk - 1 - q0 : q0;
+    if (w.pa) q = (int)(((uint64_t)q * w.pa + w.pc) % (uint64_t)nblk);
     if (w.tb <= 1) return q;
     const int i = q % w.tpp;
     int rest = q / w.tpp;

@@ -42,7 +42,33 @@ struct Ctx {
     int nc;
     int nt;           // nontemporal access to updated links (field well above the Infinity Cache)
     int rev;          // this phase walks its tiles in reverse order
+    uint64_t order = 0;  // nonzero: a random tile order drawn from this value (race check)
 };
+
+// The affine permutation q -> (pa q + pc) mod n of a random tile order,
+// drawn from `order` (splitmix64 steps); pa is coprime to n.
+inline void random_tile_order(uint64_t order, int n, Walk& w) {
+    auto mix = [](uint64_t& x) {
+        uint64_t z = (x += 0x9E3779B97F4A7C15ull);
+        z = (z ^ (z >> 30)) * 0xBF58476D1CE4E5B9ull;
+        z = (z ^ (z >> 27)) * 0x94D049BB133111EBull;
+        return z ^ (z >> 31);
+    };
+    auto gcd = [](uint64_t a, uint64_t b) {
+        while (b) {
+            const uint64_t t = a % b;
+            a = b;
+            b = t;
+        }
+        return a;
+    };
+    if (n <= 1) return;
+    uint64_t x = order;
+    uint64_t a = 1 + mix(x) % (uint64_t)(n - 1);
+    while (gcd(a, (uint64_t)n) != 1) a = a % (uint64_t)(n - 1) + 1;
+    w.pa = (uint32_t)a;
+    w.pc = (uint32_t)(mix(x) % (uint64_t)n);
+}
 
 // Infinity Cache (MALL) of an MI355X is 256 MB.  Updated links keep plain
 // (cached) access up to 1.25 x that size: measured on 32^4 SU(3), a 302 MB

@@ -15,10 +15,12 @@ struct OpsImpl {
                           const Walk& w) {
         P* u = (P*)c.links;
         const int nblk = half_blocks(c.g, BS), grid = grid_for(nblk, w.spt);
+        Walk wk = w;
+        if (c.order) random_tile_order(c.order, nblk, wk);
         if (c.nt)
-            k_update<N, T, R, HB, MU, BS, true><<<grid, BS, lds, c.stream>>>(u, c.g, par, beta, k0, k1, step, w, nblk);
+            k_update<N, T, R, HB, MU, BS, true><<<grid, BS, lds, c.stream>>>(u, c.g, par, beta, k0, k1, step, wk, nblk);
         else
-            k_update<N, T, R, HB, MU, BS, false><<<grid, BS, lds, c.stream>>>(u, c.g, par, beta, k0, k1, step, w, nblk);
+            k_update<N, T, R, HB, MU, BS, false><<<grid, BS, lds, c.stream>>>(u, c.g, par, beta, k0, k1, step, wk, nblk);
     }
 
     template <bool HB, int MU>

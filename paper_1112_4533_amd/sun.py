@@ -82,6 +82,7 @@ def load():
         "sun_get_sites_per_item": [vp, c_int, ctypes.POINTER(c_int)],
         "sun_batch_set_sites_per_item": [vp, c_int, c_int],
         "sun_plaquette_static": [c_int, L4, c_int, vp, vp, vp],
+        "sun_set_tile_order": [vp, c_u64],
     }
     for name, args in sigs.items():
         f = getattr(L, name)
@@ -107,7 +108,8 @@ def exported_symbols():
                         "sun_batch_bytes", "sun_batch_create", "sun_batch_sweep", "sun_batch_plaquette",
                         "sun_batch_capture", "sun_batch_replay", "sun_batch_sync", "sun_batch_destroy",
                         "sun_set_launch", "sun_get_launch", "sun_batch_set_launch", "sun_set_sites_per_item",
-                        "sun_get_sites_per_item", "sun_batch_set_sites_per_item", "sun_plaquette_static")
+                        "sun_get_sites_per_item", "sun_batch_set_sites_per_item", "sun_plaquette_static",
+                        "sun_set_tile_order")
             if hasattr(L, n)]
 
 
@@ -293,6 +295,10 @@ class Lattice:
         return v.value
 
     # -- event timing ----------------------------------------------------
+    def set_tile_order(self, seed):
+        """Random tile order per phase (race check; 0 restores the default)."""
+        _check(load().sun_set_tile_order(self._h, int(seed)))
+
     def profile(self, enable=True, every=1):
         """Starts (or with enable=False stops) event timing of one launch in
         `every` per kernel kind; clears the totals."""

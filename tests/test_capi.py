@@ -223,3 +223,17 @@ def test_sampler_hook_argument_checks(lib):
         assert lib.sun_sample_su2(dtype, None, 8, 1, 0, 0, p, p, None) == -2
         assert lib.sun_sample_su2(dtype, p, 8, 1, 0, 0, p, None, None) == -2
         assert lib.sun_sample_su2(dtype, p, 0, 1, 0, 0, p, p, None) == 0
+
+
+def test_tile_order_argument_checks(lib):
+    """The race-check tile order needs a handle; any seed is accepted (0
+    restores the default order)."""
+    assert lib.sun_set_tile_order(None, 1) == -1
+    L = (4, 4, 4, 4)
+    rc, lb, sb = _bytes(lib, 3, L, 0)
+    h = ctypes.c_void_p()
+    assert lib.sun_lattice_create(3, (ctypes.c_int * 4)(*L), 0, ctypes.c_void_p(0x10000), lb,
+                                  ctypes.c_void_p(0x200000), sb, ctypes.byref(h)) == 0
+    for seed in (0, 1, 2 ** 64 - 1):
+        assert lib.sun_set_tile_order(h, seed) == 0
+    lib.sun_lattice_destroy(h)

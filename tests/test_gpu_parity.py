@@ -642,6 +642,33 @@ def test_every_launch_shape_gives_the_same_bits(gpu, nc, dtype):
             assert torch.equal(ref, lat.links), (shape, spt)
 
 
+@pytest.mark.parametrize("nc,dtype,L", [(3, "f32r12", (16, 16, 4, 8)), (3, "f64", (6, 4, 2, 6)),
+                                         (2, "f32", (8, 8, 8, 8)), (4, "f32", (4, 4, 4, 4))])
+def test_random_tile_orders_give_the_same_bits(gpu, nc, dtype, L):
+    """Race canary: every phase takes its tiles in a random order of its own
+    (a random affine permutation of the walk positions), with several
+    seeds, launch shapes and sites per work-item; the field after two
+    sweeps must equal the default order's bitwise.  A phase whose updates
+    depended on one another -- a link read after another workgroup wrote
+    it -- would change with the order."""
+    sun = gpu
+    ref = gpu_lattice(sun, nc, L, dtype, hot=True, seed=8)
+    for _ in range(2):
+        ref.sweep(BETA[nc], 1, 2, seed=8)
+    torch.cuda.synchronize()
+    for seed, shape, spt in [(1, (256, 1, 12, 4), 1), (2, (64, 0, 0, 0), 1), (3, (128, 1, 16, 4), 2),
+                             (0xDEADBEEF, (256, 1, 0, 0), 4)]:
+        lat = gpu_lattice(sun, nc, L, dtype, hot=True, seed=8)
+        lat.set_launch(*shape)
+        lat.set_sites_per_item(spt)
+        lat.set_tile_order(seed)
+        for _ in range(2):
+            lat.sweep(BETA[nc], 1, 2, seed=8)
+        torch.cuda.synchronize()
+        assert torch.equal(ref.links, lat.links), (seed, shape, spt)
+    lat.set_tile_order(0)
+
+
 def test_batch_launch_shapes_and_tuner(gpu, tmp_path, monkeypatch):
     sun = gpu
     from paper_1112_4533_amd import autotune
