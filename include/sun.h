@@ -212,7 +212,8 @@ int sun_set_launch(sun_lattice_t h, int kind, int block, int xcd, int waves, int
 int sun_get_launch(sun_lattice_t h, int kind, int *block, int *xcd, int *waves, int *tblock);
 
 /* Sites per work-item of the phase kernels of one update kind (SUN_HEATBATH,
- * SUN_OVERRELAX, or -1 for both): 1, 2 or 4 (default 1).  A workgroup then
+ * SUN_OVERRELAX, or -1 for both): 1, 2 or 4 (default 2 for the heatbath, 1
+ * for overrelaxation).  A workgroup then
  * updates that many tiles of its walk in turn and the grid is that many
  * times smaller.  Kept by sun_set_launch.  A tuning choice only: results are
  * bitwise the same. */
@@ -283,8 +284,13 @@ int sun_batch_bytes(int n, size_t *table_bytes);
 int sun_batch_create(int n, const sun_lattice_t *chains, const double *betas, const uint64_t *seeds,
                      void *table, size_t table_bytes, sun_batch_t *out);
 
-/* One sweep of every chain (same schedule as sun_sweep). */
-int sun_batch_sweep(sun_batch_t b, int n_hb, int n_or, int reunit, sun_stream_t stream);
+/* One sweep of every chain (same schedule as sun_sweep).  dev_beta: NULL, or
+ * a device array of n couplings in the caller's chain order, which a kernel
+ * on stream copies into the table ahead of the sweep (the couplings then
+ * stay in force for later sweeps given NULL, until another array or a
+ * launch-shape change, which restores the couplings given at creation). */
+int sun_batch_sweep(sun_batch_t b, int n_hb, int n_or, int reunit, const double *dev_beta,
+                    sun_stream_t stream);
 
 /* Mean plaquettes, FP64: dev_out[3 i .. 3 i + 2] = {total, spatial, temporal}
  * of chain i (caller's order). */
@@ -292,9 +298,12 @@ int sun_batch_plaquette(sun_batch_t b, double *dev_out, sun_stream_t stream);
 
 /* Captures n_sweeps sweeps (each followed by the plaquettes into dev_plaq if
  * not NULL) as one HIP graph owned by the batch, replacing any earlier one.
- * stream must not be the null stream.  Nothing runs until sun_batch_replay. */
-int sun_batch_capture(sun_batch_t b, int n_sweeps, int n_hb, int n_or, int reunit, double *dev_plaq,
-                      sun_stream_t stream);
+ * With dev_beta (as for sun_batch_sweep) every captured sweep first copies
+ * the couplings from that array, so each replay reads its contents at that
+ * time: a coupling scan rewrites the array between replays.  stream must not
+ * be the null stream.  Nothing runs until sun_batch_replay. */
+int sun_batch_capture(sun_batch_t b, int n_sweeps, int n_hb, int n_or, int reunit, const double *dev_beta,
+                      double *dev_plaq, sun_stream_t stream);
 int sun_batch_replay(sun_batch_t b, sun_stream_t stream);
 
 /* Launch shape of the batch's phase kernels (as sun_set_launch, always with

@@ -50,7 +50,10 @@ struct sun_lattice_s {
     int64_t launches[kKernels] = {};
     // launch shapes of the phase kernels (sun_set_launch); the overrelaxation
     // cap is set at creation from the link size
-    sun::Shape shape[2] = {sun::Shape{256, 1, 16, 4}, sun::Shape{256, 1, 12, 4}};
+    // the heatbath takes two tiles per workgroup (SU(3) 32^4 sweep: two-row
+    // 2.040 -> 2.004 ms, 18 reals 3.156 -> 3.151 ms, FP64 two-row 4.378 ->
+    // 4.356 ms against one tile)
+    sun::Shape shape[2] = {sun::Shape{256, 1, 16, 4, 2}, sun::Shape{256, 1, 12, 4}};
 
     size_t link_bytes = 0;
     uint64_t phases_run = 0;  // alternates the walk direction of successive phases
@@ -483,9 +486,21 @@ struct sun_batch_s {
     uint64_t hb_per_replay = 0;
 };
 
+// Couplings of a batch sweep from a device array in the caller's chain
+// order: d[c].beta = beta[d[c].out_index].  Runs on the stream ahead of the
+// sweep's phases, so a captured graph reads the array's contents at replay.
+__global__ void k_set_betas(sun::ChainDesc* __restrict__ d, int n, const double* __restrict__ beta) {
+    const int c = blockIdx.x * blockDim.x + threadIdx.x;
+    if (c < n) d[c].beta = beta[d[c].out_index];
+}
+
 namespace {
 
-int batch_sweep_launches(sun_batch_t b, int n_hb, int n_or, int reunit, hipStream_t s) {
+int batch_sweep_launches(sun_batch_t b, int n_hb, int n_or, int reunit, const double* dev_beta, hipStream_t s) {
+    if (dev_beta) {
+        const int n = (int)b->chains.size();
+        k_set_betas<<<(n + 63) / 64, 64, 0, s>>>(b->table, n, dev_beta);
+    }
     for (const auto& gr : b->groups) {
         const sun::ChainDesc* d = b->table + gr.first;
         for (int k = 0; k < n_hb; ++k)
@@ -637,10 +652,10 @@ int sun_batch_create(int n, const sun_lattice_t* chains, const double* betas, co
     return SUN_OK;
 }
 
-int sun_batch_sweep(sun_batch_t b, int n_hb, int n_or, int reunit, sun_stream_t stream) {
+int sun_batch_sweep(sun_batch_t b, int n_hb, int n_or, int reunit, const double* dev_beta, sun_stream_t stream) {
     if (!b) return fail(SUN_EINVAL, "null batch");
     if (n_hb < 0 || n_or < 0) return fail(SUN_EINVAL, "negative step count (n_hb %d, n_or %d)", n_hb, n_or);
-    if (int rc = batch_sweep_launches(b, n_hb, n_or, reunit, as_stream(stream))) return rc;
+    if (int rc = batch_sweep_launches(b, n_hb, n_or, reunit, dev_beta, as_stream(stream))) return rc;
     b->hb_steps_done += (uint64_t)n_hb;
     return SUN_OK;
 }
@@ -651,8 +666,8 @@ int sun_batch_plaquette(sun_batch_t b, double* dev_out, sun_stream_t stream) {
     return batch_plaquette_launches(b, dev_out, as_stream(stream));
 }
 
-int sun_batch_capture(sun_batch_t b, int n_sweeps, int n_hb, int n_or, int reunit, double* dev_plaq,
-                      sun_stream_t stream) {
+int sun_batch_capture(sun_batch_t b, int n_sweeps, int n_hb, int n_or, int reunit, const double* dev_beta,
+                      double* dev_plaq, sun_stream_t stream) {
     if (!b) return fail(SUN_EINVAL, "null batch");
     if (n_sweeps <= 0 || n_hb < 0 || n_or < 0) return fail(SUN_EINVAL, "n_sweeps %d, n_hb %d, n_or %d", n_sweeps, n_hb, n_or);
     const hipStream_t s = as_stream(stream);
@@ -669,7 +684,7 @@ int sun_batch_capture(sun_batch_t b, int n_sweeps, int n_hb, int n_or, int reuni
         return rc;
     int rc = SUN_OK;
     for (int k = 0; k < n_sweeps && rc == SUN_OK; ++k) {
-        rc = batch_sweep_launches(b, n_hb, n_or, reunit, s);
+        rc = batch_sweep_launches(b, n_hb, n_or, reunit, dev_beta, s);
         if (rc == SUN_OK && dev_plaq) rc = batch_plaquette_launches(b, dev_plaq, s);
     }
     hipGraph_t g = nullptr;

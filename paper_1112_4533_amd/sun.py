@@ -69,9 +69,9 @@ def load():
         "sun_batch_bytes": [c_int, ctypes.POINTER(sz)],
         "sun_batch_create": [c_int, ctypes.POINTER(vp), ctypes.POINTER(c_dbl), ctypes.POINTER(c_u64), vp, sz,
                              ctypes.POINTER(vp)],
-        "sun_batch_sweep": [vp, c_int, c_int, c_int, vp],
+        "sun_batch_sweep": [vp, c_int, c_int, c_int, vp, vp],
         "sun_batch_plaquette": [vp, vp, vp],
-        "sun_batch_capture": [vp, c_int, c_int, c_int, c_int, vp, vp],
+        "sun_batch_capture": [vp, c_int, c_int, c_int, c_int, vp, vp, vp],
         "sun_batch_replay": [vp, vp],
         "sun_batch_sync": [vp],
         "sun_set_launch": [vp, c_int, c_int, c_int, c_int, c_int],
@@ -294,11 +294,11 @@ class Lattice:
         _check(load().sun_get_sites_per_item(self._h, int(kind), ctypes.byref(v)))
         return v.value
 
-    # -- event timing ----------------------------------------------------
     def set_tile_order(self, seed):
         """Random tile order per phase (race check; 0 restores the default)."""
         _check(load().sun_set_tile_order(self._h, int(seed)))
 
+    # -- event timing ----------------------------------------------------
     def profile(self, enable=True, every=1):
         """Starts (or with enable=False stops) event timing of one launch in
         `every` per kernel kind; clears the totals."""
@@ -348,8 +348,11 @@ class Batch:
             _lib.sun_batch_destroy(h)
             self._h = None
 
-    def sweep(self, n_hb=1, n_or=4, reunit=True):
-        _check(load().sun_batch_sweep(self._h, int(n_hb), int(n_or), int(bool(reunit)), _stream()))
+    def sweep(self, n_hb=1, n_or=4, reunit=True, beta=None):
+        """One sweep of every chain; beta: None (the couplings in force), or an
+        (n,) float64 device tensor of couplings in chain order."""
+        _check(load().sun_batch_sweep(self._h, int(n_hb), int(n_or), int(bool(reunit)),
+                                      _ptr(beta) if beta is not None else None, _stream()))
 
     def plaquette(self, out=None):
         out = out if out is not None else torch.empty((self.n, 3), dtype=torch.float64,
@@ -357,12 +360,14 @@ class Batch:
         _check(load().sun_batch_plaquette(self._h, _ptr(out), _stream()))
         return out
 
-    def capture(self, n_sweeps=1, n_hb=1, n_or=4, reunit=True, plaq_out=None):
+    def capture(self, n_sweeps=1, n_hb=1, n_or=4, reunit=True, plaq_out=None, beta=None):
         """Captures n_sweeps sweeps (plus plaquettes into plaq_out, an (n, 3)
-        float64 device tensor, if given) as one graph."""
+        float64 device tensor, if given) as one graph; with beta (an (n,)
+        float64 device tensor) each replay takes the couplings it holds then."""
         cur = torch.cuda.current_stream()
         self.stream.wait_stream(cur)
         _check(load().sun_batch_capture(self._h, int(n_sweeps), int(n_hb), int(n_or), int(bool(reunit)),
+                                        _ptr(beta) if beta is not None else None,
                                         _ptr(plaq_out) if plaq_out is not None else None,
                                         ctypes.c_void_p(self.stream.cuda_stream)))
 

@@ -117,13 +117,14 @@ def test_create_validates_buffers_without_touching_them(lib):
     assert lib.sun_get_launch(h, 0, None, None, None, None) == -1
     # sites per work-item: 1, 2 or 4 per kind, kept by sun_set_launch
     s = ctypes.c_int()
-    assert lib.sun_get_sites_per_item(h, 0, ctypes.byref(s)) == 0 and s.value == 1
+    assert lib.sun_get_sites_per_item(h, 0, ctypes.byref(s)) == 0 and s.value == 2   # heatbath default
+    assert lib.sun_get_sites_per_item(h, 1, ctypes.byref(s)) == 0 and s.value == 1
     assert lib.sun_set_sites_per_item(h, -1, 3) == -1
     assert lib.sun_set_sites_per_item(h, 2, 2) == -1
     assert lib.sun_set_sites_per_item(None, -1, 2) == -1
     assert lib.sun_set_sites_per_item(h, 1, 4) == 0
     assert lib.sun_get_sites_per_item(h, 1, ctypes.byref(s)) == 0 and s.value == 4
-    assert lib.sun_get_sites_per_item(h, 0, ctypes.byref(s)) == 0 and s.value == 1
+    assert lib.sun_get_sites_per_item(h, 0, ctypes.byref(s)) == 0 and s.value == 2
     assert lib.sun_set_launch(h, -1, 128, 1, 8, 0) == 0
     assert lib.sun_get_sites_per_item(h, 1, ctypes.byref(s)) == 0 and s.value == 4
     assert lib.sun_get_sites_per_item(h, 1, None) == -1
@@ -183,7 +184,7 @@ def test_batch_argument_checks(lib):
         assert b"share device memory" in lib.sun_last_error(), pair
     for hv in hs:
         lib.sun_lattice_destroy(ctypes.c_void_p(hv))
-    assert lib.sun_batch_sweep(None, 1, 1, 1, None) == -1
+    assert lib.sun_batch_sweep(None, 1, 1, 1, None, None) == -1
     assert lib.sun_batch_replay(None, None) == -1
 
 

@@ -568,6 +568,38 @@ def test_batch_is_bitwise_the_chains_alone(gpu):
         assert torch.equal(a.plaquette(), plaq[i]), f"plaquette of chain {i}"
 
 
+def test_batch_couplings_from_a_device_array(gpu):
+    """A coupling scan without a new batch: sweeps given a device array of
+    couplings, eager and from a graph whose replays read the array's
+    contents at that time, equal the chains run alone with those couplings
+    (bitwise); sweeps given no array keep the last couplings."""
+    sun = gpu
+    cfg = BATCH[:3] + BATCH[4:]
+    b1 = torch.tensor([c[3] + 0.3 for c in cfg], dtype=torch.float64, device="cuda")
+    b2 = torch.tensor([c[3] - 0.2 for c in cfg], dtype=torch.float64, device="cuda")
+    alone = [gpu_lattice(sun, nc, L, dt, hot=True, seed=sd) for nc, L, dt, b, sd in cfg]
+    batched = [gpu_lattice(sun, nc, L, dt, hot=True, seed=sd) for nc, L, dt, b, sd in cfg]
+    for i, (lat, (nc, L, dt, beta, sd)) in enumerate(zip(alone, cfg)):
+        lat.sweep(float(b1[i]), 1, 2, seed=sd)          # eager, array b1
+        lat.sweep(float(b1[i]), 1, 2, seed=sd)          # no array: b1 stays
+        lat.sweep(float(b2[i]), 1, 2, seed=sd)          # graph replay with b2 in the array
+        lat.sweep(float(b1[i]), 1, 2, seed=sd)          # same graph, b1 written back
+    bt = sun.Batch(batched, [c[3] for c in cfg], [c[4] for c in cfg])
+    bt.sweep(1, 2, beta=b1)
+    bt.sweep(1, 2)
+    arr = b2.clone()
+    bt.capture(n_sweeps=1, n_hb=1, n_or=2, beta=arr)
+    bt.replay()
+    torch.cuda.synchronize()
+    arr.copy_(b1)
+    torch.cuda.synchronize()
+    bt.replay()
+    torch.cuda.synchronize()
+    bt.sync()
+    for i, (a, b) in enumerate(zip(alone, batched)):
+        assert torch.equal(a.links, b.links), f"chain {i} differs"
+
+
 @pytest.mark.parametrize("nc,L,dt", [(3, (6, 4, 2, 4), "f32r12"), (2, (4, 2, 2, 6), "f64")])
 def test_one_chain_batch_is_the_chain_alone(gpu, nc, L, dt):
     """The degenerate batch: one chain, ragged extents (V/2 not a multiple
