@@ -485,7 +485,8 @@ def run_cpu_baseline(run, sweeps, single_thread=True):
 
 PEAK_FP32_TFLOPS = 78.6          # MI355X vector FP32 without packed instructions (= the FP64 rate)
 PEAK_FP64_TFLOPS = 78.6
-NC_SCAN = {"f32": (4, 5, 6, 8, 10, 12, 16, 20, 24, 28, 32), "f64": (4, 5, 6, 8, 10, 12, 16, 20, 24, 28, 32)}
+NC_SCAN = {"f32": (4, 5, 6, 8, 10, 12, 16, 20, 22, 24, 26, 28, 30, 32),
+           "f64": (4, 5, 6, 8, 10, 12, 16, 20, 22, 24, 26, 28, 30, 32)}
 
 
 def wide_update_flops(nc):

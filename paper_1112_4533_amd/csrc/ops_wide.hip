@@ -10,24 +10,34 @@ struct OpsWide {
     using P = T2<T>;
     static constexpr int f64 = sizeof(T) == 8;
 
+    template <bool MM, bool RA>
+    static void update_as(const Ctx& c, int kind, int mu, int par, double beta, uint32_t k0, uint32_t k1,
+                          uint32_t step) {
+        wide::k_update<T, MM, RA><<<c.g.Vh, wide::kLanes, wide_update_lds(c.nc, f64), c.stream>>>(
+            (P*)c.links, c.g, c.nc, mu, par, kind == 0 ? 1 : 0, (T)beta, k0, k1, step);
+    }
     static void update(const Ctx& c, int kind, int mu, int par, double beta, uint32_t k0, uint32_t k1, uint32_t step) {
-        const size_t lds = wide_update_lds(c.nc, f64);
+        const bool ra = wide_update_regacc(c.nc, f64);
         if constexpr (!f64) {
             if (c.nc > wide::kMfmaMinN) {
-                wide::k_update<T, true><<<c.g.Vh, wide::kLanes, lds, c.stream>>>(
-                    (P*)c.links, c.g, c.nc, mu, par, kind == 0 ? 1 : 0, (T)beta, k0, k1, step);
+                if (ra)
+                    update_as<true, true>(c, kind, mu, par, beta, k0, k1, step);
+                else
+                    update_as<true, false>(c, kind, mu, par, beta, k0, k1, step);
                 return;
             }
         }
-        wide::k_update<T, false><<<c.g.Vh, wide::kLanes, lds, c.stream>>>((P*)c.links, c.g, c.nc, mu, par,
-                                                                          kind == 0 ? 1 : 0, (T)beta, k0, k1, step);
+        if (ra)
+            update_as<false, true>(c, kind, mu, par, beta, k0, k1, step);
+        else
+            update_as<false, false>(c, kind, mu, par, beta, k0, k1, step);
     }
     static void init(const Ctx& c, int hot, uint32_t k0, uint32_t k1) {
         wide::k_init<T><<<4 * c.g.V, wide::kLanes, wide::fp64_lds(c.nc, 2), c.stream>>>((P*)c.links, c.g, c.nc, hot, k0,
                                                                                         k1);
     }
     static int reunit(const Ctx& c, double* partial) {
-        const size_t lds = wide::fp64_lds(c.nc, 2);
+        const size_t lds = wide::fp64_lds(c.nc, 1) + (size_t)c.nc * sizeof(double2);  // M and the projections
         if (partial)
             wide::k_reunit<T, true><<<4 * c.g.V, wide::kLanes, lds, c.stream>>>((P*)c.links, c.g, c.nc, partial);
         else
@@ -35,7 +45,7 @@ struct OpsWide {
         return 4 * c.g.V;
     }
     static int unitarity(const Ctx& c, double* partial) {
-        wide::k_unitarity<T><<<4 * c.g.V, wide::kLanes, wide::fp64_lds(c.nc, 2), c.stream>>>((const P*)c.links, c.g,
+        wide::k_unitarity<T><<<4 * c.g.V, wide::kLanes, wide::fp64_lds(c.nc, 1), c.stream>>>((const P*)c.links, c.g,
                                                                                              c.nc, partial);
         return 4 * c.g.V;
     }

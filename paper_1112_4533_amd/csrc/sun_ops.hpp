@@ -142,9 +142,16 @@ const Ops* ops_nc4(int f64);
 const Ops* ops_nc3_two_row(int f64);  // SU(3), rows 0 and 1 stored
 const Ops* ops_wide(int f64);         // 4 <= Nc <= 32: one workgroup per link, link-major storage
 
-// Dynamic LDS of the wide phase kernel, and whether it fits a workgroup.
+// Dynamic LDS of the wide phase kernel, and whether it fits a workgroup.  The
+// kernel keeps three Nc x Nc matrices in LDS, or two with the staple sum in
+// registers; the latter where three would leave fewer than 8 workgroups per
+// CU (FP32 from Nc = 30, FP64 from Nc = 21), since a phase at 8^4 is 2048
+// workgroups and fewer than 8 per CU take it two or more rounds.
 constexpr size_t kWideLdsMax = 64 * 1024;
-inline size_t wide_update_lds(int nc, int f64) { return (size_t)3 * nc * nc * (f64 ? 16 : 8); }
+inline bool wide_update_regacc(int nc, int f64) { return (size_t)3 * nc * nc * (f64 ? 16 : 8) > kLdsPerCu / 8; }
+inline size_t wide_update_lds(int nc, int f64) {
+    return (size_t)(wide_update_regacc(nc, f64) ? 2 : 3) * nc * nc * (f64 ? 16 : 8);
+}
 
 void launch_finalize_max2(const double* partial, int nblk, double* out, hipStream_t s);
 void launch_finalize_sum2(const double* partial, int nblk, double* out, double scale, hipStream_t s);

@@ -201,7 +201,8 @@ __device__ __forceinline__ void lds_mm_mfma(T2<float>* C, const T2<float>* A, co
 
 // MM: the matrix-core form (FP32, kMfmaMinN < n), compiled into its own
 // kernel variant so that the others keep their register budget.
-template <typename T, bool MM = false>
+// RMAX caps the rows a lane takes at a time (fewer registers).
+template <typename T, bool MM = false, int RMAX = 4>
 __device__ __forceinline__ void lds_mm(T2<T>* C, const T2<T>* A, const T2<T>* B, int n, bool acc) {
     if constexpr (MM) {
         static_assert(sizeof(T) == 4, "the matrix-core product is FP32");
@@ -214,12 +215,143 @@ __device__ __forceinline__ void lds_mm(T2<T>* C, const T2<T>* A, const T2<T>* B,
     const int j = lane % n, i0 = lane / n;
     const int cnt = (n - i0 + g - 1) / g;   // rows i0 + g t < n of this lane
     const int most = (n + g - 1) / g;       // rows of lane 0, the most of any lane
-    if (most >= 4)
+    if (RMAX >= 4 && most >= 4)
         lds_mm_rows<T, 4>(C, A, B, n, acc, g, j, i0, cnt);
     else if (most >= 2)
         lds_mm_rows<T, 2>(C, A, B, n, acc, g, j, i0, cnt);
     else
         lds_mm_rows<T, 1>(C, A, B, n, acc, g, j, i0, cnt);
+}
+
+// ---------------------------------------------------------------------------
+// A product accumulator in registers instead of LDS (the staple sum, and W =
+// U A on its way into LDS), so that the update kernel holds two matrices in
+// LDS instead of three where LDS limits the workgroups per CU.  Each lane
+// keeps the entries it owns in the LDS products above: on the vector units
+// column j = lane mod n, rows i0 + g t (at most kAccRows of them); on the
+// matrix cores the 16 result registers of its 32 x 32 tile.  The products
+// are the same operations in the same order as lds_mm with C in LDS, so the
+// results are the same bits.
+// ---------------------------------------------------------------------------
+constexpr int kAccRows = 16;   // rows of the most loaded lane: ceil(n / (64 / n)) <= 16 for n <= 32
+
+template <typename T, bool MM>
+struct Acc {
+    T2<T> e[kAccRows];
+    __device__ __forceinline__ void zero() {
+#pragma unroll
+        for (int t = 0; t < kAccRows; ++t) e[t] = cpx<T>(T(0), T(0));
+    }
+};
+template <>
+struct Acc<float, true> {
+    f32x16 re, im;
+    __device__ __forceinline__ void zero() {
+#pragma unroll
+        for (int r = 0; r < 16; ++r) re[r] = im[r] = 0.f;
+    }
+};
+
+// c += A B (A, B in LDS) on the vector units, R rows of the lane at a time.
+template <typename T, int R>
+__device__ __forceinline__ void acc_mm_rows(Acc<T, false>& c, const T2<T>* A, const T2<T>* B, int n, int g, int j,
+                                            int i0, int cnt, int most) {
+#pragma unroll
+    for (int t0 = 0; t0 < kAccRows; t0 += R) {
+        if (t0 >= most) break;  // the same for every lane
+        int row[R];
+        T r[R], m[R];
+#pragma unroll
+        for (int t = 0; t < R; ++t) {
+            const int tt = t0 + t < cnt ? t0 + t : cnt - 1;
+            row[t] = (i0 + g * tt) * n;
+            r[t] = c.e[t0 + t].x;
+            m[t] = c.e[t0 + t].y;
+        }
+        int k = 0;
+        for (; k + 4 <= n; k += 4) {
+            T2<T> y[4], x[4][R];
+#pragma unroll
+            for (int q = 0; q < 4; ++q) {
+                y[q] = B[(k + q) * n + j];
+#pragma unroll
+                for (int t = 0; t < R; ++t) x[q][t] = A[row[t] + k + q];
+            }
+#pragma unroll
+            for (int q = 0; q < 4; ++q)
+#pragma unroll
+                for (int t = 0; t < R; ++t) cmac(r[t], m[t], x[q][t].x, x[q][t].y, y[q].x, y[q].y);
+        }
+        for (; k < n; ++k) {
+            const T2<T> y = B[k * n + j];
+#pragma unroll
+            for (int t = 0; t < R; ++t) {
+                const T2<T> x = A[row[t] + k];
+                cmac(r[t], m[t], x.x, x.y, y.x, y.y);
+            }
+        }
+#pragma unroll
+        for (int t = 0; t < R; ++t)
+            if (t0 + t < cnt) c.e[t0 + t] = cpx<T>(r[t], m[t]);
+    }
+}
+
+template <typename T, bool MM>
+__device__ __forceinline__ void acc_mm(Acc<T, MM>& c, const T2<T>* A, const T2<T>* B, int n) {
+    if constexpr (MM) {
+        const int l = threadIdx.x;
+        const int lo = l & 31, hi = l >> 5;
+#pragma unroll 2
+        for (int k0 = 0; k0 < n; k0 += 2) {
+            const int k = k0 + hi;
+            T2<float> a = cpx<float>(0.f, 0.f), b = cpx<float>(0.f, 0.f);
+            if (k < n && lo < n) {
+                a = A[lo * n + k];
+                b = B[k * n + lo];
+            }
+            c.re = __builtin_amdgcn_mfma_f32_32x32x2f32(a.x, b.x, c.re, 0, 0, 0);
+            c.im = __builtin_amdgcn_mfma_f32_32x32x2f32(a.x, b.y, c.im, 0, 0, 0);
+            c.re = __builtin_amdgcn_mfma_f32_32x32x2f32(-a.y, b.y, c.re, 0, 0, 0);
+            c.im = __builtin_amdgcn_mfma_f32_32x32x2f32(a.y, b.x, c.im, 0, 0, 0);
+        }
+    } else {
+        const int g = kLanes / n;
+        const int lane = threadIdx.x;
+        if (lane >= g * n) return;
+        const int j = lane % n, i0 = lane / n;
+        const int cnt = (n - i0 + g - 1) / g;
+        const int most = (n + g - 1) / g;
+        // FP64 takes two rows at a time: with four, the kernel's registers
+        // (the sum itself is 64 VGPRs at Nc = 32) left one wave per SIMD
+        if (sizeof(T) == 4 && most >= 4)
+            acc_mm_rows<T, 4>(c, A, B, n, g, j, i0, cnt, most);
+        else if (most >= 2)
+            acc_mm_rows<T, 2>(c, A, B, n, g, j, i0, cnt, most);
+        else
+            acc_mm_rows<T, 1>(c, A, B, n, g, j, i0, cnt, most);
+    }
+}
+
+// C (LDS) = the accumulator.
+template <typename T, bool MM>
+__device__ __forceinline__ void acc_store(T2<T>* C, const Acc<T, MM>& c, int n) {
+    const int l = threadIdx.x;
+    if constexpr (MM) {
+        const int lo = l & 31, hi = l >> 5;
+#pragma unroll
+        for (int r = 0; r < 16; ++r) {
+            const int i = 8 * (r / 4) + 4 * hi + (r % 4);
+            if (i < n && lo < n) C[i * n + lo] = cpx<float>(c.re[r], c.im[r]);
+        }
+    } else {
+        const int g = kLanes / n;
+        if (l >= g * n) return;
+        const int j = l % n, i0 = l / n;
+        const int cnt = (n - i0 + g - 1) / g;
+#pragma unroll
+        for (int t = 0; t < kAccRows; ++t)
+            if (t < cnt) C[(i0 + g * t) * n + j] = c.e[t];
+    }
 }
 
 // Wave reductions with a fixed butterfly order (deterministic).
@@ -371,21 +503,31 @@ __device__ __forceinline__ void rows_left_mul_col(T2<T>* M, int n, int i, int j,
 // staple term overwrites its left factor (B0 <- B0 B1), and after the staple
 // B1 holds U and B0 holds W = U A.
 // ---------------------------------------------------------------------------
-template <typename T, bool MM>
-__global__ __launch_bounds__(kLanes) void k_update(T2<T>* __restrict__ U, Geom g, int n, int mu, int par, int hb,
+// RA: the staple sum (and W on its way into LDS) in registers (Acc), so that
+// LDS holds two matrices instead of three: B0 and B1, and after the staple U
+// (B1) and W (B0).  At least two waves per SIMD (at most 256 registers): the
+// FP64 form with the sum in registers would otherwise take a few more and
+// leave one.
+template <typename T, bool MM, bool RA>
+__global__ __launch_bounds__(kLanes, 2) void k_update(T2<T>* __restrict__ U, Geom g, int n, int mu, int par, int hb,
                                                    T beta, uint32_t k0, uint32_t k1, uint32_t step) {
     extern __shared__ double4 smem_update[];
     const int n2 = n * n;
-    T2<T>* A = reinterpret_cast<T2<T>*>(smem_update);
-    T2<T>* B0 = A + n2;
+    T2<T>* A = reinterpret_cast<T2<T>*>(smem_update);  // the staple sum (without RA)
+    T2<T>* B0 = RA ? A : A + n2;
     T2<T>* B1 = B0 + n2;
+    Acc<T, MM> acc;  // the staple sum (with RA)
+    constexpr int kRows = (RA && sizeof(T) == 8) ? 2 : 4;  // FP64 with the sum in registers: fewer at a time
     const int h = blockIdx.x;
     const int Vh = g.Vh;
     const Site x = site_of(g, par, h);
     const Site xp = step_up(g, x, mu);
     const int op = par ^ 1;
 
-    for (int e = threadIdx.x; e < n2; e += kLanes) A[e] = cpx<T>(T(0), T(0));
+    if constexpr (RA)
+        acc.zero();
+    else
+        for (int e = threadIdx.x; e < n2; e += kLanes) A[e] = cpx<T>(T(0), T(0));
     for (int nu = 0; nu < 4; ++nu) {
         if (nu == mu || !((g.present >> nu) & 1)) continue;
         const Site xpn = step_up(g, x, nu), xmn = step_down(g, x, nu), xpmn = step_down(g, xp, nu);
@@ -393,28 +535,43 @@ __global__ __launch_bounds__(kLanes) void k_update(T2<T>* __restrict__ U, Geom g
         lds_load<T, T>(B0, link_at<T>(U, n2, nu, op, xp.s >> 1, Vh), n, false);
         lds_load<T, T>(B1, link_at<T>(U, n2, mu, op, xpn.s >> 1, Vh), n, true);
         __syncthreads();
-        lds_mm<T, MM>(B0, B0, B1, n, false);
+        lds_mm<T, MM, kRows>(B0, B0, B1, n, false);
         __syncthreads();
         lds_load<T, T>(B1, link_at<T>(U, n2, nu, par, h, Vh), n, true);
         __syncthreads();
-        lds_mm<T, MM>(A, B0, B1, n, true);
+        if constexpr (RA)
+            acc_mm<T, MM>(acc, B0, B1, n);
+        else
+            lds_mm<T, MM>(A, B0, B1, n, true);
         __syncthreads();
         // lower staple U_nu(x+mu-nu)^dag U_mu(x-nu)^dag U_nu(x-nu)
         lds_load<T, T>(B0, link_at<T>(U, n2, nu, par, xpmn.s >> 1, Vh), n, true);
         lds_load<T, T>(B1, link_at<T>(U, n2, mu, op, xmn.s >> 1, Vh), n, true);
         __syncthreads();
-        lds_mm<T, MM>(B0, B0, B1, n, false);
+        lds_mm<T, MM, kRows>(B0, B0, B1, n, false);
         __syncthreads();
         lds_load<T, T>(B1, link_at<T>(U, n2, nu, op, xmn.s >> 1, Vh), n, false);
         __syncthreads();
-        lds_mm<T, MM>(A, B0, B1, n, true);
+        if constexpr (RA)
+            acc_mm<T, MM>(acc, B0, B1, n);
+        else
+            lds_mm<T, MM>(A, B0, B1, n, true);
         __syncthreads();
     }
     T2<T>* Us = B1;
     lds_load<T, T>(Us, link_at<T>(U, n2, mu, par, h, Vh), n, false);
-    __syncthreads();
     T2<T>* W = B0;  // W = U A
-    lds_mm<T, MM>(W, Us, A, n, false);
+    if constexpr (RA) {
+        acc_store<T, MM>(B0, acc, n);  // A into B0, which the last staple product has finished reading
+        __syncthreads();
+        acc.zero();
+        acc_mm<T, MM>(acc, Us, B0, n);
+        __syncthreads();               // every lane has read A
+        acc_store<T, MM>(W, acc, n);
+    } else {
+        __syncthreads();
+        lds_mm<T, MM>(W, Us, A, n, false);
+    }
     __syncthreads();
 
     const int lane = threadIdx.x;
@@ -542,8 +699,8 @@ __device__ __forceinline__ void lds_det(double2* D, int n, double& dr, double& d
     }
 }
 
-// {max_ij |(M^dag M - 1)_ij|, |det M - 1|}; D is a work buffer.
-__device__ __forceinline__ void lds_unitarity(const double2* M, double2* D, int n, double& du, double& dd) {
+// max_ij |(M^dag M - 1)_ij| (M unchanged).
+__device__ __forceinline__ double lds_unitarity_dev(const double2* M, int n) {
     const int n2 = n * n;
     double du2 = 0.0;
     for (int e = threadIdx.x; e < n2; e += kLanes) {
@@ -556,11 +713,7 @@ __device__ __forceinline__ void lds_unitarity(const double2* M, double2* D, int 
         }
         du2 = fmax(du2, nan_to_inf(fmadd(m, m, r * r)));  // a NaN entry counts as infinite
     }
-    du = sqrt(wave_max(du2));
-    for (int e = threadIdx.x; e < n2; e += kLanes) D[e] = M[e];
-    double dr, di;
-    lds_det(D, n, dr, di);
-    dd = nan_to_inf(sqrt(fmadd(di, di, (dr - 1.0) * (dr - 1.0))));
+    return sqrt(wave_max(du2));
 }
 
 // Gram-Schmidt on all rows, then the last row times conj(det)/|det| (paper
@@ -568,9 +721,12 @@ __device__ __forceinline__ void lds_unitarity(const double2* M, double2* D, int 
 // earlier ones by classical Gram-Schmidt applied twice (as stable as the
 // modified form): lane k forms <r_k, r_i> from LDS, then lane c subtracts
 // every projection from column c of r_i, so a row costs two LDS hand-offs per
-// pass instead of a chain of wave reductions per projection.  D (first n entries)
-// holds the projections.
-__device__ __forceinline__ void lds_reunit(double2* M, double2* D, int n) {
+// pass instead of a chain of wave reductions per projection.  P (n entries)
+// holds the projections.  (dr, di) is det M of the matrix before the
+// projection: row Gram-Schmidt writes M = L Q with L lower triangular and
+// real positive on its diagonal, so det Q = det M / prod L_ii has the phase
+// of det M, and the fix needs no determinant of Q.
+__device__ __forceinline__ void lds_reunit(double2* M, double2* P, int n, double dr, double di) {
     const int lane = threadIdx.x;
     const bool own = lane < n;
     // n <= 32.  Above n = 8 the two halves of the wavefront share each sum,
@@ -580,7 +736,6 @@ __device__ __forceinline__ void lds_reunit(double2* M, double2* D, int n) {
     const int q = lane & 31, half = lane >> 5;
     const int m0 = split ? n / 2 : n;                    // columns of the lower half
     const int cbeg = half ? m0 : 0, clen = half ? n - m0 : m0;
-    double2* P = D;
     for (int i = 0; i < n; ++i) {
         for (int pass = 0; pass < 2 && i > 0; ++pass) {
             // p_q = <r_q, r_i> for q < i; columns taken from a lane-dependent
@@ -632,9 +787,6 @@ __device__ __forceinline__ void lds_reunit(double2* M, double2* D, int n) {
         }
         wave_lds_order();
     }
-    for (int e = threadIdx.x; e < n * n; e += kLanes) D[e] = M[e];
-    double dr, di;
-    lds_det(D, n, dr, di);
     const double mod = sqrt(dr * dr + di * di);
     const double cr = dr / mod, ci = -di / mod;
     if (own) {
@@ -653,14 +805,16 @@ __device__ __forceinline__ void link_id(const Geom& g, int id, int& mu, int& par
 }
 
 // Re-unitarization of link blockIdx.x; with REPORT the deviation found before
-// the projection goes to partial[2 id], [2 id + 1].  LDS: M, D (FP64).
+// the projection goes to partial[2 id], [2 id + 1].  LDS: one FP64 matrix M
+// and the n projections P.  The link is read twice: once for det M (the LU
+// elimination destroys its copy), once for the Gram-Schmidt.
 template <typename T, bool REPORT>
 __global__ __launch_bounds__(kLanes) void k_reunit(T2<T>* __restrict__ U, Geom g, int n,
                                                    double* __restrict__ partial) {
     extern __shared__ double4 smem_reunit[];
     const int n2 = n * n;
     double2* M = reinterpret_cast<double2*>(smem_reunit);
-    double2* D = M + n2;
+    double2* P = M + n2;
     const int id = blockIdx.x;
     int mu, par, h;
     link_id(g, id, mu, par, h);
@@ -669,9 +823,15 @@ __global__ __launch_bounds__(kLanes) void k_reunit(T2<T>* __restrict__ U, Geom g
         const T2<T>* src = link_at<T>(U, n2, mu, par, h, g.Vh);
         lds_load<double, T>(M, src, n, false);
         __syncthreads();
-        if (REPORT) lds_unitarity(M, D, n, du, dd);
+        if (REPORT) du = lds_unitarity_dev(M, n);
         __syncthreads();
-        lds_reunit(M, D, n);
+        double dr, di;
+        lds_det(M, n, dr, di);
+        if (REPORT) dd = nan_to_inf(sqrt(fmadd(di, di, (dr - 1.0) * (dr - 1.0))));
+        __syncthreads();
+        lds_load<double, T>(M, src, n, false);
+        __syncthreads();
+        lds_reunit(M, P, n, dr, di);
         T2<T>* dst = const_cast<T2<T>*>(src);
         for (int e = threadIdx.x; e < n2; e += kLanes) dst[e] = cpx<T>((T)M[e].x, (T)M[e].y);
     }
@@ -687,7 +847,6 @@ __global__ __launch_bounds__(kLanes) void k_unitarity(const T2<T>* __restrict__ 
     extern __shared__ double4 smem_unit[];
     const int n2 = n * n;
     double2* M = reinterpret_cast<double2*>(smem_unit);
-    double2* D = M + n2;
     const int id = blockIdx.x;
     int mu, par, h;
     link_id(g, id, mu, par, h);
@@ -695,7 +854,11 @@ __global__ __launch_bounds__(kLanes) void k_unitarity(const T2<T>* __restrict__ 
     if ((g.present >> mu) & 1) {
         lds_load<double, T>(M, link_at<T>(U, n2, mu, par, h, g.Vh), n, false);
         __syncthreads();
-        lds_unitarity(M, D, n, du, dd);
+        du = lds_unitarity_dev(M, n);
+        __syncthreads();
+        double dr, di;
+        lds_det(M, n, dr, di);
+        dd = nan_to_inf(sqrt(fmadd(di, di, (dr - 1.0) * (dr - 1.0))));
     }
     if (threadIdx.x == 0) {
         partial[2 * (size_t)id] = du;
@@ -705,7 +868,8 @@ __global__ __launch_bounds__(kLanes) void k_unitarity(const T2<T>* __restrict__ 
 
 // Start configuration of link blockIdx.x: identity, or a Haar draw (Gaussian
 // entries from Box-Muller on the same Philox counters as the register
-// kernels, then re-unitarization).  LDS: M, D.
+// kernels, then re-unitarization).  LDS: M, D (a copy for the determinant,
+// then the projections).
 template <typename T>
 __global__ __launch_bounds__(kLanes) void k_init(T2<T>* __restrict__ U, Geom g, int n, int hot, uint32_t k0,
                                                  uint32_t k1) {
@@ -729,7 +893,12 @@ __global__ __launch_bounds__(kLanes) void k_init(T2<T>* __restrict__ U, Geom g, 
             }
         }
         __syncthreads();
-        lds_reunit(M, D, n);
+        for (int e = threadIdx.x; e < n2; e += kLanes) D[e] = M[e];
+        __syncthreads();
+        double dr, di;
+        lds_det(D, n, dr, di);
+        __syncthreads();
+        lds_reunit(M, D, n, dr, di);
     } else {
         for (int e = threadIdx.x; e < n2; e += kLanes) {
             const int i = e / n;

@@ -84,7 +84,8 @@ PHASES = [(0, 0, 0), (0, 3, 1), (1, 1, 1), (1, 2, 0)]   # (kind, mu, parity)
 
 @pytest.mark.parametrize("nc,dtype", [(4, "f64w"), (4, "f32w"), (5, "f64w"), (9, "f64"), (9, "f32"),
                                       (16, "f64"), (16, "f32"), (24, "f64"), (32, "f64"), (32, "f32"),
-                                      (21, "f32"), (27, "f32")])   # matrix-core products on ragged tiles
+                                      (21, "f32"), (27, "f32"),    # matrix-core products on ragged tiles
+                                      (30, "f32")])                # with the staple sum in registers
 def test_wide_phase_parity(gpu, nc, dtype):
     beta = beta_for(nc)
     base = thermal_field(nc, SMALL, beta, sweeps=1) if nc <= 16 else O.new_field(nc, SMALL, hot=True, seed=21)
