@@ -584,7 +584,15 @@ def main():
                     help="only time one iteration against Nc (4..32) on 8^4 and fit a cubic, then exit")
     ap.add_argument("--nc-list", type=int, nargs="+", default=None,
                     help="with --nc-scan: only these Nc (no fit below five sizes)")
+    ap.add_argument("--batch-only", action="store_true",
+                    help="only the 64-chain batch with its default launch shapes and link layout (no tuner), "
+                         "then exit")
     args = ap.parse_args()
+    if args.batch_only:
+        b = run_batch(max(4, args.steps), sweeps=max(8, args.steps), cut=max(8, args.steps) // 2, tune=False)
+        print(json.dumps({"batch": {k: b[k] for k in ("chains", "sites", "fp32_batched_graph",
+                                                      "fp64_per_chain_eager", "speedup")}}), flush=True)
+        return
     if args.nc_scan:
         print(json.dumps(run_nc_scan(max(1, args.steps // 10), max(1, args.warmup // 3), only=args.nc_list)),
               flush=True)

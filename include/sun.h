@@ -212,8 +212,8 @@ int sun_set_launch(sun_lattice_t h, int kind, int block, int xcd, int waves, int
 int sun_get_launch(sun_lattice_t h, int kind, int *block, int *xcd, int *waves, int *tblock);
 
 /* Sites per work-item of the phase kernels of one update kind (SUN_HEATBATH,
- * SUN_OVERRELAX, or -1 for both): 1, 2 or 4 (default 2 for the heatbath, 1
- * for overrelaxation).  A workgroup then
+ * SUN_OVERRELAX, or -1 for both): 1, 2 or 4 (default 1; 2 for the heatbath
+ * on lattices of at least 2048 tiles of 256 sites per parity, e.g. 32^4).  A workgroup then
  * updates that many tiles of its walk in turn and the grid is that many
  * times smaller.  Kept by sun_set_launch.  A tuning choice only: results are
  * bitwise the same. */

@@ -50,10 +50,7 @@ struct sun_lattice_s {
     int64_t launches[kKernels] = {};
     // launch shapes of the phase kernels (sun_set_launch); the overrelaxation
     // cap is set at creation from the link size
-    // the heatbath takes two tiles per workgroup (SU(3) 32^4 sweep: two-row
-    // 2.040 -> 2.004 ms, 18 reals 3.156 -> 3.151 ms, FP64 two-row 4.378 ->
-    // 4.356 ms against one tile)
-    sun::Shape shape[2] = {sun::Shape{256, 1, 16, 4, 2}, sun::Shape{256, 1, 12, 4}};
+    sun::Shape shape[2] = {sun::Shape{256, 1, 16, 4}, sun::Shape{256, 1, 12, 4}};
 
     size_t link_bytes = 0;
     uint64_t phases_run = 0;  // alternates the walk direction of successive phases
@@ -177,6 +174,12 @@ int sun_lattice_create(int nc, const int L[4], int dtype, void* links, size_t li
     // overrelaxation kernel with 12 for 48-byte links (FP32 two-row) and 8
     // for larger ones (18-real FP32: 70.0 -> 67.3 us, FP64: 161 -> 152 us).
     h->shape[SUN_OVERRELAX].waves = h->link_bytes / (4 * (size_t)g.V) > 48 ? 8 : 12;
+    // On large lattices the heatbath takes two tiles per workgroup (SU(3)
+    // 32^4 sweep: two-row 2.040 -> 2.004 ms, 18 reals 3.156 -> 3.151 ms, FP64
+    // two-row 4.378 -> 4.356 ms); where that would leave fewer than 1024
+    // workgroups (4 per CU) it takes one (SU(4) 12^4: 41 tiles; two per
+    // workgroup cost 40% there).
+    if (sun::half_blocks(g, 256) >= 2 * 1024) h->shape[SUN_HEATBATH].spt = 2;
     h->scratch = static_cast<double*>(scratch);
     h->watch_state = reinterpret_cast<double*>(static_cast<char*>(scratch) + partial_bytes_of(g, is_wide(nc, dtype)));
     h->ops = ops_for(nc, dtype);

@@ -117,14 +117,14 @@ def test_create_validates_buffers_without_touching_them(lib):
     assert lib.sun_get_launch(h, 0, None, None, None, None) == -1
     # sites per work-item: 1, 2 or 4 per kind, kept by sun_set_launch
     s = ctypes.c_int()
-    assert lib.sun_get_sites_per_item(h, 0, ctypes.byref(s)) == 0 and s.value == 2   # heatbath default
+    assert lib.sun_get_sites_per_item(h, 0, ctypes.byref(s)) == 0 and s.value == 1   # small lattice
     assert lib.sun_get_sites_per_item(h, 1, ctypes.byref(s)) == 0 and s.value == 1
     assert lib.sun_set_sites_per_item(h, -1, 3) == -1
     assert lib.sun_set_sites_per_item(h, 2, 2) == -1
     assert lib.sun_set_sites_per_item(None, -1, 2) == -1
     assert lib.sun_set_sites_per_item(h, 1, 4) == 0
     assert lib.sun_get_sites_per_item(h, 1, ctypes.byref(s)) == 0 and s.value == 4
-    assert lib.sun_get_sites_per_item(h, 0, ctypes.byref(s)) == 0 and s.value == 2
+    assert lib.sun_get_sites_per_item(h, 0, ctypes.byref(s)) == 0 and s.value == 1
     assert lib.sun_set_launch(h, -1, 128, 1, 8, 0) == 0
     assert lib.sun_get_sites_per_item(h, 1, ctypes.byref(s)) == 0 and s.value == 4
     assert lib.sun_get_sites_per_item(h, 1, None) == -1
@@ -238,3 +238,17 @@ def test_tile_order_argument_checks(lib):
     for seed in (0, 1, 2 ** 64 - 1):
         assert lib.sun_set_tile_order(h, seed) == 0
     lib.sun_lattice_destroy(h)
+
+
+def test_heatbath_takes_two_tiles_on_large_lattices_only(lib):
+    """Default sites per work-item of the heatbath: 2 where the grid keeps
+    at least 1024 workgroups (32^4: 2048 tiles of 256), else 1."""
+    s = ctypes.c_int()
+    for L, want in (((32, 32, 32, 32), 2), ((24, 24, 24, 24), 1), ((12, 12, 12, 12), 1)):
+        rc, lb, sb = _bytes(lib, 3, L, 2)
+        h = ctypes.c_void_p()
+        assert lib.sun_lattice_create(3, (ctypes.c_int * 4)(*L), 2, ctypes.c_void_p(0x10000), lb,
+                                      ctypes.c_void_p(0x10000 + ((lb + 255) // 256) * 256), sb, ctypes.byref(h)) == 0
+        assert lib.sun_get_sites_per_item(h, 0, ctypes.byref(s)) == 0 and s.value == want, (L, s.value)
+        assert lib.sun_get_sites_per_item(h, 1, ctypes.byref(s)) == 0 and s.value == 1
+        lib.sun_lattice_destroy(h)
