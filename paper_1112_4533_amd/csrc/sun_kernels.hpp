@@ -668,16 +668,17 @@ __device__ __forceinline__ double re_tr_plaq(const T2<T>* __restrict__ U, const 
                                              int h) {
     const Site xm = step_up(g, x, MU), xn = step_up(g, x, NU);
     const int op = par ^ 1;
+    // ReTr(U_mu(x) U_nu(x+mu) [U_nu(x) U_mu(x+nu)]^dag): two independent
+    // products, then sum_ij Re(a_ij conj(c_ij))
     const Mat<N, double> a = mul_nn(load_link_f64<N, T, R>(U, MU, par, h, g.Vh),
                                     load_link_f64<N, T, R>(U, NU, op, xm.s >> 1, g.Vh));
-    const Mat<N, double> b = mul_nd(a, load_link_f64<N, T, R>(U, MU, op, xn.s >> 1, g.Vh));
-    const Mat<N, double> un = load_link_f64<N, T, R>(U, NU, par, h, g.Vh);
-    // ReTr(b un^dag) = sum_ij Re(b_ij conj(un_ij))
+    const Mat<N, double> c = mul_nn(load_link_f64<N, T, R>(U, NU, par, h, g.Vh),
+                                    load_link_f64<N, T, R>(U, MU, op, xn.s >> 1, g.Vh));
     double t = 0.0;
 SUN_MAT_UNROLL
     for (int i = 0; i < N; ++i)
 SUN_MAT_UNROLL
-        for (int j = 0; j < N; ++j) t += b.re[i][j] * un.re[i][j] + b.im[i][j] * un.im[i][j];
+        for (int j = 0; j < N; ++j) t = fmadd(a.im[i][j], c.im[i][j], fmadd(a.re[i][j], c.re[i][j], t));
     return t;
 }
 
