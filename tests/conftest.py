@@ -41,8 +41,9 @@ def pytest_terminal_summary(terminalreporter, exitstatus, config):
             json.dump(EVIDENCE, f, indent=0)
     tr = terminalreporter
     tr.section("parity evidence")
-    keys = ("max_dU_over_tol", "max_dU_over_ctol", "max_K", "max_cond", "max_dU_over_spread",
-            "spread_admitted", "max_dU_over_spread_admitted", "flips")
+    keys = ("max_dU_over_tol", "max_dU_over_ctol", "max_K", "median_K", "max_cond", "max_dU_over_spread",
+            "spread_admitted", "max_dU_over_spread_admitted", "flips", "expected_flips", "drift", "mean", "err",
+            "exact", "z")
     for r in EVIDENCE:
         vals = " ".join(f"{k}={r[k]:.3g}" if isinstance(r.get(k), float) else f"{k}={r.get(k)}"
                         for k in keys if k in r)

@@ -438,6 +438,34 @@ def test_2d_su2_exact_plaquette_on_gpu(gpu):
     assert abs(m - exact) < 4 * e
 
 
+@pytest.mark.parametrize("nc,dtype,beta", [(3, "f32r12", 6.0), (3, "f64", 3.0), (4, "f32", 11.1),
+                                           (4, "f64w", 11.1), (8, "f32", 44.4)])
+def test_2d_sun_one_link_plaquette_on_gpu(gpu, nc, dtype, beta):
+    """The GPU chain alone against the exact 2D SU(Nc) result (the
+    plaquettes of a 2D lattice are independent up to the torus constraint,
+    so the mean of (1/Nc) ReTr P is d ln z / d beta of the one-link
+    integral z = sum_k det I_{k+j-i}(beta/Nc)): the register path in FP32
+    (two-row and 18 reals) and FP64, and the workgroup-per-link path at
+    Nc = 4 and 8."""
+    from closed_forms import one_link_plaquette
+    L = (32, 32, 1, 1)
+    lat = gpu_lattice(gpu, nc, L, dtype, hot=True, seed=7)
+    out = torch.empty(3, dtype=torch.float64, device="cuda")
+    n = 3000
+    series = torch.empty(n, dtype=torch.float64, device="cuda")
+    for k in range(200 + n):
+        lat.sweep(beta, 1, 3, seed=7)
+        if k >= 200:
+            lat.plaquette(out)
+            series[k - 200] = out[0]
+    m, e = binned_mean_err(to_np(series))
+    exact = one_link_plaquette(nc, beta)
+    record(what=f"2D SU({nc}) beta {beta} plaquette", dtype=dtype, mean=m, err=e, exact=float(exact),
+           z=float((m - exact) / e))
+    print(f"2D SU({nc}) {dtype} beta {beta}: GPU {m:.5f} +- {e:.5f}, exact {exact:.5f}")
+    assert abs(m - exact) < 4 * e
+
+
 # ---------------------------------------------------------------------------
 # Full size, launch configuration of the benchmark (SU(3) 32^4; FP32 two-row
 # is the headline, FP32 18-real and FP64 the precision comparison)
