@@ -63,8 +63,7 @@ enum {
  * contiguous in memory; SUN_F32 and SUN_F64 select it by themselves there,
  * and the WIDE codes select it at Nc = 4 too (for comparisons with the
  * register path).  Its update keeps 3 Nc^2 complex entries in LDS (48 KiB
- * at Nc = 32 in FP64).  Launch shapes do not apply to it, and batches do
- * not accept it. */
+ * at Nc = 32 in FP64).  Launch shapes do not apply to it. */
 enum {
     SUN_F32 = 0,
     SUN_F64 = 1,
@@ -264,7 +263,9 @@ int sun_sample_su2(int dtype, const double *dev_alpha, int n, uint64_t seed, uin
  * Batches of independent chains (many small lattices in one launch per
  * phase).  A batch groups n lattices of any Nc, precision and extents; each
  * chain has its own coupling beta[i] and seed[i].  One launch per phase and
- * per (Nc, precision) group covers every chain of the group; the chains'
+ * per (Nc, storage) group covers every chain of the group (register path:
+ * one group per dtype; workgroup-per-link path: one per precision, a
+ * workgroup per link of every chain in the group); the chains'
  * RNG step counters live in the device table, so a captured graph replays
  * with fresh random numbers.  A chain run in a batch gives bitwise the same
  * field as the same chain run alone with sun_sweep.
@@ -277,8 +278,7 @@ typedef struct sun_batch_s *sun_batch_t;
 int sun_batch_bytes(int n, size_t *table_bytes);
 
 /* Creates a batch over n existing lattice handles (which must outlive it);
- * SUN_EUNSUP if one of them runs the workgroup-per-link path.
- * betas, seeds: host arrays of n values.  table: caller-owned device memory
+ * SUN_EINVAL if two of them share link or scratch memory.  betas, seeds: host arrays of n values.  table: caller-owned device memory
  * of sun_batch_bytes() bytes, 256-byte aligned; it is written once here with
  * a synchronous copy. */
 int sun_batch_create(int n, const sun_lattice_t *chains, const double *betas, const uint64_t *seeds,
@@ -306,8 +306,9 @@ int sun_batch_capture(sun_batch_t b, int n_sweeps, int n_hb, int n_or, int reuni
                       double *dev_plaq, sun_stream_t stream);
 int sun_batch_replay(sun_batch_t b, sun_stream_t stream);
 
-/* Launch shape of the batch's phase kernels (as sun_set_launch, always with
- * the linear tile walk; default (256, 1, 0) for both kinds).  Waits for the
+/* Launch shape of the batch's register-path phase kernels (as
+ * sun_set_launch, always with the linear tile walk; default (256, 1, 0) for
+ * both kinds; the workgroup-per-link groups ignore it).  Waits for the
  * device, rewrites the table, and drops any captured graph. */
 int sun_batch_set_launch(sun_batch_t b, int kind, int block, int xcd, int waves);
 /* Sites per work-item of the batch's phase kernels (as

@@ -70,9 +70,43 @@ struct OpsWide {
         wide::k_import<T><<<entry_blocks(c), 256, 0, c.stream>>>((P*)c.links, c.g, c.nc, in);
     }
 
+    // Batches: one launch per phase covers every chain of the group (same
+    // Nc and precision), one workgroup per link.
+    template <bool MM, bool RA>
+    static void update_batch_as(const ChainDesc* d, int n, int tiles, int kind, int mu, int par, uint32_t off, int nc,
+                                hipStream_t s) {
+        wide::k_update_batch<T, MM, RA><<<tiles, wide::kLanes, wide_update_lds(nc, f64), s>>>(
+            d, n, nc, mu, par, kind == 0 ? 1 : 0, off);
+    }
+    static void update_batch(const ChainDesc* d, int n, int tiles, int kind, int mu, int par, uint32_t off,
+                             const Shape& /*shape*/, int nc, hipStream_t s) {
+        const bool ra = wide_update_regacc(nc, f64);
+        if constexpr (!f64) {
+            if (nc > wide::kMfmaMinN) {
+                if (ra)
+                    update_batch_as<true, true>(d, n, tiles, kind, mu, par, off, nc, s);
+                else
+                    update_batch_as<true, false>(d, n, tiles, kind, mu, par, off, nc, s);
+                return;
+            }
+        }
+        if (ra)
+            update_batch_as<false, true>(d, n, tiles, kind, mu, par, off, nc, s);
+        else
+            update_batch_as<false, false>(d, n, tiles, kind, mu, par, off, nc, s);
+    }
+    static void reunit_batch(const ChainDesc* d, int n, int tiles, int nc, hipStream_t s) {
+        wide::k_reunit_batch<T><<<tiles, wide::kLanes, wide::fp64_lds(nc, 1) + (size_t)nc * sizeof(double2), s>>>(
+            d, n, nc);
+    }
+    static void plaquette_batch(const ChainDesc* d, int n, int tiles, double* out, int nc, hipStream_t s) {
+        wide::k_plaquette_batch<T><<<tiles, wide::kLanes, wide::fp64_lds(nc, 3), s>>>(d, n, nc);
+        wide::k_plaquette_final_batch_wide<><<<n, kBlock, 0, s>>>(d, n, nc, out);
+    }
+
     static const Ops* table() {
         static const Ops ops = {&update, &init, &reunit, &unitarity, &plaquette, &polyakov, &export_field,
-                                &import_field, nullptr, nullptr, nullptr};
+                                &import_field, &update_batch, &reunit_batch, &plaquette_batch};
         return &ops;
     }
 };

@@ -473,6 +473,8 @@ struct sun_batch_s {
         const sun::Ops* ops;
         int first, count;      // range of the device table
         int tiles[5];          // total tiles per grid kind (see TileKind)
+        int nc;
+        bool wide;             // workgroup-per-link path: tiles count links / sites, one workgroup each
     };
     std::vector<sun_lattice_t> chains;  // in the caller's order
     std::vector<Group> groups;
@@ -510,13 +512,13 @@ int batch_sweep_launches(sun_batch_t b, int n_hb, int n_or, int reunit, const do
             for (int mu = 0; mu < 4; ++mu)
                 for (int p = 0; p < 2; ++p)
                     gr.ops->update_batch(d, gr.count, gr.tiles[sun::TILE_HALF_HB], SUN_HEATBATH, mu, p, (uint32_t)k,
-                                         b->shape[SUN_HEATBATH], s);
+                                         b->shape[SUN_HEATBATH], gr.nc, s);
         for (int k = 0; k < n_or; ++k)
             for (int mu = 0; mu < 4; ++mu)
                 for (int p = 0; p < 2; ++p)
                     gr.ops->update_batch(d, gr.count, gr.tiles[sun::TILE_HALF_OR], SUN_OVERRELAX, mu, p, 0,
-                                         b->shape[SUN_OVERRELAX], s);
-        if (reunit) gr.ops->reunit_batch(d, gr.count, gr.tiles[sun::TILE_LINK], s);
+                                         b->shape[SUN_OVERRELAX], gr.nc, s);
+        if (reunit) gr.ops->reunit_batch(d, gr.count, gr.tiles[sun::TILE_LINK], gr.nc, s);
     }
     if (n_hb > 0) sun::launch_advance_steps(b->table, (int)b->chains.size(), n_hb, s);
     return launch_check("batch sweep");
@@ -530,6 +532,14 @@ int upload_table(sun_batch_t b) {
         for (int i = gr.first; i < gr.first + gr.count; ++i) {
             sun::ChainDesc& c = b->host[i];
             for (int k = 0; k < 5; ++k) c.tile0[k] = t[k];
+            if (gr.wide) {  // one workgroup per updated link, per site, per link
+                t[sun::TILE_HALF_HB] += c.g.Vh;
+                t[sun::TILE_SITE] += c.g.V;
+                t[sun::TILE_LINK] += 4 * c.g.V;
+                t[sun::TILE_SPATIAL] += c.g.V / c.g.L[3];
+                t[sun::TILE_HALF_OR] += c.g.Vh;
+                continue;
+            }
             t[sun::TILE_HALF_HB] += sun::half_blocks(c.g, b->shape[SUN_HEATBATH].block);
             t[sun::TILE_SITE] += sun::plaquette_tiles(c.g);
             t[sun::TILE_LINK] += sun::link_blocks(c.g);
@@ -545,7 +555,7 @@ int upload_table(sun_batch_t b) {
 
 int batch_plaquette_launches(sun_batch_t b, double* out, hipStream_t s) {
     for (const auto& gr : b->groups)
-        gr.ops->plaquette_batch(b->table + gr.first, gr.count, gr.tiles[sun::TILE_SITE], out, s);
+        gr.ops->plaquette_batch(b->table + gr.first, gr.count, gr.tiles[sun::TILE_SITE], out, gr.nc, s);
     return launch_check("batch plaquette");
 }
 
@@ -591,12 +601,8 @@ int sun_batch_create(int n, const sun_lattice_t* chains, const double* betas, co
     if (!chains || !betas || !seeds) return fail(SUN_EINVAL, "null chain, beta or seed array");
     if (!table || table_bytes < need) return fail(SUN_ESIZE, "table of %zu bytes, need %zu", table_bytes, need);
     if ((uintptr_t)table & 255) return fail(SUN_EINVAL, "table must be 256-byte aligned");
-    for (int i = 0; i < n; ++i) {
+    for (int i = 0; i < n; ++i)
         if (!chains[i]) return fail(SUN_EINVAL, "chain %d is null", i);
-        if (is_wide(chains[i]->nc, chains[i]->dtype))
-            return fail(SUN_EUNSUP, "chain %d uses the workgroup-per-link path (Nc = %d), which batches do not run", i,
-                        chains[i]->nc);
-    }
     // Two descriptors over the same memory would update the same links (or
     // write the same partials) in one launch: refuse a lattice listed twice
     // and lattices whose link or scratch buffers overlap.
@@ -624,28 +630,40 @@ int sun_batch_create(int n, const sun_lattice_t* chains, const double* betas, co
     auto* b = new sun_batch_s;
     b->chains.assign(chains, chains + n);
     b->table = static_cast<sun::ChainDesc*>(table);
-    // group by (Nc, dtype), keeping the caller's order inside a group
+    // group by path, Nc and storage (register path: the dtype; workgroup-per-
+    // link path: the precision), keeping the caller's order inside a group
+    struct Key {
+        int nc, dt;
+        bool wide;
+    };
+    std::vector<Key> keys;
     for (int nc = 2; nc <= SUN_NC_MAX_REGISTER; ++nc)
-        for (int dt = SUN_F32; dt <= SUN_F64_TWO_ROW; ++dt) {
-            if (is_two_row(dt) && nc != 3) continue;
-            sun_batch_s::Group gr{ops_for(nc, dt), (int)b->host.size(), 0, {0, 0, 0, 0, 0}};
-            for (int i = 0; i < n; ++i) {
-                const sun_lattice_t h = chains[i];
-                if (h->nc != nc || h->dtype != dt) continue;
-                sun::ChainDesc c{};
-                c.links = h->links;
-                c.scratch = h->scratch;
-                c.g = h->g;
-                c.beta = betas[i];
-                c.k0 = (uint32_t)seeds[i];
-                c.k1 = (uint32_t)(seeds[i] >> 32);
-                c.step = h->step;
-                c.out_index = i;
-                b->host.push_back(c);
-                ++gr.count;
-            }
-            if (gr.count) b->groups.push_back(gr);
+        for (int dt = SUN_F32; dt <= SUN_F64_TWO_ROW; ++dt)
+            if (!is_two_row(dt) || nc == 3) keys.push_back({nc, dt, false});
+    for (int nc = 4; nc <= SUN_NC_MAX; ++nc)
+        for (int f64 = 0; f64 <= 1; ++f64) keys.push_back({nc, f64 ? SUN_F64_WIDE : SUN_F32_WIDE, true});
+    for (const Key& key : keys) {
+        const int nc = key.nc, dt = key.dt;
+        sun_batch_s::Group gr{ops_for(nc, dt), (int)b->host.size(), 0, {0, 0, 0, 0, 0}, nc, key.wide};
+        for (int i = 0; i < n; ++i) {
+            const sun_lattice_t h = chains[i];
+            const bool w = is_wide(h->nc, h->dtype);
+            if (h->nc != nc || w != key.wide) continue;
+            if (w ? is_f64(h->dtype) != is_f64(dt) : h->dtype != dt) continue;
+            sun::ChainDesc c{};
+            c.links = h->links;
+            c.scratch = h->scratch;
+            c.g = h->g;
+            c.beta = betas[i];
+            c.k0 = (uint32_t)seeds[i];
+            c.k1 = (uint32_t)(seeds[i] >> 32);
+            c.step = h->step;
+            c.out_index = i;
+            b->host.push_back(c);
+            ++gr.count;
         }
+        if (gr.count) b->groups.push_back(gr);
+    }
     for (int i = 0; i < n; ++i) b->step0.push_back(chains[i]->step);
     if (int rc = upload_table(b)) {
         delete b;

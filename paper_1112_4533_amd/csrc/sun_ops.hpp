@@ -120,12 +120,13 @@ struct Ops {
     int (*polyakov)(const Ctx&, double* partial);
     void (*export_field)(const Ctx&, double* out);
     void (*import_field)(const Ctx&, const double* in);
-    // batches: d is a device table of n chains of this Nc and storage type;
-    // tiles is the total tile count of the grid kind the call uses
+    // batches: d is a device table of n chains of this Nc (nc) and storage
+    // type; tiles is the total tile count of the grid kind the call uses (on
+    // the workgroup-per-link path: links, sites or links, one workgroup each)
     void (*update_batch)(const ChainDesc* d, int n, int tiles, int kind, int mu, int par, uint32_t step_offset,
-                         const Shape& shape, hipStream_t s);
-    void (*reunit_batch)(const ChainDesc* d, int n, int tiles, hipStream_t s);
-    void (*plaquette_batch)(const ChainDesc* d, int n, int tiles, double* out, hipStream_t s);
+                         const Shape& shape, int nc, hipStream_t s);
+    void (*reunit_batch)(const ChainDesc* d, int n, int tiles, int nc, hipStream_t s);
+    void (*plaquette_batch)(const ChainDesc* d, int n, int tiles, double* out, int nc, hipStream_t s);
 };
 
 constexpr int kLaunchBlock = 256;

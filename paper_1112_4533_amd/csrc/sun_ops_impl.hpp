@@ -59,7 +59,7 @@ struct OpsImpl {
     }
 
     static void update_batch(const ChainDesc* d, int n, int tiles, int kind, int mu, int par, uint32_t off,
-                             const Shape& sh, hipStream_t s) {
+                             const Shape& sh, int /*nc*/, hipStream_t s) {
         const int lds = lds_for_wave_cap(sh.waves, sh.block);
         if (kind == 0)
             update_batch_kind<true>(d, n, tiles, mu, par, off, sh, lds, s);
@@ -67,11 +67,11 @@ struct OpsImpl {
             update_batch_kind<false>(d, n, tiles, mu, par, off, sh, lds, s);
     }
 
-    static void reunit_batch(const ChainDesc* d, int n, int tiles, hipStream_t s) {
+    static void reunit_batch(const ChainDesc* d, int n, int tiles, int /*nc*/, hipStream_t s) {
         k_reunit_batch<N, T, R><<<tiles, kBlock, 0, s>>>(d, n);
     }
 
-    static void plaquette_batch(const ChainDesc* d, int n, int tiles, double* out, hipStream_t s) {
+    static void plaquette_batch(const ChainDesc* d, int n, int tiles, double* out, int /*nc*/, hipStream_t s) {
         // the chains of a batch are small, cache-resident lattices
         k_plaquette_batch<N, T, R><<<tiles, kBlock, lds_for_wave_cap(plaquette_wave_cap(0), kBlock), s>>>(d, n);
         k_plaquette_final_batch<N><<<n, kBlock, 0, s>>>(d, n, out);

@@ -509,8 +509,8 @@ __device__ __forceinline__ void rows_left_mul_col(T2<T>* M, int n, int i, int j,
 // FP64 form with the sum in registers would otherwise take a few more and
 // leave one.
 template <typename T, bool MM, bool RA>
-__global__ __launch_bounds__(kLanes, 2) void k_update(T2<T>* __restrict__ U, Geom g, int n, int mu, int par, int hb,
-                                                   T beta, uint32_t k0, uint32_t k1, uint32_t step) {
+__device__ __forceinline__ void update_link_wide(T2<T>* __restrict__ U, const Geom& g, int n, int mu, int par,
+                                                 int hb, T beta, uint32_t k0, uint32_t k1, uint32_t step, int h) {
     extern __shared__ double4 smem_update[];
     const int n2 = n * n;
     T2<T>* A = reinterpret_cast<T2<T>*>(smem_update);  // the staple sum (without RA)
@@ -518,7 +518,6 @@ __global__ __launch_bounds__(kLanes, 2) void k_update(T2<T>* __restrict__ U, Geo
     T2<T>* B1 = B0 + n2;
     Acc<T, MM> acc;  // the staple sum (with RA)
     constexpr int kRows = (RA && sizeof(T) == 8) ? 2 : 4;  // FP64 with the sum in registers: fewer at a time
-    const int h = blockIdx.x;
     const int Vh = g.Vh;
     const Site x = site_of(g, par, h);
     const Site xp = step_up(g, x, mu);
@@ -616,6 +615,27 @@ __global__ __launch_bounds__(kLanes, 2) void k_update(T2<T>* __restrict__ U, Geo
     __syncthreads();
     T2<T>* dst = const_cast<T2<T>*>(link_at<T>(U, n2, mu, par, h, Vh));
     for (int e = threadIdx.x; e < n2; e += kLanes) dst[e] = Us[e];
+}
+
+// One checkerboard phase of one lattice: workgroup h updates link h.
+template <typename T, bool MM, bool RA>
+__global__ __launch_bounds__(kLanes, 2) void k_update(T2<T>* __restrict__ U, Geom g, int n, int mu, int par, int hb,
+                                                   T beta, uint32_t k0, uint32_t k1, uint32_t step) {
+    update_link_wide<T, MM, RA>(U, g, n, mu, par, hb, beta, k0, k1, step, (int)blockIdx.x);
+}
+
+// One phase of every chain of a batch group (same Nc and precision): one
+// workgroup per updated link of each chain, the chain found by binary search
+// over the first-link prefix of the descriptor table (TILE_HALF_HB counts
+// links here); coupling, Philox key and RNG step come from the table.
+template <typename T, bool MM, bool RA>
+__global__ __launch_bounds__(kLanes, 2) void k_update_batch(const ChainDesc* __restrict__ d, int nchains, int n,
+                                                         int mu, int par, int hb, uint32_t step_offset) {
+    const int c = find_chain<TILE_HALF_HB>(d, nchains, (int)blockIdx.x);
+    const Geom g = d[c].g;
+    if (!((g.present >> mu) & 1)) return;
+    update_link_wide<T, MM, RA>((T2<T>*)d[c].links, g, n, mu, par, hb, (T)d[c].beta, d[c].k0, d[c].k1,
+                                (uint32_t)(d[c].step + step_offset), (int)blockIdx.x - d[c].tile0[TILE_HALF_HB]);
 }
 
 // ---------------------------------------------------------------------------
@@ -809,13 +829,12 @@ __device__ __forceinline__ void link_id(const Geom& g, int id, int& mu, int& par
 // and the n projections P.  The link is read twice: once for det M (the LU
 // elimination destroys its copy), once for the Gram-Schmidt.
 template <typename T, bool REPORT>
-__global__ __launch_bounds__(kLanes) void k_reunit(T2<T>* __restrict__ U, Geom g, int n,
-                                                   double* __restrict__ partial) {
+__device__ __forceinline__ void reunit_link_wide(T2<T>* __restrict__ U, const Geom& g, int n, int id,
+                                                 double* __restrict__ partial) {
     extern __shared__ double4 smem_reunit[];
     const int n2 = n * n;
     double2* M = reinterpret_cast<double2*>(smem_reunit);
     double2* P = M + n2;
-    const int id = blockIdx.x;
     int mu, par, h;
     link_id(g, id, mu, par, h);
     double du = 0.0, dd = 0.0;
@@ -839,6 +858,20 @@ __global__ __launch_bounds__(kLanes) void k_reunit(T2<T>* __restrict__ U, Geom g
         partial[2 * (size_t)id] = du;
         partial[2 * (size_t)id + 1] = dd;
     }
+}
+
+template <typename T, bool REPORT>
+__global__ __launch_bounds__(kLanes) void k_reunit(T2<T>* __restrict__ U, Geom g, int n,
+                                                   double* __restrict__ partial) {
+    reunit_link_wide<T, REPORT>(U, g, n, (int)blockIdx.x, partial);
+}
+
+// Re-unitarization of every chain of a batch group: one workgroup per link
+// (TILE_LINK counts links here).
+template <typename T>
+__global__ __launch_bounds__(kLanes) void k_reunit_batch(const ChainDesc* __restrict__ d, int nchains, int n) {
+    const int c = find_chain<TILE_LINK>(d, nchains, (int)blockIdx.x);
+    reunit_link_wide<T, false>((T2<T>*)d[c].links, d[c].g, n, (int)blockIdx.x - d[c].tile0[TILE_LINK], nullptr);
 }
 
 template <typename T>
@@ -915,14 +948,13 @@ __global__ __launch_bounds__(kLanes) void k_init(T2<T>* __restrict__ U, Geom g, 
 // ReTr(U_mu(x) U_nu(x+mu) U_mu(x+nu)^dag U_nu(x)^dag) = Re sum_ij A_ij conj(B_ij)
 // with A = U_mu(x) U_nu(x+mu), B = U_nu(x) U_mu(x+nu).  LDS: A, X, Y.
 template <typename T>
-__global__ __launch_bounds__(kLanes) void k_plaquette(const T2<T>* __restrict__ U, Geom g, int n,
-                                                      double* __restrict__ partial) {
+__device__ __forceinline__ void plaquette_site_wide(const T2<T>* __restrict__ U, const Geom& g, int n, int s,
+                                                    double* __restrict__ partial) {
     extern __shared__ double4 smem_plaq[];
     const int n2 = n * n;
     double2* A = reinterpret_cast<double2*>(smem_plaq);
     double2* X = A + n2;
     double2* Y = X + n2;
-    const int s = blockIdx.x;
     Site x;
     {
         int r = s;
@@ -965,6 +997,37 @@ __global__ __launch_bounds__(kLanes) void k_plaquette(const T2<T>* __restrict__ 
         partial[2 * (size_t)s] = acc[0];
         partial[2 * (size_t)s + 1] = acc[1];
     }
+}
+
+template <typename T>
+__global__ __launch_bounds__(kLanes) void k_plaquette(const T2<T>* __restrict__ U, Geom g, int n,
+                                                      double* __restrict__ partial) {
+    plaquette_site_wide<T>(U, g, n, (int)blockIdx.x, partial);
+}
+
+// Plaquette sums of every chain of a batch group: one workgroup per site
+// (TILE_SITE counts sites here), the partials in each chain's own scratch at
+// the index the single-lattice kernel uses.
+template <typename T>
+__global__ __launch_bounds__(kLanes) void k_plaquette_batch(const ChainDesc* __restrict__ d, int nchains, int n) {
+    const int c = find_chain<TILE_SITE>(d, nchains, (int)blockIdx.x);
+    plaquette_site_wide<T>((const T2<T>*)d[c].links, d[c].g, n, (int)blockIdx.x - d[c].tile0[TILE_SITE],
+                           d[c].scratch);
+}
+
+// One block per chain: out[3 c .. 3 c + 2] from its V site partials.
+template <int Dummy = 0>
+__global__ __launch_bounds__(kBlock) void k_plaquette_final_batch_wide(const ChainDesc* __restrict__ d, int nchains,
+                                                                       int n, double* __restrict__ out) {
+    const int c = blockIdx.x;
+    if (c >= nchains) return;
+    int n_sp = 0, n_tm = 0;
+    for (int m = 0; m < 4; ++m)
+        for (int k = m + 1; k < 4; ++k)
+            if (((d[c].g.present >> m) & 1) && ((d[c].g.present >> k) & 1)) (k == 3 ? n_tm : n_sp)++;
+    const double norm = (double)n * (double)d[c].g.V;
+    plaquette_final<2>(d[c].scratch, d[c].g.V, out + 3 * (size_t)d[c].out_index, norm * n_sp, norm * n_tm,
+                       norm * (n_sp + n_tm));
 }
 
 // Polyakov loop at spatial site blockIdx.x: Tr prod_t U_3(x, t), FP64.

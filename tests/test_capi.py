@@ -156,7 +156,8 @@ def test_batch_argument_checks(lib):
     d = (ctypes.c_double * 1)(1.0)
     s = (ctypes.c_uint64 * 1)(1)
     assert lib.sun_batch_create(1, one, d, s, ctypes.c_void_p(0x10000), tb.value, ctypes.byref(out)) == -1
-    # a lattice on the workgroup-per-link path is refused before anything runs
+    # a lattice on the workgroup-per-link path passes the checks (here the
+    # table upload then fails for want of a device, never as unsupported)
     L = (ctypes.c_int * 4)(4, 4, 2, 2)
     lb, sb = ctypes.c_size_t(), ctypes.c_size_t()
     assert lib.sun_lattice_bytes(9, L, 0, ctypes.byref(lb), ctypes.byref(sb)) == 0
@@ -164,7 +165,12 @@ def test_batch_argument_checks(lib):
     assert lib.sun_lattice_create(9, L, 0, ctypes.c_void_p(0x100000), lb.value, ctypes.c_void_p(0x200000), sb.value,
                                   ctypes.byref(h)) == 0
     wide = (ctypes.c_void_p * 1)(h.value)
-    assert lib.sun_batch_create(1, wide, d, s, ctypes.c_void_p(0x10000), tb.value, ctypes.byref(out)) == -4
+    rc = lib.sun_batch_create(1, wide, d, s, ctypes.c_void_p(0x10000), tb.value, ctypes.byref(out))
+    assert rc in (0, -3), rc
+    if rc == 0:
+        lib.sun_batch_destroy(out)
+    else:
+        assert b"batch table upload" in lib.sun_last_error()
     lib.sun_lattice_destroy(h)
     # a lattice listed twice, or two lattices over overlapping buffers, would
     # update the same links in one launch: refused before the table is written

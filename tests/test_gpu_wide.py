@@ -182,11 +182,74 @@ def test_wide_sweep_is_its_phase_sequence(gpu):
     assert a.step == 1
 
 
-def test_wide_rejected_by_batches(gpu):
+WIDE_BATCH = [  # (nc, L, dtype, beta, seed)
+    (5, (4, 4, 2, 2), "f32", beta_for(5), 21),
+    (5, (4, 2, 4, 2), "f32", beta_for(5) + 0.7, 22),    # same group, other extents and coupling
+    (8, (4, 4, 2, 2), "f64", beta_for(8), 23),
+    (4, (4, 4, 2, 2), "f32w", 11.1, 24),                # SU(4) on the workgroup-per-link path
+    (3, (4, 4, 4, 4), "f32", 6.0, 25),                  # a register-path chain in the same batch
+    (6, (4, 4, 1, 4), "f64", beta_for(6), 26),          # 3D: an absent direction
+    (24, (4, 2, 2, 2), "f32", beta_for(24), 27),        # matrix-core products
+    (22, (2, 2, 4, 2), "f64", beta_for(22), 28),        # staple sum in registers
+]
+
+
+def test_wide_chains_in_a_batch_are_bitwise_the_chains_alone(gpu):
+    """Large-Nc chains join a batch (one launch per phase for each Nc and
+    precision): two eager sweeps, then a captured sweep replayed three times
+    with eager work between the replays, give bitwise the fields and
+    plaquettes of the chains swept alone, and the step counters advance
+    alike."""
     sun = gpu
-    lat = gpu_lattice(sun, 9, (4, 4, 2, 2), "f32")
-    with pytest.raises(sun.SunError):
-        sun.Batch([lat], [6.0], [1])
+    alone = [gpu_lattice(sun, nc, L, dt, hot=True, seed=sd) for nc, L, dt, b, sd in WIDE_BATCH]
+    batched = [gpu_lattice(sun, nc, L, dt, hot=True, seed=sd) for nc, L, dt, b, sd in WIDE_BATCH]
+    for lat, (nc, L, dt, beta, sd) in zip(alone, WIDE_BATCH):
+        for _ in range(5):
+            lat.sweep(beta, 1, 2, seed=sd)
+    bt = sun.Batch(batched, [c[3] for c in WIDE_BATCH], [c[4] for c in WIDE_BATCH])
+    bt.sweep(1, 2)
+    bt.sweep(1, 2)
+    plaq = torch.zeros((len(WIDE_BATCH), 3), dtype=torch.float64, device="cuda")
+    bt.capture(n_sweeps=1, n_hb=1, n_or=2, plaq_out=plaq)
+    for _ in range(3):
+        bt.replay()
+        torch.cuda.synchronize()
+        _ = bt.plaquette()
+        torch.cuda.synchronize()
+    bt.sync()
+    for i, (a, b) in enumerate(zip(alone, batched)):
+        assert torch.equal(a.links, b.links), f"chain {i} {WIDE_BATCH[i][:3]} differs"
+        assert a.step == b.step == 5
+        assert torch.equal(a.plaquette(), plaq[i]), f"plaquette of chain {i}"
+        assert torch.equal(a.plaquette(), bt.plaquette()[i]), f"eager batch plaquette of chain {i}"
+
+
+def test_wide_batch_couplings_from_a_device_array(gpu):
+    """As the register path's coupling-array test, for a batch of large-Nc
+    chains: a graph replay reads the coupling array's contents at that
+    time."""
+    sun = gpu
+    cfg = WIDE_BATCH[:4]
+    b1 = torch.tensor([c[3] + 0.3 for c in cfg], dtype=torch.float64, device="cuda")
+    b2 = torch.tensor([c[3] - 0.2 for c in cfg], dtype=torch.float64, device="cuda")
+    alone = [gpu_lattice(sun, nc, L, dt, hot=True, seed=sd) for nc, L, dt, b, sd in cfg]
+    batched = [gpu_lattice(sun, nc, L, dt, hot=True, seed=sd) for nc, L, dt, b, sd in cfg]
+    for i, (lat, (nc, L, dt, beta, sd)) in enumerate(zip(alone, cfg)):
+        for bb in (b1, b2, b1):
+            lat.sweep(float(bb[i]), 1, 1, seed=sd)
+    bt = sun.Batch(batched, [c[3] for c in cfg], [c[4] for c in cfg])
+    bt.sweep(1, 1, beta=b1)
+    arr = b2.clone()
+    bt.capture(n_sweeps=1, n_hb=1, n_or=1, beta=arr)
+    bt.replay()
+    torch.cuda.synchronize()
+    arr.copy_(b1)
+    torch.cuda.synchronize()
+    bt.replay()
+    torch.cuda.synchronize()
+    bt.sync()
+    for i, (a, b) in enumerate(zip(alone, batched)):
+        assert torch.equal(a.links, b.links), f"chain {i} differs"
 
 
 @pytest.mark.parametrize("nc,dtype,L", [(5, "f64", (4, 4, 1, 4)), (9, "f32", (4, 2, 4, 1)), (6, "f64", (4, 1, 4, 1))])
