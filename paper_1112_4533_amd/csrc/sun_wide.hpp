@@ -19,6 +19,8 @@
 // result).  Reductions and re-unitarization are FP64.
 #pragma once
 
+#include <cfloat>
+
 #include "sun_kernels.hpp"
 
 namespace sun {
@@ -385,6 +387,40 @@ __device__ __forceinline__ double lane_value(double v, int lane) {
     return __builtin_bit_cast(double, ((unsigned long long)hi << 32) | lo);
 }
 
+// The scalar steps of the FP32 subgroup chain -- the block's norm and its
+// inverse, 1 / alpha, the draw's square roots -- use the hardware reciprocal,
+// reciprocal square root and square root (about 1 ulp each).  Every lane
+// computes them for the whole link, one step after another, so their latency
+// is the chain's: the correctly rounded sequences take a dozen dependent
+// instructions each, and their extra half ulp is far inside the FP32
+// tolerance of a link update.  Zero and subnormal arguments, and FP64, keep
+// the correctly rounded forms.
+__device__ __forceinline__ float chain_sqrt(float x) { return __builtin_amdgcn_sqrtf(x); }
+__device__ __forceinline__ double chain_sqrt(double x) { return sqrt(x); }
+
+template <typename T>
+__device__ __forceinline__ T chain_inverse(T alpha) {
+    if constexpr (sizeof(T) == 4) {
+        if (alpha >= FLT_MIN) return __builtin_amdgcn_rcpf(alpha);
+    }
+    return alpha > T(0) ? T(1) / alpha : T(0);
+}
+
+// k = |p| and v = p / k (v = 1 for p = 0), as unit_quat.
+template <typename T>
+__device__ __forceinline__ T chain_unit_quat(const Quat<T>& p, Quat<T>& v) {
+    if constexpr (sizeof(T) == 4) {
+        const float k2 = p.q[0] * p.q[0] + p.q[1] * p.q[1] + p.q[2] * p.q[2] + p.q[3] * p.q[3];
+        if (k2 >= FLT_MIN) {
+            const float r = __builtin_amdgcn_rsqf(k2);
+#pragma unroll
+            for (int c = 0; c < 4; ++c) v.q[c] = p.q[c] * r;
+            return k2 * r;
+        }
+    }
+    return unit_quat(p, v);
+}
+
 // SU(2) draws of the subgroup steps, eight subgroups per pair of Philox
 // passes.  The hybrid sampler accepts an attempt with probability at least
 // about 0.71, so the first few attempts almost always decide: lane l holds
@@ -438,7 +474,7 @@ __device__ __forceinline__ bool su2_attempt_batched(T alpha, T ia, bool creutz, 
         x0 = (alpha == T(0)) ? T(2) * b.r0 - T(1) : T(1) + d_log1p((T(1) - b.r0) * em) * ia;
         const T rhs = T(1) - x0 * x0;
         if (b.r1 * b.r1 <= rhs) {
-            rad = d_sqrt(rhs);
+            rad = chain_sqrt(rhs);
             return true;
         }
     } else {
@@ -446,7 +482,7 @@ __device__ __forceinline__ bool su2_attempt_batched(T alpha, T ia, bool creutz, 
         const T rhs = T(1) - lam2;
         if (b.r3 * b.r3 <= rhs) {
             x0 = T(1) - T(2) * lam2;
-            rad = T(2) * d_sqrt(lam2) * d_sqrt(rhs);
+            rad = T(2) * chain_sqrt(lam2) * chain_sqrt(rhs);
             return true;
         }
     }
@@ -461,7 +497,7 @@ __device__ __forceinline__ int sample_su2_lanes(T alpha, const DrawBatch<T>& b, 
                                                 uint32_t site, uint32_t step, uint32_t mu_sg, Quat<T>& x) {
     const bool creutz = alpha < Const<T>::switch_alpha;
     const T em = creutz ? d_expm1(T(-2) * alpha) : T(0);
-    const T ia = alpha > T(0) ? T(1) / alpha : T(0);
+    const T ia = chain_inverse(alpha);
     T x0 = T(1), rad = T(0);
     bool ok = su2_attempt_batched(alpha, ia, creutz, em, b, x0, rad);
     unsigned long long mask = __ballot(ok) & (0xFFull << (kFirstHits * s));
@@ -595,7 +631,7 @@ __device__ __forceinline__ void update_link_wide(T2<T>* __restrict__ U, const Ge
             p.q[2] = T(0.5) * (wij.x - wji.x);
             p.q[1] = T(0.5) * (wij.y + wji.y);
             Quat<T> v;
-            const T k = unit_quat(p, v);
+            const T k = chain_unit_quat(p, v);
             Quat<T> a;
             bool apply = true;
             if (hb) {
