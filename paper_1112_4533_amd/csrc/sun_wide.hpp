@@ -387,36 +387,64 @@ __device__ __forceinline__ double lane_value(double v, int lane) {
     return __builtin_bit_cast(double, ((unsigned long long)hi << 32) | lo);
 }
 
-// The scalar steps of the FP32 subgroup chain -- the block's norm and its
-// inverse, 1 / alpha, the draw's square roots -- use the hardware reciprocal,
-// reciprocal square root and square root (about 1 ulp each).  Every lane
-// computes them for the whole link, one step after another, so their latency
-// is the chain's: the correctly rounded sequences take a dozen dependent
-// instructions each, and their extra half ulp is far inside the FP32
-// tolerance of a link update.  Zero and subnormal arguments, and FP64, keep
-// the correctly rounded forms.
+// The scalar steps of the subgroup chain -- the block's norm and its
+// inverse, 1 / alpha, the draw's square roots -- are computed by every lane
+// for the whole link, one step after another, so their latency is the
+// chain's; the correctly rounded sequences take a dozen dependent
+// instructions each.  FP32 uses the hardware reciprocal, reciprocal square
+// root and square root (about 1 ulp each); FP64 the hardware reciprocal and
+// reciprocal square root refined by two Newton steps each (about 1 ulp) and
+// the correctly rounded square root.  The extra half ulp is far inside the
+// tolerance of a link update.  Zero and subnormal arguments keep the
+// correctly rounded forms.
 __device__ __forceinline__ float chain_sqrt(float x) { return __builtin_amdgcn_sqrtf(x); }
 __device__ __forceinline__ double chain_sqrt(double x) { return sqrt(x); }
 
+// 1 / sqrt(x) for a normal x > 0.
+__device__ __forceinline__ float chain_rsqrt(float x) { return __builtin_amdgcn_rsqf(x); }
+__device__ __forceinline__ double chain_rsqrt(double x) {
+    double r = __builtin_amdgcn_rsq(x);
+#pragma unroll
+    for (int it = 0; it < 2; ++it) {  // r <- r + r (1 - x r^2) / 2
+        const double e = fma(-x * r, r, 1.0);
+        r = fma(0.5 * r, e, r);
+    }
+    return r;
+}
+
+// 1 / x for a normal x > 0.
+__device__ __forceinline__ float chain_rcp(float x) { return __builtin_amdgcn_rcpf(x); }
+__device__ __forceinline__ double chain_rcp(double x) {
+    double r = __builtin_amdgcn_rcp(x);
+#pragma unroll
+    for (int it = 0; it < 2; ++it) {  // r <- r + r (1 - x r)
+        const double e = fma(-x, r, 1.0);
+        r = fma(r, e, r);
+    }
+    return r;
+}
+
+// The smallest normal number of T.
+template <typename T>
+__device__ __forceinline__ constexpr T min_normal() {
+    return sizeof(T) == 4 ? T(FLT_MIN) : T(DBL_MIN);
+}
+
 template <typename T>
 __device__ __forceinline__ T chain_inverse(T alpha) {
-    if constexpr (sizeof(T) == 4) {
-        if (alpha >= FLT_MIN) return __builtin_amdgcn_rcpf(alpha);
-    }
+    if (alpha >= min_normal<T>()) return chain_rcp(alpha);
     return alpha > T(0) ? T(1) / alpha : T(0);
 }
 
 // k = |p| and v = p / k (v = 1 for p = 0), as unit_quat.
 template <typename T>
 __device__ __forceinline__ T chain_unit_quat(const Quat<T>& p, Quat<T>& v) {
-    if constexpr (sizeof(T) == 4) {
-        const float k2 = p.q[0] * p.q[0] + p.q[1] * p.q[1] + p.q[2] * p.q[2] + p.q[3] * p.q[3];
-        if (k2 >= FLT_MIN) {
-            const float r = __builtin_amdgcn_rsqf(k2);
+    const T k2 = p.q[0] * p.q[0] + p.q[1] * p.q[1] + p.q[2] * p.q[2] + p.q[3] * p.q[3];
+    if (k2 >= min_normal<T>()) {
+        const T r = chain_rsqrt(k2);
 #pragma unroll
-            for (int c = 0; c < 4; ++c) v.q[c] = p.q[c] * r;
-            return k2 * r;
-        }
+        for (int c = 0; c < 4; ++c) v.q[c] = p.q[c] * r;
+        return k2 * r;
     }
     return unit_quat(p, v);
 }
