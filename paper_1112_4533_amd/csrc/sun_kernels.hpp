@@ -218,6 +218,15 @@ __device__ __forceinline__ Quat<T> staple_su2(const T2<T>* __restrict__ U, const
 template <typename T>
 __device__ __forceinline__ T unit_quat(const Quat<T>& p, Quat<T>& v) {
     const T k2 = p.q[0] * p.q[0] + p.q[1] * p.q[1] + p.q[2] * p.q[2] + p.q[3] * p.q[3];
+    if constexpr (sizeof(T) == 4) {
+        // FP32: the hardware reciprocal square root (about 1 ulp)
+        if (k2 >= 1.17549435e-38f) {
+            const float r = __builtin_amdgcn_rsqf(k2);
+#pragma unroll
+            for (int c = 0; c < 4; ++c) v.q[c] = p.q[c] * r;
+            return k2 * r;
+        }
+    }
     const T k = k2 > T(0) ? d_sqrt(k2) : T(0);
     if (k > T(0)) {
         const T inv = T(1) / k;
