@@ -391,18 +391,13 @@ __device__ __forceinline__ double lane_value(double v, int lane) {
 // inverse, 1 / alpha, the draw's square roots -- are computed by every lane
 // for the whole link, one step after another, so their latency is the
 // chain's; the correctly rounded sequences take a dozen dependent
-// instructions each.  FP32 uses the hardware reciprocal, reciprocal square
-// root and square root (about 1 ulp each); FP64 the hardware reciprocal and
-// reciprocal square root refined by two Newton steps each (about 1 ulp) and
-// the correctly rounded square root.  The extra half ulp is far inside the
-// tolerance of a link update.  Zero and subnormal arguments keep the
-// correctly rounded forms.
-__device__ __forceinline__ float chain_sqrt(float x) { return __builtin_amdgcn_sqrtf(x); }
-__device__ __forceinline__ double chain_sqrt(double x) { return sqrt(x); }
-
-// 1 / sqrt(x) for a normal x > 0.
-__device__ __forceinline__ float chain_rsqrt(float x) { return __builtin_amdgcn_rsqf(x); }
-__device__ __forceinline__ double chain_rsqrt(double x) {
+// instructions each.  FP32 takes the hardware forms shared with the
+// register path (fast_sqrt, fast_inverse, unit_quat: about 1 ulp each); FP64
+// here takes the hardware reciprocal and reciprocal square root refined by
+// two Newton steps each (about 1 ulp) and the correctly rounded square root.
+// The extra half ulp is far inside the tolerance of a link update.  Zero and
+// subnormal arguments keep the correctly rounded forms.
+__device__ __forceinline__ double newton_rsqrt(double x) {  // normal x > 0
     double r = __builtin_amdgcn_rsq(x);
 #pragma unroll
     for (int it = 0; it < 2; ++it) {  // r <- r + r (1 - x r^2) / 2
@@ -411,10 +406,7 @@ __device__ __forceinline__ double chain_rsqrt(double x) {
     }
     return r;
 }
-
-// 1 / x for a normal x > 0.
-__device__ __forceinline__ float chain_rcp(float x) { return __builtin_amdgcn_rcpf(x); }
-__device__ __forceinline__ double chain_rcp(double x) {
+__device__ __forceinline__ double newton_rcp(double x) {  // normal x > 0
     double r = __builtin_amdgcn_rcp(x);
 #pragma unroll
     for (int it = 0; it < 2; ++it) {  // r <- r + r (1 - x r)
@@ -424,27 +416,25 @@ __device__ __forceinline__ double chain_rcp(double x) {
     return r;
 }
 
-// The smallest normal number of T.
-template <typename T>
-__device__ __forceinline__ constexpr T min_normal() {
-    return sizeof(T) == 4 ? T(FLT_MIN) : T(DBL_MIN);
-}
-
 template <typename T>
 __device__ __forceinline__ T chain_inverse(T alpha) {
-    if (alpha >= min_normal<T>()) return chain_rcp(alpha);
-    return alpha > T(0) ? T(1) / alpha : T(0);
+    if constexpr (sizeof(T) == 8) {
+        if (alpha >= DBL_MIN) return newton_rcp(alpha);
+    }
+    return fast_inverse(alpha);
 }
 
 // k = |p| and v = p / k (v = 1 for p = 0), as unit_quat.
 template <typename T>
 __device__ __forceinline__ T chain_unit_quat(const Quat<T>& p, Quat<T>& v) {
-    const T k2 = p.q[0] * p.q[0] + p.q[1] * p.q[1] + p.q[2] * p.q[2] + p.q[3] * p.q[3];
-    if (k2 >= min_normal<T>()) {
-        const T r = chain_rsqrt(k2);
+    if constexpr (sizeof(T) == 8) {
+        const double k2 = p.q[0] * p.q[0] + p.q[1] * p.q[1] + p.q[2] * p.q[2] + p.q[3] * p.q[3];
+        if (k2 >= DBL_MIN) {
+            const double r = newton_rsqrt(k2);
 #pragma unroll
-        for (int c = 0; c < 4; ++c) v.q[c] = p.q[c] * r;
-        return k2 * r;
+            for (int c = 0; c < 4; ++c) v.q[c] = p.q[c] * r;
+            return k2 * r;
+        }
     }
     return unit_quat(p, v);
 }
@@ -502,7 +492,7 @@ __device__ __forceinline__ bool su2_attempt_batched(T alpha, T ia, bool creutz, 
         x0 = (alpha == T(0)) ? T(2) * b.r0 - T(1) : T(1) + d_log1p((T(1) - b.r0) * em) * ia;
         const T rhs = T(1) - x0 * x0;
         if (b.r1 * b.r1 <= rhs) {
-            rad = chain_sqrt(rhs);
+            rad = fast_sqrt(rhs);
             return true;
         }
     } else {
@@ -510,7 +500,7 @@ __device__ __forceinline__ bool su2_attempt_batched(T alpha, T ia, bool creutz, 
         const T rhs = T(1) - lam2;
         if (b.r3 * b.r3 <= rhs) {
             x0 = T(1) - T(2) * lam2;
-            rad = T(2) * chain_sqrt(lam2) * chain_sqrt(rhs);
+            rad = T(2) * fast_sqrt(lam2) * fast_sqrt(rhs);
             return true;
         }
     }
