@@ -12,9 +12,11 @@ TOL = {"f64": 1e-12, "f32": 1e-5, "f64r12": 1e-12, "f32r12": 1e-5, "f64w": 1e-12
 # derivation): a link whose update has conditioning c = |A|_F / k_min (the
 # staple's norm over the smallest subgroup weight k the update divides by)
 # lands within K eps (1 + c) of the oracle, eps the unit roundoff of the
-# storage precision.  K_LINK is that K; the largest K measured over every
-# register-path comparison is 19 (FP64) and 34 (FP32 links drifted by 6e-6
-# across a sweep without re-unitarization; 14 on fresh fields).
+# storage precision.  K_LINK is that K.  The median K measured is about 1
+# and the largest grows with the number of links compared: up to 29 (FP64)
+# and 34 (FP32 links drifted by 6e-6 across a sweep without
+# re-unitarization) over phases of at most 524k links, and 35 (FP64) and 60
+# (FP32) over the 12.6M links of a hot-start heatbath phase on 64^3 x 96.
 K_LINK = 64.0
 # A decision (Creutz / Kennedy-Pendleton switch at alpha = 1.7, accept test
 # r^2 <= 1 - x0^2 or r^2 <= 1 - lambda^2) compares quantities of order one
@@ -74,8 +76,9 @@ def record(**kw):
 
 def compare_links(gpu_field, orc_field, dtype, margin=None, cond=None, what="", spread=None,
                   spread_factor=None, decisions=None):
-    """Link-by-link comparison.  margin and cond are (4, V) arrays from the
-    oracle's phase diagnostics (entries < 0: link not updated, margin inf: no
+    """Link-by-link comparison of (D, V, Nc, Nc) fields (D directions, 4 or
+    a slice of them).  margin and cond are (D, V) arrays from the oracle's
+    phase diagnostics (entries < 0: link not updated, margin inf: no
     decision).  With cond, a link must agree to K_LINK eps (1 + c); without,
     to TOL[dtype].  spread, if given, is the oracle's own per-link
     sensitivity (twin_spread); a link may then also differ by up to
@@ -83,7 +86,7 @@ def compare_links(gpu_field, orc_field, dtype, margin=None, cond=None, what="", 
     its oracle margin lies within K_FLIP eps (1 + c) (FP32 only); the number
     of flips must stay within three times the expected count (K_TYP) or 3.
     decisions: the number of heatbath decisions the phase took, if known."""
-    d = np.abs(gpu_field - orc_field).reshape(4, gpu_field.shape[1], -1).max(axis=2)
+    d = np.abs(gpu_field - orc_field).reshape(gpu_field.shape[0], gpu_field.shape[1], -1).max(axis=2)
     eps = EPS[dtype[:3]]
     c = None
     if cond is not None:

@@ -496,6 +496,29 @@ def test_full_size_su3_32_phase_parity(gpu, dtype):
     np.testing.assert_allclose(to_np(lat.plaquette()), O.plaquette(before, nc, L), rtol=0, atol=1e-12)
 
 
+@pytest.mark.parametrize("dtype", ["f32r12", "f64"])
+def test_field_past_4_gib_phase_parity(gpu, dtype):
+    """A field larger than 4 GiB (SU(3) on 64^3 x 96: 4.8 GB two-row FP32,
+    14.5 GB FP64), so that link addresses pass 2^32 bytes: a heatbath and an
+    overrelaxation phase of direction 3, whose links lie at the top of the
+    field, checked link by link against the oracle, the other directions
+    unchanged bit for bit, then the plaquette of the final field."""
+    nc, L, beta, seed = 3, (64, 64, 64, 96), 6.2, 4242
+    lat = gpu_lattice(gpu, nc, L, dtype, hot=True, seed=seed)
+    assert lat.links.numel() * lat.links.element_size() > 2 ** 32
+    before = to_np(lat.export())
+    for kind, par in ((0, 1), (1, 0)):
+        lat.phase(kind, 3, par, beta, seed=seed, step=0)
+        got = to_np(lat.export())
+        for mu in range(3):
+            assert np.array_equal(got[mu], before[mu]), mu
+        m, k = oracle_phase_diag(before, nc, L, kind, 3, par, beta, seed, 0)   # before -> the oracle's field
+        compare_links(got[3:], before[3:], dtype, m[3:], k[3:], f"64^3x96 kind {kind} mu 3 p {par}")
+        del before
+        before = got
+    np.testing.assert_allclose(to_np(lat.plaquette()), O.plaquette(before, nc, L), rtol=0, atol=1e-12)
+
+
 # ---------------------------------------------------------------------------
 # Chain state, determinism, timing hooks
 # ---------------------------------------------------------------------------
