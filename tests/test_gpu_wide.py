@@ -182,6 +182,25 @@ def test_wide_sweep_is_its_phase_sequence(gpu):
     assert a.step == 1
 
 
+def test_wide_field_past_4_gib_phase_parity(gpu):
+    """The workgroup-per-link path on a field larger than 4 GiB (SU(8) FP64
+    on 32^3 x 34: 4.6 GB), so that link addresses pass 2^32 bytes: a heatbath
+    phase of direction 3 (the top of the field) link by link against the
+    oracle, the other directions unchanged bit for bit."""
+    nc, L, dtype, seed = 8, (32, 32, 32, 34), "f64", 99
+    beta = beta_for(nc)
+    lat = gpu_lattice(gpu, nc, L, dtype, hot=True, seed=seed)
+    assert lat.links.numel() * lat.links.element_size() > 2 ** 32
+    before = to_np(lat.export())
+    lat.phase(0, 3, 1, beta, seed=seed, step=0)
+    got = to_np(lat.export())
+    for mu in range(3):
+        assert np.array_equal(got[mu], before[mu]), mu
+    sp = twin_spread(before, nc, L, 0, 3, 1, beta, seed, 0, rel=REL["f64"], twins=1)
+    m, k = oracle_phase_diag(before, nc, L, 0, 3, 1, beta, seed, 0)
+    compare_links(got[3:], before[3:], dtype, m[3:], k[3:], "SU(8) 32^3x34 kind 0 mu 3 p 1", spread=sp[3:])
+
+
 WIDE_BATCH = [  # (nc, L, dtype, beta, seed)
     (5, (4, 4, 2, 2), "f32", beta_for(5), 21),
     (5, (4, 2, 4, 2), "f32", beta_for(5) + 0.7, 22),    # same group, other extents and coupling
