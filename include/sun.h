@@ -63,7 +63,12 @@ enum {
  * contiguous in memory; SUN_F32 and SUN_F64 select it by themselves there,
  * and the WIDE codes select it at Nc = 4 too (for comparisons with the
  * register path).  Its update keeps 3 Nc^2 complex entries in LDS (48 KiB
- * at Nc = 32 in FP64).  Launch shapes do not apply to it. */
+ * at Nc = 32 in FP64).  Of a launch shape only the block size applies to
+ * it: 64 runs each link's update on one wavefront, 128 on two (the link
+ * loads and the vector-unit products shared, the subgroup steps on the
+ * first; the same bits either way; the FP32 matrix-core form above Nc = 20
+ * always runs on one), and any other block, the default 256 included, picks
+ * by Nc, precision and update kind. */
 enum {
     SUN_F32 = 0,
     SUN_F64 = 1,
@@ -308,7 +313,8 @@ int sun_batch_replay(sun_batch_t b, sun_stream_t stream);
 
 /* Launch shape of the batch's register-path phase kernels (as
  * sun_set_launch, always with the linear tile walk; default (256, 1, 0) for
- * both kinds; the workgroup-per-link groups ignore it).  Waits for the
+ * both kinds; the workgroup-per-link groups take only its block size, as a
+ * single lattice does).  Waits for the
  * device, rewrites the table, and drops any captured graph. */
 int sun_batch_set_launch(sun_batch_t b, int kind, int block, int xcd, int waves);
 /* Sites per work-item of the batch's phase kernels (as

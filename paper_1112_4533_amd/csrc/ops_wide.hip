@@ -10,27 +10,42 @@ struct OpsWide {
     using P = T2<T>;
     static constexpr int f64 = sizeof(T) == 8;
 
-    template <bool MM, bool RA>
+    template <bool MM, bool RA, int NT>
     static void update_as(const Ctx& c, int kind, int mu, int par, double beta, uint32_t k0, uint32_t k1,
                           uint32_t step) {
-        wide::k_update<T, MM, RA><<<c.g.Vh, wide::kLanes, wide_update_lds(c.nc, f64), c.stream>>>(
+        wide::k_update<T, MM, RA, NT><<<c.g.Vh, NT, wide_update_lds(c.nc, f64), c.stream>>>(
             (P*)c.links, c.g, c.nc, mu, par, kind == 0 ? 1 : 0, (T)beta, k0, k1, step);
+    }
+    // Threads per workgroup: a launch shape's block of 64 or 128 asks for one
+    // or two wavefronts; any other block (the default 256) takes
+    // wide_update_threads.  The matrix-core form runs on one.
+    static bool two_waves(const Shape& sh, int nc, int kind) {
+        if (sh.block == wide::kLanes || sh.block == 2 * wide::kLanes) return sh.block > wide::kLanes;
+        return wide_update_threads(nc, f64, kind) > wide::kLanes;
     }
     static void update(const Ctx& c, int kind, int mu, int par, double beta, uint32_t k0, uint32_t k1, uint32_t step) {
         const bool ra = wide_update_regacc(c.nc, f64);
+        const bool two = two_waves(c.shape[kind], c.nc, kind);
         if constexpr (!f64) {
             if (c.nc > wide::kMfmaMinN) {
                 if (ra)
-                    update_as<true, true>(c, kind, mu, par, beta, k0, k1, step);
+                    update_as<true, true, wide::kLanes>(c, kind, mu, par, beta, k0, k1, step);
                 else
-                    update_as<true, false>(c, kind, mu, par, beta, k0, k1, step);
+                    update_as<true, false, wide::kLanes>(c, kind, mu, par, beta, k0, k1, step);
                 return;
             }
         }
-        if (ra)
-            update_as<false, true>(c, kind, mu, par, beta, k0, k1, step);
-        else
-            update_as<false, false>(c, kind, mu, par, beta, k0, k1, step);
+        if (ra) {
+            if (two)
+                update_as<false, true, 2 * wide::kLanes>(c, kind, mu, par, beta, k0, k1, step);
+            else
+                update_as<false, true, wide::kLanes>(c, kind, mu, par, beta, k0, k1, step);
+        } else {
+            if (two)
+                update_as<false, false, 2 * wide::kLanes>(c, kind, mu, par, beta, k0, k1, step);
+            else
+                update_as<false, false, wide::kLanes>(c, kind, mu, par, beta, k0, k1, step);
+        }
     }
     static void init(const Ctx& c, int hot, uint32_t k0, uint32_t k1) {
         wide::k_init<T><<<4 * c.g.V, wide::kLanes, wide::fp64_lds(c.nc, 2), c.stream>>>((P*)c.links, c.g, c.nc, hot, k0,
@@ -72,28 +87,36 @@ struct OpsWide {
 
     // Batches: one launch per phase covers every chain of the group (same
     // Nc and precision), one workgroup per link.
-    template <bool MM, bool RA>
+    template <bool MM, bool RA, int NT>
     static void update_batch_as(const ChainDesc* d, int n, int tiles, int kind, int mu, int par, uint32_t off, int nc,
                                 hipStream_t s) {
-        wide::k_update_batch<T, MM, RA><<<tiles, wide::kLanes, wide_update_lds(nc, f64), s>>>(
+        wide::k_update_batch<T, MM, RA, NT><<<tiles, NT, wide_update_lds(nc, f64), s>>>(
             d, n, nc, mu, par, kind == 0 ? 1 : 0, off);
     }
     static void update_batch(const ChainDesc* d, int n, int tiles, int kind, int mu, int par, uint32_t off,
-                             const Shape& /*shape*/, int nc, hipStream_t s) {
+                             const Shape& shape, int nc, hipStream_t s) {
         const bool ra = wide_update_regacc(nc, f64);
+        const bool two = two_waves(shape, nc, kind);
         if constexpr (!f64) {
             if (nc > wide::kMfmaMinN) {
                 if (ra)
-                    update_batch_as<true, true>(d, n, tiles, kind, mu, par, off, nc, s);
+                    update_batch_as<true, true, wide::kLanes>(d, n, tiles, kind, mu, par, off, nc, s);
                 else
-                    update_batch_as<true, false>(d, n, tiles, kind, mu, par, off, nc, s);
+                    update_batch_as<true, false, wide::kLanes>(d, n, tiles, kind, mu, par, off, nc, s);
                 return;
             }
         }
-        if (ra)
-            update_batch_as<false, true>(d, n, tiles, kind, mu, par, off, nc, s);
-        else
-            update_batch_as<false, false>(d, n, tiles, kind, mu, par, off, nc, s);
+        if (ra) {
+            if (two)
+                update_batch_as<false, true, 2 * wide::kLanes>(d, n, tiles, kind, mu, par, off, nc, s);
+            else
+                update_batch_as<false, true, wide::kLanes>(d, n, tiles, kind, mu, par, off, nc, s);
+        } else {
+            if (two)
+                update_batch_as<false, false, 2 * wide::kLanes>(d, n, tiles, kind, mu, par, off, nc, s);
+            else
+                update_batch_as<false, false, wide::kLanes>(d, n, tiles, kind, mu, par, off, nc, s);
+        }
     }
     static void reunit_batch(const ChainDesc* d, int n, int tiles, int nc, hipStream_t s) {
         wide::k_reunit_batch<T><<<tiles, wide::kLanes, wide::fp64_lds(nc, 1) + (size_t)nc * sizeof(double2), s>>>(

@@ -58,10 +58,10 @@ __device__ __forceinline__ const T2<T>* link_at(const T2<T>* U, int n2, int mu, 
 // so a link costs a few load latencies instead of one per entry.
 constexpr int kLoadBatch = 8;
 
-template <typename D, typename S>
+template <typename D, typename S, int NT = kLanes>
 __device__ __forceinline__ void lds_load(T2<D>* dst, const T2<S>* src, int n, bool dag) {
     const int n2 = n * n;
-    if (n2 <= kLanes) {  // one entry per lane
+    if (n2 <= NT) {  // one entry per lane
         const int e = threadIdx.x;
         if (e < n2) {
             const T2<S> v = src[e];
@@ -74,16 +74,16 @@ __device__ __forceinline__ void lds_load(T2<D>* dst, const T2<S>* src, int n, bo
         }
         return;
     }
-    for (int e0 = threadIdx.x; e0 < n2; e0 += kLoadBatch * kLanes) {
+    for (int e0 = threadIdx.x; e0 < n2; e0 += kLoadBatch * NT) {
         T2<S> v[kLoadBatch];
 #pragma unroll
         for (int c = 0; c < kLoadBatch; ++c) {
-            const int e = e0 + c * kLanes;
+            const int e = e0 + c * NT;
             if (e < n2) v[c] = src[e];
         }
 #pragma unroll
         for (int c = 0; c < kLoadBatch; ++c) {
-            const int e = e0 + c * kLanes;
+            const int e = e0 + c * NT;
             if (e >= n2) break;
             if (dag) {
                 const int i = e / n, j = e - i * n;
@@ -201,28 +201,47 @@ __device__ __forceinline__ void lds_mm_mfma(T2<float>* C, const T2<float>* A, co
     }
 }
 
+// Row groups of the vector-unit products on NT threads (NT / 64
+// wavefronts): each wavefront holds 64 / n groups of n lanes, group i0 =
+// (wavefront) * (64 / n) + lane / n taking column j = lane mod n and rows
+// i0, i0 + g, ... (g groups in all).  A group never spans two wavefronts,
+// and every entry is computed by one lane with the same operations in the
+// same order whatever NT is, so the products give the same bits with one
+// wavefront or two.
+template <int NT>
+struct RowMap {
+    int g, j, i0, cnt, most;
+    bool active;
+    __device__ __forceinline__ explicit RowMap(int n) {
+        const int gw = kLanes / n;
+        const int w = (int)threadIdx.x / kLanes, l = (int)threadIdx.x % kLanes;
+        g = gw * (NT / kLanes);
+        active = l < gw * n;
+        j = l % n;
+        i0 = w * gw + l / n;
+        cnt = (n - i0 + g - 1) / g;  // rows i0 + g t < n of this lane
+        most = (n + g - 1) / g;      // rows of group 0, the most of any group
+    }
+};
+
 // MM: the matrix-core form (FP32, kMfmaMinN < n), compiled into its own
 // kernel variant so that the others keep their register budget.
 // RMAX caps the rows a lane takes at a time (fewer registers).
-template <typename T, bool MM = false, int RMAX = 4>
+template <typename T, bool MM = false, int RMAX = 4, int NT = kLanes>
 __device__ __forceinline__ void lds_mm(T2<T>* C, const T2<T>* A, const T2<T>* B, int n, bool acc) {
     if constexpr (MM) {
-        static_assert(sizeof(T) == 4, "the matrix-core product is FP32");
+        static_assert(sizeof(T) == 4 && NT == kLanes, "the matrix-core product is FP32 on one wavefront");
         lds_mm_mfma(C, A, B, n, acc);
         return;
     }
-    const int g = kLanes / n;
-    const int lane = threadIdx.x;
-    if (lane >= g * n) return;
-    const int j = lane % n, i0 = lane / n;
-    const int cnt = (n - i0 + g - 1) / g;   // rows i0 + g t < n of this lane
-    const int most = (n + g - 1) / g;       // rows of lane 0, the most of any lane
-    if (RMAX >= 4 && most >= 4)
-        lds_mm_rows<T, 4>(C, A, B, n, acc, g, j, i0, cnt);
-    else if (most >= 2)
-        lds_mm_rows<T, 2>(C, A, B, n, acc, g, j, i0, cnt);
+    const RowMap<NT> m(n);
+    if (!m.active) return;
+    if (RMAX >= 4 && m.most >= 4)
+        lds_mm_rows<T, 4>(C, A, B, n, acc, m.g, m.j, m.i0, m.cnt);
+    else if (m.most >= 2)
+        lds_mm_rows<T, 2>(C, A, B, n, acc, m.g, m.j, m.i0, m.cnt);
     else
-        lds_mm_rows<T, 1>(C, A, B, n, acc, g, j, i0, cnt);
+        lds_mm_rows<T, 1>(C, A, B, n, acc, m.g, m.j, m.i0, m.cnt);
 }
 
 // ---------------------------------------------------------------------------
@@ -237,16 +256,18 @@ __device__ __forceinline__ void lds_mm(T2<T>* C, const T2<T>* A, const T2<T>* B,
 // ---------------------------------------------------------------------------
 constexpr int kAccRows = 16;   // rows of the most loaded lane: ceil(n / (64 / n)) <= 16 for n <= 32
 
-template <typename T, bool MM>
+// NT threads: at most kAccRows * 64 / NT rows per lane.
+template <typename T, bool MM, int NT = kLanes>
 struct Acc {
-    T2<T> e[kAccRows];
+    static constexpr int kRows = kAccRows * kLanes / NT;
+    T2<T> e[kRows];
     __device__ __forceinline__ void zero() {
 #pragma unroll
-        for (int t = 0; t < kAccRows; ++t) e[t] = cpx<T>(T(0), T(0));
+        for (int t = 0; t < kRows; ++t) e[t] = cpx<T>(T(0), T(0));
     }
 };
 template <>
-struct Acc<float, true> {
+struct Acc<float, true, kLanes> {
     f32x16 re, im;
     __device__ __forceinline__ void zero() {
 #pragma unroll
@@ -255,11 +276,11 @@ struct Acc<float, true> {
 };
 
 // c += A B (A, B in LDS) on the vector units, R rows of the lane at a time.
-template <typename T, int R>
-__device__ __forceinline__ void acc_mm_rows(Acc<T, false>& c, const T2<T>* A, const T2<T>* B, int n, int g, int j,
-                                            int i0, int cnt, int most) {
+template <typename T, int R, int NT>
+__device__ __forceinline__ void acc_mm_rows(Acc<T, false, NT>& c, const T2<T>* A, const T2<T>* B, int n, int g,
+                                            int j, int i0, int cnt, int most) {
 #pragma unroll
-    for (int t0 = 0; t0 < kAccRows; t0 += R) {
+    for (int t0 = 0; t0 < Acc<T, false, NT>::kRows; t0 += R) {
         if (t0 >= most) break;  // the same for every lane
         int row[R];
         T r[R], m[R];
@@ -298,8 +319,8 @@ __device__ __forceinline__ void acc_mm_rows(Acc<T, false>& c, const T2<T>* A, co
     }
 }
 
-template <typename T, bool MM>
-__device__ __forceinline__ void acc_mm(Acc<T, MM>& c, const T2<T>* A, const T2<T>* B, int n) {
+template <typename T, bool MM, int NT>
+__device__ __forceinline__ void acc_mm(Acc<T, MM, NT>& c, const T2<T>* A, const T2<T>* B, int n) {
     if constexpr (MM) {
         const int l = threadIdx.x;
         const int lo = l & 31, hi = l >> 5;
@@ -317,28 +338,24 @@ __device__ __forceinline__ void acc_mm(Acc<T, MM>& c, const T2<T>* A, const T2<T
             c.im = __builtin_amdgcn_mfma_f32_32x32x2f32(a.y, b.x, c.im, 0, 0, 0);
         }
     } else {
-        const int g = kLanes / n;
-        const int lane = threadIdx.x;
-        if (lane >= g * n) return;
-        const int j = lane % n, i0 = lane / n;
-        const int cnt = (n - i0 + g - 1) / g;
-        const int most = (n + g - 1) / g;
+        const RowMap<NT> m(n);
+        if (!m.active) return;
         // FP64 takes two rows at a time: with four, the kernel's registers
         // (the sum itself is 64 VGPRs at Nc = 32) left one wave per SIMD
-        if (sizeof(T) == 4 && most >= 4)
-            acc_mm_rows<T, 4>(c, A, B, n, g, j, i0, cnt, most);
-        else if (most >= 2)
-            acc_mm_rows<T, 2>(c, A, B, n, g, j, i0, cnt, most);
+        if (sizeof(T) == 4 && m.most >= 4)
+            acc_mm_rows<T, 4, NT>(c, A, B, n, m.g, m.j, m.i0, m.cnt, m.most);
+        else if (m.most >= 2)
+            acc_mm_rows<T, 2, NT>(c, A, B, n, m.g, m.j, m.i0, m.cnt, m.most);
         else
-            acc_mm_rows<T, 1>(c, A, B, n, g, j, i0, cnt, most);
+            acc_mm_rows<T, 1, NT>(c, A, B, n, m.g, m.j, m.i0, m.cnt, m.most);
     }
 }
 
 // C (LDS) = the accumulator.
-template <typename T, bool MM>
-__device__ __forceinline__ void acc_store(T2<T>* C, const Acc<T, MM>& c, int n) {
-    const int l = threadIdx.x;
+template <typename T, bool MM, int NT>
+__device__ __forceinline__ void acc_store(T2<T>* C, const Acc<T, MM, NT>& c, int n) {
     if constexpr (MM) {
+        const int l = threadIdx.x;
         const int lo = l & 31, hi = l >> 5;
 #pragma unroll
         for (int r = 0; r < 16; ++r) {
@@ -346,13 +363,11 @@ __device__ __forceinline__ void acc_store(T2<T>* C, const Acc<T, MM>& c, int n) 
             if (i < n && lo < n) C[i * n + lo] = cpx<float>(c.re[r], c.im[r]);
         }
     } else {
-        const int g = kLanes / n;
-        if (l >= g * n) return;
-        const int j = l % n, i0 = l / n;
-        const int cnt = (n - i0 + g - 1) / g;
+        const RowMap<NT> m(n);
+        if (!m.active) return;
 #pragma unroll
-        for (int t = 0; t < kAccRows; ++t)
-            if (t < cnt) C[(i0 + g * t) * n + j] = c.e[t];
+        for (int t = 0; t < Acc<T, MM, NT>::kRows; ++t)
+            if (t < m.cnt) C[(m.i0 + m.g * t) * n + m.j] = c.e[t];
     }
 }
 
@@ -562,15 +577,19 @@ __device__ __forceinline__ void rows_left_mul_col(T2<T>* M, int n, int i, int j,
 // (B1) and W (B0).  At least two waves per SIMD (at most 256 registers): the
 // FP64 form with the sum in registers would otherwise take a few more and
 // leave one.
-template <typename T, bool MM, bool RA>
+// NT: threads per workgroup, one wavefront or two.  With two, the loads and
+// the vector-unit products are shared by both wavefronts (RowMap: the same
+// bits), and the first wavefront runs the subgroup steps alone.
+template <typename T, bool MM, bool RA, int NT = kLanes>
 __device__ __forceinline__ void update_link_wide(T2<T>* __restrict__ U, const Geom& g, int n, int mu, int par,
                                                  int hb, T beta, uint32_t k0, uint32_t k1, uint32_t step, int h) {
+    static_assert(NT == kLanes || (NT == 2 * kLanes && !MM), "two wavefronts share vector-unit products only");
     extern __shared__ double4 smem_update[];
     const int n2 = n * n;
     T2<T>* A = reinterpret_cast<T2<T>*>(smem_update);  // the staple sum (without RA)
     T2<T>* B0 = RA ? A : A + n2;
     T2<T>* B1 = B0 + n2;
-    Acc<T, MM> acc;  // the staple sum (with RA)
+    Acc<T, MM, NT> acc;  // the staple sum (with RA)
     constexpr int kRows = (RA && sizeof(T) == 8) ? 2 : 4;  // FP64 with the sum in registers: fewer at a time
     const int Vh = g.Vh;
     const Site x = site_of(g, par, h);
@@ -580,52 +599,58 @@ __device__ __forceinline__ void update_link_wide(T2<T>* __restrict__ U, const Ge
     if constexpr (RA)
         acc.zero();
     else
-        for (int e = threadIdx.x; e < n2; e += kLanes) A[e] = cpx<T>(T(0), T(0));
+        for (int e = threadIdx.x; e < n2; e += NT) A[e] = cpx<T>(T(0), T(0));
     for (int nu = 0; nu < 4; ++nu) {
         if (nu == mu || !((g.present >> nu) & 1)) continue;
         const Site xpn = step_up(g, x, nu), xmn = step_down(g, x, nu), xpmn = step_down(g, xp, nu);
         // upper staple U_nu(x+mu) U_mu(x+nu)^dag U_nu(x)^dag
-        lds_load<T, T>(B0, link_at<T>(U, n2, nu, op, xp.s >> 1, Vh), n, false);
-        lds_load<T, T>(B1, link_at<T>(U, n2, mu, op, xpn.s >> 1, Vh), n, true);
+        lds_load<T, T, NT>(B0, link_at<T>(U, n2, nu, op, xp.s >> 1, Vh), n, false);
+        lds_load<T, T, NT>(B1, link_at<T>(U, n2, mu, op, xpn.s >> 1, Vh), n, true);
         __syncthreads();
-        lds_mm<T, MM, kRows>(B0, B0, B1, n, false);
+        lds_mm<T, MM, kRows, NT>(B0, B0, B1, n, false);
         __syncthreads();
-        lds_load<T, T>(B1, link_at<T>(U, n2, nu, par, h, Vh), n, true);
+        lds_load<T, T, NT>(B1, link_at<T>(U, n2, nu, par, h, Vh), n, true);
         __syncthreads();
         if constexpr (RA)
-            acc_mm<T, MM>(acc, B0, B1, n);
+            acc_mm<T, MM, NT>(acc, B0, B1, n);
         else
-            lds_mm<T, MM>(A, B0, B1, n, true);
+            lds_mm<T, MM, 4, NT>(A, B0, B1, n, true);
         __syncthreads();
         // lower staple U_nu(x+mu-nu)^dag U_mu(x-nu)^dag U_nu(x-nu)
-        lds_load<T, T>(B0, link_at<T>(U, n2, nu, par, xpmn.s >> 1, Vh), n, true);
-        lds_load<T, T>(B1, link_at<T>(U, n2, mu, op, xmn.s >> 1, Vh), n, true);
+        lds_load<T, T, NT>(B0, link_at<T>(U, n2, nu, par, xpmn.s >> 1, Vh), n, true);
+        lds_load<T, T, NT>(B1, link_at<T>(U, n2, mu, op, xmn.s >> 1, Vh), n, true);
         __syncthreads();
-        lds_mm<T, MM, kRows>(B0, B0, B1, n, false);
+        lds_mm<T, MM, kRows, NT>(B0, B0, B1, n, false);
         __syncthreads();
-        lds_load<T, T>(B1, link_at<T>(U, n2, nu, op, xmn.s >> 1, Vh), n, false);
+        lds_load<T, T, NT>(B1, link_at<T>(U, n2, nu, op, xmn.s >> 1, Vh), n, false);
         __syncthreads();
         if constexpr (RA)
-            acc_mm<T, MM>(acc, B0, B1, n);
+            acc_mm<T, MM, NT>(acc, B0, B1, n);
         else
-            lds_mm<T, MM>(A, B0, B1, n, true);
+            lds_mm<T, MM, 4, NT>(A, B0, B1, n, true);
         __syncthreads();
     }
     T2<T>* Us = B1;
-    lds_load<T, T>(Us, link_at<T>(U, n2, mu, par, h, Vh), n, false);
+    lds_load<T, T, NT>(Us, link_at<T>(U, n2, mu, par, h, Vh), n, false);
     T2<T>* W = B0;  // W = U A
     if constexpr (RA) {
-        acc_store<T, MM>(B0, acc, n);  // A into B0, which the last staple product has finished reading
+        acc_store<T, MM, NT>(B0, acc, n);  // A into B0, which the last staple product has finished reading
         __syncthreads();
         acc.zero();
-        acc_mm<T, MM>(acc, Us, B0, n);
-        __syncthreads();               // every lane has read A
-        acc_store<T, MM>(W, acc, n);
+        acc_mm<T, MM, NT>(acc, Us, B0, n);
+        __syncthreads();                   // every lane has read A
+        acc_store<T, MM, NT>(W, acc, n);
     } else {
         __syncthreads();
-        lds_mm<T, MM>(W, Us, A, n, false);
+        lds_mm<T, MM, 4, NT>(W, Us, A, n, false);
     }
     __syncthreads();
+    if (NT > kLanes && threadIdx.x >= kLanes) {  // the subgroup steps are the first wavefront's
+        __syncthreads();
+        T2<T>* dst = const_cast<T2<T>*>(link_at<T>(U, n2, mu, par, h, Vh));
+        for (int e = threadIdx.x; e < n2; e += NT) dst[e] = Us[e];
+        return;
+    }
 
     const int lane = threadIdx.x;
     const uint32_t mu_hi = (uint32_t)mu << 16;
@@ -668,27 +693,27 @@ __device__ __forceinline__ void update_link_wide(T2<T>* __restrict__ U, const Ge
         }
     __syncthreads();
     T2<T>* dst = const_cast<T2<T>*>(link_at<T>(U, n2, mu, par, h, Vh));
-    for (int e = threadIdx.x; e < n2; e += kLanes) dst[e] = Us[e];
+    for (int e = threadIdx.x; e < n2; e += NT) dst[e] = Us[e];
 }
 
 // One checkerboard phase of one lattice: workgroup h updates link h.
-template <typename T, bool MM, bool RA>
-__global__ __launch_bounds__(kLanes, 2) void k_update(T2<T>* __restrict__ U, Geom g, int n, int mu, int par, int hb,
-                                                   T beta, uint32_t k0, uint32_t k1, uint32_t step) {
-    update_link_wide<T, MM, RA>(U, g, n, mu, par, hb, beta, k0, k1, step, (int)blockIdx.x);
+template <typename T, bool MM, bool RA, int NT>
+__global__ __launch_bounds__(NT, 2) void k_update(T2<T>* __restrict__ U, Geom g, int n, int mu, int par, int hb,
+                                               T beta, uint32_t k0, uint32_t k1, uint32_t step) {
+    update_link_wide<T, MM, RA, NT>(U, g, n, mu, par, hb, beta, k0, k1, step, (int)blockIdx.x);
 }
 
 // One phase of every chain of a batch group (same Nc and precision): one
 // workgroup per updated link of each chain, the chain found by binary search
 // over the first-link prefix of the descriptor table (TILE_HALF_HB counts
 // links here); coupling, Philox key and RNG step come from the table.
-template <typename T, bool MM, bool RA>
-__global__ __launch_bounds__(kLanes, 2) void k_update_batch(const ChainDesc* __restrict__ d, int nchains, int n,
-                                                         int mu, int par, int hb, uint32_t step_offset) {
+template <typename T, bool MM, bool RA, int NT>
+__global__ __launch_bounds__(NT, 2) void k_update_batch(const ChainDesc* __restrict__ d, int nchains, int n,
+                                                     int mu, int par, int hb, uint32_t step_offset) {
     const int c = find_chain<TILE_HALF_HB>(d, nchains, (int)blockIdx.x);
     const Geom g = d[c].g;
     if (!((g.present >> mu) & 1)) return;
-    update_link_wide<T, MM, RA>((T2<T>*)d[c].links, g, n, mu, par, hb, (T)d[c].beta, d[c].k0, d[c].k1,
+    update_link_wide<T, MM, RA, NT>((T2<T>*)d[c].links, g, n, mu, par, hb, (T)d[c].beta, d[c].k0, d[c].k1,
                                 (uint32_t)(d[c].step + step_offset), (int)blockIdx.x - d[c].tile0[TILE_HALF_HB]);
 }
 

@@ -182,6 +182,29 @@ def test_wide_sweep_is_its_phase_sequence(gpu):
     assert a.step == 1
 
 
+@pytest.mark.parametrize("nc,dtype", [(9, "f32"), (16, "f32"), (20, "f32"), (12, "f64"), (26, "f64"), (32, "f64"),
+                                      (24, "f32")])
+def test_wide_one_or_two_wavefronts_give_the_same_bits(gpu, nc, dtype):
+    """A link's update on one wavefront (launch block 64), on two (block
+    128: loads and vector-unit products shared by row groups) and with the
+    default choice give the same field bit for bit, heatbath and
+    overrelaxation (at Nc = 24 in FP32 the matrix-core form runs on one
+    wavefront whatever the block)."""
+    sun = gpu
+    L, beta = (4, 4, 2, 2), beta_for(nc)
+    base = O.new_field(nc, L, hot=True, seed=41)
+    fields = []
+    for block in (64, 128, 256):
+        lat = gpu_lattice(sun, nc, L, dtype, field=base)
+        lat.set_launch(block)
+        for kind, mu, par in [(0, 1, 0), (1, 2, 1), (0, 3, 1), (1, 0, 0)]:
+            lat.phase(kind, mu, par, beta, seed=5, step=3)
+        torch.cuda.synchronize()
+        fields.append(lat.links.clone())
+    assert torch.equal(fields[0], fields[1])
+    assert torch.equal(fields[0], fields[2])
+
+
 def test_wide_field_past_4_gib_phase_parity(gpu):
     """The workgroup-per-link path on a field larger than 4 GiB (SU(8) FP64
     on 32^3 x 34: 4.6 GB), so that link addresses pass 2^32 bytes: a heatbath
@@ -210,6 +233,8 @@ WIDE_BATCH = [  # (nc, L, dtype, beta, seed)
     (6, (4, 4, 1, 4), "f64", beta_for(6), 26),          # 3D: an absent direction
     (24, (4, 2, 2, 2), "f32", beta_for(24), 27),        # matrix-core products
     (22, (2, 2, 4, 2), "f64", beta_for(22), 28),        # staple sum in registers
+    (12, (4, 2, 2, 4), "f32", beta_for(12), 29),        # two wavefronts per link
+    (26, (2, 2, 2, 4), "f64", beta_for(26), 30),        # two wavefronts for the overrelaxation
 ]
 
 
