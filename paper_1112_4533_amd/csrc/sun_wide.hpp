@@ -371,16 +371,51 @@ __device__ __forceinline__ void acc_store(T2<T>* C, const Acc<T, MM, NT>& c, int
     }
 }
 
-// Wave reductions with a fixed butterfly order (deterministic).
-__device__ __forceinline__ double wave_sum(double v) {
-#pragma unroll
-    for (int off = 32; off > 0; off >>= 1) v += __shfl_xor(v, off, kLanes);
+// Cross-lane moves of a wavefront without the LDS: lane l receives the
+// value of its partner lane, for five pairings that together join all 64
+// lanes -- l xor 1 and l xor 2 (quad permutes), 7 - l and 15 - l within
+// groups of 8 and 16 (row mirrors), l xor 16 (swizzle) -- and l xor 32
+// (the swap of the two halves).
+template <int STEP>
+__device__ __forceinline__ int partner(int v) {
+    if constexpr (STEP == 0) return __builtin_amdgcn_update_dpp(0, v, 0xB1, 0xF, 0xF, false);   // quad [1,0,3,2]
+    if constexpr (STEP == 1) return __builtin_amdgcn_update_dpp(0, v, 0x4E, 0xF, 0xF, false);   // quad [2,3,0,1]
+    if constexpr (STEP == 2) return __builtin_amdgcn_update_dpp(0, v, 0x141, 0xF, 0xF, false);  // row half mirror
+    if constexpr (STEP == 3) return __builtin_amdgcn_update_dpp(0, v, 0x140, 0xF, 0xF, false);  // row mirror
+    if constexpr (STEP == 4) return __builtin_amdgcn_ds_swizzle(v, 0x401F);                     // xor 16
+    if constexpr (STEP == 5) {                                                                   // xor 32
+        const auto r = __builtin_amdgcn_permlane32_swap(v, v, false, false);
+        return threadIdx.x < 32 ? (int)r[1] : (int)r[0];
+    }
     return v;
 }
-__device__ __forceinline__ double wave_max(double v) {
-#pragma unroll
-    for (int off = 32; off > 0; off >>= 1) v = fmax(v, __shfl_xor(v, off, kLanes));
+template <int STEP>
+__device__ __forceinline__ double partner(double v) {
+    const unsigned long long u = __builtin_bit_cast(unsigned long long, v);
+    const unsigned lo = (unsigned)partner<STEP>((int)(u & 0xffffffffu));
+    const unsigned hi = (unsigned)partner<STEP>((int)(u >> 32));
+    return __builtin_bit_cast(double, ((unsigned long long)hi << 32) | lo);
+}
+
+// Wave reductions over the six pairings above in a fixed order: every lane
+// combines the same two partial results at each step (in one order or the
+// other, which for + and max gives the same bits), so all lanes end with
+// the same deterministic value.
+template <typename F>
+__device__ __forceinline__ double wave_reduce(double v, F op) {
+    v = op(v, partner<0>(v));
+    v = op(v, partner<1>(v));
+    v = op(v, partner<2>(v));
+    v = op(v, partner<3>(v));
+    v = op(v, partner<4>(v));
+    v = op(v, partner<5>(v));
     return v;
+}
+__device__ __forceinline__ double wave_sum(double v) {
+    return wave_reduce(v, [](double a, double b) { return a + b; });
+}
+__device__ __forceinline__ double wave_max(double v) {
+    return wave_reduce(v, [](double a, double b) { return fmax(a, b); });
 }
 
 // Every kernel here runs one wavefront per workgroup, and a wavefront's LDS
@@ -747,15 +782,20 @@ __device__ __forceinline__ void lds_det(double2* D, int n, double& dr, double& d
         } else {
             piv = c;
             if (c >= col && c < n) best = D[c * n + col].x * D[c * n + col].x + D[c * n + col].y * D[c * n + col].y;
-#pragma unroll
-            for (int off = 32; off > 0; off >>= 1) {
-                const double ob = __shfl_xor(best, off, kLanes);
-                const int op = __shfl_xor(piv, off, kLanes);
+            // the largest, the lowest row among equals: an order-free choice,
+            // so every lane ends with the same pair
+            auto take = [&](double ob, int op) {
                 if (ob > best || (ob == best && op < piv)) {
                     best = ob;
                     piv = op;
                 }
-            }
+            };
+            take(partner<0>(best), partner<0>(piv));
+            take(partner<1>(best), partner<1>(piv));
+            take(partner<2>(best), partner<2>(piv));
+            take(partner<3>(best), partner<3>(piv));
+            take(partner<4>(best), partner<4>(piv));
+            take(partner<5>(best), partner<5>(piv));
         }
         if (best == 0.0) {
             dr = di = 0.0;
@@ -775,7 +815,8 @@ __device__ __forceinline__ void lds_det(double2* D, int n, double& dr, double& d
         const double nr = dr * pr - di * pi, ni = dr * pi + di * pr;
         dr = nr;
         di = ni;
-        const double inv = 1.0 / (pr * pr + pi * pi);
+        const double pm = pr * pr + pi * pi;
+        const double inv = pm >= DBL_MIN ? newton_rcp(pm) : 1.0 / pm;
         // rows below the pivot are independent: above n = 8 the lower half
         // of the wavefront eliminates rows col + 1, col + 3, ... and the upper
         // half rows col + 2, col + 4, ..., lane q taking column q (n <= 32);
@@ -851,8 +892,8 @@ __device__ __forceinline__ void lds_reunit(double2* M, double2* P, int n, double
                 }
             }
             if (split) {
-                pr += __shfl_xor(pr, 32, kLanes);
-                pi += __shfl_xor(pi, 32, kLanes);
+                pr += partner<5>(pr);
+                pi += partner<5>(pi);
             }
             if (q < i && half == 0) P[q] = make_double2(pr, pi);
             wave_lds_order();
@@ -868,8 +909,8 @@ __device__ __forceinline__ void lds_reunit(double2* M, double2* P, int n, double
                 }
             }
             if (split) {
-                sr += __shfl_xor(sr, 32, kLanes);
-                si += __shfl_xor(si, 32, kLanes);
+                sr += partner<5>(sr);
+                si += partner<5>(si);
             }
             if (own) {
                 const double2 b = M[i * n + lane];
@@ -879,7 +920,8 @@ __device__ __forceinline__ void lds_reunit(double2* M, double2* P, int n, double
         }
         double s = 0.0;
         if (own) s = fmadd(M[i * n + lane].y, M[i * n + lane].y, M[i * n + lane].x * M[i * n + lane].x);
-        const double inv = rsqrt(wave_sum(s));
+        const double s2 = wave_sum(s);
+        const double inv = s2 >= DBL_MIN ? newton_rsqrt(s2) : rsqrt(s2);
         if (own) {
             M[i * n + lane].x *= inv;
             M[i * n + lane].y *= inv;
