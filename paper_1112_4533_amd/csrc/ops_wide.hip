@@ -13,7 +13,8 @@ struct OpsWide {
     template <bool MM, bool RA, int NT>
     static void update_as(const Ctx& c, int kind, int mu, int par, double beta, uint32_t k0, uint32_t k1,
                           uint32_t step) {
-        wide::k_update<T, MM, RA, NT><<<c.g.Vh, NT, wide_update_lds(c.nc, f64), c.stream>>>(
+        const size_t lds = wide_update_lds(c.nc, f64) + wide::handoff_lds<T, NT>();
+        wide::k_update<T, MM, RA, NT><<<c.g.Vh, NT, lds, c.stream>>>(
             (P*)c.links, c.g, c.nc, mu, par, kind == 0 ? 1 : 0, (T)beta, k0, k1, step);
     }
     // Threads per workgroup: a launch shape's block of 64 or 128 asks for one
@@ -90,7 +91,8 @@ struct OpsWide {
     template <bool MM, bool RA, int NT>
     static void update_batch_as(const ChainDesc* d, int n, int tiles, int kind, int mu, int par, uint32_t off, int nc,
                                 hipStream_t s) {
-        wide::k_update_batch<T, MM, RA, NT><<<tiles, NT, wide_update_lds(nc, f64), s>>>(
+        const size_t lds = wide_update_lds(nc, f64) + wide::handoff_lds<T, NT>();
+        wide::k_update_batch<T, MM, RA, NT><<<tiles, NT, lds, s>>>(
             d, n, nc, mu, par, kind == 0 ? 1 : 0, off);
     }
     static void update_batch(const ChainDesc* d, int n, int tiles, int kind, int mu, int par, uint32_t off,

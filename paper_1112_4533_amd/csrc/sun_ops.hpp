@@ -151,16 +151,15 @@ const Ops* ops_wide(int f64);         // 4 <= Nc <= 32: one workgroup per link, 
 constexpr size_t kWideLdsMax = 64 * 1024;
 inline bool wide_update_regacc(int nc, int f64) { return (size_t)3 * nc * nc * (f64 ? 16 : 8) > kLdsPerCu / 8; }
 // Threads of a large-Nc update workgroup: two wavefronts (the loads and
-// vector-unit products shared, the subgroup steps on the first) where that
-// measured faster on 8^4 -- FP32 with the products on the vector units from
-// Nc = 9 (5-9% per iteration; below, the second wavefront costs more than it
-// saves), and FP64 where a phase takes two rounds anyway (two matrices of
-// more than 10 KB, Nc >= 26): the overrelaxation (10-20%), and the heatbath
-// only from Nc = 32, below which its time grew by 2-5% -- one otherwise.
-inline int wide_update_threads(int nc, int f64, int kind) {
+// vector-unit products shared, the subgroup steps on the first, and in an
+// FP64 heatbath the draws on the second) where that measured faster on 8^4
+// -- FP32 with the products on the vector units from Nc = 9 (5-9% per
+// iteration; below, the second wavefront costs more than it saves), and
+// FP64 where a phase takes two rounds anyway (two matrices of more than
+// 10 KB, Nc >= 26; SU(32) 25.3 -> 20.8 ms) -- one otherwise.
+inline int wide_update_threads(int nc, int f64, int /*kind*/) {
     if (!f64) return (nc >= 9 && nc <= 20) ? 128 : 64;
-    const bool two_rounds = (size_t)2 * nc * nc * 16 > kLdsPerCu / 8;
-    return (two_rounds && (kind == 1 || nc >= 32)) ? 128 : 64;
+    return (size_t)2 * nc * nc * 16 > kLdsPerCu / 8 ? 128 : 64;
 }
 inline size_t wide_update_lds(int nc, int f64) {
     return (size_t)(wide_update_regacc(nc, f64) ? 2 : 3) * nc * nc * (f64 ? 16 : 8);

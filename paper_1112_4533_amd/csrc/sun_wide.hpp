@@ -514,8 +514,7 @@ struct DrawBatch {
 
 template <typename T>
 __device__ __forceinline__ DrawBatch<T> draw_batch(uint32_t k0, uint32_t k1, uint32_t site, uint32_t step,
-                                                   uint32_t mu_hi, uint32_t sg0) {
-    const uint32_t l = threadIdx.x;
+                                                   uint32_t mu_hi, uint32_t sg0, uint32_t l) {
     const U4 a = philox(site, step, mu_hi | (sg0 + l / kFirstHits), (RNG_ATTEMPT << 24) | (l % kFirstHits), k0, k1);
     const U4 d = philox(site, step, mu_hi | (sg0 + l % kSgBatch), RNG_DIRECTION << 24, k0, k1);
     DrawBatch<T> b;
@@ -530,6 +529,46 @@ __device__ __forceinline__ DrawBatch<T> draw_batch(uint32_t k0, uint32_t k1, uin
     const T phi = Const<T>::two_pi * uniform<T>(d.w[1]);
     b.cos_p = draw_cos(phi);
     b.sin_p = draw_sin(phi);
+    return b;
+}
+
+// A ring of two batches in LDS (slot, field, lane), through which a second
+// wavefront hands the first the draws of the next eight subgroups.
+constexpr int kBatchFields = 8;
+template <typename T>
+__host__ __device__ inline size_t batch_ring_bytes() {
+    return (size_t)2 * kBatchFields * kLanes * sizeof(T);
+}
+// Dynamic LDS of an update launch beyond its matrices: the ring, where the
+// second of two wavefronts draws the FP64 heatbath batches.
+template <typename T, int NT>
+__host__ __device__ inline size_t handoff_lds() {
+    return (NT > kLanes && sizeof(T) == 8) ? batch_ring_bytes<T>() : 0;
+}
+template <typename T>
+__device__ __forceinline__ void ring_store(T* ring, int slot, int l, const DrawBatch<T>& b) {
+    T* r = ring + (size_t)slot * kBatchFields * kLanes + l;
+    r[0 * kLanes] = b.r0;
+    r[1 * kLanes] = b.r1;
+    r[2 * kLanes] = b.r3;
+    r[3 * kLanes] = b.kp;
+    r[4 * kLanes] = b.cos_t;
+    r[5 * kLanes] = b.sin_t;
+    r[6 * kLanes] = b.cos_p;
+    r[7 * kLanes] = b.sin_p;
+}
+template <typename T>
+__device__ __forceinline__ DrawBatch<T> ring_load(const T* ring, int slot, int l) {
+    const T* r = ring + (size_t)slot * kBatchFields * kLanes + l;
+    DrawBatch<T> b;
+    b.r0 = r[0 * kLanes];
+    b.r1 = r[1 * kLanes];
+    b.r3 = r[2 * kLanes];
+    b.kp = r[3 * kLanes];
+    b.cos_t = r[4 * kLanes];
+    b.sin_t = r[5 * kLanes];
+    b.cos_p = r[6 * kLanes];
+    b.sin_p = r[7 * kLanes];
     return b;
 }
 
@@ -680,7 +719,30 @@ __device__ __forceinline__ void update_link_wide(T2<T>* __restrict__ U, const Ge
         lds_mm<T, MM, 4, NT>(W, Us, A, n, false);
     }
     __syncthreads();
-    if (NT > kLanes && threadIdx.x >= kLanes) {  // the subgroup steps are the first wavefront's
+    // With two wavefronts the subgroup steps are the first's.  In an FP64
+    // heatbath the second draws the batches (whose FP64 logarithms and
+    // cosines would otherwise sit on the chain every eighth step): batch 0
+    // before the chain, batch b + 1 after barrier b, into slot (b + 1) mod 2
+    // of a ring after the matrices, which the first read (into registers)
+    // before barrier b.  The first takes barrier b at subgroup 8 b, then
+    // reads slot b mod 2.  Both wavefronts pass the same ceil(S / 8)
+    // barriers, S = n (n - 1) / 2 subgroups.  (FP32 draws are cheap: there
+    // the first wavefront draws its own, as with one wavefront.)
+    constexpr bool kHandOff = NT > kLanes && sizeof(T) == 8;
+    T* const ring = reinterpret_cast<T*>(reinterpret_cast<char*>(smem_update) + (RA ? 2 : 3) * n2 * sizeof(T2<T>));
+    const int nbatch = (n * (n - 1) / 2 + kSgBatch - 1) / kSgBatch;
+    if (NT > kLanes && threadIdx.x >= kLanes) {
+        if (kHandOff && hb) {
+            const uint32_t l = threadIdx.x - kLanes;
+            const uint32_t mh = (uint32_t)mu << 16;
+            ring_store<T>(ring, 0, (int)l, draw_batch<T>(k0, k1, (uint32_t)x.s, step, mh, 0u, l));
+            for (int b = 0; b < nbatch; ++b) {
+                __syncthreads();
+                if (b + 1 < nbatch)
+                    ring_store<T>(ring, (b + 1) & 1, (int)l,
+                                  draw_batch<T>(k0, k1, (uint32_t)x.s, step, mh, (uint32_t)(kSgBatch * (b + 1)), l));
+            }
+        }
         __syncthreads();
         T2<T>* dst = const_cast<T2<T>*>(link_at<T>(U, n2, mu, par, h, Vh));
         for (int e = threadIdx.x; e < n2; e += NT) dst[e] = Us[e];
@@ -714,7 +776,14 @@ __device__ __forceinline__ void update_link_wide(T2<T>* __restrict__ U, const Ge
             bool apply = true;
             if (hb) {
                 const int slot = (int)(sg % kSgBatch);
-                if (slot == 0) batch = draw_batch<T>(k0, k1, (uint32_t)x.s, step, mu_hi, sg);
+                if (slot == 0) {
+                    if constexpr (kHandOff) {
+                        __syncthreads();
+                        batch = ring_load<T>(ring, (int)((sg / kSgBatch) & 1), lane);
+                    } else {
+                        batch = draw_batch<T>(k0, k1, (uint32_t)x.s, step, mu_hi, sg, (uint32_t)lane);
+                    }
+                }
                 const T alpha = cb * k;
                 Quat<T> xs;
                 apply = sample_su2_lanes<T>(alpha, batch, slot, k0, k1, (uint32_t)x.s, step, mu_hi | sg, xs) != 0;
@@ -1242,7 +1311,7 @@ __global__ __launch_bounds__(kLanes) void k_sample_su2_batched(const double* __r
                                                                uint32_t k1, uint32_t step, uint32_t mu_sg,
                                                                double* __restrict__ x, int* __restrict__ attempts) {
     const uint32_t site = blockIdx.x;
-    const DrawBatch<T> b = draw_batch<T>(k0, k1, site, step, 0u, mu_sg);
+    const DrawBatch<T> b = draw_batch<T>(k0, k1, site, step, 0u, mu_sg, threadIdx.x);
     for (int s = 0; s < kSgBatch; ++s) {
         const int i = (int)site * kSgBatch + s;
         if (i >= n) break;
