@@ -68,7 +68,7 @@ enum {
  * loads and the vector-unit products shared, the subgroup steps on the
  * first; the same bits either way; the FP32 matrix-core form above Nc = 20
  * always runs on one), and any other block, the default 256 included, picks
- * by Nc, precision and update kind. */
+ * by Nc and precision. */
 enum {
     SUN_F32 = 0,
     SUN_F64 = 1,

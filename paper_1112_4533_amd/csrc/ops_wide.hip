@@ -20,13 +20,13 @@ struct OpsWide {
     // Threads per workgroup: a launch shape's block of 64 or 128 asks for one
     // or two wavefronts; any other block (the default 256) takes
     // wide_update_threads.  The matrix-core form runs on one.
-    static bool two_waves(const Shape& sh, int nc, int kind) {
+    static bool two_waves(const Shape& sh, int nc) {
         if (sh.block == wide::kLanes || sh.block == 2 * wide::kLanes) return sh.block > wide::kLanes;
-        return wide_update_threads(nc, f64, kind) > wide::kLanes;
+        return wide_update_threads(nc, f64) > wide::kLanes;
     }
     static void update(const Ctx& c, int kind, int mu, int par, double beta, uint32_t k0, uint32_t k1, uint32_t step) {
         const bool ra = wide_update_regacc(c.nc, f64);
-        const bool two = two_waves(c.shape[kind], c.nc, kind);
+        const bool two = two_waves(c.shape[kind], c.nc);
         if constexpr (!f64) {
             if (c.nc > wide::kMfmaMinN) {
                 if (ra)
@@ -98,7 +98,7 @@ struct OpsWide {
     static void update_batch(const ChainDesc* d, int n, int tiles, int kind, int mu, int par, uint32_t off,
                              const Shape& shape, int nc, hipStream_t s) {
         const bool ra = wide_update_regacc(nc, f64);
-        const bool two = two_waves(shape, nc, kind);
+        const bool two = two_waves(shape, nc);
         if constexpr (!f64) {
             if (nc > wide::kMfmaMinN) {
                 if (ra)

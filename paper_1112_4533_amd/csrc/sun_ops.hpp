@@ -157,7 +157,7 @@ inline bool wide_update_regacc(int nc, int f64) { return (size_t)3 * nc * nc * (
 // iteration; below, the second wavefront costs more than it saves), and
 // FP64 where a phase takes two rounds anyway (two matrices of more than
 // 10 KB, Nc >= 26; SU(32) 25.3 -> 20.8 ms) -- one otherwise.
-inline int wide_update_threads(int nc, int f64, int /*kind*/) {
+inline int wide_update_threads(int nc, int f64) {
     if (!f64) return (nc >= 9 && nc <= 20) ? 128 : 64;
     return (size_t)2 * nc * nc * 16 > kLdsPerCu / 8 ? 128 : 64;
 }
