@@ -653,7 +653,9 @@ __device__ __forceinline__ void rows_left_mul_col(T2<T>* M, int n, int i, int j,
 // leave one.
 // NT: threads per workgroup, one wavefront or two.  With two, the loads and
 // the vector-unit products are shared by both wavefronts (RowMap: the same
-// bits), and the first wavefront runs the subgroup steps alone.
+// bits), the first wavefront runs the subgroup steps, and in an FP64
+// heatbath the second draws their batches (below); LDS then also holds the
+// ring of two batches after the matrices (handoff_lds).
 template <typename T, bool MM, bool RA, int NT = kLanes>
 __device__ __forceinline__ void update_link_wide(T2<T>* __restrict__ U, const Geom& g, int n, int mu, int par,
                                                  int hb, T beta, uint32_t k0, uint32_t k1, uint32_t step, int h) {
