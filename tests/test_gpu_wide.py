@@ -266,6 +266,17 @@ def test_wide_chains_in_a_batch_are_bitwise_the_chains_alone(gpu):
         assert a.step == b.step == 5
         assert torch.equal(a.plaquette(), plaq[i]), f"plaquette of chain {i}"
         assert torch.equal(a.plaquette(), bt.plaquette()[i]), f"eager batch plaquette of chain {i}"
+    # the batch's launch block reaches its large-Nc groups too (64: one
+    # wavefront per link, 128: two), with the same bits
+    for block in (64, 128):
+        again = [gpu_lattice(sun, nc, L, dt, hot=True, seed=sd) for nc, L, dt, b, sd in WIDE_BATCH]
+        bb = sun.Batch(again, [c[3] for c in WIDE_BATCH], [c[4] for c in WIDE_BATCH])
+        bb.set_launch(block)
+        for _ in range(5):
+            bb.sweep(1, 2)
+        torch.cuda.synchronize()
+        for i, (a, b) in enumerate(zip(alone, again)):
+            assert torch.equal(a.links, b.links), f"block {block}: chain {i} {WIDE_BATCH[i][:3]} differs"
 
 
 def test_wide_batch_couplings_from_a_device_array(gpu):
