@@ -267,7 +267,9 @@ class Lattice:
 
     def set_launch(self, block=256, xcd=1, waves=0, tblock=0, kind=-1):
         """Launch shape of the heatbath (kind 0), overrelaxation (1) or both
-        (-1) phase kernels."""
+        (-1) phase kernels.  On the workgroup-per-link path (Nc >= 5, or the
+        WIDE storages) only the block applies: 64 or 128 threads per link
+        (one or two wavefronts), any other value the library's choice."""
         _check(load().sun_set_launch(self._h, int(kind), int(block), int(xcd), int(waves), int(tblock)))
 
     def get_launch(self, kind):
