@@ -66,9 +66,9 @@ enum {
  * at Nc = 32 in FP64).  Of a launch shape only the block size applies to
  * it: 64 runs each link's update on one wavefront, 128 on two (the link
  * loads and the vector-unit products shared, the subgroup steps on the
- * first; the same bits either way; the FP32 matrix-core form above Nc = 20
- * always runs on one), and any other block, the default 256 included, picks
- * by Nc and precision. */
+ * first; the same bits either way; in the FP32 matrix-core form above
+ * Nc = 20 the products stay on the first), and any other block, the default
+ * 256 included, picks by Nc and precision. */
 enum {
     SUN_F32 = 0,
     SUN_F64 = 1,

@@ -19,7 +19,8 @@ struct OpsWide {
     }
     // Threads per workgroup: a launch shape's block of 64 or 128 asks for one
     // or two wavefronts; any other block (the default 256) takes
-    // wide_update_threads.  The matrix-core form runs on one.
+    // wide_update_threads.  In the matrix-core form the second wavefront
+    // shares the loads only: the products run on the first.
     static bool two_waves(const Shape& sh, int nc) {
         if (sh.block == wide::kLanes || sh.block == 2 * wide::kLanes) return sh.block > wide::kLanes;
         return wide_update_threads(nc, f64) > wide::kLanes;
@@ -29,10 +30,17 @@ struct OpsWide {
         const bool two = two_waves(c.shape[kind], c.nc);
         if constexpr (!f64) {
             if (c.nc > wide::kMfmaMinN) {
-                if (ra)
-                    update_as<true, true, wide::kLanes>(c, kind, mu, par, beta, k0, k1, step);
-                else
-                    update_as<true, false, wide::kLanes>(c, kind, mu, par, beta, k0, k1, step);
+                if (ra) {
+                    if (two)
+                        update_as<true, true, 2 * wide::kLanes>(c, kind, mu, par, beta, k0, k1, step);
+                    else
+                        update_as<true, true, wide::kLanes>(c, kind, mu, par, beta, k0, k1, step);
+                } else {
+                    if (two)
+                        update_as<true, false, 2 * wide::kLanes>(c, kind, mu, par, beta, k0, k1, step);
+                    else
+                        update_as<true, false, wide::kLanes>(c, kind, mu, par, beta, k0, k1, step);
+                }
                 return;
             }
         }
@@ -101,10 +109,17 @@ struct OpsWide {
         const bool two = two_waves(shape, nc);
         if constexpr (!f64) {
             if (nc > wide::kMfmaMinN) {
-                if (ra)
-                    update_batch_as<true, true, wide::kLanes>(d, n, tiles, kind, mu, par, off, nc, s);
-                else
-                    update_batch_as<true, false, wide::kLanes>(d, n, tiles, kind, mu, par, off, nc, s);
+                if (ra) {
+                    if (two)
+                        update_batch_as<true, true, 2 * wide::kLanes>(d, n, tiles, kind, mu, par, off, nc, s);
+                    else
+                        update_batch_as<true, true, wide::kLanes>(d, n, tiles, kind, mu, par, off, nc, s);
+                } else {
+                    if (two)
+                        update_batch_as<true, false, 2 * wide::kLanes>(d, n, tiles, kind, mu, par, off, nc, s);
+                    else
+                        update_batch_as<true, false, wide::kLanes>(d, n, tiles, kind, mu, par, off, nc, s);
+                }
                 return;
             }
         }

@@ -153,12 +153,14 @@ inline bool wide_update_regacc(int nc, int f64) { return (size_t)3 * nc * nc * (
 // Threads of a large-Nc update workgroup: two wavefronts (the loads and
 // vector-unit products shared, the subgroup steps on the first, and in an
 // FP64 heatbath the draws on the second) where that measured faster on 8^4
-// -- FP32 with the products on the vector units from Nc = 9 (5-9% per
-// iteration; below, the second wavefront costs more than it saves), and
-// FP64 where a phase takes two rounds anyway (two matrices of more than
-// 10 KB, Nc >= 26; SU(32) 25.3 -> 20.8 ms) -- one otherwise.
+// -- FP32 from Nc = 9 (5-9% per iteration up to Nc = 20; above, where the
+// matrix-core products stay on the first wavefront and only the loads are
+// shared, 2% -- the overrelaxation 6%; below Nc = 9 the second wavefront
+// costs more than it saves), and FP64 where a phase takes two rounds anyway
+// (two matrices of more than 10 KB, Nc >= 26; SU(32) 25.3 -> 20.8 ms) --
+// one otherwise.
 inline int wide_update_threads(int nc, int f64) {
-    if (!f64) return (nc >= 9 && nc <= 20) ? 128 : 64;
+    if (!f64) return nc >= 9 ? 128 : 64;
     return (size_t)2 * nc * nc * 16 > kLdsPerCu / 8 ? 128 : 64;
 }
 inline size_t wide_update_lds(int nc, int f64) {

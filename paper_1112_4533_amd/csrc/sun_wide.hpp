@@ -230,8 +230,8 @@ struct RowMap {
 template <typename T, bool MM = false, int RMAX = 4, int NT = kLanes>
 __device__ __forceinline__ void lds_mm(T2<T>* C, const T2<T>* A, const T2<T>* B, int n, bool acc) {
     if constexpr (MM) {
-        static_assert(sizeof(T) == 4 && NT == kLanes, "the matrix-core product is FP32 on one wavefront");
-        lds_mm_mfma(C, A, B, n, acc);
+        static_assert(sizeof(T) == 4, "the matrix-core product is FP32");
+        if (threadIdx.x < kLanes) lds_mm_mfma(C, A, B, n, acc);  // the whole tile on the first wavefront
         return;
     }
     const RowMap<NT> m(n);
@@ -266,8 +266,8 @@ struct Acc {
         for (int t = 0; t < kRows; ++t) e[t] = cpx<T>(T(0), T(0));
     }
 };
-template <>
-struct Acc<float, true, kLanes> {
+template <int NT>
+struct Acc<float, true, NT> {
     f32x16 re, im;
     __device__ __forceinline__ void zero() {
 #pragma unroll
@@ -323,6 +323,7 @@ template <typename T, bool MM, int NT>
 __device__ __forceinline__ void acc_mm(Acc<T, MM, NT>& c, const T2<T>* A, const T2<T>* B, int n) {
     if constexpr (MM) {
         const int l = threadIdx.x;
+        if (l >= kLanes) return;  // the whole tile on the first wavefront
         const int lo = l & 31, hi = l >> 5;
 #pragma unroll 2
         for (int k0 = 0; k0 < n; k0 += 2) {
@@ -356,6 +357,7 @@ template <typename T, bool MM, int NT>
 __device__ __forceinline__ void acc_store(T2<T>* C, const Acc<T, MM, NT>& c, int n) {
     if constexpr (MM) {
         const int l = threadIdx.x;
+        if (l >= kLanes) return;
         const int lo = l & 31, hi = l >> 5;
 #pragma unroll
         for (int r = 0; r < 16; ++r) {
@@ -659,7 +661,7 @@ __device__ __forceinline__ void rows_left_mul_col(T2<T>* M, int n, int i, int j,
 template <typename T, bool MM, bool RA, int NT = kLanes>
 __device__ __forceinline__ void update_link_wide(T2<T>* __restrict__ U, const Geom& g, int n, int mu, int par,
                                                  int hb, T beta, uint32_t k0, uint32_t k1, uint32_t step, int h) {
-    static_assert(NT == kLanes || (NT == 2 * kLanes && !MM), "two wavefronts share vector-unit products only");
+    static_assert(NT == kLanes || NT == 2 * kLanes, "one wavefront or two");
     extern __shared__ double4 smem_update[];
     const int n2 = n * n;
     T2<T>* A = reinterpret_cast<T2<T>*>(smem_update);  // the staple sum (without RA)

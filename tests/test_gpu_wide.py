@@ -188,8 +188,8 @@ def test_wide_one_or_two_wavefronts_give_the_same_bits(gpu, nc, dtype):
     """A link's update on one wavefront (launch block 64), on two (block
     128: loads and vector-unit products shared by row groups) and with the
     default choice give the same field bit for bit, heatbath and
-    overrelaxation (at Nc = 24 in FP32 the matrix-core form runs on one
-    wavefront whatever the block)."""
+    overrelaxation (at Nc = 24 in FP32 the matrix-core products stay on the
+    first wavefront and the second shares the loads)."""
     sun = gpu
     L, beta = (4, 4, 2, 2), beta_for(nc)
     base = O.new_field(nc, L, hot=True, seed=41)
