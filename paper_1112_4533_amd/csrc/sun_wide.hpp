@@ -3,25 +3,28 @@
 // large-Nc runs at 8^4).
 //
 // At large Nc a link no longer fits in one work-item's registers (Nc = 32 is
-// 2048 reals), so a workgroup of one wavefront owns one link: the matrices of
-// the update live in LDS, every product is spread over the lanes element by
-// element, and the SU(2) subgroup steps (Nc(Nc-1)/2 of them, sequential by
-// definition) update two rows with one lane per column.  Links are stored
+// 2048 reals), so a workgroup of one wavefront (or two) owns one link: the
+// matrices of the update live in LDS, every product is spread over the lanes
+// element by element, and the SU(2) subgroup steps (Nc(Nc-1)/2 of them)
+// update two rows with one lane per column, two steps at a time.  Links are stored
 // link-major (the Nc^2 complex entries of one link are contiguous), so the
 // workgroup reads a link with unit stride.  Operands that enter a product
 // daggered are transposed while they are copied into LDS, so that every
 // product reads one operand by broadcast and the other with unit stride.
 //
 // The arithmetic is that of the register kernels: the same closing staple,
-// W = U A, the lexicographic subgroup order, the quaternion projection, the
-// same Philox counters, and an SU(2) draw whose 64 attempts are evaluated one
-// per lane, the first accepted one winning (which is the sequential draw's
-// result).  Reductions and re-unitarization are FP64.
+// W = U A, the lexicographic subgroup order (run two steps at a time where
+// they share no index, which gives the same bits: sun_pairs.hpp), the
+// quaternion projection, the same Philox counters, and an SU(2) draw whose
+// 64 attempts are evaluated one per lane, the first accepted one winning
+// (which is the sequential draw's result).  Reductions and re-unitarization
+// are FP64.
 #pragma once
 
 #include <cfloat>
 
 #include "sun_kernels.hpp"
+#include "sun_pairs.hpp"
 
 namespace sun {
 namespace wide {
@@ -514,11 +517,14 @@ struct DrawBatch {
     T cos_t, sin_t, cos_p, sin_p;
 };
 
+// Lane l's share of a batch whose lane group l / 8 draws the attempts of
+// subgroup sg_att and whose lanes l mod 8 = g hold the direction of the
+// subgroup of group g, sg_dir.
 template <typename T>
-__device__ __forceinline__ DrawBatch<T> draw_batch(uint32_t k0, uint32_t k1, uint32_t site, uint32_t step,
-                                                   uint32_t mu_hi, uint32_t sg0, uint32_t l) {
-    const U4 a = philox(site, step, mu_hi | (sg0 + l / kFirstHits), (RNG_ATTEMPT << 24) | (l % kFirstHits), k0, k1);
-    const U4 d = philox(site, step, mu_hi | (sg0 + l % kSgBatch), RNG_DIRECTION << 24, k0, k1);
+__device__ __forceinline__ DrawBatch<T> draw_batch_of(uint32_t k0, uint32_t k1, uint32_t site, uint32_t step,
+                                                      uint32_t mu_hi, uint32_t sg_att, uint32_t sg_dir, uint32_t l) {
+    const U4 a = philox(site, step, mu_hi | sg_att, (RNG_ATTEMPT << 24) | (l % kFirstHits), k0, k1);
+    const U4 d = philox(site, step, mu_hi | sg_dir, RNG_DIRECTION << 24, k0, k1);
     DrawBatch<T> b;
     b.r0 = uniform<T>(a.w[0]);
     b.r1 = uniform<T>(a.w[1]);
@@ -532,6 +538,66 @@ __device__ __forceinline__ DrawBatch<T> draw_batch(uint32_t k0, uint32_t k1, uin
     b.cos_p = draw_cos(phi);
     b.sin_p = draw_sin(phi);
     return b;
+}
+// The batch of subgroups sg0 .. sg0 + 7.
+template <typename T>
+__device__ __forceinline__ DrawBatch<T> draw_batch(uint32_t k0, uint32_t k1, uint32_t site, uint32_t step,
+                                                   uint32_t mu_hi, uint32_t sg0, uint32_t l) {
+    return draw_batch_of<T>(k0, k1, site, step, mu_hi, sg0 + l / kFirstHits, sg0 + l % kSgBatch, l);
+}
+
+// ---------------------------------------------------------------------------
+// The subgroup steps in slots of two (the order of pairs::make_table, which
+// gives the link of the fixed order bit for bit): in each slot lanes 0..31
+// run the first step and lanes 32..63 the second, each lane owning one
+// column of U and of W.  A batch then covers the eight subgroups of four
+// slots, lane group g drawing for member g mod 2 of slot g / 2.
+// ---------------------------------------------------------------------------
+static __constant__ pairs::Table kPairTable = pairs::make_table();
+constexpr int kSlotsPerBatch = kSgBatch / 2;
+constexpr pairs::Table kPairTableHost = pairs::make_table();
+// The slots of a link, 64 to a register across the wavefront (lane l holds
+// slot 64 w + l of window w), so that a step reads its pair with readlane.
+constexpr int kPairWindows = (pairs::slots(kPairTableHost, kNcMax) + kLanes - 1) / kLanes;
+static_assert(kLanes % kSlotsPerBatch == 0, "a batch's slots share a window");
+static_assert(kSlotsPerBatch == 4, "draw_pair_batch selects among four slots");
+constexpr uint32_t kNoSlot = 0xFFFFFFFFu;  // beyond the last slot: no steps
+
+__device__ __forceinline__ void pair_windows(int n, uint32_t (&win)[kPairWindows], int& nslot) {
+    const int f = kPairTable.first[n];
+    nslot = kPairTable.first[n + 1] - f;
+    const int l = (int)(threadIdx.x & (kLanes - 1));
+#pragma unroll
+    for (int w = 0; w < kPairWindows; ++w) win[w] = kLanes * w + l < nslot ? kPairTable.slot[f + kLanes * w + l] : kNoSlot;
+}
+// The next window to the front (after every 64 slots).
+__device__ __forceinline__ void pair_windows_shift(uint32_t (&win)[kPairWindows]) {
+#pragma unroll
+    for (int w = 0; w + 1 < kPairWindows; ++w) win[w] = win[w + 1];
+    win[kPairWindows - 1] = kNoSlot;
+}
+__device__ __forceinline__ uint32_t pair_at(uint32_t win0, int u) {
+    return (uint32_t)__builtin_amdgcn_readlane((int)win0, u);
+}
+// Subgroup number (the Philox counter) of member m of a packed slot; 0 for
+// an absent member, whose draws go unused.
+__device__ __forceinline__ uint32_t pair_sg(uint32_t e, int m, int n) {
+    const int i = (int)((e >> (16 * m)) & 0xFF), j = (int)((e >> (16 * m + 8)) & 0xFF);
+    return i == pairs::kNone ? 0u : pairs::step_index(n, i, j);
+}
+// The batch of the four slots u0 .. u0 + 3 of window win0.
+template <typename T>
+__device__ __forceinline__ DrawBatch<T> draw_pair_batch(uint32_t k0, uint32_t k1, uint32_t site, uint32_t step,
+                                                        uint32_t mu_hi, uint32_t win0, int u0, int n, uint32_t l) {
+    uint32_t e[kSlotsPerBatch];
+#pragma unroll
+    for (int q = 0; q < kSlotsPerBatch; ++q) e[q] = pair_at(win0, u0 + q);
+    auto sg_of = [&](uint32_t g) {
+        const uint32_t q = g >> 1;
+        const uint32_t es = q == 0 ? e[0] : q == 1 ? e[1] : q == 2 ? e[2] : e[3];
+        return pair_sg(es, (int)(g & 1), n);
+    };
+    return draw_batch_of<T>(k0, k1, site, step, mu_hi, sg_of(l / kFirstHits), sg_of(l % kSgBatch), l);
 }
 
 // A ring of two batches in LDS (slot, field, lane), through which a second
@@ -631,6 +697,71 @@ __device__ __forceinline__ int sample_su2_lanes(T alpha, const DrawBatch<T>& b, 
     return hit0 + first + 1;
 }
 
+// The draws of the two subgroups of slot q of a batch (lane groups 2q and
+// 2q + 1 hold their attempts), as sample_su2_lanes draws each: alpha is
+// the lane's own subgroup's (lanes 0..31: the first, 32..63: the second),
+// two whether the slot has a second subgroup, mu_sg0 and mu_sg1 their
+// counters.  Returns, for the lane's own subgroup, the accepted attempt's
+// number (0: skip the step), and its element in x.
+template <typename T>
+__device__ __forceinline__ int sample_su2_pair(T alpha, const DrawBatch<T>& b, int q, bool two, uint32_t k0,
+                                               uint32_t k1, uint32_t site, uint32_t step, uint32_t mu_sg0,
+                                               uint32_t mu_sg1, Quat<T>& x) {
+    const int l = (int)threadIdx.x;
+    const T al0 = lane_value(alpha, 0);
+    const T al1 = two ? lane_value(alpha, kLanes / 2) : al0;
+    // each lane tries its attempt with the alpha of the subgroup it draws for
+    const T al = ((l / kFirstHits) & 1) ? al1 : al0;
+    const bool creutz = al < Const<T>::switch_alpha;
+    const T em = creutz ? d_expm1(T(-2) * al) : T(0);
+    const T ia = chain_inverse(al);
+    T x0 = T(1), rad = T(0);
+    const bool ok = su2_attempt_batched(al, ia, creutz, em, b, x0, rad);
+    const unsigned long long ball = __ballot(ok);
+    T mx0[2] = {T(1), T(1)}, mrad[2] = {T(0), T(0)};
+    int hit[2] = {0, 0};
+#pragma unroll
+    for (int m = 0; m < 2; ++m) {
+        if (m == 1 && !two) break;
+        const int g = 2 * q + m;
+        unsigned long long mask = ball & (0xFFull << (kFirstHits * g));
+        int hit0 = -kFirstHits * g;
+        T fx0 = x0, frad = rad;
+        if (mask == 0ull) {  // the first eight attempts all rejected: attempts 8 .. 63, one per lane
+            const T a = m ? al1 : al0;
+            const bool cr = a < Const<T>::switch_alpha;
+            const T e2 = cr ? d_expm1(T(-2) * a) : T(0);
+            const T i2 = chain_inverse(a);
+            const uint32_t h = (uint32_t)l + kFirstHits;
+            const U4 r = philox(site, step, m ? mu_sg1 : mu_sg0, (RNG_ATTEMPT << 24) | h, k0, k1);
+            fx0 = T(1);
+            frad = T(0);
+            const bool ok2 = h < (uint32_t)kMaxAttempts && su2_attempt(a, i2, cr, e2, r, fx0, frad);
+            mask = __ballot(ok2);
+            hit0 = kFirstHits;
+        }
+        if (mask != 0ull) {
+            const int first = __ffsll(mask) - 1;  // the same on every lane
+            mx0[m] = lane_value(fx0, first);
+            mrad[m] = lane_value(frad, first);
+            hit[m] = hit0 + first + 1;
+        }
+    }
+    // the lane's own subgroup; the direction of lane group g sits in the
+    // lanes l mod 8 = g (read at uniform lanes, then selected)
+    const bool m1 = two && l >= kLanes / 2;
+    const T cos_t = m1 ? lane_value(b.cos_t, 2 * q + 1) : lane_value(b.cos_t, 2 * q);
+    const T sin_t = m1 ? lane_value(b.sin_t, 2 * q + 1) : lane_value(b.sin_t, 2 * q);
+    const T cos_p = m1 ? lane_value(b.cos_p, 2 * q + 1) : lane_value(b.cos_p, 2 * q);
+    const T sin_p = m1 ? lane_value(b.sin_p, 2 * q + 1) : lane_value(b.sin_p, 2 * q);
+    const T r = m1 ? mrad[1] : mrad[0];
+    x.q[0] = m1 ? mx0[1] : mx0[0];
+    x.q[1] = r * sin_t * cos_p;
+    x.q[2] = r * sin_t * sin_p;
+    x.q[3] = r * cos_t;
+    return m1 ? hit[1] : hit[0];
+}
+
 // Rows i, j of M (LDS), column c, left-multiplied by the 2x2 form of a,
 // given their current entries x = M_ic and y = M_jc.
 template <typename T>
@@ -725,26 +856,32 @@ __device__ __forceinline__ void update_link_wide(T2<T>* __restrict__ U, const Ge
     __syncthreads();
     // With two wavefronts the subgroup steps are the first's.  In an FP64
     // heatbath the second draws the batches (whose FP64 logarithms and
-    // cosines would otherwise sit on the chain every eighth step): batch 0
+    // cosines would otherwise sit on the chain every fourth slot): batch 0
     // before the chain, batch b + 1 after barrier b, into slot (b + 1) mod 2
     // of a ring after the matrices, which the first read (into registers)
-    // before barrier b.  The first takes barrier b at subgroup 8 b, then
-    // reads slot b mod 2.  Both wavefronts pass the same ceil(S / 8)
-    // barriers, S = n (n - 1) / 2 subgroups.  (FP32 draws are cheap: there
+    // before barrier b.  The first takes barrier b at step slot 4 b, then
+    // reads ring slot b mod 2.  Both wavefronts pass the same ceil(S / 4)
+    // barriers, S the number of step slots.  (FP32 draws are cheap: there
     // the first wavefront draws its own, as with one wavefront.)
     constexpr bool kHandOff = NT > kLanes && sizeof(T) == 8;
     T* const ring = reinterpret_cast<T*>(reinterpret_cast<char*>(smem_update) + (RA ? 2 : 3) * n2 * sizeof(T2<T>));
-    const int nbatch = (n * (n - 1) / 2 + kSgBatch - 1) / kSgBatch;
+    uint32_t win[kPairWindows];
+    int nslot = 0;
+    pair_windows(n, win, nslot);
+    const int nbatch = (nslot + kSlotsPerBatch - 1) / kSlotsPerBatch;
     if (NT > kLanes && threadIdx.x >= kLanes) {
         if (kHandOff && hb) {
             const uint32_t l = threadIdx.x - kLanes;
             const uint32_t mh = (uint32_t)mu << 16;
-            ring_store<T>(ring, 0, (int)l, draw_batch<T>(k0, k1, (uint32_t)x.s, step, mh, 0u, l));
+            ring_store<T>(ring, 0, (int)l, draw_pair_batch<T>(k0, k1, (uint32_t)x.s, step, mh, win[0], 0, n, l));
             for (int b = 0; b < nbatch; ++b) {
                 __syncthreads();
-                if (b + 1 < nbatch)
+                const int t = kSlotsPerBatch * (b + 1);  // the next batch's first slot
+                if (b + 1 < nbatch) {
+                    if ((t & (kLanes - 1)) == 0) pair_windows_shift(win);
                     ring_store<T>(ring, (b + 1) & 1, (int)l,
-                                  draw_batch<T>(k0, k1, (uint32_t)x.s, step, mh, (uint32_t)(kSgBatch * (b + 1)), l));
+                                  draw_pair_batch<T>(k0, k1, (uint32_t)x.s, step, mh, win[0], t & (kLanes - 1), n, l));
+                }
             }
         }
         __syncthreads();
@@ -757,48 +894,58 @@ __device__ __forceinline__ void update_link_wide(T2<T>* __restrict__ U, const Ge
     const uint32_t mu_hi = (uint32_t)mu << 16;
     DrawBatch<T> batch{};
     const T cb = T(2) * beta / T(n);  // alpha = 2 beta k / n
-    // The subgroup steps are ordered by wave_lds_order, and each lane reads
-    // its entries of rows i and j together with the 2x2 block.  Lanes 0..31
-    // own column lane of U, lanes 32..63 column lane - 32 of W.
-    T2<T>* const M = lane < 32 ? Us : W;
+    // The slots are ordered by wave_lds_order; in each, lanes 0..31 run the
+    // slot's first step and lanes 32..63 its second, lane l owning column
+    // l mod 32 of U and of W and reading its entries of rows i and j together
+    // with the 2x2 block.
     const int col = lane & 31;
     const bool owner = col < n;
     const int c = owner ? col : 0;
-    uint32_t sg = 0;
-    for (int i = 0; i < n; ++i)
-        for (int j = i + 1; j < n; ++j, ++sg) {
-            const T2<T> wii = W[i * n + i], wij = W[i * n + j], wji = W[j * n + i], wjj = W[j * n + j];
-            const T2<T> mi = M[i * n + c], mj = M[j * n + c];
-            Quat<T> p;
-            p.q[0] = T(0.5) * (wii.x + wjj.x);
-            p.q[3] = T(0.5) * (wii.y - wjj.y);
-            p.q[2] = T(0.5) * (wij.x - wji.x);
-            p.q[1] = T(0.5) * (wij.y + wji.y);
-            Quat<T> v;
-            const T k = chain_unit_quat(p, v);
-            Quat<T> a;
-            bool apply = true;
-            if (hb) {
-                const int slot = (int)(sg % kSgBatch);
-                if (slot == 0) {
-                    if constexpr (kHandOff) {
-                        __syncthreads();
-                        batch = ring_load<T>(ring, (int)((sg / kSgBatch) & 1), lane);
-                    } else {
-                        batch = draw_batch<T>(k0, k1, (uint32_t)x.s, step, mu_hi, sg, (uint32_t)lane);
-                    }
+    const bool upper = lane >= kLanes / 2;
+    for (int t = 0; t < nslot; ++t) {
+        const int u = t & (kLanes - 1);
+        if (u == 0 && t > 0) pair_windows_shift(win);
+        const uint32_t e = pair_at(win[0], u);
+        const bool two = ((e >> 16) & 0xFF) != (uint32_t)pairs::kNone;
+        const bool mine = !upper || two;  // this half has a step
+        const uint32_t es = (upper && two) ? e >> 16 : e;
+        const int i = (int)(es & 0xFF), j = (int)((es >> 8) & 0xFF);
+        const T2<T> wii = W[i * n + i], wij = W[i * n + j], wji = W[j * n + i], wjj = W[j * n + j];
+        const T2<T> ui = Us[i * n + c], uj = Us[j * n + c], xi = W[i * n + c], xj = W[j * n + c];
+        Quat<T> p;
+        p.q[0] = T(0.5) * (wii.x + wjj.x);
+        p.q[3] = T(0.5) * (wii.y - wjj.y);
+        p.q[2] = T(0.5) * (wij.x - wji.x);
+        p.q[1] = T(0.5) * (wij.y + wji.y);
+        Quat<T> v;
+        const T k = chain_unit_quat(p, v);
+        Quat<T> a;
+        bool apply = true;
+        if (hb) {
+            const int q = t % kSlotsPerBatch;
+            if (q == 0) {
+                if constexpr (kHandOff) {
+                    __syncthreads();
+                    batch = ring_load<T>(ring, (t / kSlotsPerBatch) & 1, lane);
+                } else {
+                    batch = draw_pair_batch<T>(k0, k1, (uint32_t)x.s, step, mu_hi, win[0], u, n, (uint32_t)lane);
                 }
-                const T alpha = cb * k;
-                Quat<T> xs;
-                apply = sample_su2_lanes<T>(alpha, batch, slot, k0, k1, (uint32_t)x.s, step, mu_hi | sg, xs) != 0;
-                if (apply) a = qmul(xs, qconj(v));
-            } else {
-                const Quat<T> vc = qconj(v);
-                a = qmul(vc, vc);
             }
-            if (apply && owner) rows_left_mul_col<T>(M, n, i, j, c, a, mi, mj);
-            wave_lds_order();
+            const T alpha = cb * k;
+            Quat<T> xs;
+            apply = sample_su2_pair<T>(alpha, batch, q, two, k0, k1, (uint32_t)x.s, step, mu_hi | pair_sg(e, 0, n),
+                                       mu_hi | pair_sg(e, 1, n), xs) != 0;
+            if (apply) a = qmul(xs, qconj(v));
+        } else {
+            const Quat<T> vc = qconj(v);
+            a = qmul(vc, vc);
         }
+        if (apply && owner && mine) {
+            rows_left_mul_col<T>(Us, n, i, j, c, a, ui, uj);
+            rows_left_mul_col<T>(W, n, i, j, c, a, xi, xj);
+        }
+        wave_lds_order();
+    }
     __syncthreads();
     T2<T>* dst = const_cast<T2<T>*>(link_at<T>(U, n2, mu, par, h, Vh));
     for (int e = threadIdx.x; e < n2; e += NT) dst[e] = Us[e];
