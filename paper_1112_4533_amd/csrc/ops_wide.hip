@@ -10,12 +10,23 @@ struct OpsWide {
     using P = T2<T>;
     static constexpr int f64 = sizeof(T) == 8;
 
+    // Subgroup steps per slot (the same bits either way): the matrix-core and
+    // register-accumulator forms exist only above Nc = 20, so only with four.
+    template <bool MM, bool RA>
+    static bool four_per_slot(int nc) {
+        return MM || RA || wide::slot_steps(nc) == 4;
+    }
     template <bool MM, bool RA, int NT>
     static void update_as(const Ctx& c, int kind, int mu, int par, double beta, uint32_t k0, uint32_t k1,
                           uint32_t step) {
         const size_t lds = wide_update_lds(c.nc, f64) + wide::handoff_lds<T, NT>();
-        wide::k_update<T, MM, RA, NT><<<c.g.Vh, NT, lds, c.stream>>>(
-            (P*)c.links, c.g, c.nc, mu, par, kind == 0 ? 1 : 0, (T)beta, k0, k1, step);
+        const int hb = kind == 0 ? 1 : 0;
+        if (four_per_slot<MM, RA>(c.nc))
+            wide::k_update<T, MM, RA, NT, 4><<<c.g.Vh, NT, lds, c.stream>>>((P*)c.links, c.g, c.nc, mu, par, hb,
+                                                                            (T)beta, k0, k1, step);
+        else if constexpr (!MM && !RA)
+            wide::k_update<T, MM, RA, NT, 2><<<c.g.Vh, NT, lds, c.stream>>>((P*)c.links, c.g, c.nc, mu, par, hb,
+                                                                            (T)beta, k0, k1, step);
     }
     // Threads per workgroup: a launch shape's block of 64 or 128 asks for one
     // or two wavefronts; any other block (the default 256) takes
@@ -100,8 +111,11 @@ struct OpsWide {
     static void update_batch_as(const ChainDesc* d, int n, int tiles, int kind, int mu, int par, uint32_t off, int nc,
                                 hipStream_t s) {
         const size_t lds = wide_update_lds(nc, f64) + wide::handoff_lds<T, NT>();
-        wide::k_update_batch<T, MM, RA, NT><<<tiles, NT, lds, s>>>(
-            d, n, nc, mu, par, kind == 0 ? 1 : 0, off);
+        const int hb = kind == 0 ? 1 : 0;
+        if (four_per_slot<MM, RA>(nc))
+            wide::k_update_batch<T, MM, RA, NT, 4><<<tiles, NT, lds, s>>>(d, n, nc, mu, par, hb, off);
+        else if constexpr (!MM && !RA)
+            wide::k_update_batch<T, MM, RA, NT, 2><<<tiles, NT, lds, s>>>(d, n, nc, mu, par, hb, off);
     }
     static void update_batch(const ChainDesc* d, int n, int tiles, int kind, int mu, int par, uint32_t off,
                              const Shape& shape, int nc, hipStream_t s) {

@@ -1,5 +1,5 @@
 // sun_pairs.hpp -- the order in which the large-Nc update runs its SU(2)
-// subgroup steps, two at a time (plain C++, evaluated at compile time).
+// subgroup steps, several at a time (plain C++, evaluated at compile time).
 //
 // The Cabibbo-Marinari update (Sec. 4) left-multiplies the link by one
 // SU(2) element per index pair (i, j), i < j, in the fixed order (0, 1),
@@ -8,10 +8,10 @@
 // in common therefore read and write disjoint entries and commute: any order
 // that keeps, for every index k, the order of the steps touching k gives
 // the same link bit for bit.  The table below is such an order in slots of
-// at most two steps, listed greedily -- each slot takes the two earliest
-// steps (in the fixed order) whose predecessors are all in earlier slots --
-// which takes ceil(S / 2) slots plus a short start-up, S = Nc (Nc - 1) / 2
-// (SU(32): 257 slots for 496 steps; SU(8): 17 for 28).
+// at most W steps, listed greedily -- each slot takes the W earliest steps
+// (in the fixed order) whose predecessors are all in earlier slots -- which
+// takes about S / W slots plus a short start-up, S = Nc (Nc - 1) / 2 (two
+// at a time, SU(32): 257 slots for 496 steps; four at a time: 139).
 #pragma once
 
 #include <cstdint>
@@ -20,16 +20,21 @@ namespace sun {
 namespace pairs {
 
 constexpr int kMaxN = 32;
-constexpr int kNone = 0xFF;                       // no second step in the slot
+constexpr int kNone = 0xFF;                       // no step in this place of the slot
+constexpr uint32_t kNoStep = 0xFFFFu;             // (kNone, kNone)
 constexpr int kMaxSteps = kMaxN * (kMaxN - 1) / 2;
-constexpr int kMaxSlotsTotal = 4096;              // over Nc = 2 .. 32 (2886 used)
+constexpr int kMaxWords = 3328;                   // over Nc = 2 .. 32 (two steps: 2886, four: 3294)
 
-// Slots of Nc: slot[first[Nc] .. first[Nc + 1]), each packed as
-// iA | jA << 8 | iB << 16 | jB << 24, with iB = jB = kNone when the slot holds
-// one step.  The first step of a slot precedes the second in the fixed order.
+// Slots of W steps each.  The slots of Nc are slots first[Nc] ..
+// first[Nc + 1] - 1; slot t holds W steps i | j << 8 (kNoStep for an empty
+// place), two to a 32-bit word: place m of slot t is half m mod 2 of word
+// t W / 2 + m / 2.  The places of a slot follow the fixed order, empty
+// places last.
+template <int W>
 struct Table {
+    static_assert(W == 2 || W == 4, "two or four steps per slot");
     uint16_t first[kMaxN + 2];
-    uint32_t slot[kMaxSlotsTotal];
+    uint32_t word[kMaxWords];
 };
 
 // Number of step (i, j) in the fixed order: the Philox counter of its draws.
@@ -37,7 +42,8 @@ constexpr uint32_t step_index(int n, int i, int j) {
     return (uint32_t)(i * n - i * (i + 1) / 2 + (j - i - 1));
 }
 
-constexpr void schedule(int n, Table& t, int& at) {
+template <int W>
+constexpr void schedule(int n, Table<W>& t, int& at) {
     int si[kMaxSteps] = {}, sj[kMaxSteps] = {};
     int npred[kMaxSteps] = {}, succ[kMaxSteps][2] = {};
     bool done[kMaxSteps] = {};
@@ -62,8 +68,8 @@ constexpr void schedule(int n, Table& t, int& at) {
         }
     int lo = 0, ndone = 0;
     while (ndone < S) {
-        int pick[2] = {-1, -1}, np = 0;
-        for (int s = lo; s < S && np < 2; ++s)
+        int pick[W] = {}, np = 0;
+        for (int s = lo; s < S && np < W; ++s)
             if (!done[s] && npred[s] == 0) pick[np++] = s;
         for (int e = 0; e < np; ++e) {
             const int s = pick[e];
@@ -73,24 +79,30 @@ constexpr void schedule(int n, Table& t, int& at) {
                 if (succ[s][f] >= 0) --npred[succ[s][f]];
         }
         while (lo < S && done[lo]) ++lo;
-        const uint32_t a = (uint32_t)si[pick[0]] | (uint32_t)sj[pick[0]] << 8;
-        const uint32_t b = np > 1 ? ((uint32_t)si[pick[1]] | (uint32_t)sj[pick[1]] << 8) : (kNone | kNone << 8);
-        t.slot[at++] = a | b << 16;
+        for (int w = 0; w < W / 2; ++w) {
+            uint32_t h[2] = {kNoStep, kNoStep};
+            for (int m = 0; m < 2; ++m)
+                if (2 * w + m < np) h[m] = (uint32_t)si[pick[2 * w + m]] | (uint32_t)sj[pick[2 * w + m]] << 8;
+            t.word[at * (W / 2) + w] = h[0] | h[1] << 16;
+        }
+        ++at;
     }
 }
 
-constexpr Table make_table() {
-    Table t{};
+template <int W>
+constexpr Table<W> make_table() {
+    Table<W> t{};
     int at = 0;
     for (int n = 0; n <= kMaxN; ++n) {
         t.first[n] = (uint16_t)at;
-        if (n >= 2) schedule(n, t, at);
+        if (n >= 2) schedule<W>(n, t, at);
     }
     t.first[kMaxN + 1] = (uint16_t)at;
     return t;
 }
 
-constexpr int slots(const Table& t, int n) { return t.first[n + 1] - t.first[n]; }
+template <int W>
+constexpr int slots(const Table<W>& t, int n) { return t.first[n + 1] - t.first[n]; }
 
 }  // namespace pairs
 }  // namespace sun

@@ -6,15 +6,15 @@
 // 2048 reals), so a workgroup of one wavefront (or two) owns one link: the
 // matrices of the update live in LDS, every product is spread over the lanes
 // element by element, and the SU(2) subgroup steps (Nc(Nc-1)/2 of them)
-// update two rows with one lane per column, two steps at a time.  Links are stored
+// update two rows with one lane per column, several steps at a time.  Links are stored
 // link-major (the Nc^2 complex entries of one link are contiguous), so the
 // workgroup reads a link with unit stride.  Operands that enter a product
 // daggered are transposed while they are copied into LDS, so that every
 // product reads one operand by broadcast and the other with unit stride.
 //
 // The arithmetic is that of the register kernels: the same closing staple,
-// W = U A, the lexicographic subgroup order (run two steps at a time where
-// they share no index, which gives the same bits: sun_pairs.hpp), the
+// W = U A, the lexicographic subgroup order (run several steps at a time
+// where they share no index, which gives the same bits: sun_pairs.hpp), the
 // quaternion projection, the same Philox counters, and an SU(2) draw whose
 // 64 attempts are evaluated one per lane, the first accepted one winning
 // (which is the sequential draw's result).  Reductions and re-unitarization
@@ -547,51 +547,75 @@ __device__ __forceinline__ DrawBatch<T> draw_batch(uint32_t k0, uint32_t k1, uin
 }
 
 // ---------------------------------------------------------------------------
-// The subgroup steps in slots of two (the order of pairs::make_table, which
-// gives the link of the fixed order bit for bit): in each slot lanes 0..31
-// run the first step and lanes 32..63 the second, each lane owning one
-// column of U and of W.  A batch then covers the eight subgroups of four
-// slots, lane group g drawing for member g mod 2 of slot g / 2.
+// The subgroup steps in slots of SW (the order of pairs::make_table, which
+// gives the link of the fixed order bit for bit): in each slot the lanes
+// 64 m / SW .. 64 (m + 1) / SW - 1 run place m, each lane owning columns of
+// U and of W.  A batch covers the eight subgroups of 8 / SW slots, lane
+// group g drawing for place g mod SW of slot g / SW; its eight steps are
+// four table words.  Four steps per slot from Nc = 10 (SU(32): 139 slots
+// instead of 257), where the shorter chain pays for four column updates
+// per lane; two below, where it does not (Nc = 5: 7 slots either way).
+// Every width gives the same bits.
 // ---------------------------------------------------------------------------
-static __constant__ pairs::Table kPairTable = pairs::make_table();
-constexpr int kSlotsPerBatch = kSgBatch / 2;
-constexpr pairs::Table kPairTableHost = pairs::make_table();
-// The slots of a link, 64 to a register across the wavefront (lane l holds
-// slot 64 w + l of window w), so that a step reads its pair with readlane.
-constexpr int kPairWindows = (pairs::slots(kPairTableHost, kNcMax) + kLanes - 1) / kLanes;
-static_assert(kLanes % kSlotsPerBatch == 0, "a batch's slots share a window");
-static_assert(kSlotsPerBatch == 4, "draw_pair_batch selects among four slots");
-constexpr uint32_t kNoSlot = 0xFFFFFFFFu;  // beyond the last slot: no steps
+constexpr int kSlot4MinN = 10;
+__host__ __device__ constexpr int slot_steps(int n) { return n >= kSlot4MinN ? 4 : 2; }
+template <int SW>
+struct SlotShape {
+    static constexpr int kStepLanes = kLanes / SW;                              // lanes per step
+    static constexpr int kStepCols = (kNcMax + kStepLanes - 1) / kStepLanes;     // columns per lane
+    static constexpr int kWords = SW / 2;                                        // table words per slot
+    static constexpr int kPerBatch = kSgBatch / SW;                              // slots per batch
+};
+constexpr int kBatchWords = kSgBatch / 2;
+static __constant__ pairs::Table<2> kPairTable2 = pairs::make_table<2>();
+static __constant__ pairs::Table<4> kPairTable4 = pairs::make_table<4>();
+constexpr pairs::Table<2> kPairTable2Host = pairs::make_table<2>();
+constexpr pairs::Table<4> kPairTable4Host = pairs::make_table<4>();
+// The table words of a link, 64 to a register across the wavefront (lane l
+// holds word 64 w + l of window w), so that a slot reads its steps with
+// readlane.
+constexpr int max_words() {
+    const int a = pairs::slots(kPairTable2Host, kNcMax), b = 2 * pairs::slots(kPairTable4Host, kNcMax);
+    return a > b ? a : b;
+}
+constexpr int kPairWindows = (max_words() + kLanes - 1) / kLanes;
+static_assert(kLanes % kBatchWords == 0, "a batch's words share a window");
+static_assert(kBatchWords == 4, "draw_pair_batch selects among four words");
+constexpr uint32_t kNoWord = 0xFFFFFFFFu;  // beyond the last slot: no steps
 
+template <int SW>
 __device__ __forceinline__ void pair_windows(int n, uint32_t (&win)[kPairWindows], int& nslot) {
-    const int f = kPairTable.first[n];
-    nslot = kPairTable.first[n + 1] - f;
+    const uint16_t* first = SW == 2 ? kPairTable2.first : kPairTable4.first;
+    const uint32_t* word = SW == 2 ? kPairTable2.word : kPairTable4.word;
+    constexpr int kw = SlotShape<SW>::kWords;
+    const int f = first[n] * kw;
+    nslot = first[n + 1] - first[n];
     const int l = (int)(threadIdx.x & (kLanes - 1));
 #pragma unroll
-    for (int w = 0; w < kPairWindows; ++w) win[w] = kLanes * w + l < nslot ? kPairTable.slot[f + kLanes * w + l] : kNoSlot;
+    for (int w = 0; w < kPairWindows; ++w) win[w] = kLanes * w + l < nslot * kw ? word[f + kLanes * w + l] : kNoWord;
 }
-// The next window to the front (after every 64 slots).
+// The next window to the front (after every 64 words).
 __device__ __forceinline__ void pair_windows_shift(uint32_t (&win)[kPairWindows]) {
 #pragma unroll
     for (int w = 0; w + 1 < kPairWindows; ++w) win[w] = win[w + 1];
-    win[kPairWindows - 1] = kNoSlot;
+    win[kPairWindows - 1] = kNoWord;
 }
 __device__ __forceinline__ uint32_t pair_at(uint32_t win0, int u) {
     return (uint32_t)__builtin_amdgcn_readlane((int)win0, u);
 }
-// Subgroup number (the Philox counter) of member m of a packed slot; 0 for
-// an absent member, whose draws go unused.
+// Subgroup number (the Philox counter) of half m of a table word; 0 for an
+// empty place, whose draws go unused.
 __device__ __forceinline__ uint32_t pair_sg(uint32_t e, int m, int n) {
     const int i = (int)((e >> (16 * m)) & 0xFF), j = (int)((e >> (16 * m + 8)) & 0xFF);
     return i == pairs::kNone ? 0u : pairs::step_index(n, i, j);
 }
-// The batch of the four slots u0 .. u0 + 3 of window win0.
+// The batch of the four table words u0 .. u0 + 3 of window win0.
 template <typename T>
 __device__ __forceinline__ DrawBatch<T> draw_pair_batch(uint32_t k0, uint32_t k1, uint32_t site, uint32_t step,
                                                         uint32_t mu_hi, uint32_t win0, int u0, int n, uint32_t l) {
-    uint32_t e[kSlotsPerBatch];
+    uint32_t e[kBatchWords];
 #pragma unroll
-    for (int q = 0; q < kSlotsPerBatch; ++q) e[q] = pair_at(win0, u0 + q);
+    for (int q = 0; q < kBatchWords; ++q) e[q] = pair_at(win0, u0 + q);
     auto sg_of = [&](uint32_t g) {
         const uint32_t q = g >> 1;
         const uint32_t es = q == 0 ? e[0] : q == 1 ? e[1] : q == 2 ? e[2] : e[3];
@@ -697,43 +721,51 @@ __device__ __forceinline__ int sample_su2_lanes(T alpha, const DrawBatch<T>& b, 
     return hit0 + first + 1;
 }
 
-// The draws of the two subgroups of slot q of a batch (lane groups 2q and
-// 2q + 1 hold their attempts), as sample_su2_lanes draws each: alpha is
-// the lane's own subgroup's (lanes 0..31: the first, 32..63: the second),
-// two whether the slot has a second subgroup, mu_sg0 and mu_sg1 their
-// counters.  Returns, for the lane's own subgroup, the accepted attempt's
-// number (0: skip the step), and its element in x.
-template <typename T>
-__device__ __forceinline__ int sample_su2_pair(T alpha, const DrawBatch<T>& b, int q, bool two, uint32_t k0,
-                                               uint32_t k1, uint32_t site, uint32_t step, uint32_t mu_sg0,
-                                               uint32_t mu_sg1, Quat<T>& x) {
+// The draws of the np subgroups of slot q of a batch (lane groups
+// kSlotSteps q + m hold the attempts of place m), as sample_su2_lanes draws
+// each: alpha is the lane's own step's (place lane / (64 / kSlotSteps)),
+// mu_sg the places' counters.  Returns, for the lane's own step, the accepted
+// attempt's number (0: skip the step), and its element in x.
+template <typename T, int kSlotSteps>
+__device__ __forceinline__ int sample_su2_slot(T alpha, const DrawBatch<T>& b, int q, int np, uint32_t k0,
+                                               uint32_t k1, uint32_t site, uint32_t step,
+                                               const uint32_t (&mu_sg)[kSlotSteps], Quat<T>& x) {
+    constexpr int kStepLanes = SlotShape<kSlotSteps>::kStepLanes;
     const int l = (int)threadIdx.x;
-    const T al0 = lane_value(alpha, 0);
-    const T al1 = two ? lane_value(alpha, kLanes / 2) : al0;
+    T alm[kSlotSteps];
+#pragma unroll
+    for (int m = 0; m < kSlotSteps; ++m) alm[m] = m < np ? lane_value(alpha, m * kStepLanes) : alm[0];
     // each lane tries its attempt with the alpha of the subgroup it draws for
-    const T al = ((l / kFirstHits) & 1) ? al1 : al0;
+    const int gm = (l / kFirstHits) % kSlotSteps;
+    T al = alm[0];
+#pragma unroll
+    for (int m = 1; m < kSlotSteps; ++m)
+        if (gm == m) al = alm[m];
     const bool creutz = al < Const<T>::switch_alpha;
     const T em = creutz ? d_expm1(T(-2) * al) : T(0);
     const T ia = chain_inverse(al);
     T x0 = T(1), rad = T(0);
     const bool ok = su2_attempt_batched(al, ia, creutz, em, b, x0, rad);
     const unsigned long long ball = __ballot(ok);
-    T mx0[2] = {T(1), T(1)}, mrad[2] = {T(0), T(0)};
-    int hit[2] = {0, 0};
+    T mx0[kSlotSteps], mrad[kSlotSteps];
+    int hit[kSlotSteps];
 #pragma unroll
-    for (int m = 0; m < 2; ++m) {
-        if (m == 1 && !two) break;
-        const int g = 2 * q + m;
+    for (int m = 0; m < kSlotSteps; ++m) {
+        mx0[m] = T(1);
+        mrad[m] = T(0);
+        hit[m] = 0;
+        if (m >= np) continue;
+        const int g = kSlotSteps * q + m;
         unsigned long long mask = ball & (0xFFull << (kFirstHits * g));
         int hit0 = -kFirstHits * g;
         T fx0 = x0, frad = rad;
         if (mask == 0ull) {  // the first eight attempts all rejected: attempts 8 .. 63, one per lane
-            const T a = m ? al1 : al0;
+            const T a = alm[m];
             const bool cr = a < Const<T>::switch_alpha;
             const T e2 = cr ? d_expm1(T(-2) * a) : T(0);
             const T i2 = chain_inverse(a);
             const uint32_t h = (uint32_t)l + kFirstHits;
-            const U4 r = philox(site, step, m ? mu_sg1 : mu_sg0, (RNG_ATTEMPT << 24) | h, k0, k1);
+            const U4 r = philox(site, step, mu_sg[m], (RNG_ATTEMPT << 24) | h, k0, k1);
             fx0 = T(1);
             frad = T(0);
             const bool ok2 = h < (uint32_t)kMaxAttempts && su2_attempt(a, i2, cr, e2, r, fx0, frad);
@@ -747,19 +779,32 @@ __device__ __forceinline__ int sample_su2_pair(T alpha, const DrawBatch<T>& b, i
             hit[m] = hit0 + first + 1;
         }
     }
-    // the lane's own subgroup; the direction of lane group g sits in the
-    // lanes l mod 8 = g (read at uniform lanes, then selected)
-    const bool m1 = two && l >= kLanes / 2;
-    const T cos_t = m1 ? lane_value(b.cos_t, 2 * q + 1) : lane_value(b.cos_t, 2 * q);
-    const T sin_t = m1 ? lane_value(b.sin_t, 2 * q + 1) : lane_value(b.sin_t, 2 * q);
-    const T cos_p = m1 ? lane_value(b.cos_p, 2 * q + 1) : lane_value(b.cos_p, 2 * q);
-    const T sin_p = m1 ? lane_value(b.sin_p, 2 * q + 1) : lane_value(b.sin_p, 2 * q);
-    const T r = m1 ? mrad[1] : mrad[0];
-    x.q[0] = m1 ? mx0[1] : mx0[0];
-    x.q[1] = r * sin_t * cos_p;
-    x.q[2] = r * sin_t * sin_p;
-    x.q[3] = r * cos_t;
-    return m1 ? hit[1] : hit[0];
+    // the lane's own step; the direction of lane group g sits in the lanes
+    // l mod 8 = g (read at uniform lanes, then selected)
+    const int mo = l / kStepLanes;
+    T x0o = mx0[0], ro = mrad[0];
+    int ho = hit[0];
+    T ct = lane_value(b.cos_t, kSlotSteps * q), st = lane_value(b.sin_t, kSlotSteps * q);
+    T cp = lane_value(b.cos_p, kSlotSteps * q), sp = lane_value(b.sin_p, kSlotSteps * q);
+#pragma unroll
+    for (int m = 1; m < kSlotSteps; ++m) {
+        const T ctm = lane_value(b.cos_t, kSlotSteps * q + m), stm = lane_value(b.sin_t, kSlotSteps * q + m);
+        const T cpm = lane_value(b.cos_p, kSlotSteps * q + m), spm = lane_value(b.sin_p, kSlotSteps * q + m);
+        if (mo == m && m < np) {
+            x0o = mx0[m];
+            ro = mrad[m];
+            ho = hit[m];
+            ct = ctm;
+            st = stm;
+            cp = cpm;
+            sp = spm;
+        }
+    }
+    x.q[0] = x0o;
+    x.q[1] = ro * st * cp;
+    x.q[2] = ro * st * sp;
+    x.q[3] = ro * ct;
+    return ho;
 }
 
 // Rows i, j of M (LDS), column c, left-multiplied by the 2x2 form of a,
@@ -789,7 +834,7 @@ __device__ __forceinline__ void rows_left_mul_col(T2<T>* M, int n, int i, int j,
 // bits), the first wavefront runs the subgroup steps, and in an FP64
 // heatbath the second draws their batches (below); LDS then also holds the
 // ring of two batches after the matrices (handoff_lds).
-template <typename T, bool MM, bool RA, int NT = kLanes>
+template <typename T, bool MM, bool RA, int NT, int SW>
 __device__ __forceinline__ void update_link_wide(T2<T>* __restrict__ U, const Geom& g, int n, int mu, int par,
                                                  int hb, T beta, uint32_t k0, uint32_t k1, uint32_t step, int h) {
     static_assert(NT == kLanes || NT == 2 * kLanes, "one wavefront or two");
@@ -856,18 +901,21 @@ __device__ __forceinline__ void update_link_wide(T2<T>* __restrict__ U, const Ge
     __syncthreads();
     // With two wavefronts the subgroup steps are the first's.  In an FP64
     // heatbath the second draws the batches (whose FP64 logarithms and
-    // cosines would otherwise sit on the chain every fourth slot): batch 0
-    // before the chain, batch b + 1 after barrier b, into slot (b + 1) mod 2
-    // of a ring after the matrices, which the first read (into registers)
-    // before barrier b.  The first takes barrier b at step slot 4 b, then
-    // reads ring slot b mod 2.  Both wavefronts pass the same ceil(S / 4)
-    // barriers, S the number of step slots.  (FP32 draws are cheap: there
-    // the first wavefront draws its own, as with one wavefront.)
+    // cosines would otherwise sit on the chain at the first step slot of
+    // each batch): batch 0 before the chain, batch b + 1 after barrier b,
+    // into slot (b + 1) mod 2 of a ring after the matrices, which the first
+    // read (into registers) before barrier b.  The first takes barrier b at
+    // step slot kSlotsPerBatch b, then reads ring slot b mod 2.  Both
+    // wavefronts pass the same ceil(S / kSlotsPerBatch) barriers, S the
+    // number of step slots.  (FP32 draws are cheap: there the first
+    // wavefront draws its own, as with one wavefront.)
     constexpr bool kHandOff = NT > kLanes && sizeof(T) == 8;
     T* const ring = reinterpret_cast<T*>(reinterpret_cast<char*>(smem_update) + (RA ? 2 : 3) * n2 * sizeof(T2<T>));
+    constexpr int kSlotSteps = SW, kStepLanes = SlotShape<SW>::kStepLanes, kStepCols = SlotShape<SW>::kStepCols;
+    constexpr int kSlotWords = SlotShape<SW>::kWords, kSlotsPerBatch = SlotShape<SW>::kPerBatch;
     uint32_t win[kPairWindows];
     int nslot = 0;
-    pair_windows(n, win, nslot);
+    pair_windows<SW>(n, win, nslot);
     const int nbatch = (nslot + kSlotsPerBatch - 1) / kSlotsPerBatch;
     if (NT > kLanes && threadIdx.x >= kLanes) {
         if (kHandOff && hb) {
@@ -876,11 +924,11 @@ __device__ __forceinline__ void update_link_wide(T2<T>* __restrict__ U, const Ge
             ring_store<T>(ring, 0, (int)l, draw_pair_batch<T>(k0, k1, (uint32_t)x.s, step, mh, win[0], 0, n, l));
             for (int b = 0; b < nbatch; ++b) {
                 __syncthreads();
-                const int t = kSlotsPerBatch * (b + 1);  // the next batch's first slot
+                const int wb = kBatchWords * (b + 1);  // the next batch's first table word
                 if (b + 1 < nbatch) {
-                    if ((t & (kLanes - 1)) == 0) pair_windows_shift(win);
+                    if ((wb & (kLanes - 1)) == 0) pair_windows_shift(win);
                     ring_store<T>(ring, (b + 1) & 1, (int)l,
-                                  draw_pair_batch<T>(k0, k1, (uint32_t)x.s, step, mh, win[0], t & (kLanes - 1), n, l));
+                                  draw_pair_batch<T>(k0, k1, (uint32_t)x.s, step, mh, win[0], wb & (kLanes - 1), n, l));
                 }
             }
         }
@@ -894,24 +942,43 @@ __device__ __forceinline__ void update_link_wide(T2<T>* __restrict__ U, const Ge
     const uint32_t mu_hi = (uint32_t)mu << 16;
     DrawBatch<T> batch{};
     const T cb = T(2) * beta / T(n);  // alpha = 2 beta k / n
-    // The slots are ordered by wave_lds_order; in each, lanes 0..31 run the
-    // slot's first step and lanes 32..63 its second, lane l owning column
-    // l mod 32 of U and of W and reading its entries of rows i and j together
-    // with the 2x2 block.
-    const int col = lane & 31;
-    const bool owner = col < n;
-    const int c = owner ? col : 0;
-    const bool upper = lane >= kLanes / 2;
+    // The slots are ordered by wave_lds_order; in each, lane l runs place
+    // l / kStepLanes, owning columns l mod kStepLanes + k kStepLanes of U and
+    // of W and reading its entries of rows i and j together with the 2x2
+    // block.  A slot's places are filled first, so place 0 always holds a
+    // step; the lanes of an empty place read that step's rows and write
+    // nothing.
+    const int place = lane / kStepLanes;
+    const int c0 = lane % kStepLanes;
     for (int t = 0; t < nslot; ++t) {
-        const int u = t & (kLanes - 1);
+        const int u = (t * kSlotWords) & (kLanes - 1);
         if (u == 0 && t > 0) pair_windows_shift(win);
-        const uint32_t e = pair_at(win[0], u);
-        const bool two = ((e >> 16) & 0xFF) != (uint32_t)pairs::kNone;
-        const bool mine = !upper || two;  // this half has a step
-        const uint32_t es = (upper && two) ? e >> 16 : e;
+        uint32_t wd[kSlotWords], stp[kSlotSteps];
+        int np = 0;
+#pragma unroll
+        for (int k = 0; k < kSlotWords; ++k) wd[k] = pair_at(win[0], u + k);
+#pragma unroll
+        for (int m = 0; m < kSlotSteps; ++m) {
+            stp[m] = (wd[m / 2] >> (16 * (m % 2))) & 0xFFFFu;
+            np += stp[m] != pairs::kNoStep;
+        }
+        uint32_t es = stp[0];
+#pragma unroll
+        for (int m = 1; m < kSlotSteps; ++m)
+            if (place == m && m < np) es = stp[m];
+        const bool mine = place < np;
         const int i = (int)(es & 0xFF), j = (int)((es >> 8) & 0xFF);
         const T2<T> wii = W[i * n + i], wij = W[i * n + j], wji = W[j * n + i], wjj = W[j * n + j];
-        const T2<T> ui = Us[i * n + c], uj = Us[j * n + c], xi = W[i * n + c], xj = W[j * n + c];
+        T2<T> ui[kStepCols], uj[kStepCols], xi[kStepCols], xj[kStepCols];
+#pragma unroll
+        for (int cc = 0; cc < kStepCols; ++cc) {
+            const int ck = c0 + cc * kStepLanes;
+            const int c = ck < n ? ck : 0;
+            ui[cc] = Us[i * n + c];
+            uj[cc] = Us[j * n + c];
+            xi[cc] = W[i * n + c];
+            xj[cc] = W[j * n + c];
+        }
         Quat<T> p;
         p.q[0] = T(0.5) * (wii.x + wjj.x);
         p.q[3] = T(0.5) * (wii.y - wjj.y);
@@ -932,17 +999,25 @@ __device__ __forceinline__ void update_link_wide(T2<T>* __restrict__ U, const Ge
                 }
             }
             const T alpha = cb * k;
+            uint32_t sgs[kSlotSteps];
+#pragma unroll
+            for (int m = 0; m < kSlotSteps; ++m) sgs[m] = mu_hi | pair_sg(wd[m / 2], m % 2, n);
             Quat<T> xs;
-            apply = sample_su2_pair<T>(alpha, batch, q, two, k0, k1, (uint32_t)x.s, step, mu_hi | pair_sg(e, 0, n),
-                                       mu_hi | pair_sg(e, 1, n), xs) != 0;
+            apply = sample_su2_slot<T, SW>(alpha, batch, q, np, k0, k1, (uint32_t)x.s, step, sgs, xs) != 0;
             if (apply) a = qmul(xs, qconj(v));
         } else {
             const Quat<T> vc = qconj(v);
             a = qmul(vc, vc);
         }
-        if (apply && owner && mine) {
-            rows_left_mul_col<T>(Us, n, i, j, c, a, ui, uj);
-            rows_left_mul_col<T>(W, n, i, j, c, a, xi, xj);
+        if (apply && mine) {
+#pragma unroll
+            for (int cc = 0; cc < kStepCols; ++cc) {
+                const int ck = c0 + cc * kStepLanes;
+                if (ck < n) {
+                    rows_left_mul_col<T>(Us, n, i, j, ck, a, ui[cc], uj[cc]);
+                    rows_left_mul_col<T>(W, n, i, j, ck, a, xi[cc], xj[cc]);
+                }
+            }
         }
         wave_lds_order();
     }
@@ -952,23 +1027,23 @@ __device__ __forceinline__ void update_link_wide(T2<T>* __restrict__ U, const Ge
 }
 
 // One checkerboard phase of one lattice: workgroup h updates link h.
-template <typename T, bool MM, bool RA, int NT>
+template <typename T, bool MM, bool RA, int NT, int SW>
 __global__ __launch_bounds__(NT, 2) void k_update(T2<T>* __restrict__ U, Geom g, int n, int mu, int par, int hb,
                                                T beta, uint32_t k0, uint32_t k1, uint32_t step) {
-    update_link_wide<T, MM, RA, NT>(U, g, n, mu, par, hb, beta, k0, k1, step, (int)blockIdx.x);
+    update_link_wide<T, MM, RA, NT, SW>(U, g, n, mu, par, hb, beta, k0, k1, step, (int)blockIdx.x);
 }
 
 // One phase of every chain of a batch group (same Nc and precision): one
 // workgroup per updated link of each chain, the chain found by binary search
 // over the first-link prefix of the descriptor table (TILE_HALF_HB counts
 // links here); coupling, Philox key and RNG step come from the table.
-template <typename T, bool MM, bool RA, int NT>
+template <typename T, bool MM, bool RA, int NT, int SW>
 __global__ __launch_bounds__(NT, 2) void k_update_batch(const ChainDesc* __restrict__ d, int nchains, int n,
                                                      int mu, int par, int hb, uint32_t step_offset) {
     const int c = find_chain<TILE_HALF_HB>(d, nchains, (int)blockIdx.x);
     const Geom g = d[c].g;
     if (!((g.present >> mu) & 1)) return;
-    update_link_wide<T, MM, RA, NT>((T2<T>*)d[c].links, g, n, mu, par, hb, (T)d[c].beta, d[c].k0, d[c].k1,
+    update_link_wide<T, MM, RA, NT, SW>((T2<T>*)d[c].links, g, n, mu, par, hb, (T)d[c].beta, d[c].k0, d[c].k1,
                                 (uint32_t)(d[c].step + step_offset), (int)blockIdx.x - d[c].tile0[TILE_HALF_HB]);
 }
 

@@ -1,11 +1,12 @@
 """The order in which the large-Nc update runs its SU(2) subgroup steps, two
-at a time (sun_pairs.hpp), checked on the host: the table is compiled with
-the host compiler from the same header the kernels use and printed.
+or four at a time (sun_pairs.hpp), checked on the host: the tables are
+compiled with the host compiler from the same header the kernels use and
+printed.
 
 Sec. 4's update left-multiplies the link by one SU(2) element per index pair
 (i, j), i < j, in the fixed order; step (i, j) reads the 2x2 block (i, j) of
 W = U A and rewrites rows i and j of U and W.  A slot may therefore hold
-two steps only if they share no index, and the steps touching any one
+several steps only if no two share an index, and the steps touching any one
 index must keep their fixed order; then the link is the same bit for bit,
 which the last test checks by running both orders on random data."""
 import os
@@ -22,13 +23,19 @@ NONE = 0xFF
 PROGRAM = r"""
 #include "sun_pairs.hpp"
 #include <cstdio>
-constexpr sun::pairs::Table kT = sun::pairs::make_table();
-int main() {
+constexpr sun::pairs::Table<2> kT2 = sun::pairs::make_table<2>();
+constexpr sun::pairs::Table<4> kT4 = sun::pairs::make_table<4>();
+template <int W>
+void dump(const sun::pairs::Table<W>& t) {
     for (int n = 2; n <= sun::pairs::kMaxN; ++n) {
-        printf("%d", n);
-        for (int s = kT.first[n]; s < kT.first[n + 1]; ++s) printf(" %u", kT.slot[s]);
+        printf("%d %d", W, n);
+        for (int s = t.first[n] * (W / 2); s < t.first[n + 1] * (W / 2); ++s) printf(" %u", t.word[s]);
         printf("\n");
     }
+}
+int main() {
+    dump(kT2);
+    dump(kT4);
     for (int n = 2; n <= sun::pairs::kMaxN; ++n)
         for (int i = 0; i < n; ++i)
             for (int j = i + 1; j < n; ++j) printf("%u ", sun::pairs::step_index(n, i, j));
@@ -48,10 +55,15 @@ def table(tmp_path_factory):
     subprocess.run([gxx, "-std=c++17", "-O1", f"-I{os.path.dirname(HEADER)}", str(src), "-o", str(exe)],
                    check=True, capture_output=True)
     lines = subprocess.run([str(exe)], check=True, capture_output=True, text=True).stdout.strip().split("\n")
-    slots = {}
+    slots = {2: {}, 4: {}}
     for ln in lines[:-1]:
         v = [int(x) for x in ln.split()]
-        slots[v[0]] = [(e & 0xFF, (e >> 8) & 0xFF, (e >> 16) & 0xFF, e >> 24) for e in v[1:]]
+        w, n, words = v[0], v[1], v[2:]
+        places = []
+        for e in words:
+            places += [e & 0xFFFF, e >> 16]
+        # slot t: places t W .. t W + W - 1, each i | j << 8 (0xFFFF: empty)
+        slots[w][n] = [tuple(places[t:t + w]) for t in range(0, len(places), w)]
     return slots, [int(x) for x in lines[-1].split()]
 
 
@@ -60,38 +72,45 @@ def fixed_order(n):
 
 
 def steps_of(slot):
-    iA, jA, iB, jB = slot
-    out = [(iA, jA)]
-    if iB != NONE:
-        assert jB != NONE
-        out.append((iB, jB))
-    else:
-        assert jB == NONE
+    """The steps of a slot: its places up to the first empty one, after
+    which every place is empty."""
+    out = []
+    for k, e in enumerate(slot):
+        if e == 0xFFFF:
+            assert all(f == 0xFFFF for f in slot[k:]), slot
+            break
+        i, j = e & 0xFF, e >> 8
+        assert i != NONE and j != NONE
+        out.append((i, j))
+    assert out, "place 0 always holds a step"
     return out
 
 
-def test_every_step_once_and_slots_of_disjoint_pairs(table):
+@pytest.mark.parametrize("w", [2, 4])
+def test_every_step_once_and_slots_of_disjoint_steps(table, w):
     slots, _ = table
     for n in range(2, 33):
         seen = []
-        for sl in slots[n]:
+        for sl in slots[w][n]:
             st = steps_of(sl)
-            if len(st) == 2:
-                assert not set(st[0]) & set(st[1]), (n, st)
+            idx = [k for s in st for k in s]
+            assert len(set(idx)) == len(idx), (n, st)
             seen += st
         assert sorted(seen) == fixed_order(n), n
 
 
-def test_the_steps_on_each_index_keep_the_fixed_order(table):
+@pytest.mark.parametrize("w", [2, 4])
+def test_the_steps_on_each_index_keep_the_fixed_order(table, w):
     slots, _ = table
     for n in range(2, 33):
         order = {s: k for k, s in enumerate(fixed_order(n))}
         pos = {}
-        for t, sl in enumerate(slots[n]):
-            for s in steps_of(sl):
+        for t, sl in enumerate(slots[w][n]):
+            st = steps_of(sl)
+            for s in st:
                 pos[s] = t
-            if sl[2] != NONE:  # the first of a slot precedes the second
-                assert order[sl[:2]] < order[sl[2:]], (n, sl)
+            ks = [order[s] for s in st]  # the places follow the fixed order
+            assert ks == sorted(ks), (n, sl)
         for k in range(n):
             touching = [s for s in fixed_order(n) if k in s]
             ts = [pos[s] for s in touching]
@@ -99,13 +118,16 @@ def test_the_steps_on_each_index_keep_the_fixed_order(table):
 
 
 def test_slot_counts(table):
-    """Greedy two at a time: ceil(S / 2) plus a short start-up (the first
-    steps all touch index 0); SU(32) runs its 496 steps in 257 slots."""
+    """Greedy W at a time: about S / W slots plus a short start-up (the first
+    steps all touch index 0); SU(32) runs its 496 steps in 257 slots of two
+    or 139 of four."""
     slots, _ = table
-    for n in range(2, 33):
-        S = n * (n - 1) // 2
-        assert (S + 1) // 2 <= len(slots[n]) <= (S + 1) // 2 + n, n
-    assert len(slots[32]) == 257 and len(slots[8]) == 17 and len(slots[3]) == 3
+    for w in (2, 4):
+        for n in range(2, 33):
+            S = n * (n - 1) // 2
+            assert -(-S // w) <= len(slots[w][n]) <= -(-S // w) + 2 * n, (w, n)
+    assert len(slots[2][32]) == 257 and len(slots[2][8]) == 17 and len(slots[2][3]) == 3
+    assert len(slots[4][32]) == 139 and len(slots[4][8]) == 13 and len(slots[4][5]) == 7
 
 
 def test_step_index_is_the_position_in_the_fixed_order(table):
@@ -122,8 +144,9 @@ def _left_mul_rows(M, i, j, a):
     M[j] = a[1, 0] * r_i + a[1, 1] * r_j
 
 
+@pytest.mark.parametrize("w", [2, 4])
 @pytest.mark.parametrize("n", [4, 5, 8, 13, 32])
-def test_slot_order_gives_the_fixed_order_link_bit_for_bit(table, n):
+def test_slot_order_gives_the_fixed_order_link_bit_for_bit(table, n, w):
     """Each step's 2x2 factor is a function of the block (i, j) of W it reads
     (here the normalised projection plus a per-step constant), as in the
     update; the slot order must reproduce the fixed order exactly."""
@@ -148,7 +171,7 @@ def test_slot_order_gives_the_fixed_order_link_bit_for_bit(table, n):
     for i, j in fixed_order(n):
         step(U1, W1, i, j)
     U2, W2 = U0.copy(), U0 @ A
-    for sl in slots[n]:
+    for sl in slots[w][n]:
         for i, j in steps_of(sl):
             step(U2, W2, i, j)
     assert np.isfinite(U1).all() and not np.allclose(U1, U0)
