@@ -443,9 +443,9 @@ __device__ __forceinline__ double lane_value(double v, int lane) {
 }
 
 // The scalar steps of the subgroup chain -- the block's norm and its
-// inverse, 1 / alpha, the draw's square roots -- are computed by every lane
-// for the whole link, one step after another, so their latency is the
-// chain's; the correctly rounded sequences take a dozen dependent
+// inverse, 1 / alpha, the draw's square roots -- are computed by the lanes
+// of a step for the whole link, one slot after another, so their latency is
+// the chain's; the correctly rounded sequences take a dozen dependent
 // instructions each.  FP32 takes the hardware forms shared with the
 // register path (fast_sqrt, fast_inverse, unit_quat: about 1 ulp each); FP64
 // here takes the hardware reciprocal and reciprocal square root refined by
