@@ -16,17 +16,24 @@ struct OpsWide {
     static bool four_per_slot(int nc) {
         return MM || RA || wide::slot_steps(nc) == 4;
     }
+    // The second of two wavefronts draws the heatbath batches where the ring
+    // it hands them over in keeps the workgroups a CU holds (wide_handoff).
+    template <int NT>
+    static bool hand_off(int nc) {
+        return NT > wide::kLanes && wide_handoff(nc, f64, wide::batch_ring_bytes<T>());
+    }
     template <bool MM, bool RA, int NT>
     static void update_as(const Ctx& c, int kind, int mu, int par, double beta, uint32_t k0, uint32_t k1,
                           uint32_t step) {
-        const size_t lds = wide_update_lds(c.nc, f64) + wide::handoff_lds<T, NT>();
+        const bool ho = hand_off<NT>(c.nc);
+        const size_t lds = wide_update_lds(c.nc, f64) + wide::handoff_lds<T>(ho);
         const int hb = kind == 0 ? 1 : 0;
         if (four_per_slot<MM, RA>(c.nc))
             wide::k_update<T, MM, RA, NT, 4><<<c.g.Vh, NT, lds, c.stream>>>((P*)c.links, c.g, c.nc, mu, par, hb,
-                                                                            (T)beta, k0, k1, step);
+                                                                            (T)beta, k0, k1, step, ho);
         else if constexpr (!MM && !RA)
             wide::k_update<T, MM, RA, NT, 2><<<c.g.Vh, NT, lds, c.stream>>>((P*)c.links, c.g, c.nc, mu, par, hb,
-                                                                            (T)beta, k0, k1, step);
+                                                                            (T)beta, k0, k1, step, ho);
     }
     // Threads per workgroup: a launch shape's block of 64 or 128 asks for one
     // or two wavefronts; any other block (the default 256) takes
@@ -110,12 +117,13 @@ struct OpsWide {
     template <bool MM, bool RA, int NT>
     static void update_batch_as(const ChainDesc* d, int n, int tiles, int kind, int mu, int par, uint32_t off, int nc,
                                 hipStream_t s) {
-        const size_t lds = wide_update_lds(nc, f64) + wide::handoff_lds<T, NT>();
+        const bool ho = hand_off<NT>(nc);
+        const size_t lds = wide_update_lds(nc, f64) + wide::handoff_lds<T>(ho);
         const int hb = kind == 0 ? 1 : 0;
         if (four_per_slot<MM, RA>(nc))
-            wide::k_update_batch<T, MM, RA, NT, 4><<<tiles, NT, lds, s>>>(d, n, nc, mu, par, hb, off);
+            wide::k_update_batch<T, MM, RA, NT, 4><<<tiles, NT, lds, s>>>(d, n, nc, mu, par, hb, off, ho);
         else if constexpr (!MM && !RA)
-            wide::k_update_batch<T, MM, RA, NT, 2><<<tiles, NT, lds, s>>>(d, n, nc, mu, par, hb, off);
+            wide::k_update_batch<T, MM, RA, NT, 2><<<tiles, NT, lds, s>>>(d, n, nc, mu, par, hb, off, ho);
     }
     static void update_batch(const ChainDesc* d, int n, int tiles, int kind, int mu, int par, uint32_t off,
                              const Shape& shape, int nc, hipStream_t s) {

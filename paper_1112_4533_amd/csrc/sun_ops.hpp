@@ -151,8 +151,9 @@ const Ops* ops_wide(int f64);         // 4 <= Nc <= 32: one workgroup per link, 
 constexpr size_t kWideLdsMax = 64 * 1024;
 inline bool wide_update_regacc(int nc, int f64) { return (size_t)3 * nc * nc * (f64 ? 16 : 8) > kLdsPerCu / 8; }
 // Threads of a large-Nc update workgroup: two wavefronts (the loads and
-// vector-unit products shared, the subgroup steps on the first, and in an
-// FP64 heatbath the draws on the second) where that measured faster on 8^4
+// vector-unit products shared, the subgroup steps on the first, and the
+// heatbath draws on the second where wide_handoff allows) where that
+// measured faster on 8^4
 // -- FP32 from Nc = 9 (5-9% per iteration up to Nc = 20; above, where the
 // matrix-core products stay on the first wavefront and only the loads are
 // shared, 2% -- the overrelaxation 6%; below Nc = 9 the second wavefront
@@ -165,6 +166,15 @@ inline int wide_update_threads(int nc, int f64) {
 }
 inline size_t wide_update_lds(int nc, int f64) {
     return (size_t)(wide_update_regacc(nc, f64) ? 2 : 3) * nc * nc * (f64 ? 16 : 8);
+}
+// Whether the second of two wavefronts draws the heatbath batches for the
+// first (through a ring of ring_bytes in LDS): always in FP64, whose draws
+// (FP64 logarithms and cosines) are costly; in FP32 where the ring still
+// leaves the 8 workgroups per CU a phase at 8^4 needs for one round (the
+// chain gains 2-4% from Nc = 9 to 24 and at 32; at Nc = 28 the ring would
+// cost the second round: 5.6 -> 7.8 ms).
+inline bool wide_handoff(int nc, int f64, size_t ring_bytes) {
+    return f64 || wide_update_lds(nc, f64) + ring_bytes <= (size_t)kLdsPerCu / 8;
 }
 
 void launch_finalize_max2(const double* partial, int nblk, double* out, hipStream_t s);

@@ -632,10 +632,10 @@ __host__ __device__ inline size_t batch_ring_bytes() {
     return (size_t)2 * kBatchFields * kLanes * sizeof(T);
 }
 // Dynamic LDS of an update launch beyond its matrices: the ring, where the
-// second of two wavefronts draws the FP64 heatbath batches.
-template <typename T, int NT>
-__host__ __device__ inline size_t handoff_lds() {
-    return (NT > kLanes && sizeof(T) == 8) ? batch_ring_bytes<T>() : 0;
+// second of two wavefronts draws the heatbath batches (ho: hand-off on).
+template <typename T>
+__host__ __device__ inline size_t handoff_lds(bool ho) {
+    return ho ? batch_ring_bytes<T>() : 0;
 }
 template <typename T>
 __device__ __forceinline__ void ring_store(T* ring, int slot, int l, const DrawBatch<T>& b) {
@@ -831,12 +831,13 @@ __device__ __forceinline__ void rows_left_mul_col(T2<T>* M, int n, int i, int j,
 // leave one.
 // NT: threads per workgroup, one wavefront or two.  With two, the loads and
 // the vector-unit products are shared by both wavefronts (RowMap: the same
-// bits), the first wavefront runs the subgroup steps, and in an FP64
-// heatbath the second draws their batches (below); LDS then also holds the
-// ring of two batches after the matrices (handoff_lds).
+// bits), the first wavefront runs the subgroup steps, and with ho the
+// second draws their heatbath batches (below); LDS then also holds the ring
+// of two batches after the matrices (handoff_lds).
 template <typename T, bool MM, bool RA, int NT, int SW>
 __device__ __forceinline__ void update_link_wide(T2<T>* __restrict__ U, const Geom& g, int n, int mu, int par,
-                                                 int hb, T beta, uint32_t k0, uint32_t k1, uint32_t step, int h) {
+                                                 int hb, T beta, uint32_t k0, uint32_t k1, uint32_t step, int h,
+                                                 bool ho) {
     static_assert(NT == kLanes || NT == 2 * kLanes, "one wavefront or two");
     extern __shared__ double4 smem_update[];
     const int n2 = n * n;
@@ -899,17 +900,19 @@ __device__ __forceinline__ void update_link_wide(T2<T>* __restrict__ U, const Ge
         lds_mm<T, MM, 4, NT>(W, Us, A, n, false);
     }
     __syncthreads();
-    // With two wavefronts the subgroup steps are the first's.  In an FP64
-    // heatbath the second draws the batches (whose FP64 logarithms and
-    // cosines would otherwise sit on the chain at the first step slot of
-    // each batch): batch 0 before the chain, batch b + 1 after barrier b,
+    // With two wavefronts the subgroup steps are the first's.  With the
+    // hand-off the second draws the heatbath batches (whose Philox passes,
+    // logarithms and cosines would otherwise sit on the chain at the first
+    // step slot of each batch): batch 0 before the chain, batch b + 1 after barrier b,
     // into slot (b + 1) mod 2 of a ring after the matrices, which the first
     // read (into registers) before barrier b.  The first takes barrier b at
     // step slot kSlotsPerBatch b, then reads ring slot b mod 2.  Both
     // wavefronts pass the same ceil(S / kSlotsPerBatch) barriers, S the
-    // number of step slots.  (FP32 draws are cheap: there the first
-    // wavefront draws its own, as with one wavefront.)
-    constexpr bool kHandOff = NT > kLanes && sizeof(T) == 8;
+    // number of step slots.  Without it the first wavefront draws its own,
+    // as with one wavefront.  FP64 always hands off with two wavefronts
+    // (decided at compile time: keeping both draw paths in the FP64 kernel
+    // costs it 3-4%); FP32 as ho says.
+    const bool hand_off = NT > kLanes && (sizeof(T) == 8 || ho);
     T* const ring = reinterpret_cast<T*>(reinterpret_cast<char*>(smem_update) + (RA ? 2 : 3) * n2 * sizeof(T2<T>));
     constexpr int kSlotSteps = SW, kStepLanes = SlotShape<SW>::kStepLanes, kStepCols = SlotShape<SW>::kStepCols;
     constexpr int kSlotWords = SlotShape<SW>::kWords, kSlotsPerBatch = SlotShape<SW>::kPerBatch;
@@ -918,7 +921,7 @@ __device__ __forceinline__ void update_link_wide(T2<T>* __restrict__ U, const Ge
     pair_windows<SW>(n, win, nslot);
     const int nbatch = (nslot + kSlotsPerBatch - 1) / kSlotsPerBatch;
     if (NT > kLanes && threadIdx.x >= kLanes) {
-        if (kHandOff && hb) {
+        if (hand_off && hb) {
             const uint32_t l = threadIdx.x - kLanes;
             const uint32_t mh = (uint32_t)mu << 16;
             ring_store<T>(ring, 0, (int)l, draw_pair_batch<T>(k0, k1, (uint32_t)x.s, step, mh, win[0], 0, n, l));
@@ -991,7 +994,7 @@ __device__ __forceinline__ void update_link_wide(T2<T>* __restrict__ U, const Ge
         if (hb) {
             const int q = t % kSlotsPerBatch;
             if (q == 0) {
-                if constexpr (kHandOff) {
+                if (hand_off) {
                     __syncthreads();
                     batch = ring_load<T>(ring, (t / kSlotsPerBatch) & 1, lane);
                 } else {
@@ -1029,8 +1032,8 @@ __device__ __forceinline__ void update_link_wide(T2<T>* __restrict__ U, const Ge
 // One checkerboard phase of one lattice: workgroup h updates link h.
 template <typename T, bool MM, bool RA, int NT, int SW>
 __global__ __launch_bounds__(NT, 2) void k_update(T2<T>* __restrict__ U, Geom g, int n, int mu, int par, int hb,
-                                               T beta, uint32_t k0, uint32_t k1, uint32_t step) {
-    update_link_wide<T, MM, RA, NT, SW>(U, g, n, mu, par, hb, beta, k0, k1, step, (int)blockIdx.x);
+                                               T beta, uint32_t k0, uint32_t k1, uint32_t step, int ho) {
+    update_link_wide<T, MM, RA, NT, SW>(U, g, n, mu, par, hb, beta, k0, k1, step, (int)blockIdx.x, ho != 0);
 }
 
 // One phase of every chain of a batch group (same Nc and precision): one
@@ -1039,12 +1042,13 @@ __global__ __launch_bounds__(NT, 2) void k_update(T2<T>* __restrict__ U, Geom g,
 // links here); coupling, Philox key and RNG step come from the table.
 template <typename T, bool MM, bool RA, int NT, int SW>
 __global__ __launch_bounds__(NT, 2) void k_update_batch(const ChainDesc* __restrict__ d, int nchains, int n,
-                                                     int mu, int par, int hb, uint32_t step_offset) {
+                                                     int mu, int par, int hb, uint32_t step_offset, int ho) {
     const int c = find_chain<TILE_HALF_HB>(d, nchains, (int)blockIdx.x);
     const Geom g = d[c].g;
     if (!((g.present >> mu) & 1)) return;
     update_link_wide<T, MM, RA, NT, SW>((T2<T>*)d[c].links, g, n, mu, par, hb, (T)d[c].beta, d[c].k0, d[c].k1,
-                                (uint32_t)(d[c].step + step_offset), (int)blockIdx.x - d[c].tile0[TILE_HALF_HB]);
+                                (uint32_t)(d[c].step + step_offset), (int)blockIdx.x - d[c].tile0[TILE_HALF_HB],
+                                ho != 0);
 }
 
 // ---------------------------------------------------------------------------
