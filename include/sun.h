@@ -58,15 +58,17 @@ enum {
  * Nc <= SUN_NC_MAX_REGISTER runs one link per work-item with the link
  * matrices in registers and the field split into planes by (direction,
  * parity, matrix entry).  Larger Nc (the paper's generic SU(Nc) code, Sec. 4:
- * up to 32 in single and 16 in double precision at 8^4) runs one 64-lane
- * workgroup per link, matrices in LDS and the entries of each link
- * contiguous in memory; SUN_F32 and SUN_F64 select it by themselves there,
- * and the WIDE codes select it at Nc = 4 too (for comparisons with the
- * register path).  Its update keeps 3 Nc^2 complex entries in LDS (48 KiB
- * at Nc = 32 in FP64).  Of a launch shape only the block size applies to
- * it: 64 runs each link's update on one wavefront, 128 on two (the link
- * loads and the vector-unit products shared, the subgroup steps on the
- * first; the same bits either way; in the FP32 matrix-core form above
+ * up to 32 in single and 16 in double precision at 8^4) runs one workgroup
+ * of one or two wavefronts per link, matrices in LDS and the entries of each
+ * link contiguous in memory; SUN_F32 and SUN_F64 select it by themselves
+ * there, and the WIDE codes select it at Nc = 4 too (for comparisons with
+ * the register path).  Its update keeps three or, at large Nc, two Nc^2
+ * complex matrices in LDS (32 KiB at Nc = 32 in FP64), plus a ring of
+ * heatbath draws when two wavefronts share it.  Of a launch shape only the
+ * block size applies to it: 64 runs each link's update on one wavefront,
+ * 128 on two (the link loads and the vector-unit products shared, the
+ * subgroup steps on the first and, where LDS allows, the heatbath draws on
+ * the second; the same bits either way; in the FP32 matrix-core form above
  * Nc = 20 the products stay on the first), and any other block, the default
  * 256 included, picks by Nc and precision. */
 enum {
