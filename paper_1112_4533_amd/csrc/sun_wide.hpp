@@ -1157,10 +1157,12 @@ __device__ __forceinline__ double lds_unitarity_dev(const double2* M, int n) {
 
 // Gram-Schmidt on all rows, then the last row times conj(det)/|det| (paper
 // Sec. 2, re-unitarization; Nc > 3).  Each row is orthogonalized against the
-// earlier ones by classical Gram-Schmidt applied twice (as stable as the
-// modified form): lane k forms <r_k, r_i> from LDS, then lane c subtracts
-// every projection from column c of r_i, so a row costs two LDS hand-offs per
-// pass instead of a chain of wave reductions per projection.  P (n entries)
+// earlier ones by classical Gram-Schmidt, with a second pass where the
+// first removed more than half the row's squared norm (Daniel, Gragg,
+// Kaufman and Stewart, Math. Comp. 30 (1976): twice is enough, as stable as
+// the modified form): lane k forms <r_k, r_i> from LDS, then lane c
+// subtracts every projection from column c of r_i, so a row costs two LDS
+// hand-offs per pass instead of a chain of wave reductions per projection.  P (n entries)
 // holds the projections.  (dr, di) is det M of the matrix before the
 // projection: row Gram-Schmidt writes M = L Q with L lower triangular and
 // real positive on its diagonal, so det Q = det M / prod L_ii has the phase
@@ -1175,51 +1177,71 @@ __device__ __forceinline__ void lds_reunit(double2* M, double2* P, int n, double
     const int q = lane & 31, half = lane >> 5;
     const int m0 = split ? n / 2 : n;                    // columns of the lower half
     const int cbeg = half ? m0 : 0, clen = half ? n - m0 : m0;
-    for (int i = 0; i < n; ++i) {
-        for (int pass = 0; pass < 2 && i > 0; ++pass) {
-            // p_q = <r_q, r_i> for q < i; columns taken from a lane-dependent
-            // start within the half's range, so lanes hit different banks
-            double pr = 0.0, pi = 0.0;
-            if (q < i && clen > 0) {
-                int t = q % clen;
-#pragma unroll 4
-                for (int u = 0; u < clen; ++u) {
-                    const int c = cbeg + t;
-                    const double2 a = M[q * n + c], b = M[i * n + c];
-                    cmac(pr, pi, a.x, -a.y, b.x, b.y);
-                    t = (t + 1 == clen) ? 0 : t + 1;
-                }
-            }
-            if (split) {
-                pr += partner<5>(pr);
-                pi += partner<5>(pi);
-            }
-            if (q < i && half == 0) P[q] = make_double2(pr, pi);
-            wave_lds_order();
-            // r_i -= sum_{k < i} p_k r_k, the k range split between the halves
-            double sr = 0.0, si = 0.0;
-            if (q < n) {
-                const int kmid = split ? i / 2 : i;
-                const int kb = half ? kmid : 0, ke = half ? i : kmid;
-#pragma unroll 4
-                for (int k = kb; k < ke; ++k) {
-                    const double2 p = P[k], a = M[k * n + q];
-                    cmac(sr, si, p.x, p.y, a.x, a.y);
-                }
-            }
-            if (split) {
-                sr += partner<5>(sr);
-                si += partner<5>(si);
-            }
-            if (own) {
-                const double2 b = M[i * n + lane];
-                M[i * n + lane] = make_double2(b.x - sr, b.y - si);
-            }
-            wave_lds_order();
-        }
+    // |r_i|^2, the same value on every lane
+    auto row_norm2 = [&](int i) {
         double s = 0.0;
         if (own) s = fmadd(M[i * n + lane].y, M[i * n + lane].y, M[i * n + lane].x * M[i * n + lane].x);
-        const double s2 = wave_sum(s);
+        return wave_sum(s);
+    };
+    // one classical pass: r_i -= sum_{k < i} <r_k, r_i> r_k
+    auto project = [&](int i) {
+        // p_q = <r_q, r_i> for q < i; columns taken from a lane-dependent
+        // start within the half's range, so lanes hit different banks
+        double pr = 0.0, pi = 0.0;
+        if (q < i && clen > 0) {
+            int t = q % clen;
+#pragma unroll 4
+            for (int u = 0; u < clen; ++u) {
+                const int c = cbeg + t;
+                const double2 a = M[q * n + c], b = M[i * n + c];
+                cmac(pr, pi, a.x, -a.y, b.x, b.y);
+                t = (t + 1 == clen) ? 0 : t + 1;
+            }
+        }
+        if (split) {
+            pr += partner<5>(pr);
+            pi += partner<5>(pi);
+        }
+        if (q < i && half == 0) P[q] = make_double2(pr, pi);
+        wave_lds_order();
+        // r_i -= sum_{k < i} p_k r_k, the k range split between the halves
+        double sr = 0.0, si = 0.0;
+        if (q < n) {
+            const int kmid = split ? i / 2 : i;
+            const int kb = half ? kmid : 0, ke = half ? i : kmid;
+#pragma unroll 4
+            for (int k = kb; k < ke; ++k) {
+                const double2 p = P[k], a = M[k * n + q];
+                cmac(sr, si, p.x, p.y, a.x, a.y);
+            }
+        }
+        if (split) {
+            sr += partner<5>(sr);
+            si += partner<5>(si);
+        }
+        if (own) {
+            const double2 b = M[i * n + lane];
+            M[i * n + lane] = make_double2(b.x - sr, b.y - si);
+        }
+        wave_lds_order();
+    };
+    for (int i = 0; i < n; ++i) {
+        double s2;
+        if (i > 0) {
+            // a second pass only where the first removed more than half of
+            // the row's squared norm (the DGKS criterion, "twice is
+            // enough"): a row of a nearly unitary link keeps almost all of
+            // it, and its one pass is orthogonal to rounding already
+            const double s0 = row_norm2(i);
+            project(i);
+            s2 = row_norm2(i);
+            if (s2 < 0.5 * s0) {
+                project(i);
+                s2 = row_norm2(i);
+            }
+        } else {
+            s2 = row_norm2(i);
+        }
         const double inv = s2 >= DBL_MIN ? newton_rsqrt(s2) : rsqrt(s2);
         if (own) {
             M[i * n + lane].x *= inv;
