@@ -64,18 +64,23 @@ def test_wide_observables_parity(gpu, nc, dtype):
     np.testing.assert_allclose(to_np(lat.unitarity()), O.unitarity(U, nc, L), rtol=1e-6, atol=1e-14)
 
 
-@pytest.mark.parametrize("nc", [4, 9, 16, 32])
-def test_wide_reunitarize_parity(gpu, nc):
+@pytest.mark.parametrize("nc,noise,tol", [(4, 1e-3, 1e-12), (9, 1e-3, 1e-12), (16, 1e-3, 1e-12), (32, 1e-3, 1e-12),
+                                          (9, 1.0, 1e-10), (16, 1.0, 1e-10), (32, 1.0, 1e-10)])
+def test_wide_reunitarize_parity(gpu, nc, noise, tol):
+    """Near-unitary links (noise 1e-3: one Gram-Schmidt pass per row) and
+    general ones (noise 1: the later rows lose more than half their norm to
+    the projection and take the second pass); the latter agree with the
+    oracle to the conditioning of a random matrix times the unit roundoff."""
     L = (4, 2, 2, 2)
     rng = np.random.default_rng(nc)
     U = O.new_field(nc, L, hot=True, seed=9)
-    U = U + 1e-3 * (rng.standard_normal(U.shape) + 1j * rng.standard_normal(U.shape))
+    U = U + noise * (rng.standard_normal(U.shape) + 1j * rng.standard_normal(U.shape))
     lat = gpu_lattice(gpu, nc, L, "f64" if nc > 8 else "f64w", field=U)
     before = to_np(lat.reunitarize(report=True))
     after = to_np(lat.export())
     np.testing.assert_allclose(before, O.unitarity(U, nc, L), rtol=1e-10)
     O.reunitarize(U, nc, L)
-    assert np.abs(after - U).max() < 1e-12
+    assert np.abs(after - U).max() < tol
     assert to_np(lat.unitarity()).max() < 1e-13
 
 
