@@ -1123,12 +1123,14 @@ __device__ __forceinline__ void lds_det(double2* D, int n, double& dr, double& d
         const bool split = n > 8;
         const int q = c & 31, half = c >> 5;
         const bool works = (split || half == 0) && q >= col && q < n;
+        // the pivot row's entry of column q, read once: only rows below it
+        // change in this column's elimination
+        const double2 u = works ? D[col * n + q] : make_double2(0.0, 0.0);
         for (int r = col + 1 + (split ? half : 0); r < n; r += split ? 2 : 1) {
             const double2 m = D[r * n + col];
             const double fr = (m.x * pr + m.y * pi) * inv;
             const double fi = (m.y * pr - m.x * pi) * inv;
             if (works) {
-                const double2 u = D[col * n + q];
                 double2 w = D[r * n + q];
                 w.x -= fr * u.x - fi * u.y;
                 w.y -= fr * u.y + fi * u.x;
